@@ -1,0 +1,320 @@
+"""FP64 oracle: open-shell pair residual, closed-shell residual, Jacobi, energies.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+"""
+import numpy as np
+
+SPIN = {"AA": (0, 0), "BB": (1, 1), "AB": (0, 1), "BA": (1, 0)}
+ORDER = ("AA", "BB", "AB", "BA")
+
+
+def stored_blocks(i, j, is_somo):
+    """Spin blocks kept for pair (i, j), i <= j (Sec. II.A, high-spin cases).
+
+    SOMOs are occupied for alpha only.  A block s s' needs i in occ_s and
+    j in occ_s'; same-spin blocks vanish for i == j (Pauli); for i == j the
+    beta-alpha block is the transpose of the alpha-beta block and is not kept.
+    DOMO-DOMO pairs thus have 4 blocks, DOMO-SOMO pairs 2 (AA and the one with
+    the SOMO as alpha electron), SOMO-SOMO pairs 1 (AA), diagonal DOMO pairs 1.
+    """
+    out = []
+    for name in ORDER:
+        s1, s2 = SPIN[name]
+        in1 = s1 == 0 or not is_somo[i]
+        in2 = s2 == 0 or not is_somo[j]
+        if not (in1 and in2):
+            continue
+        if s1 == s2 and i == j:
+            continue
+        if i == j and name == "BA":
+            continue
+        out.append(name)
+    return out
+
+
+def name_of(s1, s2):
+    for k, v in SPIN.items():
+        if v == (s1, s2):
+            return k
+    raise KeyError((s1, s2))
+
+
+class Inputs:
+    """Everything the residual reads, held per pair in plain numpy arrays.
+
+    pairs      list of (i, j) with i <= j (retained pairs)
+    B[p]       (m_p, n_p, n_p) density-fitting three-index integrals (Q|ac)
+    K[p]       (n_p, n_p) spatial exchange integrals (i a | j b)
+    eps_a[p], eps_b[p]   (n_p,) virtual PNO energies per spin
+    f_a, f_b   (n_occ, n_occ) occupied Fock matrices per spin
+    S(p, q)    overlap S_{p,q} (n_p x n_q) between the PNOs of two pairs
+    B and S may be callables (lazy regeneration for large workloads).
+    """
+
+    def __init__(self, n_occ, is_somo, pairs, B, K, eps_a, eps_b, f_a, f_b, S):
+        self.n_occ = int(n_occ)
+        self.is_somo = np.asarray(is_somo).astype(bool)
+        self.pairs = [(int(i), int(j)) for i, j in pairs]
+        self.index = {pq: p for p, pq in enumerate(self.pairs)}
+        self._B, self.K, self.eps_a, self.eps_b = B, K, eps_a, eps_b
+        self.f_a, self.f_b = np.asarray(f_a, dtype=np.float64), np.asarray(f_b, dtype=np.float64)
+        self._S = S
+
+    def B(self, p):
+        return self._B(p) if callable(self._B) else self._B[p]
+
+    def S(self, p, q):
+        return self._S(p, q) if callable(self._S) else self._S[(p, q)]
+
+    def npno(self, p):
+        return len(self.eps_a[p])
+
+    def occ(self, s):
+        return [k for k in range(self.n_occ) if s == 0 or not self.is_somo[k]]
+
+    def fock(self, s):
+        return self.f_a if s == 0 else self.f_b
+
+    def eps(self, s, p):
+        return self.eps_a[p] if s == 0 else self.eps_b[p]
+
+    def blocks(self, p):
+        i, j = self.pairs[p]
+        return stored_blocks(i, j, self.is_somo)
+
+    @classmethod
+    def from_problem(cls, prob, B=None, K=None, S=None, eps_a=None, eps_b=None):
+        """Unpack flat arrays laid out by the workload descriptors.
+
+        B, K, S: flat arrays; when B or S is None they are regenerated per pair
+        or per coupling from the seeded counters when first needed."""
+        P = prob.n_pairs
+        pairs = list(zip(prob.pi.tolist(), prob.pj.tolist()))
+        n = prob.npno.astype(int)
+        m = prob.naux.astype(int)
+        eps_a = prob.eps_a if eps_a is None else eps_a
+        eps_b = prob.eps_b if eps_b is None else eps_b
+        ea = [eps_a[prob.off_eps[p]:prob.off_eps[p] + n[p]].copy() for p in range(P)]
+        eb = [eps_b[prob.off_eps[p]:prob.off_eps[p] + n[p]].copy() for p in range(P)]
+        if K is None:
+            K = prob.materialize("K")
+        Kd = [K[prob.off_K[p]:prob.off_K[p] + n[p] ** 2].reshape(n[p], n[p]).copy() for p in range(P)]
+        if B is None:
+            cache = {}
+
+            def Bf(p):
+                if p not in cache:
+                    cache[p] = prob.pair_B(p)
+                return cache[p]
+        else:
+            def Bf(p):
+                o = prob.off_B[p]
+                return B[o:o + m[p] * n[p] ** 2].reshape(m[p], n[p], n[p])
+        # coupling lookup (target, source) -> first CSR entry
+        where = {}
+        for p in range(P):
+            for e in range(prob.cpl_rowptr[p], prob.cpl_rowptr[p + 1]):
+                where.setdefault((p, int(prob.cpl_src[e])), e)
+        S_full = S if S is not None else (prob.S_host if prob.S_host is not None else None)
+        s_cache = {}
+
+        def Sf(p, q):
+            e = where[(p, q)]
+            o = int(prob.cpl_off_S[e])
+            if S_full is not None:
+                W = S_full[o:o + n[q] * n[p]].reshape(n[q], n[p])
+            else:
+                if o not in s_cache:
+                    segs = prob.segs["S"]
+                    u = int(np.searchsorted(segs["off"], o))
+                    s_cache[o] = prob.segment("S", u)[0]
+                W = s_cache[o]
+            return W.T          # stored [c][a] = <c_q|a_p>  ->  S_{p,q}[a][c]
+        return cls(prob.n_occ, prob.is_somo, pairs, Bf, Kd, ea, eb, prob.f_a, prob.f_b, Sf)
+
+
+def unpack_T(prob, flat):
+    """Flat T/R array -> {(p, block): n x n} following the workload layout."""
+    out = {}
+    for p in range(prob.n_pairs):
+        n = int(prob.npno[p])
+        o = int(prob.off_T[p])
+        for name in stored_blocks(int(prob.pi[p]), int(prob.pj[p]), prob.is_somo.astype(bool)):
+            out[(p, name)] = flat[o:o + n * n].reshape(n, n).copy()
+            o += n * n
+    return out
+
+
+def pack_T(prob, blocks, out=None):
+    flat = np.zeros(prob.n_T) if out is None else out
+    for p in range(prob.n_pairs):
+        n = int(prob.npno[p])
+        o = int(prob.off_T[p])
+        for name in stored_blocks(int(prob.pi[p]), int(prob.pj[p]), prob.is_somo.astype(bool)):
+            if (p, name) in blocks:
+                flat[o:o + n * n] = blocks[(p, name)].ravel()
+            o += n * n
+    return flat
+
+
+def t_lookup(inp, T, k, l, s1, s2):
+    """Amplitude block T^{s1 s2} of the ordered pair (k, l) in the PNOs of {k, l}.
+
+    Returns (pair, block, transposed, matrix) or None when the pair is not
+    retained or the block vanishes.  Exchanging both electrons (occupied and
+    virtual labels together) leaves a doubles amplitude unchanged, so for
+    k > l the block is the transposed s2 s1 block of (l, k)."""
+    if k == l and s1 == s2:
+        return None
+    if k <= l:
+        q = inp.index.get((k, l))
+        if q is None:
+            return None
+        if k == l:
+            mat = T[(q, "AB")]
+            return (q, "AB", s1 == 1, mat.T if s1 == 1 else mat)
+        name = name_of(s1, s2)
+        if (q, name) not in T:
+            return None
+        return (q, name, False, T[(q, name)])
+    q = inp.index.get((l, k))
+    if q is None:
+        return None
+    name = name_of(s2, s1)
+    if (q, name) not in T:
+        return None
+    return (q, name, True, T[(q, name)].T)
+
+
+def denominators(inp, p, name):
+    i, j = inp.pairs[p]
+    s1, s2 = SPIN[name]
+    return (inp.eps(s1, p)[:, None] + inp.eps(s2, p)[None, :]
+            - inp.fock(s1)[i, i] - inp.fock(s2)[j, j])
+
+
+def driver(inp, p, name):
+    s1, s2 = SPIN[name]
+    Kp = inp.K[p]
+    return Kp - Kp.T if s1 == s2 else Kp.copy()
+
+
+def ladder(Bp, Tb):
+    """sum_Q B^Q T (B^Q)^T: R_ab = sum_Q sum_cd B^Q_ac T_cd B^Q_bd, as two matmuls
+    over the combined (Q, d) index."""
+    m, n, _ = Bp.shape
+    X = (Bp.reshape(m * n, n) @ Tb).reshape(m, n, n)            # X[Q,a,d] = sum_c B[Q,a,c] T[c,d]
+    return X.transpose(1, 0, 2).reshape(n, m * n) @ Bp.transpose(0, 2, 1).reshape(m * n, n)
+
+
+def projection_terms(inp, T, p, name):
+    """The occupied-Fock terms of block `name` of pair p: list of
+    (weight, q, S_pq, source tuple from t_lookup)."""
+    i, j = inp.pairs[p]
+    s1, s2 = SPIN[name]
+    out = []
+    for k in inp.occ(s1):                      # k replaces i
+        if k == i:
+            continue
+        w = inp.fock(s1)[k, i]
+        if w == 0.0:
+            continue
+        src = t_lookup(inp, T, k, j, s1, s2)
+        if src is None:
+            continue
+        out.append((w, src[0], inp.S(p, src[0]), src))
+    for k in inp.occ(s2):                      # k replaces j
+        if k == j:
+            continue
+        w = inp.fock(s2)[k, j]
+        if w == 0.0:
+            continue
+        src = t_lookup(inp, T, i, k, s1, s2)
+        if src is None:
+            continue
+        out.append((w, src[0], inp.S(p, src[0]), src))
+    return out
+
+
+def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladder")):
+    """Open-shell residual blocks {(p, name): R} for the given target pairs."""
+    R = {}
+    for p in (range(len(inp.pairs)) if pairs is None else pairs):
+        Bp = inp.B(p) if "ladder" in terms else None
+        for name in inp.blocks(p):
+            Tb = T[(p, name)]
+            r = np.zeros_like(Tb)
+            if "driver" in terms:
+                r += driver(inp, p, name)
+            if "fock" in terms:
+                r += denominators(inp, p, name) * Tb
+            if "projection" in terms:
+                for w, q, Spq, src in projection_terms(inp, T, p, name):
+                    r -= w * (Spq @ src[3] @ Spq.T)
+            if "ladder" in terms:
+                r += ladder(Bp, Tb)
+            R[(p, name)] = r
+    return R
+
+
+def jacobi(inp, T, R):
+    """T' = T - R / D for every stored block (all pairs at once)."""
+    return {key: T[key] - R[key] / denominators(inp, *key) for key in R}
+
+
+def pair_energies(inp, T):
+    """e[(p, name)] = w <K^{ss'}_p, T^{ss'}_p>, w = 1/2 same spin, 1 opposite."""
+    e = {}
+    for (p, name), Tb in T.items():
+        s1, s2 = SPIN[name]
+        w = 0.5 if s1 == s2 else 1.0
+        e[(p, name)] = w * float(np.sum(driver(inp, p, name) * Tb))
+    return e
+
+
+# ---------------------------------------------------------------------------
+# closed-shell reference (separate code path: spatial amplitudes only)
+# ---------------------------------------------------------------------------
+
+def residual_cs(pairs, B, K, eps, f, S, Tcs):
+    """Closed-shell residual of the same model on spatial amplitudes T_p (i <= j).
+
+    R_p = K_p + (eps + eps - f_ii - f_jj) o T_p - sum_{k != i} f_ki S T_kj S^T
+          - sum_{k != j} f_kj S T_ik S^T + sum_Q B^Q T_p B^Q^T,
+    with T_(k,l) = T_(l,k)^T for k > l."""
+    index = {pq: p for p, pq in enumerate(pairs)}
+
+    def amp(k, l):
+        if k <= l:
+            q = index.get((k, l))
+            return None if q is None else (q, Tcs[q])
+        q = index.get((l, k))
+        return None if q is None else (q, Tcs[q].T)
+
+    n_occ = f.shape[0]
+    R = []
+    for p, (i, j) in enumerate(pairs):
+        Tp = Tcs[p]
+        r = K[p] + (eps[p][:, None] + eps[p][None, :] - f[i, i] - f[j, j]) * Tp
+        for k in range(n_occ):
+            if k != i and f[k, i] != 0.0:
+                a = amp(k, j)
+                if a is not None:
+                    Spq = S(p, a[0])
+                    r = r - f[k, i] * (Spq @ a[1] @ Spq.T)
+            if k != j and f[k, j] != 0.0:
+                a = amp(i, k)
+                if a is not None:
+                    Spq = S(p, a[0])
+                    r = r - f[k, j] * (Spq @ a[1] @ Spq.T)
+        Bp = B(p)
+        for Q in range(Bp.shape[0]):
+            r = r + Bp[Q] @ Tp @ Bp[Q].T
+        R.append(r)
+    return R
+
+
+def pair_energies_cs(pairs, K, Tcs):
+    """Closed-shell pair energy (2 - delta_ij) <K, 2T - T^T>."""
+    return [(2.0 - (i == j)) * float(np.sum(K[p] * (2.0 * Tcs[p] - Tcs[p].T)))
+            for p, (i, j) in enumerate(pairs)]

@@ -1,0 +1,100 @@
+"""Brute-force spin-orbital residual for the canonical limit (tiny inputs only).
+
+TEST INFRASTRUCTURE ONLY.
+
+When PNOs are not truncated the pair method must reduce to its canonical
+counterpart (Sec. IV.A).  Here every pair shares one V-dimensional virtual
+space (all overlaps are identities), and the textbook spin-orbital doubles
+terms of the model are formed from explicit antisymmetrised integrals:
+
+  R_IJ^AB = <AB||IJ> + (e_A + e_B) t_IJ^AB - sum_K f_KI t_KJ^AB
+            - sum_K f_KJ t_IK^AB + 1/2 sum_CD <AB||CD> t_IJ^CD
+  E       = 1/4 sum_IJAB <IJ||AB> t_IJ^AB
+
+with (ac|bd) = sum_Q B^Q_ac B^Q_bd and (ia|jb) given per ordered pair.
+"""
+import numpy as np
+
+
+def _spin_orbitals(n_occ, is_somo, V):
+    occ = [(i, 0) for i in range(n_occ)] + [(i, 1) for i in range(n_occ) if not is_somo[i]]
+    vir = [(a, 0) for a in range(V)] + [(a, 1) for a in range(V)]
+    return occ, vir
+
+
+def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblocks, pairs):
+    """Pair blocks of the residual and the total energy of the given amplitudes.
+
+    Bg       (m, V, V) three-index integrals shared by all pairs
+    Kpair    {(i, j): V x V} (i a | j b) for i <= j
+    Tblocks  {((i, j), name): V x V} stored amplitude blocks (same-spin antisymmetric)
+    pairs    list of (i, j) covering every occupied pair (i <= j)
+    Returns ({((i, j), name): V x V residual block}, energy of the amplitudes).
+    """
+    V = Bg.shape[1]
+    occ, vir = _spin_orbitals(n_occ, is_somo, V)
+    no, nv = len(occ), len(vir)
+    oidx = {o: x for x, o in enumerate(occ)}
+    spins = {"AA": (0, 0), "BB": (1, 1), "AB": (0, 1), "BA": (1, 0)}
+
+    def Kord(i, j):
+        return Kpair[(i, j)] if i <= j else Kpair[(j, i)].T
+
+    # <AB||IJ>
+    g_vvoo = np.zeros((nv, nv, no, no))
+    for I, (i, si) in enumerate(occ):
+        for J, (j, sj) in enumerate(occ):
+            for A, (a, sa) in enumerate(vir):
+                for B, (b, sb) in enumerate(vir):
+                    v = 0.0
+                    if sa == si and sb == sj:
+                        v += Kord(i, j)[a, b]
+                    if sa == sj and sb == si:
+                        v -= Kord(j, i)[a, b]
+                    g_vvoo[A, B, I, J] = v
+    # <AB||CD>
+    acbd = np.einsum("qac,qbd->abcd", Bg, Bg)          # (ac|bd)
+    g_vvvv = np.zeros((nv, nv, nv, nv))
+    for sa in (0, 1):
+        for sb in (0, 1):
+            for sc in (0, 1):
+                for sd in (0, 1):
+                    blk = np.zeros((V, V, V, V))
+                    if sa == sc and sb == sd:
+                        blk += acbd
+                    if sa == sd and sb == sc:
+                        blk -= acbd.transpose(0, 1, 3, 2)      # (ad|bc)
+                    g_vvvv[sa * V:(sa + 1) * V, sb * V:(sb + 1) * V,
+                           sc * V:(sc + 1) * V, sd * V:(sd + 1) * V] = blk
+    # amplitudes as a fully antisymmetric tensor
+    t = np.zeros((no, no, nv, nv))
+    for ((i, j), name), Tb in Tblocks.items():
+        s1, s2 = spins[name]
+        I, J = oidx[(i, s1)], oidx[(j, s2)]
+        for a in range(V):
+            for b in range(V):
+                A, B = s1 * V + a, s2 * V + b
+                t[I, J, A, B] = Tb[a, b]
+                t[J, I, B, A] = Tb[a, b]
+                t[I, J, B, A] = -Tb[a, b]
+                t[J, I, A, B] = -Tb[a, b]
+    # Fock in spin orbitals
+    fo = np.zeros((no, no))
+    for K, (k, sk) in enumerate(occ):
+        for I, (i, si) in enumerate(occ):
+            if sk == si:
+                fo[K, I] = (f_a if sk == 0 else f_b)[k, i]
+    ev = np.concatenate([eps_a, eps_b])
+    R = (g_vvoo.transpose(2, 3, 0, 1)
+         + (ev[None, None, :, None] + ev[None, None, None, :]) * t
+         - np.einsum("ki,kjab->ijab", fo, t)
+         - np.einsum("kj,ikab->ijab", fo, t)
+         + 0.5 * np.einsum("abcd,ijcd->ijab", g_vvvv, t))
+    E = 0.25 * float(np.sum(g_vvoo.transpose(2, 3, 0, 1) * t))
+    out = {}
+    for (i, j) in pairs:
+        for name, (s1, s2) in spins.items():
+            if (i, s1) in oidx and (j, s2) in oidx:
+                I, J = oidx[(i, s1)], oidx[(j, s2)]
+                out[((i, j), name)] = R[I, J][s1 * V:(s1 + 1) * V, s2 * V:(s2 + 1) * V].copy()
+    return out, E

@@ -1,0 +1,298 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.model import stored_blocks, residual_cs, pair_energies_cs, ladder, t_lookup
+from oracle.solver import keys_of, flatten, unflatten, apply_operator
+from tests.oracle_helpers import make_inputs, random_T, inner
+from workload import build_problem
+
+
+# ---------------------------------------------------------------- block rule
+def test_spin_case_counts_per_pair_class():
+    # Sec. II.A: DOMO-DOMO pairs carry aa, ab, bb; SOMO-DOMO two (aa, ab); SOMO-SOMO one (aa)
+    somo = np.array([0, 0, 1, 1], dtype=bool)
+    assert stored_blocks(0, 1, somo) == ["AA", "BB", "AB", "BA"]     # ab and ba both kept for i < j
+    assert stored_blocks(0, 0, somo) == ["AB"]                       # diagonal DOMO pair
+    assert stored_blocks(0, 2, somo) == ["AA", "BA"]                 # DOMO-SOMO: the SOMO (j) is the alpha electron
+    assert stored_blocks(2, 3, somo) == ["AA"]                       # SOMO-SOMO
+    assert stored_blocks(2, 2, somo) == []                           # SOMO diagonal: nothing
+    somo2 = np.array([1, 0, 0], dtype=bool)
+    assert stored_blocks(0, 1, somo2) == ["AA", "AB"]                # SOMO (i) first: alpha-beta
+
+
+@pytest.mark.parametrize("name,blocks,pairs", [("tiny", 561, 171), ("chain", 11958, 3150)])
+def test_generator_masks_follow_oracle_rule(name, blocks, pairs):
+    prob = build_problem(name)
+    assert prob.n_pairs == pairs
+    bits = {"AA": 1, "BB": 2, "AB": 4, "BA": 8}
+    total = 0
+    for p in range(prob.n_pairs):
+        names = stored_blocks(int(prob.pi[p]), int(prob.pj[p]), prob.is_somo.astype(bool))
+        assert int(prob.blocks[p]) == sum(bits[n] for n in names)
+        total += len(names)
+    assert total == blocks
+
+
+def test_generator_lists_every_nonzero_projection_term():
+    prob = build_problem("chain", n_occ=30, band=5, somos=(9, 20))
+    inp = oracle.Inputs.from_problem(prob)
+    listed = {(p, int(prob.cpl_src[e]), int(prob.cpl_k[e]), int(prob.cpl_side[e]))
+              for p in range(prob.n_pairs) for e in range(prob.cpl_rowptr[p], prob.cpl_rowptr[p + 1])}
+    want = set()
+    for p, (i, j) in enumerate(inp.pairs):
+        for side, (rep, keep) in enumerate(((i, j), (j, i))):
+            for k in range(inp.n_occ):
+                if k != rep and inp.f_a[k, rep] != 0.0:
+                    q = inp.index.get((min(k, keep), max(k, keep)))
+                    if q is not None:
+                        want.add((p, q, k, side))
+    assert listed == want
+
+
+# ------------------------------------------------- P1 closed-shell reduction
+def test_closed_shell_reduction_exact():
+    # Abstract and Sec. II.B.2: with no SOMOs the open-shell formalism must reproduce
+    # the closed-shell one (one PNO set for all spins).
+    rng = np.random.default_rng(11)
+    inp = make_inputs(rng, n_occ=6, somos=(), npno=5, naux=7)
+    Tcs = []
+    for p, (i, j) in enumerate(inp.pairs):
+        g = 1e-2 * rng.standard_normal((5, 5))
+        Tcs.append((g + g.T) / 2 if i == j else g)
+    T = {}
+    for p, (i, j) in enumerate(inp.pairs):
+        for name in inp.blocks(p):
+            T[(p, name)] = Tcs[p] - Tcs[p].T if name in ("AA", "BB") else Tcs[p].copy()
+    R = oracle.residual_os(inp, T)
+    Rcs = residual_cs(inp.pairs, inp.B, inp.K, inp.eps_a, inp.f_a, inp.S, Tcs)
+    for p, (i, j) in enumerate(inp.pairs):
+        for name in inp.blocks(p):
+            want = Rcs[p] - Rcs[p].T if name in ("AA", "BB") else Rcs[p]
+            np.testing.assert_allclose(R[(p, name)], want, rtol=0, atol=1e-14)
+    # energies after a Jacobi step
+    Tn = oracle.jacobi(inp, T, R)
+    e_os = sum(oracle.pair_energies(inp, Tn).values())
+    Tcs_n = [Tcs[p] - Rcs[p] / (inp.eps_a[p][:, None] + inp.eps_a[p][None, :]
+                                - inp.f_a[i, i] - inp.f_a[j, j]) for p, (i, j) in enumerate(inp.pairs)]
+    e_cs = sum(pair_energies_cs(inp.pairs, inp.K, Tcs_n))
+    assert abs(e_os - e_cs) <= 1e-15 * max(1.0, abs(e_cs)) * 10
+
+
+def test_closed_shell_energy_identity_worked():
+    # same-spin + opposite-spin energies of a closed-shell i<j pair: 2<K, 2T - T^T>
+    rng = np.random.default_rng(3)
+    K = rng.standard_normal((4, 4))
+    T = rng.standard_normal((4, 4))
+    same = 0.5 * np.sum((K - K.T) * (T - T.T))
+    opp = np.sum(K * T)
+    assert np.isclose(2 * same + 2 * opp, 2 * np.sum(K * (2 * T - T.T)), rtol=1e-14)
+
+
+# ------------------------------------ P2 canonical limit vs brute force
+@pytest.mark.parametrize("somos", [(1,), (1, 3)])
+def test_canonical_limit_matches_spin_orbital_bruteforce(somos):
+    # Sec. IV.A: with no truncation the method equals its canonical counterpart
+    rng = np.random.default_rng(5 + len(somos))
+    inp = make_inputs(rng, n_occ=5, somos=somos, npno=5, naux=6, shared_space=True)
+    T = random_T(rng, inp, scale=0.05)
+    R = oracle.residual_os(inp, T)
+    Tb = {(inp.pairs[p], name): v for (p, name), v in T.items()}
+    Kp = {inp.pairs[p]: inp.K[p] for p in range(len(inp.pairs))}
+    Rbf, Ebf = oracle.residual_spinorbital(inp.n_occ, inp.is_somo, inp.B(0), Kp, inp.eps_a[0],
+                                           inp.eps_b[0], inp.f_a, inp.f_b, Tb, inp.pairs)
+    n_checked = 0
+    for (p, name), r in R.items():
+        np.testing.assert_allclose(r, Rbf[(inp.pairs[p], name)], rtol=0, atol=1e-13)
+        n_checked += 1
+    assert n_checked == len(keys_of(inp))
+    # R_(j,i) = R_(i,j)^T with spins swapped (ordered pairs), e.g. the beta-alpha diagonal block
+    for p, (i, j) in enumerate(inp.pairs):
+        if i == j and (p, "AB") in R:
+            np.testing.assert_allclose(Rbf[((i, i), "BA")], R[(p, "AB")].T, atol=1e-13)
+    # energy weights: sum of pair energies = 1/4 sum <IJ||AB> t
+    e = sum(oracle.pair_energies(inp, T).values())
+    assert abs(e - Ebf) < 1e-14
+
+
+# ----------------------------- P3/P9 relabelling and PNO permutations
+def _reversed_inputs(inp):
+    n = inp.n_occ
+    rev = lambda k: n - 1 - k
+    new_pairs = [(rev(j), rev(i)) for (i, j) in inp.pairs]
+    order = sorted(range(len(new_pairs)), key=lambda p: new_pairs[p])
+    newp = {old: new for new, old in enumerate(order)}
+    pairs = [new_pairs[o] for o in order]
+    B = {newp[p]: inp.B(p) for p in range(len(inp.pairs))}
+    K = {newp[p]: inp.K[p].T.copy() for p in range(len(inp.pairs))}
+    ea = {newp[p]: inp.eps_a[p] for p in range(len(inp.pairs))}
+    eb = {newp[p]: inp.eps_b[p] for p in range(len(inp.pairs))}
+    perm = np.arange(n)[::-1]
+    fa = inp.f_a[np.ix_(perm, perm)]
+    fb = inp.f_b[np.ix_(perm, perm)]
+    inv = {v: k for k, v in newp.items()}
+    S = lambda p, q: inp.S(inv[p], inv[q])
+    new = oracle.Inputs(n, inp.is_somo[::-1].copy(), pairs, B, K, ea, eb, fa, fb, S)
+    return new, newp
+
+
+def test_orbital_relabelling_transposes_blocks():
+    # R_(j,i)^{s's} = (R_(i,j)^{ss'})^T: reversing the chain swaps the electrons of every pair
+    rng = np.random.default_rng(21)
+    inp = make_inputs(rng, n_occ=7, somos=(2, 5), npno=4, naux=5, band=3)
+    T = random_T(rng, inp)
+    new, newp = _reversed_inputs(inp)
+    swap = {"AA": "AA", "BB": "BB", "AB": "BA", "BA": "AB"}
+    Tn = {}
+    for (p, name), v in T.items():
+        i, j = inp.pairs[p]
+        nn = "AB" if i == j else swap[name]
+        Tn[(newp[p], nn)] = v if i == j else v.T
+    R = oracle.residual_os(inp, T)
+    Rn = oracle.residual_os(new, Tn)
+    assert set(Rn) == set(Tn)
+    for (p, name), v in R.items():
+        i, j = inp.pairs[p]
+        if i == j:
+            np.testing.assert_allclose(Rn[(newp[p], "AB")], v, atol=1e-15)
+        else:
+            np.testing.assert_allclose(Rn[(newp[p], swap[name])], v.T, atol=1e-15)
+
+
+def test_pno_permutation_covariance():
+    # Sec. II.B.2: pair energies and pair functions are invariant to unitary rotations
+    # within the virtual space; a relabelling of one pair's PNOs permutes its residual
+    rng = np.random.default_rng(8)
+    inp = make_inputs(rng, n_occ=5, somos=(3,), npno=5, naux=6)
+    T = random_T(rng, inp)
+    R = oracle.residual_os(inp, T)
+    p0 = 4
+    pi = rng.permutation(5)
+    B = {p: (inp.B(p)[:, pi][:, :, pi] if p == p0 else inp.B(p)) for p in range(len(inp.pairs))}
+    K = {p: (inp.K[p][np.ix_(pi, pi)] if p == p0 else inp.K[p]) for p in range(len(inp.pairs))}
+    ea = {p: (inp.eps_a[p][pi] if p == p0 else inp.eps_a[p]) for p in range(len(inp.pairs))}
+    eb = {p: (inp.eps_b[p][pi] if p == p0 else inp.eps_b[p]) for p in range(len(inp.pairs))}
+
+    def S(p, q):
+        s = inp.S(p, q)
+        if p == p0:
+            s = s[pi, :]
+        if q == p0:
+            s = s[:, pi]
+        return s
+    new = oracle.Inputs(inp.n_occ, inp.is_somo, inp.pairs, B, K, ea, eb, inp.f_a, inp.f_b, S)
+    Tp = {k: (v[np.ix_(pi, pi)] if k[0] == p0 else v) for k, v in T.items()}
+    Rp = oracle.residual_os(new, Tp)
+    for k, v in R.items():
+        want = v[np.ix_(pi, pi)] if k[0] == p0 else v
+        np.testing.assert_allclose(Rp[k], want, atol=1e-15)
+
+
+# ------------------------------------------------------- P5 / P6 closed forms
+def test_mp2_limit_closed_form():
+    rng = np.random.default_rng(2)
+    inp = make_inputs(rng, n_occ=5, somos=(4,), npno=4, naux=3, b_scale=0.0, f_off=0.0)
+    zero = {k: np.zeros((4, 4)) for k in keys_of(inp)}
+    R = oracle.residual_os(inp, zero)
+    Tn = oracle.jacobi(inp, zero, R)
+    e = oracle.pair_energies(inp, Tn)
+    for (p, name), t in Tn.items():
+        K = inp.K[p] - inp.K[p].T if name in ("AA", "BB") else inp.K[p]
+        D = oracle.denominators(inp, p, name)
+        np.testing.assert_allclose(t, -K / D, rtol=1e-15, atol=0)
+        w = 0.5 if name in ("AA", "BB") else 1.0
+        assert abs(e[(p, name)] + w * np.sum(K * K / D)) < 1e-16
+
+
+def test_ladder_special_cases():
+    rng = np.random.default_rng(4)
+    T = rng.standard_normal((6, 6))
+    np.testing.assert_allclose(ladder(np.eye(6)[None], T), T, rtol=0, atol=1e-15)
+    u = rng.standard_normal(6)
+    Bq = np.outer(u, u)[None]
+    np.testing.assert_allclose(ladder(Bq, T), (u @ T @ u) * np.outer(u, u), rtol=1e-13)
+    # additivity over Q
+    B2 = rng.standard_normal((3, 6, 6))
+    want = sum(B2[q] @ T @ B2[q].T for q in range(3))
+    np.testing.assert_allclose(ladder(B2, T), want, rtol=1e-13)
+
+
+# ----------------------------------------------------- P7 dense linear solve
+def test_jacobi_diis_converges_to_dense_solution():
+    rng = np.random.default_rng(7)
+    inp = make_inputs(rng, n_occ=4, somos=(3,), npno=4, naux=6, b_scale=0.15)
+    Tstar, A = oracle.dense_solution(inp)
+    zero = {k: np.zeros_like(v) for k, v in Tstar.items()}
+    T, hist = oracle.solve(inp, zero, 60, use_diis=True, tol_r=1e-13, tol_e=1e-15)
+    for k in Tstar:
+        np.testing.assert_allclose(T[k], Tstar[k], atol=1e-12)
+    # converged residual vanishes
+    R = oracle.residual_os(inp, Tstar)
+    assert max(np.max(np.abs(r)) for r in R.values()) < 1e-13
+    # DIIS needs fewer iterations than plain Jacobi to reach 1e-10
+    _, h_j = oracle.solve(inp, zero, 60, use_diis=False)
+    it_j = next((k for k, (_, r) in enumerate(h_j) if r < 1e-10), 99)
+    it_d = next((k for k, (_, r) in enumerate(hist) if r < 1e-10), 99)
+    assert it_d <= it_j
+
+
+# -------------------------------------------- P8 self-adjointness, Lambda = w T
+def test_operator_self_adjoint():
+    rng = np.random.default_rng(9)
+    inp = make_inputs(rng, n_occ=6, somos=(2, 4), npno=5, naux=6, band=3)
+    keys = keys_of(inp)
+    G = {k: rng.standard_normal((5, 5)) for k in keys}
+    T = {k: rng.standard_normal((5, 5)) for k in keys}
+    a = inner(G, apply_operator(inp, T))
+    b = inner(apply_operator(inp, G), T)
+    assert abs(a - b) <= 1e-12 * abs(a)
+
+
+def test_lambda_equals_weighted_amplitudes():
+    # the paper approximates Lambda by T^dagger (Sec. II.A); for this model the Lambda
+    # equations (D + A)^T Lambda = -dE/dT give Lambda = w T exactly
+    rng = np.random.default_rng(10)
+    inp = make_inputs(rng, n_occ=4, somos=(1,), npno=3, naux=4)
+    Tstar, A = oracle.dense_solution(inp)
+    keys = keys_of(inp)
+    dE = {}
+    for (p, name) in keys:
+        K = inp.K[p] - inp.K[p].T if name in ("AA", "BB") else inp.K[p]
+        dE[(p, name)] = (0.5 if name in ("AA", "BB") else 1.0) * K
+    lam = np.linalg.solve(A.T, -flatten(dE, keys))
+    lam = unflatten(lam, keys, inp)
+    for (p, name) in keys:
+        w = 0.5 if name in ("AA", "BB") else 1.0
+        np.testing.assert_allclose(lam[(p, name)], w * Tstar[(p, name)], atol=1e-13)
+
+
+# ---------------------------------------------------- P10 VJP by finite differences
+def test_vjp_matches_central_differences_and_adjoint_identity():
+    rng = np.random.default_rng(12)
+    inp = make_inputs(rng, n_occ=5, somos=(2,), npno=4, naux=5, band=2)
+    keys = keys_of(inp)
+    T = random_T(rng, inp, scale=0.1)
+    Lam = {k: rng.standard_normal(v.shape) for k, v in T.items()}
+    dT, dB = oracle.vjp(inp, T, Lam)
+
+    def L(Tx, Bx=None):
+        src = inp if Bx is None else oracle.Inputs(inp.n_occ, inp.is_somo, inp.pairs, Bx, inp.K,
+                                                   inp.eps_a, inp.eps_b, inp.f_a, inp.f_b, inp.S)
+        R = oracle.residual_os(src, Tx)
+        return inner(Lam, R)
+
+    h = 1e-5
+    dir_T = {k: rng.standard_normal(v.shape) for k, v in T.items()}
+    Tp = {k: T[k] + h * dir_T[k] for k in T}
+    Tm = {k: T[k] - h * dir_T[k] for k in T}
+    fd = (L(Tp) - L(Tm)) / (2 * h)
+    an = inner(dT, dir_T)
+    assert abs(fd - an) <= 1e-8 * max(1.0, abs(an))
+    # B direction (general, unsymmetrised)
+    Bd = {p: rng.standard_normal(inp.B(p).shape) for p in range(len(inp.pairs))}
+    Bp = {p: inp.B(p) + h * Bd[p] for p in Bd}
+    Bm = {p: inp.B(p) - h * Bd[p] for p in Bd}
+    fd = (L(T, Bp) - L(T, Bm)) / (2 * h)
+    an = sum(float(np.sum(dB[p] * Bd[p])) for p in dB)
+    assert abs(fd - an) <= 1e-8 * max(1.0, abs(an))

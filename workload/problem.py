@@ -1,0 +1,375 @@
+"""Synthetic open-shell DLPNO pair workloads.
+
+Data model (the paper's Sec. II.A high-spin spin cases and Sec. II.B.2/II.B.4
+spin-independent PNO sets):
+  * occupied orbitals 0..n_occ-1 on a 1-D chain; SOMOs are alpha-occupied and
+    beta-virtual, so occ_alpha = all, occ_beta = DOMOs;
+  * a retained pair p = (i, j), i <= j, owns n_p PNOs shared by every spin block
+    and m_p local density-fitting functions;
+  * a spin block s s' (first spin on electron i / virtual a, second on j / b) is
+    stored iff i in occ_s, j in occ_s', not (s == s' and i == j), and for i == j
+    only the alpha-beta block is kept (beta-alpha is its transpose);
+  * stored blocks of a pair are contiguous in the order AA, BB, AB, BA.
+
+Flat layouts (element offsets, 32-element aligned):
+  B  : per pair [Q][a][c], m_p x n_p x n_p, symmetric in (a, c)
+  T/R: per pair, stored blocks back to back, each n_p x n_p row-major [a][b]
+  K  : per pair n_p x n_p, the spatial exchange integrals (i a | j b)
+  eps: per pair n_p virtual energies per spin (eps_a / eps_b arrays)
+  S  : per directed coupling (target p <- source q): n_q x n_p row-major,
+       element [c][a] = overlap of source PNO c with target PNO a
+  f_a, f_b: n_occ x n_occ occupied Fock matrices per spin
+
+Couplings (CSR by target pair): target p = (i, j) reads source q when an
+occupied k replaces i (side 0, q = {k, j}, Fock weight f[k][i]) or replaces j
+(side 1, q = {i, k}, weight f[k][j]); only retained sources with a non-zero
+occupied Fock element are listed.
+"""
+from dataclasses import dataclass, field
+import numpy as np
+
+from . import philox
+
+BLOCK_NAMES = ("AA", "BB", "AB", "BA")
+BLOCK_BITS = {"AA": 1, "BB": 2, "AB": 4, "BA": 8}
+BLOCK_SPINS = {"AA": (0, 0), "BB": (1, 1), "AB": (0, 1), "BA": (1, 0)}
+
+# Philox field ids (fourth counter word)
+F_NPNO, F_NAUX, F_B, F_T, F_K, F_EPS, F_FDIAG, F_FOFF, F_S, F_QR = range(1, 11)
+
+# segment generation modes (see segment_values)
+MODE_PLAIN, MODE_SYM, MODE_ANTI, MODE_TRANS = 0, 1, 2, 3
+
+SEG_DTYPE = np.dtype([("off", np.int64), ("stream", np.int64), ("field", np.int32),
+                      ("mode", np.int32), ("layers", np.int32), ("rows", np.int32),
+                      ("cols", np.int32), ("pad", np.int32), ("scale", np.float64)])
+
+ALIGN = 32
+
+# name -> recipe.  Sizes and distributions follow the workload shapes of the
+# paper's tests (a small radical, a 1-D chain, a C160H322-like triplet alkane).
+CONFIGS = {
+    # 16 doubly + 2 singly occupied, all 171 pairs, n=12, m=80
+    "tiny": dict(n_occ=18, somos=(16, 17), band=None, npno=("fixed", 12),
+                 naux=("fixed", 80), sigma_B=0.05, S="qr60", seed=1, kappa=0.01,
+                 sigma_T=1e-2),
+    # 160 occupied (2 SOMOs), |i-j| <= 20, n ~ lognormal(mean 28), m ~ U{300..900}
+    "chain": dict(n_occ=160, somos=(53, 106), band=20, npno=("lognormal", 28.0, 0.4, 8, 64),
+                  naux=("uniform", 300, 900), sigma_B="scaled", S="random", seed=2,
+                  kappa=0.01, sigma_T=1e-2),
+    # C160H322-shaped: 481 occupied (2 SOMOs), |i-j| <= 40, n ~ lognormal(mean 30), m ~ U{400..1200}
+    "c160": dict(n_occ=481, somos=(160, 320), band=40, npno=("lognormal", 30.0, 0.4, 8, 64),
+                 naux=("uniform", 400, 1200), sigma_B="scaled", S="random", seed=3,
+                 kappa=0.01, sigma_T=1e-2),
+}
+
+
+def _align(x):
+    return (x + ALIGN - 1) // ALIGN * ALIGN
+
+
+def stored_blocks(i, j, is_somo):
+    """Names of the stored spin blocks of pair (i, j), i <= j, in storage order."""
+    occ = (lambda k: True, lambda k: not is_somo[k])  # alpha, beta occupation
+    out = []
+    for name in BLOCK_NAMES:
+        s1, s2 = BLOCK_SPINS[name]
+        if not (occ[s1](i) and occ[s2](j)):
+            continue
+        if s1 == s2 and i == j:
+            continue
+        if i == j and name == "BA":
+            continue
+        out.append(name)
+    return out
+
+
+@dataclass
+class Problem:
+    name: str
+    seed: int
+    n_occ: int
+    is_somo: np.ndarray            # uint8 [n_occ]
+    pi: np.ndarray                 # int32 [P]
+    pj: np.ndarray
+    npno: np.ndarray
+    naux: np.ndarray
+    blocks: np.ndarray             # uint32 [P] mask
+    off_B: np.ndarray              # int64 [P]
+    off_T: np.ndarray
+    off_K: np.ndarray
+    off_eps: np.ndarray
+    cpl_rowptr: np.ndarray         # int64 [P+1]
+    cpl_src: np.ndarray            # int32 [C]
+    cpl_k: np.ndarray
+    cpl_side: np.ndarray
+    cpl_off_S: np.ndarray          # int64 [C]
+    f_a: np.ndarray
+    f_b: np.ndarray
+    eps_a: np.ndarray
+    eps_b: np.ndarray
+    n_B: int
+    n_T: int
+    n_K: int
+    n_S: int
+    segs: dict = field(default_factory=dict)   # name -> SEG_DTYPE array
+    S_host: np.ndarray = None                  # set when S is built on the host (QR recipe)
+    pair_index: dict = field(default_factory=dict)
+
+    @property
+    def n_pairs(self):
+        return len(self.pi)
+
+    @property
+    def n_couplings(self):
+        return len(self.cpl_src)
+
+    def n_blocks(self):
+        return np.array([bin(int(b)).count("1") for b in self.blocks])
+
+    def block_list(self, p):
+        return [n for n in BLOCK_NAMES if self.blocks[p] & BLOCK_BITS[n]]
+
+    # ---------------- materialisation of the large fields ----------------
+    def materialize(self, what):
+        """Full flat array of 'B', 'T', 'K' or 'S' (host memory; small problems)."""
+        size = {"B": self.n_B, "T": self.n_T, "K": self.n_K, "S": self.n_S}[what]
+        if what == "S" and self.S_host is not None:
+            return self.S_host.copy()
+        out = np.zeros(size, dtype=np.float64)
+        for seg in self.segs[what]:
+            v = segment_values(self.seed, seg)
+            out[seg["off"]:seg["off"] + v.size] = v.ravel()
+        return out
+
+    def pair_B(self, p):
+        """B_p as an (m, n, n) array regenerated from its counters."""
+        seg = self.segs["B"][p]
+        return segment_values(self.seed, seg).reshape(seg["layers"], seg["rows"], seg["cols"])
+
+    def segment(self, what, idx):
+        seg = self.segs[what][idx]
+        return segment_values(self.seed, seg).reshape(seg["layers"], seg["rows"], seg["cols"])
+
+
+def segment_values(seed, seg):
+    """Values of one generated segment: layers x rows x cols (rows, cols <= 64)."""
+    L, R, C = int(seg["layers"]), int(seg["rows"]), int(seg["cols"])
+    mode, fld, stream, scale = int(seg["mode"]), int(seg["field"]), int(seg["stream"]), float(seg["scale"])
+    lay = np.arange(L, dtype=np.uint64)[:, None, None] * np.uint64(4096)
+    x = np.arange(R, dtype=np.uint64)[None, :, None]
+    y = np.arange(C, dtype=np.uint64)[None, None, :]
+    if mode == MODE_PLAIN:
+        idx = lay + x * np.uint64(64) + y
+    elif mode == MODE_TRANS:
+        idx = lay + y * np.uint64(64) + x
+    elif mode == MODE_SYM:
+        idx = lay + np.minimum(x, y) * np.uint64(64) + np.maximum(x, y)
+    elif mode == MODE_ANTI:
+        z1 = philox.normals(seed, fld, stream, lay + x * np.uint64(64) + y)
+        z2 = philox.normals(seed, fld, stream, lay + y * np.uint64(64) + x)
+        return (z1 - z2) * scale
+    else:
+        raise ValueError(mode)
+    return philox.normals(seed, fld, stream, idx) * scale
+
+
+def _dims(rule, seed, fld, P):
+    kind = rule[0]
+    if kind == "fixed":
+        return np.full(P, rule[1], dtype=np.int32)
+    streams = np.arange(P, dtype=np.uint64)
+    if kind == "uniform":
+        lo, hi = rule[1], rule[2]
+        u = philox.uniforms(seed, fld, streams, 0)
+        return (lo + np.floor(u * (hi - lo + 1))).astype(np.int32)
+    if kind == "lognormal":
+        mean, s, lo, hi = rule[1:]
+        u1 = philox.uniforms(seed, fld, streams, 0)
+        u2 = philox.uniforms(seed, fld, streams, 1)
+        z = np.sqrt(-2.0 * np.log1p(-u1)) * np.cos(2.0 * np.pi * u2)   # Box-Muller
+        mu = np.log(mean) - 0.5 * s * s                                 # arithmetic mean = `mean`
+        return np.clip(np.rint(np.exp(mu + s * z)), lo, hi).astype(np.int32)
+    raise ValueError(kind)
+
+
+def build_problem(name="tiny", **override):
+    """Build the descriptors and small inputs of a named (or customised) workload.
+
+    Overrides: any CONFIGS key, e.g. n_occ=24, band=6, somos=(8, 16)."""
+    cfg = dict(CONFIGS[name]) if name in CONFIGS else {}
+    cfg.update(override)
+    seed = int(cfg["seed"])
+    n_occ = int(cfg["n_occ"])
+    is_somo = np.zeros(n_occ, dtype=np.uint8)
+    for s in cfg["somos"]:
+        is_somo[s] = 1
+    band = cfg["band"]
+    band = n_occ if band is None else int(band)
+
+    # ---- retained pairs, chain order (i ascending, then j) ----
+    ii, jj = [], []
+    for i in range(n_occ):
+        for j in range(i, min(n_occ, i + band + 1)):
+            ii.append(i)
+            jj.append(j)
+    pi = np.array(ii, dtype=np.int32)
+    pj = np.array(jj, dtype=np.int32)
+    P = len(pi)
+    pair_index = {(int(a), int(b)): p for p, (a, b) in enumerate(zip(pi, pj))}
+
+    npno = _dims(cfg["npno"], seed, F_NPNO, P)
+    naux = _dims(cfg["naux"], seed, F_NAUX, P)
+
+    blocks = np.zeros(P, dtype=np.uint32)
+    nblk = np.zeros(P, dtype=np.int64)
+    for p in range(P):
+        names = stored_blocks(int(pi[p]), int(pj[p]), is_somo)
+        blocks[p] = sum(BLOCK_BITS[n] for n in names)
+        nblk[p] = len(names)
+
+    n2 = npno.astype(np.int64) ** 2
+    szB = np.array([_align(int(a) * int(b)) for a, b in zip(naux, n2)], dtype=np.int64)
+    szT = np.array([_align(int(k) * int(b)) for k, b in zip(nblk, n2)], dtype=np.int64)
+    szK = np.array([_align(int(b)) for b in n2], dtype=np.int64)
+    szE = np.array([_align(int(n)) for n in npno], dtype=np.int64)
+    off_B = np.concatenate([[0], np.cumsum(szB)[:-1]]).astype(np.int64)
+    off_T = np.concatenate([[0], np.cumsum(szT)[:-1]]).astype(np.int64)
+    off_K = np.concatenate([[0], np.cumsum(szK)[:-1]]).astype(np.int64)
+    off_eps = np.concatenate([[0], np.cumsum(szE)[:-1]]).astype(np.int64)
+    n_B, n_T, n_K, n_E = int(szB.sum()), int(szT.sum()), int(szK.sum()), int(szE.sum())
+
+    # ---- occupied Fock: diagonal U[-1.2,-0.3]; off-diagonal for retained (i,k) ----
+    somos = [int(s) for s in cfg["somos"]]
+    occ_idx = np.arange(n_occ)
+    fdiag = -1.2 + 0.9 * philox.uniforms(seed, F_FDIAG, 0, np.arange(n_occ, dtype=np.uint64))
+    f_a = np.diag(fdiag)
+    for d in range(1, min(band, n_occ - 1) + 1):
+        i = np.arange(n_occ - d)
+        z = philox.normals(seed, F_FOFF, d, i.astype(np.uint64))
+        v = 0.02 * np.exp(-d / 3.0) * z
+        f_a[i, i + d] = v
+        f_a[i + d, i] = v
+    f_b = f_a.copy()
+    pol_occ = np.zeros(n_occ)
+    for s in somos:
+        pol_occ += 0.05 * np.exp(-np.abs(occ_idx - s) / 2.0)
+    f_b[occ_idx, occ_idx] += pol_occ
+
+    # ---- virtual energies per pair and spin ----
+    eps_a = np.zeros(n_E)
+    eps_b = np.zeros(n_E)
+    for p in range(P):
+        n = int(npno[p])
+        u = philox.uniforms(seed, F_EPS, p, np.arange(n, dtype=np.uint64))
+        ea = 0.2 + 2.8 * u
+        d = np.minimum(np.abs(pi[p] - np.array(somos)), np.abs(pj[p] - np.array(somos))) if somos else np.zeros(0)
+        shift = float(np.sum(0.05 * np.exp(-d / 2.0)))
+        eps_a[off_eps[p]:off_eps[p] + n] = ea
+        eps_b[off_eps[p]:off_eps[p] + n] = ea + shift
+
+    # ---- couplings (CSR by target) ----
+    src, kk, side = [], [], []
+    rowptr = np.zeros(P + 1, dtype=np.int64)
+    for p in range(P):
+        i, j = int(pi[p]), int(pj[p])
+        for sd, (rep, keep) in enumerate(((i, j), (j, i))):
+            for k in range(n_occ):
+                if k == rep or f_a[k, rep] == 0.0:
+                    continue
+                q = pair_index.get((min(k, keep), max(k, keep)))
+                if q is None:
+                    continue
+                src.append(q)
+                kk.append(k)
+                side.append(sd)
+        rowptr[p + 1] = len(src)
+    cpl_src = np.array(src, dtype=np.int32)
+    cpl_k = np.array(kk, dtype=np.int32)
+    cpl_side = np.array(side, dtype=np.int32)
+    C = len(cpl_src)
+    tgt = np.repeat(np.arange(P, dtype=np.int64), np.diff(rowptr))
+
+    # one S block per (target, source) pair of pairs; the two sides of a diagonal
+    # target that reach the same source share it
+    key = tgt * P + cpl_src
+    ukey, first, inv = np.unique(key, return_index=True, return_inverse=True)
+    sz_dir = np.array([_align(int(npno[int(k // P)]) * int(npno[int(k % P)])) for k in ukey], dtype=np.int64)
+    off_dir = np.concatenate([[0], np.cumsum(sz_dir)[:-1]]).astype(np.int64)
+    cpl_off_S = off_dir[inv]
+    n_S = int(sz_dir.sum())
+
+    # ---- generated segments ----
+    sigma_B = cfg["sigma_B"]
+    if sigma_B == "scaled":
+        sB = np.sqrt(1.0 / (naux.astype(np.float64) * (npno.astype(np.float64) + 1.0)))
+    else:
+        sB = np.full(P, float(sigma_B))
+    segB = np.zeros(P, dtype=SEG_DTYPE)
+    segB["off"], segB["stream"], segB["field"], segB["mode"] = off_B, np.arange(P), F_B, MODE_SYM
+    segB["layers"], segB["rows"], segB["cols"], segB["scale"] = naux, npno, npno, sB
+
+    kappa = float(cfg["kappa"])
+    segK = np.zeros(P, dtype=SEG_DTYPE)
+    segK["off"], segK["stream"], segK["field"] = off_K, np.arange(P), F_K
+    segK["mode"] = np.where(pi == pj, MODE_SYM, MODE_PLAIN)
+    segK["layers"], segK["rows"], segK["cols"] = 1, npno, npno
+    segK["scale"] = kappa * (1.0 + np.abs(pi - pj).astype(np.float64)) ** -3
+
+    sT = float(cfg["sigma_T"])
+    tl = []
+    for p in range(P):
+        o = int(off_T[p])
+        for name in BLOCK_NAMES:
+            if not blocks[p] & BLOCK_BITS[name]:
+                continue
+            same = name in ("AA", "BB")
+            tl.append((o, p * 4 + BLOCK_NAMES.index(name), F_T, MODE_ANTI if same else MODE_PLAIN,
+                       1, int(npno[p]), int(npno[p]), 0, sT / np.sqrt(2.0) if same else sT))
+            o += int(npno[p]) ** 2
+    segT = np.array(tl, dtype=SEG_DTYPE)
+
+    segs = {"B": segB, "K": segK, "T": segT}
+    S_host = None
+    if cfg["S"] == "qr60":
+        # orthonormal PNO bases over a shared 60-dimensional virtual space
+        Qs = []
+        for p in range(P):
+            n = int(npno[p])
+            G = philox.normals(seed, F_QR, p, (np.arange(60)[:, None] * 64 + np.arange(n)[None, :]).astype(np.uint64))
+            Qm, Rm = np.linalg.qr(G)
+            Qs.append(Qm * np.sign(np.diag(Rm))[None, :])
+        S_host = np.zeros(n_S)
+        for u, k in enumerate(ukey):
+            p, q = int(k // P), int(k % P)
+            W = Qs[q].T @ Qs[p]                     # [c][a] = <c_q | a_p>
+            S_host[off_dir[u]:off_dir[u] + W.size] = W.ravel()
+    else:
+        # random overlaps: S_{lo,hi} = sigma * Z (n_lo x n_hi), S_{hi,lo} = its transpose
+        lo = np.minimum(ukey // P, ukey % P)
+        hi = np.maximum(ukey // P, ukey % P)
+        und, und_inv = np.unique(lo * P + hi, return_inverse=True)
+        segS = np.zeros(len(ukey), dtype=SEG_DTYPE)
+        p_t, q_s = ukey // P, ukey % P
+        segS["off"] = off_dir
+        segS["stream"] = und_inv
+        segS["field"] = F_S
+        # stored W[c][a] (c on source q, a on target p) = S_{q,p}[c][a]:
+        #   q == lo: Z[c][a] (plain); q == hi: Z[a][c] (transposed)
+        segS["mode"] = np.where(q_s < p_t, MODE_PLAIN, MODE_TRANS)
+        segS["layers"] = 1
+        segS["rows"] = npno[q_s]
+        segS["cols"] = npno[p_t]
+        # decay with the distance between the replaced and the replacing orbital
+        dist = np.zeros(len(ukey))
+        a_i, a_j, b_i, b_j = pi[p_t], pj[p_t], pi[q_s], pj[q_s]
+        dist = np.abs((a_i + a_j) - (b_i + b_j)).astype(np.float64)
+        segS["scale"] = np.exp(-dist / 4.0) / (np.sqrt(npno[p_t].astype(np.float64)) + np.sqrt(npno[q_s].astype(np.float64)))
+        segs["S"] = segS
+
+    return Problem(name=name, seed=seed, n_occ=n_occ, is_somo=is_somo, pi=pi, pj=pj,
+                   npno=npno, naux=naux, blocks=blocks, off_B=off_B, off_T=off_T, off_K=off_K,
+                   off_eps=off_eps, cpl_rowptr=rowptr, cpl_src=cpl_src, cpl_k=cpl_k,
+                   cpl_side=cpl_side, cpl_off_S=cpl_off_S, f_a=f_a, f_b=f_b, eps_a=eps_a,
+                   eps_b=eps_b, n_B=n_B, n_T=n_T, n_K=n_K, n_S=n_S, segs=segs, S_host=S_host,
+                   pair_index=pair_index)
