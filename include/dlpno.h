@@ -1,0 +1,214 @@
+/*
+ * dlpno.h -- C ABI of the MI355X open-shell DLPNO doubles-residual library.
+ *
+ * The library evaluates, for every retained occupied pair p = (i, j) and every
+ * stored high-spin block s s' of that pair, the doubles residual in the pair's
+ * own PNO basis (the paper solves "the CC residual equations" in the truncated
+ * PNO basis, Sec. II.B.3; spin cases per pair class, Sec. II.A; one
+ * spin-independent PNO set per pair, Sec. II.B.2 and II.B.4):
+ *
+ *   R^{ss'}_p = K^{ss'}_p + (eps^s_a + eps^s'_b - f^s_ii - f^s'_jj) T^{ss'}_p
+ *             - sum_{k in occ_s,  k != i} f^s_ki  S_{p,kj} T^{ss'}_{kj} S_{kj,p}
+ *             - sum_{k in occ_s', k != j} f^s'_kj S_{p,ik} T^{ss'}_{ik} S_{ik,p}
+ *             + sum_Q B^Q_p T^{ss'}_p (B^Q_p)^T
+ *
+ * with K^{AA} = K^{BB} = K_p - K_p^T, K^{AB} = K^{BA} = K_p, and
+ * T_{(k,l)}, k > l, the transposed spin-swapped block of (l, k); then the
+ * Jacobi update T' = T - R / D, pair energies w <K^{ss'}, T'> (w = 1/2 for
+ * same spin, 1 for opposite spin) and Pulay DIIS.
+ *
+ * Conventions for every entry point:
+ *   - device pointers are HIP device memory owned by the caller and must stay
+ *     valid until the work queued on `stream` has finished;
+ *   - host pointers are read during the call only (the plan copies them);
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream);
+ *   - nothing throws or aborts across the ABI: every call returns a status;
+ *   - for identical inputs every result is bitwise reproducible (no floating
+ *     point atomics; all reductions run in a fixed order);
+ *   - a plan is not thread safe; calls on one plan must be serialised.
+ */
+#ifndef DLPNO_H
+#define DLPNO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DLPNO_OK = 0,
+  DLPNO_ERR_INVALID_ARG = -1,   /* NULL pointer, bad enum, inconsistent descriptor */
+  DLPNO_ERR_DIM_RANGE = -2,     /* npno outside 1..64, naux outside 1..65536, index range */
+  DLPNO_ERR_ALIGNMENT = -3,     /* buffer offsets outside the declared buffer sizes */
+  DLPNO_ERR_HIP = -4,           /* a HIP runtime call failed */
+  DLPNO_ERR_NONFINITE = -5,     /* a residual element was NaN or Inf */
+  DLPNO_ERR_NOT_CONVERGED = -6, /* reserved */
+  DLPNO_ERR_OOM = -7,           /* device allocation failed */
+  DLPNO_ERR_UNSUPPORTED = -8    /* precision / option not available for this call */
+} dlpno_status;
+
+/* Arithmetic of the ladder and projection contractions.  Dressing, Jacobi
+ * update, energies and DIIS are always FP64.
+ *   FP64     FP64 MFMA
+ *   FP32     FP32 MFMA, FP32 copies of B and S made at plan creation
+ *   BF16X2   BF16 hi+lo operand splitting on MFMA, FP32 accumulation
+ *   FP16X2   FP16 hi+lo splitting with power-of-two scaling, FP32 accumulation */
+typedef enum { DLPNO_FP64 = 0, DLPNO_FP32 = 1, DLPNO_BF16X2 = 2, DLPNO_FP16X2 = 3 } dlpno_precision;
+
+/* Spin-block mask bits, also the storage order of a pair's blocks. */
+enum { DLPNO_AA = 1, DLPNO_BB = 2, DLPNO_AB = 4, DLPNO_BA = 8 };
+
+/* One retained pair (i <= j).  Offsets are element offsets into the buffers
+ * of dlpno_inputs / the amplitude buffers:
+ *   off_B   B_p, [Q][a][c], naux x npno x npno, symmetric in (a, c)
+ *   off_T   first stored block of the pair in T / R / dT buffers; the stored
+ *           blocks follow back to back in the order AA, BB, AB, BA, each
+ *           npno x npno row-major [a][b] (a on electron i, b on electron j)
+ *   off_K   K_p = (i a | j b), npno x npno row-major
+ *   off_eps virtual PNO energies, npno values in eps_a and in eps_b
+ * `blocks` must equal the rule of Sec. II.A for (i, j) given is_somo: a block
+ * s s' is present iff i in occ_s, j in occ_s' (SOMOs are alpha-occupied only),
+ * not (s == s' and i == j), and BA is absent for i == j. */
+typedef struct {
+  int32_t i, j;
+  int32_t npno;      /* 1..64 */
+  int32_t naux;      /* 1..65536 */
+  uint32_t blocks;   /* DLPNO_AA | DLPNO_BB | DLPNO_AB | DLPNO_BA */
+  int32_t reserved;
+  int64_t off_B, off_T, off_K, off_eps;
+} dlpno_pair;
+
+/* One projection coupling of a target pair p = (i, j) (CSR row of p):
+ *   side 0: occupied k replaces i, source pair {k, j}, weight f^s[k][i]
+ *   side 1: occupied k replaces j, source pair {i, k}, weight f^s'[k][j]
+ * off_S: the overlap block between the source PNOs (rows, n_src) and the
+ * target PNOs (columns, n_target), row-major: element [c][a] = <c_src|a_tgt>.
+ * The library applies it to every spin block of the target for which the
+ * source block exists (Sec. II.B.2: one overlap set serves all spins). */
+typedef struct {
+  int32_t src_pair;
+  int32_t k;
+  int32_t side;
+  int32_t reserved;
+  int64_t off_S;
+} dlpno_coupling;
+
+/* Problem description (all host memory, copied by dlpno_plan_create). */
+typedef struct {
+  int32_t n_occ;
+  int32_t n_pairs;
+  int64_t n_couplings;
+  const uint8_t* is_somo;          /* [n_occ], 1 = singly occupied */
+  const dlpno_pair* pairs;         /* [n_pairs] */
+  const int64_t* cpl_rowptr;       /* [n_pairs + 1], CSR by target pair */
+  const dlpno_coupling* cpl;       /* [n_couplings] */
+  const double* f_a;               /* [n_occ * n_occ] alpha occupied Fock */
+  const double* f_b;               /* [n_occ * n_occ] beta occupied Fock */
+  int64_t n_B, n_T, n_K, n_eps, n_S; /* element counts of the buffers (bounds checks) */
+} dlpno_problem;
+
+/* Device inputs (caller-owned, read-only, fixed for the life of the plan). */
+typedef struct {
+  const double* B;
+  const double* S;
+  const double* K;
+  const double* eps_a;
+  const double* eps_b;
+} dlpno_inputs;
+
+typedef struct {
+  dlpno_precision precision;
+  int32_t diis_max;     /* vectors kept by DIIS, 0 = plain Jacobi, at most 8 */
+  int32_t diis_start;   /* first extrapolation once this many are stored (>= 2) */
+  int32_t n_workers;    /* persistent workgroups (0 = 2 per compute unit) */
+  int32_t chunk_flops;  /* log2 of the target work per scheduled item (0 = default) */
+  int32_t flags;        /* reserved, 0 */
+} dlpno_options;
+
+typedef struct dlpno_plan dlpno_plan;   /* opaque, owned by the library */
+
+/* Validates the descriptors (ranges, offsets against the buffer sizes, the
+ * block rule, CSR monotonicity and coupling consistency), builds the device
+ * tables, the work schedule and the workspace.  Precision copies of B and S
+ * are made here.  Synchronous.  opts may be NULL (FP64, DIIS 8/3). */
+dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno_inputs* in,
+                               const dlpno_options* opts, void* stream, dlpno_plan** out);
+dlpno_status dlpno_plan_destroy(dlpno_plan* plan);
+
+/* R = residual(T) for every stored block.  T, R: device, n_T doubles. */
+dlpno_status dlpno_residual(dlpno_plan* plan, const double* T, double* R, void* stream);
+
+/* T_out = T - R / D; e_pair[4 p + c] = energy of block c (0 AA, 1 BB, 2 AB,
+ * 3 BA) of pair p computed with T_out (0 for absent blocks); *e_total = sum.
+ * All device pointers; e_pair has 4 n_pairs doubles.  T_out may equal T. */
+dlpno_status dlpno_update(dlpno_plan* plan, const double* T, const double* R, double* T_out,
+                          double* e_pair, double* e_total, void* stream);
+
+/* n_iter iterations of: R = residual(T); T' = T - R/D; energies of T';
+ * DIIS on (T', T' - T) (when enabled); T <- extrapolated T'.  One hipGraph per
+ * iteration, replayed.  T is in/out; R, e_pair, e_total, max_abs_R receive
+ * the last iteration's values (device).  Blocks until done and returns
+ * DLPNO_ERR_NONFINITE if any residual element was not finite.  DIIS history
+ * persists across calls until dlpno_reset. */
+dlpno_status dlpno_iterate(dlpno_plan* plan, int32_t n_iter, double* T, double* R,
+                           double* e_pair, double* e_total, double* max_abs_R, void* stream);
+
+/* Clears the DIIS history and the iteration counter. */
+dlpno_status dlpno_reset(dlpno_plan* plan, void* stream);
+
+/* Per-iteration history of the last dlpno_iterate calls (host arrays of
+ * length >= n): total energy and max |R|.  Returns the number written. */
+int32_t dlpno_history(const dlpno_plan* plan, double* energy, double* max_abs_r, int32_t n);
+
+/* Vector-Jacobian product of the residual: for Gbar = dL/dR,
+ *   dT = D o Gbar + sum_Q (B^Q)^T Gbar B^Q + (projection terms)^T Gbar,
+ *   dB^Q_p = sum_blocks (Gbar B^Q T^T + Gbar^T B^Q T)   (general, unsymmetrised B).
+ * The projection transpose is evaluated by gathering over the couplings of
+ * each source pair; this requires the data the physics guarantees: f^s
+ * symmetric and the S block of coupling (q <- p) the transpose of (p <- q).
+ * dT: n_T doubles; dB: n_B doubles (NULL skips it).  X^Q = B^Q T is recomputed
+ * inside the kernel, never stored.  Asynchronous. */
+dlpno_status dlpno_residual_vjp(dlpno_plan* plan, const double* T, const double* Gbar,
+                                double* dT, double* dB, void* stream);
+
+/* Mixed-precision solve (plan precision BF16X2, FP16X2 or FP32): n_outer
+ * refinement steps, each computing the FP64 residual r = R(T) and then
+ * n_inner low-precision Jacobi+DIIS iterations on the correction equation
+ * (D + A) delta = -r, T += delta.  T in/out (device).  Synchronous. */
+dlpno_status dlpno_solve_mixed(dlpno_plan* plan, int32_t n_outer, int32_t n_inner, double* T,
+                               double* R, double* e_pair, double* e_total, double* max_abs_R,
+                               void* stream);
+
+/* Algorithmic FLOPs of one residual evaluation (ladder: 4 m n^3 per block;
+ * projection: 2 n_p n_q (n_p + n_q) per applied term). */
+dlpno_status dlpno_flop_count(const dlpno_plan* plan, double* ladder, double* projection);
+
+/* Time every variant of the grouped kernel's tile schedule on the plan's
+ * workload and keep the fastest (T: a device amplitude buffer to run on,
+ * R: scratch of n_T doubles).  Synchronous.  The choice is reported through
+ * dlpno_plan_info. */
+dlpno_status dlpno_autotune(dlpno_plan* plan, const double* T, double* R, void* stream);
+
+/* Kernel timing: when enabled, residual/iterate record HIP events around the
+ * phases on the call's stream (graphs are bypassed) and dlpno_phase_times
+ * returns the accumulated milliseconds and launch counts of:
+ *   0 grouped ladder+projection kernel, 1 finish/update, 2 energy reduction,
+ *   3 DIIS, 4 precision conversion. */
+dlpno_status dlpno_set_profiling(dlpno_plan* plan, int32_t enable);
+dlpno_status dlpno_phase_times(const dlpno_plan* plan, double* ms, int64_t* launches, int32_t n);
+
+/* Human-readable summary of the plan (schedule, variants, workspace). */
+const char* dlpno_plan_info(const dlpno_plan* plan);
+
+const char* dlpno_status_string(dlpno_status s);
+
+/* Text of the last failure reported by any call on this thread ("" if none). */
+const char* dlpno_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DLPNO_H */

@@ -1,0 +1,408 @@
+// Fock dressing, Jacobi update, pair energies, reductions and DIIS.
+//
+// All of it is FP64 and HBM-bound: one workgroup per stored spin block reads
+// its amplitudes, driver, denominators and the partial sums of the grouped
+// kernel once, and writes R and the updated amplitudes once.  Reductions run
+// in a fixed order (wavefront shuffles, then LDS across the four waves), so
+// every result is bitwise reproducible.
+#include "internal.h"
+
+#include <math.h>
+
+namespace dlpno {
+
+constexpr int kEwThreads = 256;
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+// block-wide sum/max over 256 threads in a fixed order
+__device__ __forceinline__ void block_sum_max(double& s, double& m) {
+  __shared__ double ls[4], lm[4];
+  s = wave_sum(s);
+  m = wave_max(m);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    ls[w] = s;
+    lm[w] = m;
+  }
+  __syncthreads();
+  s = ((ls[0] + ls[1]) + ls[2]) + ls[3];
+  m = fmax(fmax(lm[0], lm[1]), fmax(lm[2], lm[3]));
+}
+
+// R = K^{ss'} + D o T + sum of partial slots;  optional T' = T - R / D,
+// energy w <K^{ss'}, T'>, max |R|, DIIS error T' - T.
+__global__ __launch_bounds__(kEwThreads) void finish_kernel(FinishArgs a) {
+  const int blk = blockIdx.x;
+  const BlockDev bk = a.blocks[blk];
+  const int n = bk.n;
+  const int nn = n * n;
+  const double* ea = (bk.s1 == 0 ? a.eps_a : a.eps_b) + bk.off_eps;
+  const double* eb = (bk.s2 == 0 ? a.eps_a : a.eps_b) + bk.off_eps;
+  const double* K = a.K + bk.off_K;
+  const double* T = a.T + bk.off_T;
+  const double* ws = a.ws + bk.off_ws;
+  double* Tn = a.T_new;
+  double* err = nullptr;
+  if (a.ring) {
+    const int64_t o = (int64_t)a.ring->head * a.ring_stride;
+    Tn = a.ring_vecs + o;
+    err = a.ring_errs + o;
+  }
+  double esum = 0.0, rmax = 0.0;
+  bool bad = false;
+  for (int idx = threadIdx.x; idx < nn; idx += kEwThreads) {
+    const int x = idx / n, y = idx - x * n;          // element [a = x][b = y]
+    const double t = T[idx];
+    const double D = (ea[x] + eb[y]) - bk.fsum;
+    double kk = 0.0;
+    if (a.with_driver) {
+      kk = K[idx];
+      if (bk.anti) kk -= K[y * n + x];
+    }
+    double r = kk + D * t;
+    for (int sl = 0; sl < bk.nslot; ++sl) r += ws[(int64_t)sl * nn + y * n + x];   // slots hold Out^T
+    if (!isfinite(r)) bad = true;
+    rmax = fmax(rmax, fabs(r));
+    if (a.R) a.R[bk.off_T + idx] = r;
+    if (Tn) {
+      const double tn = t - r / D;
+      Tn[bk.off_T + idx] = tn;
+      if (err) err[bk.off_T + idx] = tn - t;
+      esum += kk * tn;
+    }
+  }
+  if (bad) atomicOr(a.nonfinite, 1);
+  block_sum_max(esum, rmax);
+  if (threadIdx.x == 0) {
+    if (a.e_block) a.e_block[blk] = bk.w * esum;
+    if (a.rmax_block) a.rmax_block[blk] = rmax;
+  }
+}
+
+// T' = T - R / D and energies from a given residual.
+__global__ __launch_bounds__(kEwThreads) void update_kernel(UpdateArgs a) {
+  const int blk = blockIdx.x;
+  const BlockDev bk = a.blocks[blk];
+  const int n = bk.n;
+  const int nn = n * n;
+  const double* ea = (bk.s1 == 0 ? a.eps_a : a.eps_b) + bk.off_eps;
+  const double* eb = (bk.s2 == 0 ? a.eps_a : a.eps_b) + bk.off_eps;
+  const double* K = a.K + bk.off_K;
+  double esum = 0.0, dummy = 0.0;
+  for (int idx = threadIdx.x; idx < nn; idx += kEwThreads) {
+    const int x = idx / n, y = idx - x * n;
+    const double D = (ea[x] + eb[y]) - bk.fsum;
+    double kk = K[idx];
+    if (bk.anti) kk -= K[y * n + x];
+    const double tn = a.T[bk.off_T + idx] - a.R[bk.off_T + idx] / D;
+    a.T_new[bk.off_T + idx] = tn;
+    esum += kk * tn;
+  }
+  block_sum_max(esum, dummy);
+  if (threadIdx.x == 0) a.e_block[blk] = bk.w * esum;
+}
+
+// pair energies, total energy, max |R|, iteration history (one workgroup)
+__global__ __launch_bounds__(1024) void reduce_kernel(ReduceArgs a) {
+  __shared__ double ls[16], lm[16];
+  double s = 0.0, m = 0.0;
+  for (int b = threadIdx.x; b < a.n_blocks; b += 1024) {
+    s += a.e_block[b];
+    if (a.rmax_block) m = fmax(m, a.rmax_block[b]);
+  }
+  if (a.e_pair) {
+    for (int p = threadIdx.x; p < a.n_pairs; p += 1024) {
+      const PairDev P = a.pairs[p];
+      double e[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int k = 0; k < P.nblk; ++k) e[a.blocks[P.blk0 + k].code] = a.e_block[P.blk0 + k];
+      for (int c = 0; c < 4; ++c) a.e_pair[4 * (int64_t)p + c] = e[c];
+    }
+  }
+  s = wave_sum(s);
+  m = wave_max(m);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    ls[w] = s;
+    lm[w] = m;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0, mx = 0.0;
+    for (int k = 0; k < 16; ++k) {
+      tot += ls[k];
+      mx = fmax(mx, lm[k]);
+    }
+    if (a.e_total) *a.e_total = tot;
+    if (a.rmax) *a.rmax = mx;
+    if (a.iter) {
+      const int it = *a.iter;
+      if (a.hist && it < a.hist_cap) {
+        a.hist[2 * it] = tot;
+        a.hist[2 * it + 1] = mx;
+      }
+      *a.iter = it + 1;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ DIIS
+__global__ void diis_reset_kernel(DiisState* st, int max, int start) {
+  st->count = 0;
+  st->head = max - 1;
+  st->max = max;
+  st->start = start;
+  st->iter = 0;
+  for (int a = 0; a < 8; ++a) {
+    st->coef[a] = 0.0;
+    for (int b = 0; b < 8; ++b) st->gram[a][b] = 0.0;
+  }
+}
+
+__global__ void diis_slot_kernel(DiisState* st) {
+  st->head = (st->head + 1) % st->max;
+  if (st->count < st->max) st->count += 1;
+}
+
+// partial[part][k] = sum over this part of err[head] * err[k] for every stored slot k
+__global__ __launch_bounds__(256) void diis_dots_kernel(const double* errs, int64_t n, const DiisState* st,
+                                                        double* partial) {
+  const int cnt = st->count, head = st->head, mx = st->max;
+  const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+  const int64_t lo = (int64_t)blockIdx.x * per;
+  const int64_t hi = lo + per < n ? lo + per : n;
+  const double* eh = errs + (int64_t)head * n;
+  double acc[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+  for (int64_t x = lo + threadIdx.x; x < hi; x += 256) {
+    const double v = eh[x];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < cnt) {
+        const int slot = (head - k + mx) % mx;      // k-th newest
+        acc[k] += v * errs[(int64_t)slot * n + x];
+      }
+  }
+  __shared__ double ls[8][4];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const double s = wave_sum(acc[k]);
+    if ((threadIdx.x & 63) == 0) ls[k][threadIdx.x >> 6] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    const int k = threadIdx.x;
+    partial[(int64_t)blockIdx.x * 8 + k] = ((ls[k][0] + ls[k][1]) + ls[k][2]) + ls[k][3];
+  }
+}
+
+// symmetric eigenvalues by cyclic Jacobi (n <= 9), for the condition number
+__device__ void sym_eigs(double* A, int n, double* ev) {
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) off += A[p * 9 + q] * A[p * 9 + q];
+    if (off < 1e-300) break;
+    for (int p = 0; p < n; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[p * 9 + q];
+        if (apq == 0.0) continue;
+        const double theta = (A[q * 9 + q] - A[p * 9 + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < n; ++k) {
+          const double akp = A[k * 9 + p], akq = A[k * 9 + q];
+          A[k * 9 + p] = c * akp - s * akq;
+          A[k * 9 + q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = A[p * 9 + k], aqk = A[q * 9 + k];
+          A[p * 9 + k] = c * apk - s * aqk;
+          A[q * 9 + k] = s * apk + c * aqk;
+        }
+      }
+  }
+  for (int k = 0; k < n; ++k) ev[k] = A[k * 9 + k];
+}
+
+// Gram update, bordered system [[<e_i,e_j>, -1], [-1, 0]] c = [0, -1] solved by
+// Gaussian elimination with partial pivoting; oldest vectors are dropped while
+// the matrix's 2-norm condition number exceeds 1e14.
+__global__ void diis_solve_kernel(DiisState* st, const double* partial, int nparts) {
+  const int cnt0 = st->count, head = st->head, mx = st->max;
+  // new Gram row (fixed-order sum over parts)
+  for (int k = 0; k < cnt0; ++k) {
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += partial[(int64_t)p * 8 + k];
+    const int slot = (head - k + mx) % mx;
+    st->gram[head][slot] = s;
+    st->gram[slot][head] = s;
+  }
+  for (int k = 0; k < 8; ++k) st->coef[k] = 0.0;
+  if (cnt0 < st->start) {
+    st->coef[head] = 1.0;
+    return;
+  }
+  int cnt = cnt0;
+  for (;;) {
+    // slots oldest -> newest
+    int sl[8];
+    for (int k = 0; k < cnt; ++k) sl[k] = (head - (cnt - 1 - k) + mx) % mx;
+    const int N = cnt + 1;
+    double M[81], E[81], rhs[9];
+    for (int a = 0; a < N; ++a) {
+      for (int b = 0; b < N; ++b) {
+        double v;
+        if (a < cnt && b < cnt) v = st->gram[sl[a]][sl[b]];
+        else if (a == cnt && b == cnt) v = 0.0;
+        else v = -1.0;
+        M[a * 9 + b] = v;
+        E[a * 9 + b] = v;
+      }
+      rhs[a] = (a == cnt) ? -1.0 : 0.0;
+    }
+    if (cnt > 1) {
+      double ev[9];
+      sym_eigs(E, N, ev);
+      double amax = 0.0, amin = 1e308;
+      for (int k = 0; k < N; ++k) {
+        amax = fmax(amax, fabs(ev[k]));
+        amin = fmin(amin, fabs(ev[k]));
+      }
+      if (!(amin > 0.0) || amax / amin > 1e14) {
+        cnt -= 1;      // drop the oldest
+        st->count = cnt;
+        continue;
+      }
+    }
+    // Gaussian elimination with partial pivoting
+    for (int c = 0; c < N; ++c) {
+      int piv = c;
+      for (int rr = c + 1; rr < N; ++rr)
+        if (fabs(M[rr * 9 + c]) > fabs(M[piv * 9 + c])) piv = rr;
+      if (piv != c) {
+        for (int k = 0; k < N; ++k) {
+          const double tmp = M[c * 9 + k];
+          M[c * 9 + k] = M[piv * 9 + k];
+          M[piv * 9 + k] = tmp;
+        }
+        const double tmp = rhs[c];
+        rhs[c] = rhs[piv];
+        rhs[piv] = tmp;
+      }
+      for (int rr = c + 1; rr < N; ++rr) {
+        const double f = M[rr * 9 + c] / M[c * 9 + c];
+        for (int k = c; k < N; ++k) M[rr * 9 + k] -= f * M[c * 9 + k];
+        rhs[rr] -= f * rhs[c];
+      }
+    }
+    double x[9];
+    for (int c = N - 1; c >= 0; --c) {
+      double s = rhs[c];
+      for (int k = c + 1; k < N; ++k) s -= M[c * 9 + k] * x[k];
+      x[c] = s / M[c * 9 + c];
+    }
+    for (int k = 0; k < cnt; ++k) st->coef[sl[k]] = x[k];
+    return;
+  }
+}
+
+// T = sum_k coef[k] vec[k], stored slots oldest -> newest
+__global__ __launch_bounds__(256) void diis_extrap_kernel(const double* vecs, int64_t n, const DiisState* st,
+                                                          double* T) {
+  const int cnt = st->count, head = st->head, mx = st->max;
+  int sl[8];
+  double c[8];
+  for (int k = 0; k < 8; ++k) {
+    sl[k] = 0;
+    c[k] = 0.0;
+  }
+  for (int k = 0; k < cnt; ++k) {
+    sl[k] = (head - (cnt - 1 - k) + mx) % mx;
+    c[k] = st->coef[sl[k]];
+  }
+  for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < n; x += (int64_t)gridDim.x * 256) {
+    double s = 0.0;
+    for (int k = 0; k < cnt; ++k) s += c[k] * vecs[(int64_t)sl[k] * n + x];
+    T[x] = s;
+  }
+}
+
+__global__ void convert_f32_kernel(const double* src, float* dst, int64_t n) {
+  for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < n; x += (int64_t)gridDim.x * 256)
+    dst[x] = (float)src[x];
+}
+__global__ void axpy_kernel(double* y, const double* x, double a, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    y[i] += a * x[i];
+}
+__global__ void copy_kernel(double* y, const double* x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = x[i];
+}
+
+static int grid_for(int64_t n) {
+  int64_t g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
+  if (a.n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(finish_kernel, dim3(a.n_blocks), dim3(kEwThreads), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_update(const UpdateArgs& a, hipStream_t s) {
+  if (a.n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(update_kernel, dim3(a.n_blocks), dim3(kEwThreads), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_diis_reset(DiisState* st, int max, int start, hipStream_t s) {
+  hipLaunchKernelGGL(diis_reset_kernel, dim3(1), dim3(1), 0, s, st, max, start);
+  return hipGetLastError();
+}
+hipError_t launch_diis_slot(DiisState* st, hipStream_t s) {
+  hipLaunchKernelGGL(diis_slot_kernel, dim3(1), dim3(1), 0, s, st);
+  return hipGetLastError();
+}
+hipError_t launch_diis_dots(const double* errs, int64_t n, DiisState* st, double* partial, int nparts,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(diis_dots_kernel, dim3(nparts), dim3(256), 0, s, errs, n, st, partial);
+  return hipGetLastError();
+}
+hipError_t launch_diis_solve(DiisState* st, const double* partial, int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(diis_solve_kernel, dim3(1), dim3(1), 0, s, st, partial, nparts);
+  return hipGetLastError();
+}
+hipError_t launch_diis_extrap(const double* vecs, int64_t n, const DiisState* st, double* T, hipStream_t s) {
+  hipLaunchKernelGGL(diis_extrap_kernel, dim3(grid_for(n)), dim3(256), 0, s, vecs, n, st, T);
+  return hipGetLastError();
+}
+hipError_t launch_convert_f32(const double* src, float* dst, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(convert_f32_kernel, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(axpy_kernel, dim3(grid_for(n)), dim3(256), 0, s, y, x, a, n);
+  return hipGetLastError();
+}
+hipError_t launch_copy(double* y, const double* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(n)), dim3(256), 0, s, y, x, n);
+  return hipGetLastError();
+}
+
+}  // namespace dlpno

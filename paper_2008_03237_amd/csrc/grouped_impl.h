@@ -1,0 +1,351 @@
+// Persistent grouped kernel: every DF ladder and PNO-overlap projection
+// contraction of one residual evaluation, over all pairs of uneven PNO and
+// auxiliary sizes, in one launch.
+//
+// Both contractions have the "sandwich" form  Out = M X M^T  summed over a
+// list of (M, X) pairs:
+//   ladder      M = B^Q_p, X = T^{ss'}_p, summed over Q: the DF factorisation
+//               (ac|bd) = sum_Q B^Q_ac B^Q_bd of the four-external integrals
+//               in the pair's PNO basis;
+//   projection  M = S_{p,q}, X = -w op(T_q), summed over the neighbour
+//               couplings of the target pair (one overlap set for all spins).
+// One wavefront evaluates a sandwich on the 16x16x4 MFMA with the first
+// product kept in registers: the accumulator layout of  Y^T = X^T M^T  is,
+// after a fixed permutation of its row index, exactly the B-operand layout of
+// Out^T = M Y^T, so  Y = M X  never leaves the VGPRs (it is recomputed for
+// every Q instead of stored).  With M symmetric (B^Q) the same registers serve
+// as the B operand of the first product and the A operand of the second.
+//
+// Register forms (lane l, r = l & 15, g = l >> 4):
+//   M-form  M[t][s]  = M[16 t + r][4 s + g]          (rows: target PNO, cols: inner)
+//   X-form  Al[t][s] = X[4 s + g][16 t + perm(r)]
+//   output  acc[tb][ta][i] = Out[16 ta + r][16 tb + orow(g, i)]
+// The 16x16x4 FP64 MFMA returns output row 4 i + g in register i of lane
+// group g (perm = identity, orow = 4 i + g); the FP32 one returns row 4 g + i,
+// so its A rows are fed in the order perm(r) = 4 (r & 3) + (r >> 2), after
+// which register i again holds rows 4 i + g.  Either way register i of the
+// first product is exactly k-step i of the second.
+// K-steps of 4 beyond the inner dimension are skipped, so only the M and N
+// tile edges are padded to 16.  Operands are read with raw buffer loads whose
+// resource covers exactly one matrix: reads past its end return zero, and the
+// remaining padded reads land inside the same matrix, are finite, and only
+// reach rows or columns that are multiplied by those zeros or never stored.
+//
+// The X-form operands live in a per-wave LDS slab (one 8-byte slot per lane
+// and operand, conflict free); the M operands of B^Q are double-buffered in
+// VGPRs so the next slice is in flight while the current one is contracted.
+//
+// Work items come from a queue ordered longest-first; every wave pops items
+// with one atomic increment until the queue is empty (the exit condition every
+// wave reaches).  Each item writes its partial sums to a private workspace
+// slot; the finishing kernel adds the slots in a fixed order, so results are
+// bitwise reproducible.
+#pragma once
+#include "internal.h"
+
+namespace dlpno {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <typename F>
+struct Mfma;
+template <>
+struct Mfma<double> {
+  typedef d4_t V;
+  static __device__ __forceinline__ V op(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ double load(__amdgpu_buffer_rsrc_t r, uint32_t off_elems) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off_elems * 8u, 0u, 0));
+  }
+  // FP64 16x16x4: register i of lane group g holds output row 4 i + g
+  static __device__ __forceinline__ int perm(int r) { return r; }
+  static __device__ __forceinline__ int orow(int g, int i) { return 4 * i + g; }
+};
+template <>
+struct Mfma<float> {
+  typedef f4_t V;
+  static __device__ __forceinline__ V op(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, uint32_t off_elems) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off_elems * 4u, 0u, 0));
+  }
+  // FP32 16x16x4: register i of lane group g holds output row 4 g + i; feeding
+  // A rows in the order pi(r) makes register i hold rows 4 i + g as well
+  static __device__ __forceinline__ int perm(int r) { return ((r & 3) << 2) | (r >> 2); }
+  static __device__ __forceinline__ int orow(int g, int i) { return 4 * g + i; }
+};
+
+// raw buffer resource over [p, p + elems): out-of-range loads return 0
+template <typename F>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const F* p, uint32_t elems) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<F*>(p), (short)0, elems * (uint32_t)sizeof(F), 0x00020000);
+}
+
+// Per-wave LDS slab for X-form operands, in 8-byte words: the largest user is
+// the 3-tile, 2-block ladder variant (2 * 3 * 12 operands of 64 lanes).
+constexpr int kLdsWaveWords = 72 * 64;
+
+// ---------------------------------------------------------------------------
+// Ladder item: pair p, NB consecutive blocks, a-tiles TA0..TA0+NTA-1,
+// Q in [lo, hi).  Partial Out^T[b][a] of sum_Q B^Q T B^Q^T.
+// ---------------------------------------------------------------------------
+template <typename F, int NT, int NB, int NTA, int TA0>
+__device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
+  typedef typename Mfma<F>::V V;
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4, pr = Mfma<F>::perm(r);
+  const PairDev P = A.pairs[it.pair];
+  const int n = P.n;
+  const int S4 = (n + 3) >> 2;
+  const uint32_t nn = (uint32_t)n * (uint32_t)n;
+  F* Al = reinterpret_cast<F*>(lds + (size_t)(threadIdx.x >> 6) * kLdsWaveWords);
+
+  // X-form operands of the NB amplitude blocks, once per item
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const BlockDev& Bk = A.blocks[P.blk0 + it.bslot0 + b];
+    const __amdgpu_buffer_rsrc_t tr = rsrc(A.T + Bk.off_T, nn);
+    const uint32_t base = (uint32_t)(g * n + pr);
+#pragma unroll
+    for (int td = 0; td < NT; ++td)
+#pragma unroll
+      for (int s = 0; s < 4 * NT; ++s)
+        Al[((b * NT + td) * 4 * NT + s) * 64 + lane] = Mfma<F>::load(tr, base + (uint32_t)(4 * s * n + 16 * td));
+  }
+
+  V acc[NB][NT][NTA];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int u = 0; u < NTA; ++u) acc[b][t][u] = V{0, 0, 0, 0};
+
+  // M-form of B^Q: M[t][s] = B^Q[4s + g][16t + r] = B^Q[16t + r][4s + g] (symmetric)
+  const F* Bp = A.B + P.off_B;
+  const uint32_t mbase = (uint32_t)(g * n + r);
+  auto loadM = [&](F (&M)[NT][4 * NT], int Q) {
+    const __amdgpu_buffer_rsrc_t br = rsrc(Bp + (size_t)Q * nn, nn);
+#pragma unroll
+    for (int s = 0; s < 4 * NT; ++s)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) M[t][s] = Mfma<F>::load(br, mbase + (uint32_t)(4 * s * n + 16 * t));
+  };
+
+  auto compute = [&](const F (&M)[NT][4 * NT]) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+      for (int td = 0; td < NT; ++td) {
+        V d1[NTA];
+#pragma unroll
+        for (int u = 0; u < NTA; ++u) d1[u] = V{0, 0, 0, 0};
+        // stage 1: Y^T[d][a] = sum_c T[c][d] B^Q[c][a]   (d-tile td)
+#pragma unroll
+        for (int s = 0; s < 4 * NT; ++s) {
+          if (s < S4) {
+            const F av = Al[((b * NT + td) * 4 * NT + s) * 64 + lane];
+#pragma unroll
+            for (int u = 0; u < NTA; ++u) d1[u] = Mfma<F>::op(av, M[TA0 + u][s], d1[u]);
+          }
+        }
+        // stage 2: Out^T[b][a] += sum_d B^Q[b][d] Y^T[d][a] over this d-tile
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int sp = 4 * td + i;
+          if (sp < S4) {
+#pragma unroll
+            for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+              for (int u = 0; u < NTA; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][sp], d1[u][i], acc[b][tb][u]);
+          }
+        }
+      }
+    }
+  };
+
+  F M0[NT][4 * NT], M1[NT][4 * NT];
+  loadM(M0, it.lo);
+  for (int Q = it.lo; Q < it.hi; Q += 2) {
+    if (Q + 1 < it.hi) loadM(M1, Q + 1);
+    compute(M0);
+    if (Q + 1 >= it.hi) break;
+    if (Q + 2 < it.hi) loadM(M0, Q + 2);
+    compute(M1);
+  }
+
+  // partial slot stored as Out^T[b][a] (row b, column a): coalesced over r
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const BlockDev& Bk = A.blocks[P.blk0 + it.bslot0 + b];
+    double* dst = A.ws + Bk.off_ws + (int64_t)it.slot * nn;
+#pragma unroll
+    for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+      for (int u = 0; u < NTA; ++u) {
+        const int a = 16 * (TA0 + u) + r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int bb = 16 * tb + Mfma<F>::orow(g, i);
+          if (a < n && bb < n) dst[bb * n + a] = (double)acc[b][tb][u][i];
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Projection item: target pair p (NT tiles), NB consecutive blocks, couplings
+// [lo, hi).  Per coupling: M = S_{p,q}; per target block the term
+// -w S_{p,q} op(T_q) S_{p,q}^T.
+// ---------------------------------------------------------------------------
+template <typename F, int NT, int NB>
+__device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
+  typedef typename Mfma<F>::V V;
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4, pr = Mfma<F>::perm(r);
+  const PairDev P = A.pairs[it.pair];
+  const int n = P.n;
+  F* Al = reinterpret_cast<F*>(lds + (size_t)(threadIdx.x >> 6) * kLdsWaveWords);
+
+  V acc[NB][NT][NT];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) acc[b][t][u] = V{0, 0, 0, 0};
+
+  for (int e = it.lo; e < it.hi; ++e) {
+    const CplDev C = A.cpl[e];
+    const int nq = C.nsrc;
+    const int S4 = (nq + 3) >> 2;
+    // M-form: M[t][s] = S_{p,q}[16t + r][4s + g] = W[(4s + g) n + 16t + r], W = [c][a]
+    const __amdgpu_buffer_rsrc_t sr = rsrc(A.S + C.off_S, (uint32_t)(nq * n));
+    const uint32_t mbase = (uint32_t)(g * n + r);
+    F M[NT][16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) M[t][s] = (s < S4) ? Mfma<F>::load(sr, mbase + (uint32_t)(4 * s * n + 16 * t)) : F(0);
+
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const TermDev tm = A.terms[(int64_t)e * 4 + it.bslot0 + b];
+      if (tm.src_off < 0) continue;
+      const __amdgpu_buffer_rsrc_t xr = rsrc(A.T + tm.src_off, (uint32_t)(nq * nq));
+      const F mw = F(-tm.w);
+      if (tm.trans) {          // X[c][d] = T_q[d][c]
+        const uint32_t base = (uint32_t)(pr * nq + g);
+#pragma unroll
+        for (int td = 0; td < 4; ++td)
+#pragma unroll
+          for (int s = 0; s < 16; ++s)
+            Al[(td * 16 + s) * 64 + lane] = mw * Mfma<F>::load(xr, base + (uint32_t)(16 * td * nq + 4 * s));
+      } else {                 // X[c][d] = T_q[c][d]
+        const uint32_t base = (uint32_t)(g * nq + pr);
+#pragma unroll
+        for (int td = 0; td < 4; ++td)
+#pragma unroll
+          for (int s = 0; s < 16; ++s)
+            Al[(td * 16 + s) * 64 + lane] = mw * Mfma<F>::load(xr, base + (uint32_t)(4 * s * nq + 16 * td));
+      }
+#pragma unroll
+      for (int td = 0; td < 4; ++td) {
+        if (16 * td < nq) {
+          V d1[NT];
+#pragma unroll
+          for (int u = 0; u < NT; ++u) d1[u] = V{0, 0, 0, 0};
+#pragma unroll
+          for (int s = 0; s < 16; ++s) {
+            if (s < S4) {
+              const F av = Al[(td * 16 + s) * 64 + lane];
+#pragma unroll
+              for (int u = 0; u < NT; ++u) d1[u] = Mfma<F>::op(av, M[u][s], d1[u]);
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int sp = 4 * td + i;
+            if (sp < S4) {
+#pragma unroll
+              for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+                for (int u = 0; u < NT; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][sp], d1[u][i], acc[b][tb][u]);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  const int64_t nn = (int64_t)n * n;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const BlockDev& Bk = A.blocks[P.blk0 + it.bslot0 + b];
+    double* dst = A.ws + Bk.off_ws + (int64_t)it.slot * nn;
+#pragma unroll
+    for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const int a = 16 * u + r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int bb = 16 * tb + Mfma<F>::orow(g, i);
+          if (a < n && bb < n) dst[bb * n + a] = (double)acc[b][tb][u][i];
+        }
+      }
+  }
+}
+
+template <typename F>
+__device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
+  if (it.kind == ITEM_LADDER) {
+    switch (it.variant) {
+      case 0: ladder_item<F, 1, 4, 1, 0>(A, it, lds); break;
+      case 1: ladder_item<F, 1, 2, 1, 0>(A, it, lds); break;
+      case 2: ladder_item<F, 2, 4, 2, 0>(A, it, lds); break;
+      case 3: ladder_item<F, 2, 2, 2, 0>(A, it, lds); break;
+      case 4: ladder_item<F, 2, 1, 2, 0>(A, it, lds); break;
+      case 5: ladder_item<F, 3, 2, 3, 0>(A, it, lds); break;
+      case 6: ladder_item<F, 3, 1, 3, 0>(A, it, lds); break;
+      case 7:
+        if (it.ta0 == 0) ladder_item<F, 4, 1, 2, 0>(A, it, lds);
+        else ladder_item<F, 4, 1, 2, 2>(A, it, lds);
+        break;
+      case 8: ladder_item<F, 1, 1, 1, 0>(A, it, lds); break;
+      default: break;
+    }
+  } else {
+    switch (it.variant) {
+      case 0: proj_item<F, 1, 4>(A, it, lds); break;
+      case 1: proj_item<F, 2, 4>(A, it, lds); break;
+      case 2: proj_item<F, 2, 2>(A, it, lds); break;
+      case 3: proj_item<F, 3, 2>(A, it, lds); break;
+      case 4: proj_item<F, 3, 1>(A, it, lds); break;
+      case 5: proj_item<F, 4, 1>(A, it, lds); break;
+      case 6: proj_item<F, 1, 2>(A, it, lds); break;
+      case 7: proj_item<F, 1, 1>(A, it, lds); break;
+      case 8: proj_item<F, 2, 1>(A, it, lds); break;
+      default: break;
+    }
+  }
+}
+
+template <typename F>
+__global__ __launch_bounds__(256) void grouped_kernel(GroupedArgs<F> A) {
+  __shared__ double lds[4 * kLdsWaveWords];
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    int idx = 0;
+    if (lane == 0) idx = atomicAdd(A.counter, 1);
+    idx = __builtin_amdgcn_readfirstlane(idx);
+    if (idx >= A.n_items) break;
+    const Item it = A.items[idx];
+    run_item<F>(A, it, lds);
+  }
+}
+
+}  // namespace dlpno

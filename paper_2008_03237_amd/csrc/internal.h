@@ -1,0 +1,162 @@
+// Internal device tables and kernel launch interfaces of the DLPNO residual library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dlpno {
+
+// Pair table (one per retained pair).
+struct PairDev {
+  int32_t i, j, n, m;
+  int32_t nblk, blk0;        // stored blocks, global index of the first one
+  int64_t off_B, off_T, off_K, off_eps;
+};
+
+// Block table (one per stored spin block).
+struct BlockDev {
+  int32_t pair, code, n, anti;   // code 0 AA, 1 BB, 2 AB, 3 BA; anti: driver is K - K^T
+  int64_t off_T, off_K, off_eps;
+  int32_t s1, s2;                // spins of electron i and j (0 alpha, 1 beta)
+  double fsum;                   // f^s1_ii + f^s2_jj
+  double w;                      // energy weight (1/2 same spin, 1 opposite spin)
+  int64_t off_ws;                // first partial slot of this block (n*n doubles per slot)
+  int32_t nslot, slot_proj;      // partial slots; first projection slot (== nslot: none)
+};
+
+// Coupling table (CSR order by target pair).
+struct CplDev {
+  int32_t src, nsrc;
+  int64_t off_S;                 // [c][a]: n_src rows x n_target cols
+};
+
+// One projection term: coupling e applied to block slot b of its target.
+struct TermDev {
+  int64_t src_off;               // source block in T; -1 = no term for this block
+  double w;                      // Fock weight; residual gets -w S X S^T
+  int32_t trans, pad;            // X = source^T when trans
+};
+
+enum ItemKind { ITEM_LADDER = 0, ITEM_PROJ = 1 };
+
+// One scheduled unit of the grouped kernel.
+struct Item {
+  int32_t kind;
+  int32_t variant;               // compiled tile variant (see variants below)
+  int32_t pair;
+  int32_t bslot0;                // first block slot of the pair handled
+  int32_t slot;                  // partial slot written
+  int32_t ta0;                   // first a-tile (ladder)
+  int32_t lo, hi;                // Q range (ladder) or coupling range (projection)
+};
+
+// Tile variants compiled into the grouped kernel.
+// Ladder: (NT tiles of 16 per PNO index, NB blocks per item, NTA a-tiles per item).
+struct LadderVariant { int nt, nb, nta; };
+struct ProjVariant { int nt, nb; };
+constexpr int kNumLadderVariants = 9;
+constexpr LadderVariant kLadderVariants[kNumLadderVariants] = {
+    {1, 4, 1}, {1, 2, 1}, {2, 4, 2}, {2, 2, 2}, {2, 1, 2}, {3, 2, 3}, {3, 1, 3}, {4, 1, 2}, {1, 1, 1}};
+constexpr int kNumProjVariants = 9;
+constexpr ProjVariant kProjVariants[kNumProjVariants] = {
+    {1, 4}, {2, 4}, {2, 2}, {3, 2}, {3, 1}, {4, 1}, {1, 2}, {1, 1}, {2, 1}};
+
+// Arguments of the grouped kernel (templated on the operand type).
+template <typename F>
+struct GroupedArgs {
+  const Item* items;
+  int32_t n_items;
+  int32_t* counter;              // work-queue head, zeroed before each launch
+  const PairDev* pairs;
+  const BlockDev* blocks;
+  const CplDev* cpl;
+  const TermDev* terms;          // [coupling][4]
+  const F* B;
+  const F* S;
+  const F* T;
+  double* ws;
+};
+
+// kernels.hip
+hipError_t launch_grouped_f64(const GroupedArgs<double>& a, int workers, hipStream_t s);
+hipError_t launch_grouped_f32(const GroupedArgs<float>& a, int workers, hipStream_t s);
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);
+
+// elementwise.hip
+// DIIS on device.  State lives in a small device struct; vectors in rings.
+struct DiisState {
+  int32_t count;           // stored vectors (<= max)
+  int32_t head;            // ring slot of the newest vector
+  int32_t max;
+  int32_t start;
+  int32_t iter;            // iterations done (history index)
+  int32_t pad[3];
+  double gram[8][8];       // <e_a, e_b> by ring slot
+  double coef[8];          // extrapolation coefficients by ring slot
+};
+struct FinishArgs {
+  const BlockDev* blocks;
+  int32_t n_blocks;
+  const double* T;         // amplitudes the residual is evaluated at
+  const double* K;
+  const double* eps_a;
+  const double* eps_b;
+  const double* ws;
+  double* R;               // residual out (may be null when only the update is wanted)
+  double* T_new;           // Jacobi update out (null: no update)
+  double* e_block;         // per block energy of T_new
+  double* rmax_block;      // per block max |R|
+  int32_t* nonfinite;      // set to 1 when a residual element is not finite
+  int32_t with_driver;     // 0: R = D o T + partials (linear part only, used by the VJP)
+  int32_t pad;
+  // DIIS ring: when ring != null, T_new -> ring_vecs[head], err = T_new - T -> ring_errs[head]
+  const DiisState* ring;
+  double* ring_vecs;
+  double* ring_errs;
+  int64_t ring_stride;
+};
+hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
+
+struct UpdateArgs {         // Jacobi from a given residual
+  const BlockDev* blocks;
+  int32_t n_blocks;
+  const double* T;
+  const double* R;
+  const double* K;
+  const double* eps_a;
+  const double* eps_b;
+  double* T_new;
+  double* e_block;
+};
+hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
+
+struct ReduceArgs {
+  const PairDev* pairs;
+  const BlockDev* blocks;
+  int32_t n_blocks;
+  int32_t n_pairs;
+  const double* e_block;
+  const double* rmax_block;
+  double* e_pair;          // [4 n_pairs] (may be null)
+  double* e_total;         // scalar (may be null)
+  double* rmax;            // scalar (may be null)
+  double* hist;            // per-iteration history [cap][2], indexed by *iter (may be null)
+  int32_t* iter;           // device iteration counter (may be null)
+  int32_t hist_cap;
+};
+hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
+
+hipError_t launch_diis_slot(DiisState* st, hipStream_t s);          // advance head before finish
+hipError_t launch_diis_dots(const double* errs, int64_t n, DiisState* st, double* partial,
+                            int nparts, hipStream_t s);
+hipError_t launch_diis_solve(DiisState* st, const double* partial, int nparts, hipStream_t s);
+hipError_t launch_diis_extrap(const double* vecs, int64_t n, const DiisState* st, double* T,
+                              hipStream_t s);
+hipError_t launch_diis_reset(DiisState* st, int max, int start, hipStream_t s);
+
+// precision copies
+hipError_t launch_convert_f32(const double* src, float* dst, int64_t n, hipStream_t s);
+hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s);
+hipError_t launch_copy(double* y, const double* x, int64_t n, hipStream_t s);
+
+}  // namespace dlpno

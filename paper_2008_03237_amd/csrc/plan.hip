@@ -1,0 +1,782 @@
+// C ABI of the DLPNO doubles-residual library: descriptor validation, device
+// tables, the longest-first work schedule of the grouped kernel, hipGraph
+// replay of one iteration, precision copies and phase timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/dlpno.h"
+#include "internal.h"
+#include "plan_internal.h"
+
+using namespace dlpno;
+
+static thread_local std::string g_last_error;
+
+namespace dlpno {
+dlpno_status fail(dlpno_status s, const std::string& msg) {
+  g_last_error = msg;
+  return s;
+}
+}  // namespace dlpno
+
+#define HIPCK(expr)                                                                          \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail(DLPNO_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+namespace {
+
+int block_code(int s1, int s2) { return s1 == s2 ? s1 : (s1 == 0 ? 2 : 3); }
+const int kCodeS1[4] = {0, 1, 0, 1};
+const int kCodeS2[4] = {0, 1, 1, 0};
+const uint32_t kCodeBit[4] = {DLPNO_AA, DLPNO_BB, DLPNO_AB, DLPNO_BA};
+
+// Block rule (paper Sec. II.A, high-spin cases): s s' kept iff i in occ_s,
+// j in occ_s', not (s == s' and i == j), and BA dropped for i == j.
+uint32_t rule_mask(int i, int j, const uint8_t* somo) {
+  uint32_t m = 0;
+  for (int c = 0; c < 4; ++c) {
+    const int s1 = kCodeS1[c], s2 = kCodeS2[c];
+    const bool in1 = s1 == 0 || !somo[i];
+    const bool in2 = s2 == 0 || !somo[j];
+    if (!in1 || !in2) continue;
+    if (s1 == s2 && i == j) continue;
+    if (i == j && c == 3) continue;
+    m |= kCodeBit[c];
+  }
+  return m;
+}
+
+int popcount4(uint32_t m) { return (m & 1) + ((m >> 1) & 1) + ((m >> 2) & 1) + ((m >> 3) & 1); }
+
+template <typename T>
+dlpno_status dev_alloc(T** p, size_t count, const char* what) {
+  *p = nullptr;
+  if (count == 0) return DLPNO_OK;
+  hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(DLPNO_ERR_OOM, std::string("hipMalloc failed for ") + what + " (" +
+                                   std::to_string(count * sizeof(T)) + " bytes)");
+  }
+  return DLPNO_OK;
+}
+
+template <typename T>
+dlpno_status upload(T** p, const std::vector<T>& h, const char* what, hipStream_t s) {
+  dlpno_status st = dev_alloc(p, h.size(), what);
+  if (st != DLPNO_OK) return st;
+  if (!h.empty()) HIPCK(hipMemcpyAsync(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return DLPNO_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// schedule
+// ---------------------------------------------------------------------------
+namespace dlpno {
+
+int ladder_mfma_per_q(int nt, int nta, int s4) { return 2 * nt * nta * s4; }
+
+// largest compiled variant with this tile shape handling at most maxnb blocks
+int pick_ladder(int nt, int nta, int maxnb) {
+  int best = -1;
+  for (int v = 0; v < kNumLadderVariants; ++v) {
+    const LadderVariant& V = kLadderVariants[v];
+    if (V.nt == nt && V.nta == nta && V.nb <= maxnb && (best < 0 || V.nb > kLadderVariants[best].nb)) best = v;
+  }
+  return best;
+}
+int pick_proj(int nt, int maxnb) {
+  int best = -1;
+  for (int v = 0; v < kNumProjVariants; ++v) {
+    const ProjVariant& V = kProjVariants[v];
+    if (V.nt == nt && V.nb <= maxnb && (best < 0 || V.nb > kProjVariants[best].nb)) best = v;
+  }
+  return best;
+}
+
+dlpno_status build_schedule(dlpno_plan* P) {
+  const int npairs = P->n_pairs;
+  std::vector<int> nL(npairs, 0), nP(npairs, 0);
+  struct Cand { Item it; double cost; };
+  std::vector<Cand> cand;
+  // total work in MFMA instructions, to size the items
+  double total = 0.0;
+  for (int p = 0; p < npairs; ++p) {
+    const PairDev& pr = P->pairs_h[p];
+    if (pr.nblk == 0) continue;
+    const int nt = (pr.n + 15) / 16, s4 = (pr.n + 3) / 4;
+    total += (double)pr.m * pr.nblk * ladder_mfma_per_q(nt, nt, s4);
+    for (int64_t e = P->rowptr_h[p]; e < P->rowptr_h[p + 1]; ++e) {
+      const int nq = P->cpl_h[e].nsrc;
+      const int ntq = (nq + 15) / 16, s4q = (nq + 3) / 4;
+      total += (double)pr.nblk * (nt * ntq + nt * nt) * s4q;
+    }
+  }
+  const int waves = std::max(1, P->workers * 4);
+  double target = total / (waves * P->tune.items_per_wave);
+  target = std::max(target, (double)P->tune.min_item_mfma);
+  P->total_mfma = total;
+
+  for (int p = 0; p < npairs; ++p) {
+    const PairDev& pr = P->pairs_h[p];
+    if (pr.nblk == 0) continue;
+    const int nt = (pr.n + 15) / 16, s4 = (pr.n + 3) / 4;
+    // ladder: block groups of the tuned variant, smaller variants of the same
+    // tile shape for the remainder
+    const int lv = P->tune.ladder_variant[nt - 1];
+    const LadderVariant V = kLadderVariants[lv];
+    const double per_q = (double)V.nb * ladder_mfma_per_q(V.nt, V.nta, s4);
+    int chunks = (int)std::ceil(per_q * pr.m / target);
+    chunks = std::max(1, std::min(chunks, pr.m));
+    nL[p] = chunks;
+    for (int c = 0; c < chunks; ++c) {
+      const int lo = (int)((int64_t)pr.m * c / chunks), hi = (int)((int64_t)pr.m * (c + 1) / chunks);
+      for (int b0 = 0; b0 < pr.nblk;) {
+        const int v = pick_ladder(nt, V.nta, std::min(V.nb, pr.nblk - b0));
+        if (v < 0) return fail(DLPNO_ERR_INVALID_ARG, "no ladder tile variant for this block group");
+        const LadderVariant W = kLadderVariants[v];
+        for (int ta0 = 0; ta0 < nt; ta0 += W.nta) {
+          Item it{};
+          it.kind = ITEM_LADDER;
+          it.variant = v;
+          it.pair = p;
+          it.bslot0 = b0;
+          it.slot = c;
+          it.ta0 = ta0;
+          it.lo = lo;
+          it.hi = hi;
+          cand.push_back({it, (double)(hi - lo) * W.nb * ladder_mfma_per_q(W.nt, W.nta, s4)});
+        }
+        b0 += W.nb;
+      }
+    }
+    // projection
+    const int64_t e0 = P->rowptr_h[p], e1 = P->rowptr_h[p + 1];
+    if (e1 > e0) {
+      const int pv = P->tune.proj_variant[nt - 1];
+      const ProjVariant U = kProjVariants[pv];
+      // chunk the coupling list by cost
+      std::vector<std::pair<int64_t, int64_t>> ranges;
+      double acc = 0.0;
+      int64_t start = e0;
+      for (int64_t e = e0; e < e1; ++e) {
+        const int nq = P->cpl_h[e].nsrc;
+        acc += (double)U.nb * (nt * ((nq + 15) / 16) + nt * nt) * ((nq + 3) / 4);
+        if (acc >= target && e + 1 < e1) {
+          ranges.push_back({start, e + 1});
+          start = e + 1;
+          acc = 0.0;
+        }
+      }
+      ranges.push_back({start, e1});
+      nP[p] = (int)ranges.size();
+      for (size_t c = 0; c < ranges.size(); ++c) {
+        double cost = 0.0;
+        for (int64_t e = ranges[c].first; e < ranges[c].second; ++e) {
+          const int nq = P->cpl_h[e].nsrc;
+          cost += (nt * ((nq + 15) / 16) + nt * nt) * ((nq + 3) / 4);
+        }
+        for (int b0 = 0; b0 < pr.nblk;) {
+          const int v = pick_proj(nt, std::min(U.nb, pr.nblk - b0));
+          if (v < 0) return fail(DLPNO_ERR_INVALID_ARG, "no projection tile variant for this block group");
+          Item it{};
+          it.kind = ITEM_PROJ;
+          it.variant = v;
+          it.pair = p;
+          it.bslot0 = b0;
+          it.slot = nL[p] + (int)c;
+          it.ta0 = 0;
+          it.lo = (int)ranges[c].first;
+          it.hi = (int)ranges[c].second;
+          cand.push_back({it, cost * kProjVariants[v].nb});
+          b0 += kProjVariants[v].nb;
+        }
+      }
+    }
+  }
+  // workspace slots
+  int64_t ws = 0;
+  for (int p = 0; p < npairs; ++p) {
+    const PairDev& pr = P->pairs_h[p];
+    for (int b = 0; b < pr.nblk; ++b) {
+      BlockDev& bk = P->blocks_h[pr.blk0 + b];
+      bk.nslot = nL[p] + nP[p];
+      bk.slot_proj = nL[p];
+      bk.off_ws = ws;
+      ws += (int64_t)bk.nslot * pr.n * pr.n;
+    }
+  }
+  P->ws_elems = ws;
+  // longest first; ties by pair for a deterministic order
+  std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) { return a.cost > b.cost; });
+  P->items_h.clear();
+  P->items_h.reserve(cand.size());
+  double maxc = 0.0;
+  for (auto& c : cand) {
+    P->items_h.push_back(c.it);
+    maxc = std::max(maxc, c.cost);
+  }
+  P->max_item_mfma = maxc;
+  return DLPNO_OK;
+}
+
+}  // namespace dlpno
+
+// ---------------------------------------------------------------------------
+// device state (re)allocation for the schedule
+// ---------------------------------------------------------------------------
+dlpno_status dlpno::upload_schedule(dlpno_plan* P, hipStream_t s) {
+  if (P->d_items) (void)hipFree(P->d_items);
+  if (P->d_blocks) (void)hipFree(P->d_blocks);
+  if (P->d_ws) (void)hipFree(P->d_ws);
+  P->d_items = nullptr;
+  P->d_blocks = nullptr;
+  P->d_ws = nullptr;
+  dlpno_status st;
+  if ((st = upload(&P->d_items, P->items_h, "work items", s)) != DLPNO_OK) return st;
+  if ((st = upload(&P->d_blocks, P->blocks_h, "block table", s)) != DLPNO_OK) return st;
+  if ((st = dev_alloc(&P->d_ws, (size_t)std::max<int64_t>(P->ws_elems, 1), "partial-sum workspace")) != DLPNO_OK)
+    return st;
+  P->graph_valid = false;
+  return DLPNO_OK;
+}
+
+std::string dlpno::describe(const dlpno_plan* P) {
+  char buf[1024];
+  int nl = 0, np = 0;
+  for (auto& it : P->items_h) (it.kind == ITEM_LADDER ? nl : np)++;
+  std::string s;
+  snprintf(buf, sizeof buf,
+           "pairs=%d blocks=%d couplings=%lld terms=%lld precision=%d workers=%d items=%zu (ladder %d, "
+           "projection %d) max_item/total=%.2e workspace=%.3f GB\n",
+           P->n_pairs, P->n_blocks, (long long)P->n_cpl, (long long)P->n_terms, (int)P->opt.precision, P->workers,
+           P->items_h.size(), nl, np, P->total_mfma > 0 ? P->max_item_mfma / P->total_mfma : 0.0,
+           P->ws_elems * 8.0 / 1e9);
+  s += buf;
+  snprintf(buf, sizeof buf, "ladder variants by tiles: %d %d %d %d; projection: %d %d %d %d; items/wave %.1f\n",
+           P->tune.ladder_variant[0], P->tune.ladder_variant[1], P->tune.ladder_variant[2], P->tune.ladder_variant[3],
+           P->tune.proj_variant[0], P->tune.proj_variant[1], P->tune.proj_variant[2], P->tune.proj_variant[3],
+           P->tune.items_per_wave);
+  s += buf;
+  snprintf(buf, sizeof buf, "flops/residual: ladder %.4e projection %.4e\n", P->flops_ladder, P->flops_proj);
+  s += buf;
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// plan creation
+// ---------------------------------------------------------------------------
+extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno_inputs* in,
+                                          const dlpno_options* opts, void* stream, dlpno_plan** out) {
+  g_last_error.clear();
+  if (!out) return fail(DLPNO_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!prob || !in) return fail(DLPNO_ERR_INVALID_ARG, "problem or inputs is NULL");
+  const int n_occ = prob->n_occ, npairs = prob->n_pairs;
+  if (n_occ < 1 || npairs < 0 || prob->n_couplings < 0)
+    return fail(DLPNO_ERR_DIM_RANGE, "n_occ must be >= 1, n_pairs and n_couplings >= 0");
+  if (!prob->is_somo || !prob->f_a || !prob->f_b || !prob->cpl_rowptr || (npairs > 0 && !prob->pairs) ||
+      (prob->n_couplings > 0 && !prob->cpl))
+    return fail(DLPNO_ERR_INVALID_ARG, "a required host array is NULL");
+  dlpno_options opt{};
+  opt.precision = DLPNO_FP64;
+  opt.diis_max = 8;
+  opt.diis_start = 3;
+  if (opts) opt = *opts;
+  if (opt.precision < DLPNO_FP64 || opt.precision > DLPNO_FP16X2)
+    return fail(DLPNO_ERR_INVALID_ARG, "unknown precision");
+  if (opt.precision == DLPNO_BF16X2 || opt.precision == DLPNO_FP16X2)
+    return fail(DLPNO_ERR_UNSUPPORTED, "split precisions are provided by the mixed-precision path");
+  if (opt.diis_max < 0 || opt.diis_max > 8) return fail(DLPNO_ERR_INVALID_ARG, "diis_max must be in 0..8");
+  if (opt.diis_max > 0 && (opt.diis_start < 1 || opt.diis_start > opt.diis_max))
+    return fail(DLPNO_ERR_INVALID_ARG, "diis_start must be in 1..diis_max");
+  for (int k = 0; k < n_occ; ++k)
+    if (prob->is_somo[k] > 1) return fail(DLPNO_ERR_INVALID_ARG, "is_somo entries must be 0 or 1");
+  const bool need_inputs = npairs > 0;
+  if (need_inputs && (!in->B || !in->K || !in->eps_a || !in->eps_b || (prob->n_couplings > 0 && !in->S)))
+    return fail(DLPNO_ERR_INVALID_ARG, "a device input pointer is NULL");
+
+  hipStream_t s = (hipStream_t)stream;
+  dlpno_plan* P = new dlpno_plan();
+  P->opt = opt;
+  P->n_occ = n_occ;
+  P->n_pairs = npairs;
+  P->n_cpl = prob->n_couplings;
+  P->in = *in;
+  P->n_B = prob->n_B;
+  P->n_T = prob->n_T;
+  P->n_K = prob->n_K;
+  P->n_eps = prob->n_eps;
+  P->n_S = prob->n_S;
+  P->somo.assign(prob->is_somo, prob->is_somo + n_occ);
+  auto destroy_fail = [&](dlpno_status st) {
+    dlpno_plan_destroy(P);
+    return st;
+  };
+
+  // ---- pairs ----
+  std::map<std::pair<int, int>, int> index;
+  P->pairs_h.resize(npairs);
+  int nblk_total = 0;
+  for (int p = 0; p < npairs; ++p) {
+    const dlpno_pair& d = prob->pairs[p];
+    if (d.i < 0 || d.j < d.i || d.j >= n_occ)
+      return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, "pair " + std::to_string(p) + ": need 0 <= i <= j < n_occ"));
+    if (d.npno < 1 || d.npno > 64)
+      return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, "pair " + std::to_string(p) + ": npno must be in 1..64"));
+    if (d.naux < 1 || d.naux > 65536)
+      return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, "pair " + std::to_string(p) + ": naux must be in 1..65536"));
+    if (!index.emplace(std::make_pair(d.i, d.j), p).second)
+      return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "pair " + std::to_string(p) + " duplicates an earlier pair"));
+    const uint32_t want = rule_mask(d.i, d.j, prob->is_somo);
+    if (d.blocks != want)
+      return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "pair " + std::to_string(p) +
+                                                          ": block mask does not follow the spin-case rule"));
+    const int64_t n = d.npno, n2 = n * n, nb = popcount4(want);
+    if (d.off_B < 0 || d.off_B + (int64_t)d.naux * n2 > prob->n_B || d.off_T < 0 || d.off_T + nb * n2 > prob->n_T ||
+        d.off_K < 0 || d.off_K + n2 > prob->n_K || d.off_eps < 0 || d.off_eps + n > prob->n_eps)
+      return destroy_fail(fail(DLPNO_ERR_ALIGNMENT, "pair " + std::to_string(p) + ": offsets exceed the buffers"));
+    PairDev& pd = P->pairs_h[p];
+    pd.i = d.i;
+    pd.j = d.j;
+    pd.n = d.npno;
+    pd.m = d.naux;
+    pd.nblk = (int)nb;
+    pd.blk0 = nblk_total;
+    pd.off_B = d.off_B;
+    pd.off_T = d.off_T;
+    pd.off_K = d.off_K;
+    pd.off_eps = d.off_eps;
+    nblk_total += (int)nb;
+  }
+  P->n_blocks = nblk_total;
+  // ---- blocks ----
+  P->blocks_h.resize(nblk_total);
+  P->flops_ladder = 0.0;
+  for (int p = 0; p < npairs; ++p) {
+    const dlpno_pair& d = prob->pairs[p];
+    const PairDev& pd = P->pairs_h[p];
+    int slot = 0;
+    for (int c = 0; c < 4; ++c) {
+      if (!(d.blocks & kCodeBit[c])) continue;
+      BlockDev& b = P->blocks_h[pd.blk0 + slot];
+      b.pair = p;
+      b.code = c;
+      b.n = pd.n;
+      b.s1 = kCodeS1[c];
+      b.s2 = kCodeS2[c];
+      b.anti = b.s1 == b.s2;
+      b.off_T = pd.off_T + (int64_t)slot * pd.n * pd.n;
+      b.off_K = pd.off_K;
+      b.off_eps = pd.off_eps;
+      const double* f1 = b.s1 == 0 ? prob->f_a : prob->f_b;
+      const double* f2 = b.s2 == 0 ? prob->f_a : prob->f_b;
+      b.fsum = f1[(size_t)d.i * n_occ + d.i] + f2[(size_t)d.j * n_occ + d.j];
+      b.w = b.anti ? 0.5 : 1.0;
+      P->flops_ladder += 4.0 * pd.m * (double)pd.n * pd.n * pd.n;
+      ++slot;
+    }
+  }
+  // ---- couplings and terms ----
+  P->rowptr_h.assign(prob->cpl_rowptr, prob->cpl_rowptr + npairs + 1);
+  if (P->rowptr_h[0] != 0 || P->rowptr_h[npairs] != prob->n_couplings)
+    return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "cpl_rowptr must start at 0 and end at n_couplings"));
+  for (int p = 0; p < npairs; ++p)
+    if (P->rowptr_h[p + 1] < P->rowptr_h[p])
+      return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "cpl_rowptr must be non-decreasing"));
+  if (prob->n_couplings > INT32_MAX) return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, "too many couplings"));
+  P->cpl_h.resize(prob->n_couplings);
+  P->terms_h.assign((size_t)prob->n_couplings * 4, TermDev{-1, 0.0, 0, 0});
+  P->flops_proj = 0.0;
+  P->n_terms = 0;
+  for (int p = 0; p < npairs; ++p) {
+    const dlpno_pair& d = prob->pairs[p];
+    const PairDev& pd = P->pairs_h[p];
+    for (int64_t e = P->rowptr_h[p]; e < P->rowptr_h[p + 1]; ++e) {
+      const dlpno_coupling& c = prob->cpl[e];
+      const std::string where = "coupling " + std::to_string(e) + " of pair " + std::to_string(p);
+      if (c.src_pair < 0 || c.src_pair >= npairs || c.k < 0 || c.k >= n_occ || (c.side != 0 && c.side != 1))
+        return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, where + ": src_pair, k or side out of range"));
+      const int rep = c.side == 0 ? d.i : d.j, keep = c.side == 0 ? d.j : d.i;
+      if (c.k == rep) return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, where + ": k equals the replaced index"));
+      const dlpno_pair& q = prob->pairs[c.src_pair];
+      if (q.i != std::min(c.k, keep) || q.j != std::max(c.k, keep))
+        return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, where + ": source pair does not match (k, side)"));
+      const int64_t nq = q.npno;
+      if (c.off_S < 0 || c.off_S + nq * d.npno > prob->n_S)
+        return destroy_fail(fail(DLPNO_ERR_ALIGNMENT, where + ": off_S exceeds the S buffer"));
+      CplDev& cd = P->cpl_h[e];
+      cd.src = c.src_pair;
+      cd.nsrc = q.npno;
+      cd.off_S = c.off_S;
+      // terms per target block
+      int slot = 0;
+      for (int code = 0; code < 4; ++code) {
+        if (!(d.blocks & kCodeBit[code])) continue;
+        const int s1 = kCodeS1[code], s2 = kCodeS2[code];
+        const int sk = c.side == 0 ? s1 : s2;              // spin of the replaced electron
+        TermDev& tm = P->terms_h[(size_t)e * 4 + slot];
+        ++slot;
+        if (sk == 1 && prob->is_somo[c.k]) continue;       // k must be occupied in that spin
+        // ordered source pair (x, y) with spins (s1, s2)
+        const int x = c.side == 0 ? c.k : d.i, y = c.side == 0 ? d.j : c.k;
+        int scode, trans;
+        if (x == y) {
+          if (s1 == s2) continue;                           // Pauli
+          scode = 2;
+          trans = s1 == 1;
+        } else if (x < y) {
+          scode = block_code(s1, s2);
+          trans = 0;
+        } else {
+          scode = block_code(s2, s1);
+          trans = 1;
+        }
+        if (!(q.blocks & kCodeBit[scode])) continue;
+        int sslot = 0;
+        for (int cc = 0; cc < scode; ++cc)
+          if (q.blocks & kCodeBit[cc]) ++sslot;
+        const double* f = sk == 0 ? prob->f_a : prob->f_b;
+        const double w = f[(size_t)c.k * n_occ + rep];
+        if (w == 0.0) continue;
+        tm.src_off = q.off_T + (int64_t)sslot * nq * nq;
+        tm.w = w;
+        tm.trans = trans;
+        P->flops_proj += 2.0 * pd.n * (double)nq * (pd.n + nq);
+        ++P->n_terms;
+      }
+    }
+  }
+  // ---- device ----
+  int dev = 0;
+  HIPCK(hipGetDevice(&dev));
+  P->device = dev;
+  hipDeviceProp_t prop;
+  HIPCK(hipGetDeviceProperties(&prop, dev));
+  P->num_cu = prop.multiProcessorCount;
+  P->workers = opt.n_workers > 0 ? opt.n_workers : P->num_cu;
+  if (opt.chunk_flops > 0) P->tune.items_per_wave = std::max(1.0, (double)opt.chunk_flops);
+  dlpno_status st;
+  if ((st = build_schedule(P)) != DLPNO_OK) return destroy_fail(st);
+  if ((st = upload(&P->d_pairs, P->pairs_h, "pair table", s)) != DLPNO_OK) return destroy_fail(st);
+  if ((st = upload(&P->d_cpl, P->cpl_h, "coupling table", s)) != DLPNO_OK) return destroy_fail(st);
+  if ((st = upload(&P->d_terms, P->terms_h, "term table", s)) != DLPNO_OK) return destroy_fail(st);
+  if ((st = upload_schedule(P, s)) != DLPNO_OK) return destroy_fail(st);
+  if ((st = dev_alloc(&P->d_counter, 4, "queue counter")) != DLPNO_OK) return destroy_fail(st);
+  if ((st = dev_alloc(&P->d_e_block, std::max(1, nblk_total), "block energies")) != DLPNO_OK) return destroy_fail(st);
+  if ((st = dev_alloc(&P->d_rmax_block, std::max(1, nblk_total), "block residual maxima")) != DLPNO_OK)
+    return destroy_fail(st);
+  if ((st = dev_alloc(&P->d_nonfinite, 4, "non-finite flag")) != DLPNO_OK) return destroy_fail(st);
+  if ((st = dev_alloc(&P->d_hist, 2 * kHistCap, "history")) != DLPNO_OK) return destroy_fail(st);
+  if ((st = dev_alloc(&P->d_diis, 1, "DIIS state")) != DLPNO_OK) return destroy_fail(st);
+  if ((st = dev_alloc(&P->d_scalars, 8, "scalars")) != DLPNO_OK) return destroy_fail(st);
+  if ((st = dev_alloc(&P->d_diis_partial, (size_t)kDiisParts * 8, "DIIS partial sums")) != DLPNO_OK)
+    return destroy_fail(st);
+  if (opt.diis_max > 0 && P->n_T > 0) {
+    if ((st = dev_alloc(&P->d_ring_vecs, (size_t)opt.diis_max * P->n_T, "DIIS vectors")) != DLPNO_OK)
+      return destroy_fail(st);
+    if ((st = dev_alloc(&P->d_ring_errs, (size_t)opt.diis_max * P->n_T, "DIIS errors")) != DLPNO_OK)
+      return destroy_fail(st);
+  }
+  HIPCK(launch_zero_i32(P->d_nonfinite, 1, s));
+  HIPCK(launch_diis_reset(P->d_diis, std::max(1, opt.diis_max), std::max(1, opt.diis_start), s));
+  if (opt.precision == DLPNO_FP32) {
+    if ((st = dev_alloc(&P->B32, (size_t)std::max<int64_t>(P->n_B, 1), "FP32 B")) != DLPNO_OK) return destroy_fail(st);
+    if ((st = dev_alloc(&P->S32, (size_t)std::max<int64_t>(P->n_S, 1), "FP32 S")) != DLPNO_OK) return destroy_fail(st);
+    if ((st = dev_alloc(&P->T32, (size_t)std::max<int64_t>(P->n_T, 1), "FP32 T")) != DLPNO_OK) return destroy_fail(st);
+    if (P->n_B > 0) HIPCK(launch_convert_f32(in->B, P->B32, P->n_B, s));
+    if (P->n_S > 0) HIPCK(launch_convert_f32(in->S, P->S32, P->n_S, s));
+  }
+  HIPCK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+  HIPCK(hipStreamSynchronize(s));
+  P->info = describe(P);
+  *out = P;
+  return DLPNO_OK;
+}
+
+extern "C" dlpno_status dlpno_plan_destroy(dlpno_plan* P) {
+  if (!P) return DLPNO_OK;
+  (void)hipDeviceSynchronize();
+  if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+  if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
+  for (auto& ev : P->events) (void)hipEventDestroy(ev);
+  void* ptrs[] = {P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms, P->d_items, P->d_counter, P->d_ws,
+                  P->d_e_block, P->d_rmax_block, P->d_nonfinite, P->d_hist, P->d_diis, P->d_scalars,
+                  P->d_diis_partial, P->d_ring_vecs, P->d_ring_errs, P->B32, P->S32, P->T32,
+                  P->d_vjp_items, P->d_mixed, P->G32};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete P;
+  return DLPNO_OK;
+}
+
+// ---------------------------------------------------------------------------
+// phases
+// ---------------------------------------------------------------------------
+namespace dlpno {
+
+void phase_begin(dlpno_plan* P, int ph, hipStream_t s) {
+  if (!P->profiling) return;
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  (void)hipEventRecord(a, s);
+  P->pending.push_back({ph, a, b});
+}
+void phase_end(dlpno_plan* P, hipStream_t s) {
+  if (!P->profiling || P->pending.empty()) return;
+  (void)hipEventRecord(P->pending.back().stop, s);
+}
+void phase_collect(dlpno_plan* P) {
+  for (auto& pe : P->pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pe.stop) == hipSuccess && hipEventElapsedTime(&ms, pe.start, pe.stop) == hipSuccess) {
+      P->phase_ms[pe.phase] += ms;
+      P->phase_n[pe.phase] += 1;
+    }
+    (void)hipEventDestroy(pe.start);
+    (void)hipEventDestroy(pe.stop);
+  }
+  P->pending.clear();
+}
+
+// grouped kernel over amplitudes T (FP64 buffer given by the caller)
+hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s) {
+  hipError_t e;
+  if (P->items_h.empty()) return hipSuccess;
+  if (P->opt.precision == DLPNO_FP32) {
+    phase_begin(P, 4, s);
+    if ((e = launch_convert_f32(T, P->T32, P->n_T, s)) != hipSuccess) return e;
+    phase_end(P, s);
+  }
+  if ((e = launch_zero_i32(P->d_counter, 1, s)) != hipSuccess) return e;
+  phase_begin(P, 0, s);
+  if (P->opt.precision == DLPNO_FP32) {
+    GroupedArgs<float> a{P->d_items, (int32_t)P->items_h.size(), P->d_counter, P->d_pairs, P->d_blocks,
+                         P->d_cpl, P->d_terms, P->B32, P->S32, P->T32, P->d_ws};
+    e = launch_grouped_f32(a, P->workers, s);
+  } else {
+    GroupedArgs<double> a{P->d_items, (int32_t)P->items_h.size(), P->d_counter, P->d_pairs, P->d_blocks,
+                          P->d_cpl, P->d_terms, P->in.B, P->in.S, T, P->d_ws};
+    e = launch_grouped_f64(a, P->workers, s);
+  }
+  phase_end(P, s);
+  return e;
+}
+
+FinishArgs finish_args(dlpno_plan* P, const double* T) {
+  FinishArgs f{};
+  f.blocks = P->d_blocks;
+  f.n_blocks = P->n_blocks;
+  f.T = T;
+  f.K = P->in.K;
+  f.eps_a = P->in.eps_a;
+  f.eps_b = P->in.eps_b;
+  f.ws = P->d_ws;
+  f.e_block = P->d_e_block;
+  f.rmax_block = P->d_rmax_block;
+  f.nonfinite = P->d_nonfinite;
+  f.with_driver = 1;
+  return f;
+}
+
+// one full iteration on stream s (capturable: kernels only)
+hipError_t enqueue_iteration(dlpno_plan* P, double* T, double* R, double* e_pair, double* e_total, double* rmax,
+                             hipStream_t s) {
+  hipError_t e;
+  const bool diis = P->opt.diis_max > 0;
+  if (diis && (e = launch_diis_slot(P->d_diis, s)) != hipSuccess) return e;
+  if ((e = run_grouped(P, T, s)) != hipSuccess) return e;
+  FinishArgs f = finish_args(P, T);
+  f.R = R;
+  if (diis) {
+    f.ring = P->d_diis;
+    f.ring_vecs = P->d_ring_vecs;
+    f.ring_errs = P->d_ring_errs;
+    f.ring_stride = P->n_T;
+  } else {
+    f.T_new = T;     // in place: every element is read before it is written by the same thread
+  }
+  phase_begin(P, 1, s);
+  if ((e = launch_finish(f, s)) != hipSuccess) return e;
+  phase_end(P, s);
+  ReduceArgs ra{};
+  ra.pairs = P->d_pairs;
+  ra.blocks = P->d_blocks;
+  ra.n_blocks = P->n_blocks;
+  ra.n_pairs = P->n_pairs;
+  ra.e_block = P->d_e_block;
+  ra.rmax_block = P->d_rmax_block;
+  ra.e_pair = e_pair;
+  ra.e_total = e_total ? e_total : P->d_scalars;
+  ra.rmax = rmax ? rmax : P->d_scalars + 1;
+  ra.hist = P->d_hist;
+  ra.iter = &P->d_diis->iter;
+  ra.hist_cap = kHistCap;
+  phase_begin(P, 2, s);
+  if ((e = launch_reduce(ra, s)) != hipSuccess) return e;
+  phase_end(P, s);
+  if (diis) {
+    phase_begin(P, 3, s);
+    if ((e = launch_diis_dots(P->d_ring_errs, P->n_T, P->d_diis, P->d_diis_partial, kDiisParts, s)) != hipSuccess)
+      return e;
+    if ((e = launch_diis_solve(P->d_diis, P->d_diis_partial, kDiisParts, s)) != hipSuccess) return e;
+    if ((e = launch_diis_extrap(P->d_ring_vecs, P->n_T, P->d_diis, T, s)) != hipSuccess) return e;
+    phase_end(P, s);
+  }
+  return hipSuccess;
+}
+
+}  // namespace dlpno
+
+// ---------------------------------------------------------------------------
+// entry points
+// ---------------------------------------------------------------------------
+extern "C" dlpno_status dlpno_residual(dlpno_plan* P, const double* T, double* R, void* stream) {
+  if (!P || ((!T || !R) && P->n_T > 0)) return fail(DLPNO_ERR_INVALID_ARG, "NULL plan or buffer");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCK(run_grouped(P, T, s));
+  FinishArgs f = finish_args(P, T);
+  f.R = R;
+  phase_begin(P, 1, s);
+  HIPCK(launch_finish(f, s));
+  phase_end(P, s);
+  if (P->profiling) phase_collect(P);
+  return DLPNO_OK;
+}
+
+extern "C" dlpno_status dlpno_update(dlpno_plan* P, const double* T, const double* R, double* T_out, double* e_pair,
+                                     double* e_total, void* stream) {
+  if (!P || ((!T || !R || !T_out) && P->n_T > 0)) return fail(DLPNO_ERR_INVALID_ARG, "NULL plan or buffer");
+  hipStream_t s = (hipStream_t)stream;
+  UpdateArgs u{P->d_blocks, P->n_blocks, T, R, P->in.K, P->in.eps_a, P->in.eps_b, T_out, P->d_e_block};
+  HIPCK(launch_update(u, s));
+  ReduceArgs ra{};
+  ra.pairs = P->d_pairs;
+  ra.blocks = P->d_blocks;
+  ra.n_blocks = P->n_blocks;
+  ra.n_pairs = P->n_pairs;
+  ra.e_block = P->d_e_block;
+  ra.rmax_block = nullptr;
+  ra.e_pair = e_pair;
+  ra.e_total = e_total;
+  HIPCK(launch_reduce(ra, s));
+  return DLPNO_OK;
+}
+
+extern "C" dlpno_status dlpno_reset(dlpno_plan* P, void* stream) {
+  if (!P) return fail(DLPNO_ERR_INVALID_ARG, "NULL plan");
+  hipStream_t s = (hipStream_t)stream;
+  HIPCK(launch_diis_reset(P->d_diis, std::max(1, P->opt.diis_max), std::max(1, P->opt.diis_start), s));
+  HIPCK(launch_zero_i32(P->d_nonfinite, 1, s));
+  HIPCK(hipStreamSynchronize(s));
+  P->host_iter = 0;
+  return DLPNO_OK;
+}
+
+extern "C" dlpno_status dlpno_iterate(dlpno_plan* P, int32_t n_iter, double* T, double* R, double* e_pair,
+                                      double* e_total, double* max_abs_R, void* stream) {
+  if (!P || n_iter < 0 || ((!T || !R) && P->n_T > 0)) return fail(DLPNO_ERR_INVALID_ARG, "bad arguments");
+  hipStream_t s = (hipStream_t)stream;
+  if (P->profiling) {
+    for (int k = 0; k < n_iter; ++k) HIPCK(enqueue_iteration(P, T, R, e_pair, e_total, max_abs_R, s));
+    phase_collect(P);
+  } else {
+    const void* key[5] = {T, R, e_pair, e_total, max_abs_R};
+    if (!P->graph_valid || memcmp(key, P->graph_key, sizeof key) != 0) {
+      if (P->gexec) {
+        (void)hipGraphExecDestroy(P->gexec);
+        P->gexec = nullptr;
+      }
+      hipGraph_t g;
+      HIPCK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = enqueue_iteration(P, T, R, e_pair, e_total, max_abs_R, P->cap_stream);
+      hipError_t ee = hipStreamEndCapture(P->cap_stream, &g);
+      if (ce != hipSuccess) return fail(DLPNO_ERR_HIP, std::string("capture: ") + hipGetErrorString(ce));
+      HIPCK(ee);
+      HIPCK(hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(g);
+      memcpy(P->graph_key, key, sizeof key);
+      P->graph_valid = true;
+    }
+    for (int k = 0; k < n_iter; ++k) HIPCK(hipGraphLaunch(P->gexec, s));
+  }
+  P->host_iter += n_iter;
+  int32_t flag = 0;
+  HIPCK(hipMemcpyAsync(&flag, P->d_nonfinite, sizeof flag, hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  if (flag) return fail(DLPNO_ERR_NONFINITE, "a residual element was not finite");
+  return DLPNO_OK;
+}
+
+extern "C" int32_t dlpno_history(const dlpno_plan* P, double* energy, double* max_abs_r, int32_t n) {
+  if (!P || n <= 0) return 0;
+  const int have = (int)std::min<int64_t>(P->host_iter, kHistCap);
+  const int m = std::min(n, have);
+  std::vector<double> h(2 * (size_t)std::max(m, 1));
+  if (m > 0 && hipMemcpy(h.data(), P->d_hist, 2 * sizeof(double) * m, hipMemcpyDeviceToHost) != hipSuccess) return 0;
+  for (int k = 0; k < m; ++k) {
+    if (energy) energy[k] = h[2 * k];
+    if (max_abs_r) max_abs_r[k] = h[2 * k + 1];
+  }
+  return m;
+}
+
+extern "C" dlpno_status dlpno_flop_count(const dlpno_plan* P, double* ladder, double* projection) {
+  if (!P) return fail(DLPNO_ERR_INVALID_ARG, "NULL plan");
+  if (ladder) *ladder = P->flops_ladder;
+  if (projection) *projection = P->flops_proj;
+  return DLPNO_OK;
+}
+
+extern "C" dlpno_status dlpno_set_profiling(dlpno_plan* P, int32_t enable) {
+  if (!P) return fail(DLPNO_ERR_INVALID_ARG, "NULL plan");
+  P->profiling = enable != 0;
+  for (int k = 0; k < kPhases; ++k) {
+    P->phase_ms[k] = 0.0;
+    P->phase_n[k] = 0;
+  }
+  return DLPNO_OK;
+}
+
+extern "C" dlpno_status dlpno_phase_times(const dlpno_plan* P, double* ms, int64_t* launches, int32_t n) {
+  if (!P) return fail(DLPNO_ERR_INVALID_ARG, "NULL plan");
+  for (int k = 0; k < n && k < kPhases; ++k) {
+    if (ms) ms[k] = P->phase_ms[k];
+    if (launches) launches[k] = P->phase_n[k];
+  }
+  return DLPNO_OK;
+}
+
+extern "C" const char* dlpno_plan_info(const dlpno_plan* P) { return P ? P->info.c_str() : ""; }
+
+extern "C" const char* dlpno_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char* dlpno_status_string(dlpno_status s) {
+  switch (s) {
+    case DLPNO_OK: return "ok";
+    case DLPNO_ERR_INVALID_ARG: return "invalid argument";
+    case DLPNO_ERR_DIM_RANGE: return "dimension out of range";
+    case DLPNO_ERR_ALIGNMENT: return "offset outside buffer";
+    case DLPNO_ERR_HIP: return "HIP runtime error";
+    case DLPNO_ERR_NONFINITE: return "non-finite residual";
+    case DLPNO_ERR_NOT_CONVERGED: return "not converged";
+    case DLPNO_ERR_OOM: return "out of device memory";
+    case DLPNO_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}

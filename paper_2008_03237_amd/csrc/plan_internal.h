@@ -1,0 +1,102 @@
+// Plan object of the DLPNO residual library (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/dlpno.h"
+#include "internal.h"
+
+namespace dlpno {
+
+constexpr int kHistCap = 4096;   // iterations kept in the device history
+constexpr int kDiisParts = 1024; // workgroups of the DIIS dot-product kernel
+constexpr int kPhases = 5;
+
+// schedule choices (set by defaults or the autotuner)
+struct Tuning {
+  int ladder_variant[4] = {0, 2, 5, 7};   // by tiles of 16 PNOs (1..4)
+  int proj_variant[4] = {0, 1, 3, 5};
+  double items_per_wave = 6.0;            // target items per wavefront of the queue
+  double min_item_mfma = 2048.0;          // smallest item worth scheduling alone
+};
+
+struct PendingEvent {
+  int phase;
+  hipEvent_t start, stop;
+};
+
+}  // namespace dlpno
+
+struct dlpno_plan {
+  dlpno_options opt{};
+  int device = 0, num_cu = 0, workers = 0;
+  int32_t n_occ = 0, n_pairs = 0, n_blocks = 0;
+  int64_t n_cpl = 0, n_terms = 0;
+  int64_t n_B = 0, n_T = 0, n_K = 0, n_eps = 0, n_S = 0;
+  dlpno_inputs in{};
+  std::vector<uint8_t> somo;
+  std::vector<dlpno::PairDev> pairs_h;
+  std::vector<dlpno::BlockDev> blocks_h;
+  std::vector<dlpno::CplDev> cpl_h;
+  std::vector<dlpno::TermDev> terms_h;
+  std::vector<int64_t> rowptr_h;
+  std::vector<dlpno::Item> items_h;
+  dlpno::Tuning tune;
+  double flops_ladder = 0.0, flops_proj = 0.0, total_mfma = 0.0, max_item_mfma = 0.0;
+  int64_t ws_elems = 0;
+  // device tables and buffers
+  dlpno::PairDev* d_pairs = nullptr;
+  dlpno::BlockDev* d_blocks = nullptr;
+  dlpno::CplDev* d_cpl = nullptr;
+  dlpno::TermDev* d_terms = nullptr;
+  dlpno::Item* d_items = nullptr;
+  int32_t* d_counter = nullptr;
+  double* d_ws = nullptr;
+  double* d_e_block = nullptr;
+  double* d_rmax_block = nullptr;
+  int32_t* d_nonfinite = nullptr;
+  double* d_hist = nullptr;
+  dlpno::DiisState* d_diis = nullptr;
+  double* d_scalars = nullptr;
+  double* d_diis_partial = nullptr;
+  double* d_ring_vecs = nullptr;
+  double* d_ring_errs = nullptr;
+  float* B32 = nullptr;
+  float* S32 = nullptr;
+  float* T32 = nullptr;
+  void* d_vjp_items = nullptr;
+  int n_vjp_items = 0;
+  float* G32 = nullptr;
+  void* d_mixed = nullptr;
+  // graph replay
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  bool graph_valid = false;
+  const void* graph_key[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  int64_t host_iter = 0;
+  // profiling
+  bool profiling = false;
+  std::vector<hipEvent_t> events;
+  std::vector<dlpno::PendingEvent> pending;
+  double phase_ms[dlpno::kPhases] = {0, 0, 0, 0, 0};
+  int64_t phase_n[dlpno::kPhases] = {0, 0, 0, 0, 0};
+  std::string info;
+};
+
+namespace dlpno {
+// plan.hip
+dlpno_status fail(dlpno_status s, const std::string& msg);
+dlpno_status build_schedule(dlpno_plan* P);
+dlpno_status upload_schedule(dlpno_plan* P, hipStream_t s);
+hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s);
+FinishArgs finish_args(dlpno_plan* P, const double* T);
+hipError_t enqueue_iteration(dlpno_plan* P, double* T, double* R, double* e_pair, double* e_total, double* rmax,
+                             hipStream_t s);
+std::string describe(const dlpno_plan* P);
+void phase_begin(dlpno_plan* P, int ph, hipStream_t s);
+void phase_end(dlpno_plan* P, hipStream_t s);
+void phase_collect(dlpno_plan* P);
+}  // namespace dlpno

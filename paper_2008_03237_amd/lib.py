@@ -1,0 +1,239 @@
+"""ctypes binding of include/dlpno.h.  Argument marshalling only."""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+
+FP64, FP32, BF16X2, FP16X2 = 0, 1, 2, 3
+_PREC = {"fp64": FP64, "fp32": FP32, "bf16x2": BF16X2, "fp16x2": FP16X2}
+
+
+class DlpnoError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("dlpno status %d: %s" % (status, msg))
+        self.status = status
+
+
+class Pair(C.Structure):
+    _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("npno", C.c_int32), ("naux", C.c_int32),
+                ("blocks", C.c_uint32), ("reserved", C.c_int32), ("off_B", C.c_int64), ("off_T", C.c_int64),
+                ("off_K", C.c_int64), ("off_eps", C.c_int64)]
+
+
+class Coupling(C.Structure):
+    _fields_ = [("src_pair", C.c_int32), ("k", C.c_int32), ("side", C.c_int32), ("reserved", C.c_int32),
+                ("off_S", C.c_int64)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("n_occ", C.c_int32), ("n_pairs", C.c_int32), ("n_couplings", C.c_int64),
+                ("is_somo", C.c_void_p), ("pairs", C.c_void_p), ("cpl_rowptr", C.c_void_p), ("cpl", C.c_void_p),
+                ("f_a", C.c_void_p), ("f_b", C.c_void_p), ("n_B", C.c_int64), ("n_T", C.c_int64),
+                ("n_K", C.c_int64), ("n_eps", C.c_int64), ("n_S", C.c_int64)]
+
+
+class Inputs(C.Structure):
+    _fields_ = [("B", C.c_void_p), ("S", C.c_void_p), ("K", C.c_void_p), ("eps_a", C.c_void_p),
+                ("eps_b", C.c_void_p)]
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("diis_max", C.c_int32), ("diis_start", C.c_int32),
+                ("n_workers", C.c_int32), ("chunk_flops", C.c_int32), ("flags", C.c_int32)]
+
+
+PAIR_DTYPE = np.dtype([("i", "<i4"), ("j", "<i4"), ("npno", "<i4"), ("naux", "<i4"), ("blocks", "<u4"),
+                       ("reserved", "<i4"), ("off_B", "<i8"), ("off_T", "<i8"), ("off_K", "<i8"),
+                       ("off_eps", "<i8")])
+CPL_DTYPE = np.dtype([("src_pair", "<i4"), ("k", "<i4"), ("side", "<i4"), ("reserved", "<i4"), ("off_S", "<i8")])
+
+_LIB = None
+
+
+def library_path():
+    return os.path.join(_HERE, "libdlpno.so")
+
+
+def lib():
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    path = library_path()
+    if not os.path.exists(path):
+        raise ImportError("libdlpno.so is not built (%s); run __graft_entry__.build()" % path)
+    L = C.CDLL(path)
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    sig = {
+        "dlpno_plan_create": [C.POINTER(Problem), C.POINTER(Inputs), C.POINTER(Options), vp, C.POINTER(vp)],
+        "dlpno_plan_destroy": [vp],
+        "dlpno_residual": [vp, vp, vp, vp],
+        "dlpno_update": [vp, vp, vp, vp, vp, vp, vp],
+        "dlpno_iterate": [vp, i32, vp, vp, vp, vp, vp, vp],
+        "dlpno_reset": [vp, vp],
+        "dlpno_residual_vjp": [vp, vp, vp, vp, vp, vp],
+        "dlpno_solve_mixed": [vp, i32, i32, vp, vp, vp, vp, vp, vp],
+        "dlpno_flop_count": [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+        "dlpno_autotune": [vp, vp, vp, vp],
+        "dlpno_set_profiling": [vp, i32],
+        "dlpno_phase_times": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    L.dlpno_history.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), i32]
+    L.dlpno_history.restype = i32
+    L.dlpno_plan_info.argtypes = [vp]
+    L.dlpno_plan_info.restype = C.c_char_p
+    L.dlpno_status_string.argtypes = [C.c_int]
+    L.dlpno_status_string.restype = C.c_char_p
+    L.dlpno_last_error.argtypes = []
+    L.dlpno_last_error.restype = C.c_char_p
+    _LIB = L
+    return L
+
+
+def _check(st):
+    if st != 0:
+        L = lib()
+        raise DlpnoError(st, "%s: %s" % (L.dlpno_status_string(st).decode(), L.dlpno_last_error().decode()))
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A residual plan over device-resident inputs (torch CUDA float64 tensors).
+
+    desc: object with the descriptor arrays (n_occ, is_somo, pi, pj, npno, naux,
+    blocks, off_B, off_T, off_K, off_eps, cpl_rowptr, cpl_src, cpl_k, cpl_side,
+    cpl_off_S, f_a, f_b, n_B, n_T, n_K, n_S and eps sizes), e.g. a
+    workload.Problem.  B, S, K, eps_a, eps_b: device tensors (kept referenced).
+    """
+
+    def __init__(self, desc, B, S, K, eps_a, eps_b, precision="fp64", diis_max=8, diis_start=3, n_workers=0,
+                 items_per_wave=0):
+        import torch
+        L = lib()
+        P = len(desc.pi)
+        pairs = np.zeros(P, dtype=PAIR_DTYPE)
+        pairs["i"], pairs["j"], pairs["npno"], pairs["naux"] = desc.pi, desc.pj, desc.npno, desc.naux
+        pairs["blocks"] = desc.blocks
+        pairs["off_B"], pairs["off_T"], pairs["off_K"], pairs["off_eps"] = desc.off_B, desc.off_T, desc.off_K, desc.off_eps
+        ncpl = len(desc.cpl_src)
+        cpl = np.zeros(max(ncpl, 1), dtype=CPL_DTYPE)
+        cpl["src_pair"][:ncpl], cpl["k"][:ncpl], cpl["side"][:ncpl] = desc.cpl_src, desc.cpl_k, desc.cpl_side
+        cpl["off_S"][:ncpl] = desc.cpl_off_S
+        self._host = dict(
+            somo=np.ascontiguousarray(desc.is_somo, dtype=np.uint8), pairs=pairs, cpl=cpl,
+            rowptr=np.ascontiguousarray(desc.cpl_rowptr, dtype=np.int64),
+            f_a=np.ascontiguousarray(desc.f_a, dtype=np.float64), f_b=np.ascontiguousarray(desc.f_b, dtype=np.float64))
+        h = self._host
+        prob = Problem(int(desc.n_occ), P, ncpl, h["somo"].ctypes.data, h["pairs"].ctypes.data, h["rowptr"].ctypes.data,
+                       h["cpl"].ctypes.data, h["f_a"].ctypes.data, h["f_b"].ctypes.data, int(desc.n_B), int(desc.n_T),
+                       int(desc.n_K), int(len(desc.eps_a)), int(desc.n_S))
+        self._dev = [B, S, K, eps_a, eps_b]
+        for t in self._dev:
+            if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()):
+                raise ValueError("inputs must be contiguous float64 CUDA tensors")
+        inp = Inputs(B.data_ptr(), S.data_ptr() if S is not None else None, K.data_ptr(), eps_a.data_ptr(),
+                     eps_b.data_ptr())
+        prec = _PREC[precision] if isinstance(precision, str) else int(precision)
+        opt = Options(prec, diis_max, diis_start, n_workers, int(items_per_wave), 0)
+        self.precision = prec
+        self.n_T, self.n_B, self.n_pairs = int(desc.n_T), int(desc.n_B), P
+        self._h = C.c_void_p()
+        _check(L.dlpno_plan_create(C.byref(prob), C.byref(inp), C.byref(opt), _stream(), C.byref(self._h)))
+
+    # ------------------------------------------------------------------ calls
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().dlpno_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _new(self, n):
+        import torch
+        return torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+
+    def residual(self, T, R=None):
+        R = self._new(self.n_T) if R is None else R
+        _check(lib().dlpno_residual(self._h, _ptr(T), _ptr(R), _stream()))
+        return R
+
+    def update(self, T, R, T_out=None):
+        T_out = self._new(self.n_T) if T_out is None else T_out
+        e_pair = self._new(4 * self.n_pairs)
+        e_tot = self._new(1)
+        _check(lib().dlpno_update(self._h, _ptr(T), _ptr(R), _ptr(T_out), _ptr(e_pair), _ptr(e_tot), _stream()))
+        return T_out, e_pair, e_tot
+
+    def iterate(self, n, T, R=None, e_pair=None, e_total=None, rmax=None):
+        R = self._new(self.n_T) if R is None else R
+        e_pair = self._new(4 * self.n_pairs) if e_pair is None else e_pair
+        e_total = self._new(1) if e_total is None else e_total
+        rmax = self._new(1) if rmax is None else rmax
+        _check(lib().dlpno_iterate(self._h, int(n), _ptr(T), _ptr(R), _ptr(e_pair), _ptr(e_total), _ptr(rmax),
+                                   _stream()))
+        return R, e_pair, e_total, rmax
+
+    def reset(self):
+        _check(lib().dlpno_reset(self._h, _stream()))
+
+    def history(self, n=4096):
+        E = np.zeros(n)
+        Rm = np.zeros(n)
+        k = lib().dlpno_history(self._h, E.ctypes.data_as(C.POINTER(C.c_double)),
+                                Rm.ctypes.data_as(C.POINTER(C.c_double)), n)
+        return E[:k], Rm[:k]
+
+    def vjp(self, T, G, dT=None, dB=None, want_dB=True):
+        dT = self._new(self.n_T) if dT is None else dT
+        if want_dB and dB is None:
+            dB = self._new(self.n_B)
+        _check(lib().dlpno_residual_vjp(self._h, _ptr(T), _ptr(G), _ptr(dT), _ptr(dB) if want_dB else None,
+                                        _stream()))
+        return dT, (dB if want_dB else None)
+
+    def solve_mixed(self, n_outer, n_inner, T, R=None, e_pair=None, e_total=None, rmax=None):
+        R = self._new(self.n_T) if R is None else R
+        e_pair = self._new(4 * self.n_pairs) if e_pair is None else e_pair
+        e_total = self._new(1) if e_total is None else e_total
+        rmax = self._new(1) if rmax is None else rmax
+        _check(lib().dlpno_solve_mixed(self._h, int(n_outer), int(n_inner), _ptr(T), _ptr(R), _ptr(e_pair),
+                                       _ptr(e_total), _ptr(rmax), _stream()))
+        return R, e_pair, e_total, rmax
+
+    def flop_count(self):
+        a, b = C.c_double(), C.c_double()
+        _check(lib().dlpno_flop_count(self._h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    def autotune(self, T, R=None):
+        R = self._new(self.n_T) if R is None else R
+        _check(lib().dlpno_autotune(self._h, _ptr(T), _ptr(R), _stream()))
+
+    def set_profiling(self, on=True):
+        _check(lib().dlpno_set_profiling(self._h, 1 if on else 0))
+
+    def phase_times(self):
+        ms = (C.c_double * 5)()
+        n = (C.c_int64 * 5)()
+        _check(lib().dlpno_phase_times(self._h, ms, n, 5))
+        return list(ms), list(n)
+
+    def info(self):
+        return lib().dlpno_plan_info(self._h).decode()

@@ -1,0 +1,155 @@
+"""FP64 GPU path vs the FP64 CPU oracle (through the C ABI)."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.model import unpack_T, pack_T
+from tests.gpu_helpers import device_problem, oracle_inputs, compare_blocks
+from workload import build_problem
+from workload.problem import segment_values
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def setup_module(module):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _oracle_step(prob, inp, Tflat):
+    T = unpack_T(prob, Tflat)
+    R = oracle.residual_os(inp, T)
+    Tn = oracle.jacobi(inp, T, R)
+    e = oracle.pair_energies(inp, Tn)
+    return T, R, Tn, e
+
+
+def test_generator_bitwise_on_device():
+    from workload.gpu import device_fields
+    prob = build_problem("chain", n_occ=16, band=4, somos=(5, 11))
+    dev = device_fields(prob)
+    for f in ("B", "K", "T", "S"):
+        host = prob.materialize(f)
+        got = dev[f][:host.size].cpu().numpy()
+        assert np.array_equal(got.view(np.uint64), host.view(np.uint64)), f
+
+
+@pytest.mark.parametrize("cfg", ["tiny", "mini"])
+def test_residual_update_energy_parity(cfg):
+    prob = build_problem("tiny") if cfg == "tiny" else build_problem("chain", n_occ=24, band=6, somos=(7, 16))
+    print("case", cfg, prob.n_pairs, "pairs", flush=True)
+    plan, dev = device_problem(prob)
+    R = plan.residual(dev["T"])
+    Tn, e_pair, e_tot = plan.update(dev["T"], R)
+    torch.cuda.synchronize()
+    inp = oracle_inputs(prob)
+    T, Ro, Tno, eo = _oracle_step(prob, inp, prob.materialize("T"))
+    compare_blocks(prob, R.cpu().numpy(), Ro, rel=1e-12)
+    compare_blocks(prob, Tn.cpu().numpy(), Tno, rel=1e-12)
+    ep = e_pair.cpu().numpy().reshape(-1, 4)
+    code = {"AA": 0, "BB": 1, "AB": 2, "BA": 3}
+    for (p, name), v in eo.items():
+        assert abs(ep[p, code[name]] - v) <= 1e-10, (p, name)
+    assert abs(float(e_tot.cpu()[0]) - sum(eo.values())) <= 1e-10
+    plan.close()
+
+
+def test_tile_classes_all_present_in_mini():
+    prob = build_problem("chain", n_occ=24, band=6, somos=(7, 16))
+    nt = set(((prob.npno + 15) // 16).tolist())
+    assert nt == {1, 2, 3, 4}
+
+
+def test_determinism_bitwise():
+    prob = build_problem("chain", n_occ=24, band=6, somos=(7, 16))
+    plan, dev = device_problem(prob)
+    R1 = plan.residual(dev["T"]).clone()
+    R2 = plan.residual(dev["T"]).clone()
+    torch.cuda.synchronize()
+    assert torch.equal(R1.view(torch.int64), R2.view(torch.int64))
+    plan.close()
+
+
+def test_iterations_match_oracle_with_diis():
+    prob = build_problem("chain", n_occ=20, band=5, somos=(6, 13))
+    plan, dev = device_problem(prob, T_random=False)
+    T = dev["T"]
+    n_it = 8
+    plan.iterate(n_it, T)
+    E_gpu, rmax_gpu = plan.history()
+    inp = oracle_inputs(prob)
+    zero = {k: np.zeros_like(v) for k, v in unpack_T(prob, np.zeros(prob.n_T)).items()}
+    To, hist = oracle.solve(inp, zero, n_it, use_diis=True)
+    assert len(E_gpu) == n_it
+    for k in range(n_it):
+        assert abs(E_gpu[k] - hist[k][0]) <= 1e-10, (k, E_gpu[k], hist[k][0])
+        assert abs(rmax_gpu[k] - hist[k][1]) <= 1e-12 * max(1.0, hist[k][1]) + 1e-14
+    compare_blocks(prob, T.cpu().numpy(), To, rel=1e-10)
+    plan.close()
+
+
+def test_plain_jacobi_iterations_match_oracle():
+    prob = build_problem("chain", n_occ=16, band=4, somos=(5, 11))
+    plan, dev = device_problem(prob, diis_max=0, T_random=False)
+    plan.iterate(5, dev["T"])
+    E_gpu, _ = plan.history()
+    inp = oracle_inputs(prob)
+    zero = unpack_T(prob, np.zeros(prob.n_T))
+    To, hist = oracle.solve(inp, zero, 5, use_diis=False)
+    for k in range(5):
+        assert abs(E_gpu[k] - hist[k][0]) <= 1e-10
+    compare_blocks(prob, dev["T"].cpu().numpy(), To, rel=1e-11)
+    plan.close()
+
+
+def test_nonfinite_detected():
+    from paper_2008_03237_amd import DlpnoError
+    prob = build_problem("tiny")
+    plan, dev = device_problem(prob)
+    dev["T"][int(prob.off_T[40]) + 3] = float("nan")
+    with pytest.raises(DlpnoError) as ei:
+        plan.iterate(1, dev["T"])
+    assert ei.value.status == -5
+    plan.close()
+
+
+@pytest.mark.parametrize("cfg,nsample", [("chain", 12), ("c160", 6)])
+def test_full_size_sampled_residual(cfg, nsample):
+    """Full workload in the benchmark's launch configuration; a seeded sample of
+    target pairs recomputed by the oracle one by one (inputs regenerated)."""
+    prob = build_problem(cfg)
+    print("case", cfg, "pairs", prob.n_pairs, flush=True)
+    plan, dev = device_problem(prob)
+    R = plan.residual(dev["T"])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1234)
+    n = prob.npno
+    nb = prob.n_blocks()
+    # always include the largest pair, a SOMO pair and a pair with one block
+    pick = set(rng.choice(prob.n_pairs, nsample, replace=False).tolist())
+    pick.add(int(np.argmax(n.astype(np.int64) ** 3 * prob.naux)))
+    pick.add(int(np.where(nb == 1)[0][0]))
+    pick.add(int(np.where(nb == 2)[0][0]))
+    inp = oracle_inputs(prob, full=False)
+    # amplitudes of the sampled pairs and of every source they read
+    need = set(pick)
+    for p in pick:
+        need.update(prob.cpl_src[prob.cpl_rowptr[p]:prob.cpl_rowptr[p + 1]].tolist())
+    T = {}
+    for p in need:
+        o = int(prob.off_T[p])
+        for name in oracle.stored_blocks(int(prob.pi[p]), int(prob.pj[p]), prob.is_somo.astype(bool)):
+            seg = prob.segs["T"][np.searchsorted(prob.segs["T"]["off"], o)]
+            T[(p, name)] = segment_values(prob.seed, seg).reshape(n[p], n[p])
+            o += int(n[p]) ** 2
+    Ro = oracle.residual_os(inp, T, pairs=sorted(pick))
+    Rg = R.cpu().numpy()
+    for (p, name), ref in Ro.items():
+        i = oracle.stored_blocks(int(prob.pi[p]), int(prob.pj[p]), prob.is_somo.astype(bool)).index(name)
+        o = int(prob.off_T[p]) + i * int(n[p]) ** 2
+        got = Rg[o:o + int(n[p]) ** 2].reshape(n[p], n[p])
+        d = np.linalg.norm(got - ref)
+        assert d <= 1e-12 * np.linalg.norm(ref), (p, name, d, np.linalg.norm(ref))
+    plan.close()
