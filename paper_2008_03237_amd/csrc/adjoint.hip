@@ -47,12 +47,15 @@ __device__ __forceinline__ void db_item(const DbArgs<F>& A, const DbItem& it) {
   typedef typename Mfma<F>::V V;
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4, pr = Mfma<F>::perm(r);
-  const PairDev P = A.pairs[it.pair];
-  const int n = P.n;
+  const PairDev& Pg = A.pairs[it.pair];
+  const int n = uni(Pg.n);
+  const int nblk = uni(Pg.nblk);
+  const int blk0 = uni(Pg.blk0);
+  const int64_t off_B = uni(Pg.off_B);
   const int S4 = (n + 3) >> 2;
   const uint32_t nn = (uint32_t)n * (uint32_t)n;
   for (int Q = it.lo; Q < it.hi; ++Q) {
-    const __amdgpu_buffer_rsrc_t br = rsrc(A.B + P.off_B + (size_t)Q * nn, nn);
+    const __amdgpu_buffer_rsrc_t br = rsrc(A.B + off_B + (size_t)Q * nn, nn);
     // A operand of U = B^Q Y^T with permuted rows: Ab[td][s] = B^Q[16 td + pi(r)][4 s + g]
     F Ab[NT][4 * NT];
 #pragma unroll
@@ -65,10 +68,10 @@ __device__ __forceinline__ void db_item(const DbArgs<F>& A, const DbItem& it) {
     for (int a = 0; a < NT; ++a)
 #pragma unroll
       for (int c = 0; c < NT; ++c) acc[a][c] = V{0, 0, 0, 0};
-    for (int b = 0; b < P.nblk; ++b) {
-      const BlockDev Bk = A.blocks[P.blk0 + b];
-      const __amdgpu_buffer_rsrc_t tr = rsrc(A.T + Bk.off_T, nn);
-      const __amdgpu_buffer_rsrc_t gr = rsrc(A.G + Bk.off_T, nn);
+    for (int b = 0; b < nblk; ++b) {
+      const int64_t off_T = uni(A.blocks[blk0 + b].off_T);
+      const __amdgpu_buffer_rsrc_t tr = rsrc(A.T + off_T, nn);
+      const __amdgpu_buffer_rsrc_t gr = rsrc(A.G + off_T, nn);
 #pragma unroll
       for (int term = 0; term < 2; ++term) {
 #pragma unroll
@@ -107,7 +110,7 @@ __device__ __forceinline__ void db_item(const DbArgs<F>& A, const DbItem& it) {
         }
       }
     }
-    double* dst = A.dB + P.off_B + (size_t)Q * nn;
+    double* dst = A.dB + off_B + (size_t)Q * nn;
 #pragma unroll
     for (int a = 0; a < NT; ++a)
 #pragma unroll
@@ -126,8 +129,12 @@ template <typename F>
 __global__ __launch_bounds__(256) void db_kernel(DbArgs<F> A) {
   const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (w >= A.n_items) return;
-  const DbItem it = A.items[w];
-  const int nt = (A.pairs[it.pair].n + 15) >> 4;
+  const DbItem& ig = A.items[w];
+  DbItem it;
+  it.pair = uni(ig.pair);
+  it.lo = uni(ig.lo);
+  it.hi = uni(ig.hi);
+  const int nt = (uni(A.pairs[it.pair].n) + 15) >> 4;
   switch (nt) {
     case 1: db_item<F, 1>(A, it); break;
     case 2: db_item<F, 2>(A, it); break;

@@ -78,43 +78,74 @@ struct Mfma<float> {
   static __device__ __forceinline__ int orow(int g, int i) { return 4 * g + i; }
 };
 
+// Wave-uniform copies of descriptor fields.  Descriptors are read with vector
+// loads (the kernel also writes memory, so they cannot go through the scalar
+// cache); broadcasting them from lane 0 tells the compiler they are uniform,
+// so resource descriptors, trip counts and branches stay in SGPRs.
+__device__ __forceinline__ int32_t uni(int32_t x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uni(int64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double uni(double x) { return __builtin_bit_cast(double, uni(__builtin_bit_cast(int64_t, x))); }
+template <typename T>
+__device__ __forceinline__ T* uni(T* p) { return reinterpret_cast<T*>(uni(reinterpret_cast<int64_t>(p))); }
+
 // raw buffer resource over [p, p + elems): out-of-range loads return 0
 template <typename F>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const F* p, uint32_t elems) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<F*>(p), (short)0, elems * (uint32_t)sizeof(F), 0x00020000);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<F*>(uni(p)), (short)0,
+                                           (uint32_t)uni((int32_t)(elems * (uint32_t)sizeof(F))), 0x00020000);
 }
 
-// Per-wave LDS slab for X-form operands, in 8-byte words: the largest user is
-// the 3-tile, 2-block ladder variant (2 * 3 * 12 operands of 64 lanes).
+// Per-wave LDS slab for X-form operands, in 8-byte words: the largest users
+// are the 3-tile, 2-block ladder variant (2 * 3 * 12 operands of 64 lanes) and
+// the projection (4 * 16 operands).
 constexpr int kLdsWaveWords = 72 * 64;
 
 // ---------------------------------------------------------------------------
 // Ladder item: pair p, NB consecutive blocks, a-tiles TA0..TA0+NTA-1,
 // Q in [lo, hi).  Partial Out^T[b][a] of sum_Q B^Q T B^Q^T.
+// The inner (k) dimension runs over S4 = 4 (NT - 1) + R steps of 4, R in
+// {2, 4}: n is padded to a multiple of 8, and with every trip count known at
+// compile time one Q slice is a single basic block that the scheduler can
+// interleave (stage 1 of every block is issued before the stage 2 that reads
+// it).  REG keeps the X-form operands in VGPRs instead of the LDS slab.
 // ---------------------------------------------------------------------------
-template <typename F, int NT, int NB, int NTA, int TA0>
+template <typename F, int NT, int NB, int NTA, int TA0, int R, bool REG>
 __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
   typedef typename Mfma<F>::V V;
+  constexpr int S4 = 4 * (NT - 1) + R;
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4, pr = Mfma<F>::perm(r);
-  const PairDev P = A.pairs[it.pair];
-  const int n = P.n;
-  const int S4 = (n + 3) >> 2;
+  const PairDev& Pg = A.pairs[it.pair];
+  const int n = uni(Pg.n);
+  const int blk0 = uni(Pg.blk0);
+  const int64_t off_B = uni(Pg.off_B);
   const uint32_t nn = (uint32_t)n * (uint32_t)n;
   F* Al = reinterpret_cast<F*>(lds + (size_t)(threadIdx.x >> 6) * kLdsWaveWords);
+  F Ar[REG ? NB : 1][REG ? NT : 1][REG ? S4 : 1];
 
   // X-form operands of the NB amplitude blocks, once per item
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const BlockDev& Bk = A.blocks[P.blk0 + it.bslot0 + b];
-    const __amdgpu_buffer_rsrc_t tr = rsrc(A.T + Bk.off_T, nn);
+    const int64_t off_T = uni(A.blocks[blk0 + it.bslot0 + b].off_T);
+    const __amdgpu_buffer_rsrc_t tr = rsrc(A.T + off_T, nn);
     const uint32_t base = (uint32_t)(g * n + pr);
 #pragma unroll
     for (int td = 0; td < NT; ++td)
 #pragma unroll
-      for (int s = 0; s < 4 * NT; ++s)
-        Al[((b * NT + td) * 4 * NT + s) * 64 + lane] = Mfma<F>::load(tr, base + (uint32_t)(4 * s * n + 16 * td));
+      for (int s = 0; s < S4; ++s) {
+        const F v = Mfma<F>::load(tr, base + (uint32_t)(4 * s * n + 16 * td));
+        if constexpr (REG) Ar[b][td][s] = v;
+        else Al[((b * NT + td) * S4 + s) * 64 + lane] = v;
+      }
   }
+  auto aop = [&](int b, int td, int s) -> F {
+    if constexpr (REG) return Ar[b][td][s];
+    else return Al[((b * NT + td) * S4 + s) * 64 + lane];
+  };
 
   V acc[NB][NT][NTA];
 #pragma unroll
@@ -125,49 +156,51 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
       for (int u = 0; u < NTA; ++u) acc[b][t][u] = V{0, 0, 0, 0};
 
   // M-form of B^Q: M[t][s] = B^Q[4s + g][16t + r] = B^Q[16t + r][4s + g] (symmetric)
-  const F* Bp = A.B + P.off_B;
+  const F* Bp = A.B + off_B;
   const uint32_t mbase = (uint32_t)(g * n + r);
-  auto loadM = [&](F (&M)[NT][4 * NT], int Q) {
+  auto loadM = [&](F (&M)[NT][S4], int Q) {
     const __amdgpu_buffer_rsrc_t br = rsrc(Bp + (size_t)Q * nn, nn);
 #pragma unroll
-    for (int s = 0; s < 4 * NT; ++s)
+    for (int s = 0; s < S4; ++s)
 #pragma unroll
       for (int t = 0; t < NT; ++t) M[t][s] = Mfma<F>::load(br, mbase + (uint32_t)(4 * s * n + 16 * t));
   };
 
-  auto compute = [&](const F (&M)[NT][4 * NT]) {
+  auto compute = [&](const F (&M)[NT][S4]) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
+    for (int td = 0; td < NT; ++td) {
+      V d1[NB][NTA];
+      // stage 1: Y^T[d][a] = sum_c T[c][d] B^Q[c][a]   (d-tile td, every block)
 #pragma unroll
-      for (int td = 0; td < NT; ++td) {
-        V d1[NTA];
+      for (int b = 0; b < NB; ++b) {
 #pragma unroll
-        for (int u = 0; u < NTA; ++u) d1[u] = V{0, 0, 0, 0};
-        // stage 1: Y^T[d][a] = sum_c T[c][d] B^Q[c][a]   (d-tile td)
+        for (int u = 0; u < NTA; ++u) d1[b][u] = V{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < 4 * NT; ++s) {
-          if (s < S4) {
-            const F av = Al[((b * NT + td) * 4 * NT + s) * 64 + lane];
+        for (int s = 0; s < S4; ++s) {
+          const F av = aop(b, td, s);
 #pragma unroll
-            for (int u = 0; u < NTA; ++u) d1[u] = Mfma<F>::op(av, M[TA0 + u][s], d1[u]);
-          }
+          for (int u = 0; u < NTA; ++u) d1[b][u] = Mfma<F>::op(av, M[TA0 + u][s], d1[b][u]);
         }
-        // stage 2: Out^T[b][a] += sum_d B^Q[b][d] Y^T[d][a] over this d-tile
+      }
+      // stage 2: Out^T[b][a] += sum_d B^Q[b][d] Y^T[d][a] over this d-tile
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int sp = 4 * td + i;
-          if (sp < S4) {
+      for (int i = 0; i < 4; ++i) {
+        if (4 * td + i < S4) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
 #pragma unroll
             for (int tb = 0; tb < NT; ++tb)
 #pragma unroll
-              for (int u = 0; u < NTA; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][sp], d1[u][i], acc[b][tb][u]);
-          }
+              for (int u = 0; u < NTA; ++u)
+                acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[b][u][i], acc[b][tb][u]);
         }
       }
+      // keep each d-tile in its own scheduling region (bounded live ranges)
+      __builtin_amdgcn_sched_barrier(0);
     }
   };
 
-  F M0[NT][4 * NT], M1[NT][4 * NT];
+  F M0[NT][S4], M1[NT][S4];
   loadM(M0, it.lo);
   for (int Q = it.lo; Q < it.hi; Q += 2) {
     if (Q + 1 < it.hi) loadM(M1, Q + 1);
@@ -180,8 +213,7 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
   // partial slot stored as Out^T[b][a] (row b, column a): coalesced over r
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const BlockDev& Bk = A.blocks[P.blk0 + it.bslot0 + b];
-    double* dst = A.ws + Bk.off_ws + (int64_t)it.slot * nn;
+    double* dst = A.ws + uni(A.blocks[blk0 + it.bslot0 + b].off_ws) + (int64_t)it.slot * nn;
 #pragma unroll
     for (int tb = 0; tb < NT; ++tb)
 #pragma unroll
@@ -199,15 +231,18 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
 // ---------------------------------------------------------------------------
 // Projection item: target pair p (NT tiles), NB consecutive blocks, couplings
 // [lo, hi).  Per coupling: M = S_{p,q}; per target block the term
-// -w S_{p,q} op(T_q) S_{p,q}^T.
+// -w S_{p,q} op(T_q) S_{p,q}^T.  The source dimension n_q varies per
+// coupling; it is processed in 16-wide chunks (uniform branches per chunk),
+// the padded rows and columns being zeros returned by the range-checked loads.
 // ---------------------------------------------------------------------------
 template <typename F, int NT, int NB>
 __device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
   typedef typename Mfma<F>::V V;
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4, pr = Mfma<F>::perm(r);
-  const PairDev P = A.pairs[it.pair];
-  const int n = P.n;
+  const PairDev& Pg = A.pairs[it.pair];
+  const int n = uni(Pg.n);
+  const int blk0 = uni(Pg.blk0);
   F* Al = reinterpret_cast<F*>(lds + (size_t)(threadIdx.x >> 6) * kLdsWaveWords);
 
   V acc[NB][NT][NT];
@@ -219,63 +254,80 @@ __device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& i
       for (int u = 0; u < NT; ++u) acc[b][t][u] = V{0, 0, 0, 0};
 
   for (int e = it.lo; e < it.hi; ++e) {
-    const CplDev C = A.cpl[e];
-    const int nq = C.nsrc;
-    const int S4 = (nq + 3) >> 2;
+    const int nq = uni(A.cpl[e].nsrc);
+    const int64_t off_S = uni(A.cpl[e].off_S);
+    const int C16 = (nq + 15) >> 4;        // 16-wide chunks of the source index
     // M-form: M[t][s] = S_{p,q}[16t + r][4s + g] = W[(4s + g) n + 16t + r], W = [c][a]
-    const __amdgpu_buffer_rsrc_t sr = rsrc(A.S + C.off_S, (uint32_t)(nq * n));
+    const __amdgpu_buffer_rsrc_t sr = rsrc(A.S + off_S, (uint32_t)(nq * n));
     const uint32_t mbase = (uint32_t)(g * n + r);
     F M[NT][16];
 #pragma unroll
-    for (int s = 0; s < 16; ++s)
+    for (int cc = 0; cc < 4; ++cc) {
+      if (cc < C16) {
 #pragma unroll
-      for (int t = 0; t < NT; ++t) M[t][s] = (s < S4) ? Mfma<F>::load(sr, mbase + (uint32_t)(4 * s * n + 16 * t)) : F(0);
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            M[t][4 * cc + s4] = Mfma<F>::load(sr, mbase + (uint32_t)(4 * (4 * cc + s4) * n + 16 * t));
+      } else {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+          for (int t = 0; t < NT; ++t) M[t][4 * cc + s4] = F(0);
+      }
+    }
 
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const TermDev tm = A.terms[(int64_t)e * 4 + it.bslot0 + b];
-      if (tm.src_off < 0) continue;
-      const __amdgpu_buffer_rsrc_t xr = rsrc(A.T + tm.src_off, (uint32_t)(nq * nq));
-      const F mw = F(-tm.w);
-      if (tm.trans) {          // X[c][d] = T_q[d][c]
-        const uint32_t base = (uint32_t)(pr * nq + g);
+      const TermDev& tg = A.terms[(int64_t)e * 4 + it.bslot0 + b];
+      const int64_t src_off = uni(tg.src_off);
+      if (src_off < 0) continue;
+      const int trans = uni(tg.trans);
+      const F mw = F(-uni(tg.w));
+      const __amdgpu_buffer_rsrc_t xr = rsrc(A.T + src_off, (uint32_t)(nq * nq));
+      // X-form of -w op(T_q) into the LDS slab: Al[td][s] = X[4s + g][16 td + perm(r)]
+      const uint32_t base = trans ? (uint32_t)(pr * nq + g) : (uint32_t)(g * nq + pr);
+      const uint32_t step_s = trans ? 4u : (uint32_t)(4 * nq);
+      const uint32_t step_t = trans ? (uint32_t)(16 * nq) : 16u;
 #pragma unroll
-        for (int td = 0; td < 4; ++td)
+      for (int td = 0; td < 4; ++td) {
+        if (td < C16) {
 #pragma unroll
-          for (int s = 0; s < 16; ++s)
-            Al[(td * 16 + s) * 64 + lane] = mw * Mfma<F>::load(xr, base + (uint32_t)(16 * td * nq + 4 * s));
-      } else {                 // X[c][d] = T_q[c][d]
-        const uint32_t base = (uint32_t)(g * nq + pr);
+          for (int cc = 0; cc < 4; ++cc) {
+            if (cc < C16) {
 #pragma unroll
-        for (int td = 0; td < 4; ++td)
-#pragma unroll
-          for (int s = 0; s < 16; ++s)
-            Al[(td * 16 + s) * 64 + lane] = mw * Mfma<F>::load(xr, base + (uint32_t)(4 * s * nq + 16 * td));
+              for (int s4 = 0; s4 < 4; ++s4) {
+                const int s = 4 * cc + s4;
+                Al[(td * 16 + s) * 64 + lane] = mw * Mfma<F>::load(xr, base + (uint32_t)s * step_s + (uint32_t)td * step_t);
+              }
+            }
+          }
+        }
       }
 #pragma unroll
       for (int td = 0; td < 4; ++td) {
-        if (16 * td < nq) {
+        if (td < C16) {
           V d1[NT];
 #pragma unroll
           for (int u = 0; u < NT; ++u) d1[u] = V{0, 0, 0, 0};
 #pragma unroll
-          for (int s = 0; s < 16; ++s) {
-            if (s < S4) {
-              const F av = Al[(td * 16 + s) * 64 + lane];
+          for (int cc = 0; cc < 4; ++cc) {
+            if (cc < C16) {
 #pragma unroll
-              for (int u = 0; u < NT; ++u) d1[u] = Mfma<F>::op(av, M[u][s], d1[u]);
+              for (int s4 = 0; s4 < 4; ++s4) {
+                const int s = 4 * cc + s4;
+                const F av = Al[(td * 16 + s) * 64 + lane];
+#pragma unroll
+                for (int u = 0; u < NT; ++u) d1[u] = Mfma<F>::op(av, M[u][s], d1[u]);
+              }
             }
           }
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int sp = 4 * td + i;
-            if (sp < S4) {
+          for (int i = 0; i < 4; ++i)
 #pragma unroll
-              for (int tb = 0; tb < NT; ++tb)
+            for (int tb = 0; tb < NT; ++tb)
 #pragma unroll
-                for (int u = 0; u < NT; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][sp], d1[u][i], acc[b][tb][u]);
-            }
-          }
+              for (int u = 0; u < NT; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
         }
       }
     }
@@ -284,8 +336,7 @@ __device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& i
   const int64_t nn = (int64_t)n * n;
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const BlockDev& Bk = A.blocks[P.blk0 + it.bslot0 + b];
-    double* dst = A.ws + Bk.off_ws + (int64_t)it.slot * nn;
+    double* dst = A.ws + uni(A.blocks[blk0 + it.bslot0 + b].off_ws) + (int64_t)it.slot * nn;
 #pragma unroll
     for (int tb = 0; tb < NT; ++tb)
 #pragma unroll
@@ -300,39 +351,53 @@ __device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& i
   }
 }
 
+// k-step class of the pair: R = 2 when n mod 16 is in 1..8, else 4
+#define DLPNO_LADDER(NT, NB, NTA, TA0, REG)                                      \
+  do {                                                                             \
+    if (rk == 2) ladder_item<F, NT, NB, NTA, TA0, 2, REG>(A, it, lds);             \
+    else ladder_item<F, NT, NB, NTA, TA0, 4, REG>(A, it, lds);                     \
+  } while (0)
+
 template <typename F>
 __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
   if (it.kind == ITEM_LADDER) {
+    const int n = uni(A.pairs[it.pair].n);
+    const int rem = n - 16 * ((n - 1) >> 4);     // 1..16 PNOs in the last tile
+    const int rk = rem <= 8 ? 2 : 4;
     switch (it.variant) {
-      case 0: ladder_item<F, 1, 4, 1, 0>(A, it, lds); break;
-      case 1: ladder_item<F, 1, 2, 1, 0>(A, it, lds); break;
-      case 2: ladder_item<F, 2, 4, 2, 0>(A, it, lds); break;
-      case 3: ladder_item<F, 2, 2, 2, 0>(A, it, lds); break;
-      case 4: ladder_item<F, 2, 1, 2, 0>(A, it, lds); break;
-      case 5: ladder_item<F, 3, 2, 3, 0>(A, it, lds); break;
-      case 6: ladder_item<F, 3, 1, 3, 0>(A, it, lds); break;
-      case 7:
-        if (it.ta0 == 0) ladder_item<F, 4, 1, 2, 0>(A, it, lds);
-        else ladder_item<F, 4, 1, 2, 2>(A, it, lds);
+      case 0: DLPNO_LADDER(1, 4, 1, 0, true); break;
+      case 1: DLPNO_LADDER(1, 2, 1, 0, true); break;
+      case 2: DLPNO_LADDER(1, 1, 1, 0, true); break;
+      case 3: DLPNO_LADDER(2, 4, 2, 0, false); break;
+      case 4: DLPNO_LADDER(2, 2, 2, 0, true); break;
+      case 5: DLPNO_LADDER(2, 1, 2, 0, true); break;
+      case 6:
+        if (it.ta0 == 0) DLPNO_LADDER(2, 4, 1, 0, true);
+        else DLPNO_LADDER(2, 4, 1, 1, true);
         break;
-      case 8: ladder_item<F, 1, 1, 1, 0>(A, it, lds); break;
+      case 7: DLPNO_LADDER(3, 1, 3, 0, false); break;
+      case 8:
+        if (it.ta0 == 0) DLPNO_LADDER(4, 1, 2, 0, false);
+        else DLPNO_LADDER(4, 1, 2, 2, false);
+        break;
       default: break;
     }
   } else {
     switch (it.variant) {
       case 0: proj_item<F, 1, 4>(A, it, lds); break;
-      case 1: proj_item<F, 2, 4>(A, it, lds); break;
-      case 2: proj_item<F, 2, 2>(A, it, lds); break;
-      case 3: proj_item<F, 3, 2>(A, it, lds); break;
-      case 4: proj_item<F, 3, 1>(A, it, lds); break;
-      case 5: proj_item<F, 4, 1>(A, it, lds); break;
-      case 6: proj_item<F, 1, 2>(A, it, lds); break;
-      case 7: proj_item<F, 1, 1>(A, it, lds); break;
-      case 8: proj_item<F, 2, 1>(A, it, lds); break;
+      case 1: proj_item<F, 1, 2>(A, it, lds); break;
+      case 2: proj_item<F, 1, 1>(A, it, lds); break;
+      case 3: proj_item<F, 2, 4>(A, it, lds); break;
+      case 4: proj_item<F, 2, 2>(A, it, lds); break;
+      case 5: proj_item<F, 2, 1>(A, it, lds); break;
+      case 6: proj_item<F, 3, 2>(A, it, lds); break;
+      case 7: proj_item<F, 3, 1>(A, it, lds); break;
+      case 8: proj_item<F, 4, 1>(A, it, lds); break;
       default: break;
     }
   }
 }
+#undef DLPNO_LADDER
 
 template <typename F>
 __global__ __launch_bounds__(256) void grouped_kernel(GroupedArgs<F> A) {
@@ -343,7 +408,16 @@ __global__ __launch_bounds__(256) void grouped_kernel(GroupedArgs<F> A) {
     if (lane == 0) idx = atomicAdd(A.counter, 1);
     idx = __builtin_amdgcn_readfirstlane(idx);
     if (idx >= A.n_items) break;
-    const Item it = A.items[idx];
+    const Item& ig = A.items[idx];
+    Item it;
+    it.kind = uni(ig.kind);
+    it.variant = uni(ig.variant);
+    it.pair = uni(ig.pair);
+    it.bslot0 = uni(ig.bslot0);
+    it.slot = uni(ig.slot);
+    it.ta0 = uni(ig.ta0);
+    it.lo = uni(ig.lo);
+    it.hi = uni(ig.hi);
     run_item<F>(A, it, lds);
   }
 }

@@ -56,10 +56,10 @@ struct LadderVariant { int nt, nb, nta; };
 struct ProjVariant { int nt, nb; };
 constexpr int kNumLadderVariants = 9;
 constexpr LadderVariant kLadderVariants[kNumLadderVariants] = {
-    {1, 4, 1}, {1, 2, 1}, {2, 4, 2}, {2, 2, 2}, {2, 1, 2}, {3, 2, 3}, {3, 1, 3}, {4, 1, 2}, {1, 1, 1}};
+    {1, 4, 1}, {1, 2, 1}, {1, 1, 1}, {2, 4, 2}, {2, 2, 2}, {2, 1, 2}, {2, 4, 1}, {3, 1, 3}, {4, 1, 2}};
 constexpr int kNumProjVariants = 9;
 constexpr ProjVariant kProjVariants[kNumProjVariants] = {
-    {1, 4}, {2, 4}, {2, 2}, {3, 2}, {3, 1}, {4, 1}, {1, 2}, {1, 1}, {2, 1}};
+    {1, 4}, {1, 2}, {1, 1}, {2, 4}, {2, 2}, {2, 1}, {3, 2}, {3, 1}, {4, 1}};
 
 // Arguments of the grouped kernel (templated on the operand type).
 template <typename F>

@@ -97,6 +97,12 @@ int pick_ladder(int nt, int nta, int maxnb) {
     const LadderVariant& V = kLadderVariants[v];
     if (V.nt == nt && V.nta == nta && V.nb <= maxnb && (best < 0 || V.nb > kLadderVariants[best].nb)) best = v;
   }
+  if (best >= 0) return best;
+  // no variant with this a-tile grouping fits: any of the same tile count
+  for (int v = 0; v < kNumLadderVariants; ++v) {
+    const LadderVariant& V = kLadderVariants[v];
+    if (V.nt == nt && V.nb <= maxnb && (best < 0 || V.nb > kLadderVariants[best].nb)) best = v;
+  }
   return best;
 }
 int pick_proj(int nt, int maxnb) {

@@ -17,8 +17,8 @@ constexpr int kPhases = 5;
 
 // schedule choices (set by defaults or the autotuner)
 struct Tuning {
-  int ladder_variant[4] = {0, 2, 5, 7};   // by tiles of 16 PNOs (1..4)
-  int proj_variant[4] = {0, 1, 3, 5};
+  int ladder_variant[4] = {0, 3, 7, 8};   // by tiles of 16 PNOs (1..4)
+  int proj_variant[4] = {0, 3, 6, 8};
   double items_per_wave = 6.0;            // target items per wavefront of the queue
   double min_item_mfma = 2048.0;          // smallest item worth scheduling alone
 };

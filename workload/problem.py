@@ -274,7 +274,7 @@ def build_problem(name="tiny", **override):
     for p in range(P):
         i, j = int(pi[p]), int(pj[p])
         for sd, (rep, keep) in enumerate(((i, j), (j, i))):
-            for k in range(n_occ):
+            for k in range(max(0, rep - band), min(n_occ, rep + band + 1)):
                 if k == rep or f_a[k, rep] == 0.0:
                     continue
                 q = pair_index.get((min(k, keep), max(k, keep)))
