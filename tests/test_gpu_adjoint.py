@@ -1,0 +1,124 @@
+"""Adjoint kernels and the autograd Function vs the FP64 oracle and finite differences."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.model import unpack_T
+from tests.gpu_helpers import device_problem, oracle_inputs, compare_blocks
+from workload import build_problem
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def setup_module(module):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _flatB(prob, dB):
+    out = np.zeros(prob.n_B)
+    for p, v in dB.items():
+        o = int(prob.off_B[p])
+        out[o:o + v.size] = v.ravel()
+    return out
+
+
+@pytest.mark.parametrize("precision,rel", [("fp64", 1e-12), ("fp32", 2e-5)])
+def test_vjp_matches_oracle(precision, rel):
+    prob = build_problem("chain", n_occ=20, band=5, somos=(6, 13))
+    plan, dev = device_problem(prob, precision=precision)
+    rng = np.random.default_rng(5)
+    G = torch.from_numpy(rng.standard_normal(prob.n_T)).cuda()
+    dT, dB = plan.vjp(dev["T"], G)
+    torch.cuda.synchronize()
+    inp = oracle_inputs(prob)
+    T = unpack_T(prob, prob.materialize("T"))
+    Gd = unpack_T(prob, G.cpu().numpy())
+    dTo, dBo = oracle.vjp(inp, T, Gd)
+    compare_blocks(prob, dT.cpu().numpy(), dTo, rel=rel)
+    got = dB.cpu().numpy()
+    want = _flatB(prob, dBo)
+    for p in range(prob.n_pairs):
+        o, sz = int(prob.off_B[p]), int(prob.naux[p] * prob.npno[p] ** 2)
+        d = np.linalg.norm(got[o:o + sz] - want[o:o + sz])
+        assert d <= rel * max(np.linalg.norm(want[o:o + sz]), 1e-300) + 1e-300, (p, d)
+    plan.close()
+
+
+def test_fp32_residual_close_to_fp64_oracle():
+    prob = build_problem("chain", n_occ=24, band=6, somos=(7, 16))
+    plan, dev = device_problem(prob, precision="fp32")
+    R = plan.residual(dev["T"])
+    torch.cuda.synchronize()
+    inp = oracle_inputs(prob)
+    Ro = oracle.residual_os(inp, unpack_T(prob, prob.materialize("T")))
+    compare_blocks(prob, R.cpu().numpy(), Ro, rel=2e-5)
+    plan.close()
+
+
+def test_dot_product_identity_on_device():
+    # <G, J dT> = <J^T G, dT> with J the residual's linear part (FP64, mini chain)
+    prob = build_problem("chain", n_occ=24, band=6, somos=(7, 16))
+    plan, dev = device_problem(prob)
+    rng = np.random.default_rng(8)
+    G = torch.from_numpy(rng.standard_normal(prob.n_T)).cuda()
+    X = torch.from_numpy(rng.standard_normal(prob.n_T)).cuda()
+    zero = torch.zeros_like(X)
+    JX = plan.residual(X) - plan.residual(zero)
+    JtG, _ = plan.vjp(X, G, want_dB=False)
+    a = float(torch.dot(G, JX))
+    b = float(torch.dot(JtG, X))
+    assert abs(a - b) <= 1e-11 * abs(a)
+    plan.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_autograd_lagrangian_central_differences_50_pairs(precision):
+    """Config of the differentiation study: chain sizes; directional central
+    differences (h = 1e-5, FP64 residuals) on 50 random pairs for T and B."""
+    from paper_2008_03237_amd import Plan
+    from paper_2008_03237_amd.autograd import residual
+    prob = build_problem("chain")
+    plan, dev = device_problem(prob, precision=precision)
+    rng = np.random.default_rng(2024)
+    pick = rng.choice(prob.n_pairs, 50, replace=False)
+    Lam = torch.from_numpy(rng.standard_normal(prob.n_T) * 1e-2).cuda()
+    T = dev["T"].clone().requires_grad_(True)
+    B = dev["B"]
+    B.requires_grad_(True)
+    # L = E(T) + <Lambda, R(T, B)>, E linear in T: sum_blocks w <K^{ss'}, T> (via update's energy of T)
+    R = residual(T, B, plan)
+    L = torch.dot(Lam, R)
+    L.backward()
+    gT, gB = T.grad.detach(), B.grad.detach()
+    B.requires_grad_(False)
+    # directions supported on the picked pairs
+    dTdir = torch.zeros(prob.n_T, dtype=torch.float64, device="cuda")
+    dBdir = torch.zeros_like(dev["B"])
+    for p in pick:
+        o, nb = int(prob.off_T[p]), int(prob.n_blocks()[p])
+        sz = nb * int(prob.npno[p]) ** 2
+        dTdir[o:o + sz] = torch.from_numpy(rng.standard_normal(sz)).cuda()
+        o, sz = int(prob.off_B[p]), int(prob.naux[p] * prob.npno[p] ** 2)
+        dBdir[o:o + sz] = torch.from_numpy(rng.standard_normal(sz)).cuda()
+    h = 1e-5
+    fp = Plan(prob, dev["B"], dev["S"], dev["K"], plan._dev[3], plan._dev[4])   # FP64 residuals for the differences
+
+    def Lof(Tx):
+        return float(torch.dot(Lam, fp.residual(Tx)))
+    with torch.no_grad():
+        fd_T = (Lof(dev["T"] + h * dTdir) - Lof(dev["T"] - h * dTdir)) / (2 * h)
+        an_T = float(torch.dot(gT, dTdir))
+        Bp = dev["B"] + h * dBdir
+        Bm = dev["B"] - h * dBdir
+        pp = Plan(prob, Bp, dev["S"], dev["K"], plan._dev[3], plan._dev[4])
+        pm = Plan(prob, Bm, dev["S"], dev["K"], plan._dev[3], plan._dev[4])
+        fd_B = (float(torch.dot(Lam, pp.residual(dev["T"]))) - float(torch.dot(Lam, pm.residual(dev["T"])))) / (2 * h)
+        an_B = float(torch.dot(gB, dBdir))
+    tol = 1e-7 if precision == "fp64" else 1e-4
+    print(precision, "dT: fd %.12e an %.12e   dB: fd %.12e an %.12e" % (fd_T, an_T, fd_B, an_B))
+    assert abs(fd_T - an_T) <= tol * abs(an_T)
+    assert abs(fd_B - an_B) <= tol * abs(an_B)
+    for x in (pp, pm, fp, plan):
+        x.close()

@@ -153,3 +153,23 @@ def test_full_size_sampled_residual(cfg, nsample):
         d = np.linalg.norm(got - ref)
         assert d <= 1e-12 * np.linalg.norm(ref), (p, name, d, np.linalg.norm(ref))
     plan.close()
+
+
+def test_graph_replay_matches_eager():
+    """hipGraph replays (several, with host work between them) equal eager launches."""
+    prob = build_problem("chain", n_occ=20, band=5, somos=(6, 13))
+    plan, dev = device_problem(prob, T_random=False)
+    T1 = dev["T"].clone()
+    T2 = dev["T"].clone()
+    plan.iterate(3, T1)              # captured graph, 3 replays
+    _ = T1.sum().item()
+    plan.iterate(2, T1)              # 2 more replays after eager torch work
+    E_graph, _ = plan.history()
+    plan.reset()
+    plan.set_profiling(True)         # profiling bypasses the graph
+    plan.iterate(5, T2)
+    plan.set_profiling(False)
+    E_eager, _ = plan.history()
+    assert np.array_equal(E_graph, E_eager)
+    assert torch.equal(T1.view(torch.int64), T2.view(torch.int64))
+    plan.close()
