@@ -69,7 +69,7 @@ __global__ __launch_bounds__(kEwThreads) void finish_kernel(FinishArgs a) {
       kk = K[idx];
       if (bk.anti) kk -= K[y * n + x];
     }
-    double r = kk + D * t;
+    double r = (a.drv ? a.drv[bk.off_T + idx] : kk) + D * t;
     for (int sl = 0; sl < bk.nslot; ++sl) r += ws[(int64_t)sl * nn + y * n + x];   // slots hold Out^T
     if (!isfinite(r)) bad = true;
     rmax = fmax(rmax, fabs(r));
@@ -346,6 +346,9 @@ __global__ void axpy_kernel(double* y, const double* x, double a, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
     y[i] += a * x[i];
 }
+__global__ void fill_kernel(double* y, double v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = v;
+}
 __global__ void copy_kernel(double* y, const double* x, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = x[i];
 }
@@ -405,4 +408,12 @@ hipError_t launch_copy(double* y, const double* x, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+}  // namespace dlpno
+
+namespace dlpno {
+hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, y, v, n);
+  return hipGetLastError();
+}
 }  // namespace dlpno

@@ -34,7 +34,8 @@ struct CplDev {
 struct TermDev {
   int64_t src_off;               // source block in T; -1 = no term for this block
   double w;                      // Fock weight; residual gets -w S X S^T
-  int32_t trans, pad;            // X = source^T when trans
+  int32_t trans;                 // X = source^T when trans
+  int32_t src_blk;               // global index of the source block
 };
 
 enum ItemKind { ITEM_LADDER = 0, ITEM_PROJ = 1 };
@@ -109,6 +110,7 @@ struct FinishArgs {
   int32_t* nonfinite;      // set to 1 when a residual element is not finite
   int32_t with_driver;     // 0: R = D o T + partials (linear part only, used by the VJP)
   int32_t pad;
+  const double* drv;       // when set, replaces the driver: R = drv + D o T + partials
   // DIIS ring: when ring != null, T_new -> ring_vecs[head], err = T_new - T -> ring_errs[head]
   const DiisState* ring;
   double* ring_vecs;
@@ -158,5 +160,6 @@ hipError_t launch_diis_reset(DiisState* st, int max, int start, hipStream_t s);
 hipError_t launch_convert_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s);
 hipError_t launch_copy(double* y, const double* x, int64_t n, hipStream_t s);
+hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t s);
 
 }  // namespace dlpno

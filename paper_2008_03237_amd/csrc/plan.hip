@@ -15,6 +15,7 @@
 #include "../../include/dlpno.h"
 #include "internal.h"
 #include "plan_internal.h"
+#include "split_internal.h"
 
 using namespace dlpno;
 
@@ -305,8 +306,6 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if (opts) opt = *opts;
   if (opt.precision < DLPNO_FP64 || opt.precision > DLPNO_FP16X2)
     return fail(DLPNO_ERR_INVALID_ARG, "unknown precision");
-  if (opt.precision == DLPNO_BF16X2 || opt.precision == DLPNO_FP16X2)
-    return fail(DLPNO_ERR_UNSUPPORTED, "split precisions are provided by the mixed-precision path");
   if (opt.diis_max < 0 || opt.diis_max > 8) return fail(DLPNO_ERR_INVALID_ARG, "diis_max must be in 0..8");
   if (opt.diis_max > 0 && (opt.diis_start < 1 || opt.diis_start > opt.diis_max))
     return fail(DLPNO_ERR_INVALID_ARG, "diis_start must be in 1..diis_max");
@@ -406,7 +405,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
       return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "cpl_rowptr must be non-decreasing"));
   if (prob->n_couplings > INT32_MAX) return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, "too many couplings"));
   P->cpl_h.resize(prob->n_couplings);
-  P->terms_h.assign((size_t)prob->n_couplings * 4, TermDev{-1, 0.0, 0, 0});
+  P->terms_h.assign((size_t)prob->n_couplings * 4, TermDev{-1, 0.0, 0, -1});
   P->flops_proj = 0.0;
   P->n_terms = 0;
   for (int p = 0; p < npairs; ++p) {
@@ -462,6 +461,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
         tm.src_off = q.off_T + (int64_t)sslot * nq * nq;
         tm.w = w;
         tm.trans = trans;
+        tm.src_blk = P->pairs_h[c.src_pair].blk0 + sslot;
         P->flops_proj += 2.0 * pd.n * (double)nq * (pd.n + nq);
         ++P->n_terms;
       }
@@ -487,6 +487,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if ((st = dev_alloc(&P->d_rmax_block, std::max(1, nblk_total), "block residual maxima")) != DLPNO_OK)
     return destroy_fail(st);
   if ((st = dev_alloc(&P->d_nonfinite, 4, "non-finite flag")) != DLPNO_OK) return destroy_fail(st);
+  if ((st = dev_alloc(&P->d_hist_iter, 4, "history counter")) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_hist, 2 * kHistCap, "history")) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_diis, 1, "DIIS state")) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_scalars, 8, "scalars")) != DLPNO_OK) return destroy_fail(st);
@@ -499,6 +500,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
       return destroy_fail(st);
   }
   HIPCK(launch_zero_i32(P->d_nonfinite, 1, s));
+  HIPCK(launch_zero_i32(P->d_hist_iter, 1, s));
   HIPCK(launch_diis_reset(P->d_diis, std::max(1, opt.diis_max), std::max(1, opt.diis_start), s));
   if (opt.precision == DLPNO_FP32) {
     if ((st = dev_alloc(&P->B32, (size_t)std::max<int64_t>(P->n_B, 1), "FP32 B")) != DLPNO_OK) return destroy_fail(st);
@@ -506,6 +508,49 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
     if ((st = dev_alloc(&P->T32, (size_t)std::max<int64_t>(P->n_T, 1), "FP32 T")) != DLPNO_OK) return destroy_fail(st);
     if (P->n_B > 0) HIPCK(launch_convert_f32(in->B, P->B32, P->n_B, s));
     if (P->n_S > 0) HIPCK(launch_convert_f32(in->S, P->S32, P->n_S, s));
+  }
+  if (is_split(opt.precision)) {
+    const bool f16 = opt.precision == DLPNO_FP16X2;
+    std::vector<int64_t> boff(npairs), toff(nblk_total), soff(prob->n_couplings), ctgt(prob->n_couplings);
+    int64_t nb = 0, nt = 0, ns = 0;
+    for (int p = 0; p < npairs; ++p) {
+      const PairDev& pd = P->pairs_h[p];
+      const int64_t n16 = 16 * ((pd.n + 15) / 16);
+      boff[p] = nb;
+      if (pd.nblk > 0) nb += (int64_t)pd.m * pd.n * n16;
+      for (int b = 0; b < pd.nblk; ++b) {
+        toff[pd.blk0 + b] = nt;
+        nt += (int64_t)pd.n * n16;
+      }
+      for (int64_t e = P->rowptr_h[p]; e < P->rowptr_h[p + 1]; ++e) {
+        ctgt[e] = p;
+        soff[e] = ns;
+        ns += (int64_t)pd.n * 16 * ((P->cpl_h[e].nsrc + 15) / 16);
+      }
+    }
+    P->n_Bs = nb;
+    P->n_Ts = nt;
+    P->n_Ss = ns;
+    if ((st = upload(&P->d_pair_boff, boff, "split B offsets", s)) != DLPNO_OK) return destroy_fail(st);
+    if ((st = upload(&P->d_blk_toff, toff, "split T offsets", s)) != DLPNO_OK) return destroy_fail(st);
+    if ((st = upload(&P->d_cpl_soff, soff, "split S offsets", s)) != DLPNO_OK) return destroy_fail(st);
+    if ((st = upload(&P->d_cpl_target, ctgt, "coupling targets", s)) != DLPNO_OK) return destroy_fail(st);
+    const size_t one = 1;
+    if ((st = dev_alloc(&P->Bs_hi, std::max<size_t>(nb, one), "split B")) != DLPNO_OK) return destroy_fail(st);
+    if ((st = dev_alloc(&P->Bs_lo, std::max<size_t>(nb, one), "split B")) != DLPNO_OK) return destroy_fail(st);
+    if ((st = dev_alloc(&P->Ss_hi, std::max<size_t>(ns, one), "split S")) != DLPNO_OK) return destroy_fail(st);
+    if ((st = dev_alloc(&P->Ss_lo, std::max<size_t>(ns, one), "split S")) != DLPNO_OK) return destroy_fail(st);
+    if ((st = dev_alloc(&P->Tts_hi, std::max<size_t>(nt, one), "split T")) != DLPNO_OK) return destroy_fail(st);
+    if ((st = dev_alloc(&P->Tts_lo, std::max<size_t>(nt, one), "split T")) != DLPNO_OK) return destroy_fail(st);
+    if ((st = dev_alloc(&P->Ts_hi, std::max<size_t>(nt, one), "split T")) != DLPNO_OK) return destroy_fail(st);
+    if ((st = dev_alloc(&P->Ts_lo, std::max<size_t>(nt, one), "split T")) != DLPNO_OK) return destroy_fail(st);
+    if (f16) {
+      if ((st = dev_alloc(&P->d_pair_bscale, std::max(npairs, 1), "B scales")) != DLPNO_OK) return destroy_fail(st);
+      if ((st = dev_alloc(&P->d_blk_tscale, std::max(nblk_total, 1), "T scales")) != DLPNO_OK) return destroy_fail(st);
+    }
+    HIPCK(launch_split_B(P->d_pairs, npairs, in->B, P->d_pair_boff, P->d_pair_bscale, P->Bs_hi, P->Bs_lo, f16, s));
+    HIPCK(launch_split_S(P->d_pairs, P->d_cpl_target, P->d_cpl, in->S, P->d_cpl_soff, prob->n_couplings, P->Ss_hi,
+                         P->Ss_lo, f16, s));
   }
   HIPCK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
   HIPCK(hipStreamSynchronize(s));
@@ -523,7 +568,9 @@ extern "C" dlpno_status dlpno_plan_destroy(dlpno_plan* P) {
   void* ptrs[] = {P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms, P->d_items, P->d_counter, P->d_ws,
                   P->d_e_block, P->d_rmax_block, P->d_nonfinite, P->d_hist, P->d_diis, P->d_scalars,
                   P->d_diis_partial, P->d_ring_vecs, P->d_ring_errs, P->B32, P->S32, P->T32,
-                  P->d_vjp_items, P->d_mixed, P->G32};
+                  P->d_vjp_items, P->d_mixed, P->G32, P->d_pair_boff, P->d_blk_toff, P->d_cpl_soff,
+                  P->d_cpl_target, P->d_pair_bscale, P->d_blk_tscale, P->Bs_hi, P->Bs_lo, P->Ss_hi, P->Ss_lo,
+                  P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo, P->d_mix_r, P->d_mix_delta, P->d_hist_iter};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete P;
@@ -560,21 +607,36 @@ void phase_collect(dlpno_plan* P) {
   P->pending.clear();
 }
 
-// grouped kernel over amplitudes T (FP64 buffer given by the caller)
-hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s) {
+bool is_split(int prec) { return prec == DLPNO_BF16X2 || prec == DLPNO_FP16X2; }
+
+// grouped kernel over amplitudes T (FP64 buffer given by the caller) in the
+// plan's precision, or in `prec` when given (FP64 residuals of a split plan)
+hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec) {
   hipError_t e;
   if (P->items_h.empty()) return hipSuccess;
-  if (P->opt.precision == DLPNO_FP32) {
+  if (prec < 0) prec = P->opt.precision;
+  if (prec == DLPNO_FP32) {
     phase_begin(P, 4, s);
     if ((e = launch_convert_f32(T, P->T32, P->n_T, s)) != hipSuccess) return e;
+    phase_end(P, s);
+  } else if (is_split(prec)) {
+    phase_begin(P, 4, s);
+    if ((e = launch_split_T(P->d_blocks, P->n_blocks, T, P->d_blk_toff, P->d_blk_tscale, P->Tts_hi, P->Tts_lo,
+                            P->Ts_hi, P->Ts_lo, prec == DLPNO_FP16X2, s)) != hipSuccess)
+      return e;
     phase_end(P, s);
   }
   if ((e = launch_zero_i32(P->d_counter, 1, s)) != hipSuccess) return e;
   phase_begin(P, 0, s);
-  if (P->opt.precision == DLPNO_FP32) {
+  if (prec == DLPNO_FP32) {
     GroupedArgs<float> a{P->d_items, (int32_t)P->items_h.size(), P->d_counter, P->d_pairs, P->d_blocks,
                          P->d_cpl, P->d_terms, P->B32, P->S32, P->T32, P->d_ws};
     e = launch_grouped_f32(a, P->workers, s);
+  } else if (is_split(prec)) {
+    SplitArgs a{P->d_items, (int32_t)P->items_h.size(), P->d_counter, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
+                P->d_pair_boff, P->d_pair_bscale, P->d_blk_toff, P->d_blk_tscale, P->d_cpl_soff, P->Bs_hi, P->Bs_lo,
+                P->Ss_hi, P->Ss_lo, P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo, P->d_ws};
+    e = launch_split_grouped(a, prec == DLPNO_FP16X2, P->workers, s);
   } else {
     GroupedArgs<double> a{P->d_items, (int32_t)P->items_h.size(), P->d_counter, P->d_pairs, P->d_blocks,
                           P->d_cpl, P->d_terms, P->in.B, P->in.S, T, P->d_ws};
@@ -602,13 +664,14 @@ FinishArgs finish_args(dlpno_plan* P, const double* T) {
 
 // one full iteration on stream s (capturable: kernels only)
 hipError_t enqueue_iteration(dlpno_plan* P, double* T, double* R, double* e_pair, double* e_total, double* rmax,
-                             hipStream_t s) {
+                             hipStream_t s, const double* drv, int prec, bool record) {
   hipError_t e;
   const bool diis = P->opt.diis_max > 0;
   if (diis && (e = launch_diis_slot(P->d_diis, s)) != hipSuccess) return e;
-  if ((e = run_grouped(P, T, s)) != hipSuccess) return e;
+  if ((e = run_grouped(P, T, s, prec)) != hipSuccess) return e;
   FinishArgs f = finish_args(P, T);
   f.R = R;
+  f.drv = drv;
   if (diis) {
     f.ring = P->d_diis;
     f.ring_vecs = P->d_ring_vecs;
@@ -630,8 +693,8 @@ hipError_t enqueue_iteration(dlpno_plan* P, double* T, double* R, double* e_pair
   ra.e_pair = e_pair;
   ra.e_total = e_total ? e_total : P->d_scalars;
   ra.rmax = rmax ? rmax : P->d_scalars + 1;
-  ra.hist = P->d_hist;
-  ra.iter = &P->d_diis->iter;
+  ra.hist = record ? P->d_hist : nullptr;
+  ra.iter = record ? P->d_hist_iter : nullptr;
   ra.hist_cap = kHistCap;
   phase_begin(P, 2, s);
   if ((e = launch_reduce(ra, s)) != hipSuccess) return e;
@@ -689,6 +752,7 @@ extern "C" dlpno_status dlpno_reset(dlpno_plan* P, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   HIPCK(launch_diis_reset(P->d_diis, std::max(1, P->opt.diis_max), std::max(1, P->opt.diis_start), s));
   HIPCK(launch_zero_i32(P->d_nonfinite, 1, s));
+  HIPCK(launch_zero_i32(P->d_hist_iter, 1, s));
   HIPCK(hipStreamSynchronize(s));
   P->host_iter = 0;
   return DLPNO_OK;

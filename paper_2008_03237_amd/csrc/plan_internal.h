@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/dlpno.h"
@@ -58,6 +59,7 @@ struct dlpno_plan {
   double* d_e_block = nullptr;
   double* d_rmax_block = nullptr;
   int32_t* d_nonfinite = nullptr;
+  int32_t* d_hist_iter = nullptr;   // iterations recorded in the history
   double* d_hist = nullptr;
   dlpno::DiisState* d_diis = nullptr;
   double* d_scalars = nullptr;
@@ -67,6 +69,18 @@ struct dlpno_plan {
   float* B32 = nullptr;
   float* S32 = nullptr;
   float* T32 = nullptr;
+  // split precision
+  int64_t n_Bs = 0, n_Ss = 0, n_Ts = 0;
+  int64_t* d_pair_boff = nullptr;
+  int64_t* d_blk_toff = nullptr;
+  int64_t* d_cpl_soff = nullptr;
+  int64_t* d_cpl_target = nullptr;
+  float* d_pair_bscale = nullptr;
+  float* d_blk_tscale = nullptr;
+  uint16_t *Bs_hi = nullptr, *Bs_lo = nullptr, *Ss_hi = nullptr, *Ss_lo = nullptr;
+  uint16_t *Tts_hi = nullptr, *Tts_lo = nullptr, *Ts_hi = nullptr, *Ts_lo = nullptr;
+  double* d_mix_r = nullptr;       // FP64 residual of the outer refinement
+  double* d_mix_delta = nullptr;   // correction of the inner solve
   void* d_vjp_items = nullptr;
   int n_vjp_items = 0;
   float* G32 = nullptr;
@@ -91,10 +105,11 @@ namespace dlpno {
 dlpno_status fail(dlpno_status s, const std::string& msg);
 dlpno_status build_schedule(dlpno_plan* P);
 dlpno_status upload_schedule(dlpno_plan* P, hipStream_t s);
-hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s);
+hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec = -1);
 FinishArgs finish_args(dlpno_plan* P, const double* T);
 hipError_t enqueue_iteration(dlpno_plan* P, double* T, double* R, double* e_pair, double* e_total, double* rmax,
-                             hipStream_t s);
+                             hipStream_t s, const double* drv = nullptr, int prec = -1, bool record = true);
+bool is_split(int prec);
 std::string describe(const dlpno_plan* P);
 void phase_begin(dlpno_plan* P, int ph, hipStream_t s);
 void phase_end(dlpno_plan* P, hipStream_t s);

@@ -1,0 +1,498 @@
+// Split-precision (BF16x2 / FP16x2) ladder and projection contractions.
+//
+// Every operand x is carried as hi + lo with hi = round(x), lo = round(x - hi)
+// in BF16 or FP16, and a product as hi*hi + hi*lo + lo*hi on the 16x16x16
+// MFMA with FP32 accumulation (the lo*lo term is below the FP32 accumulation
+// error).  This keeps about 16 (BF16) or 22 (FP16) significant bits per
+// operand; the FP64 refinement driver (mixed.hip) recovers full accuracy.
+// FP16 needs power-of-two scaling: per pair for B, per block for the
+// amplitudes; BF16 has the FP32 exponent range and runs unscaled.
+//
+// Split operands are stored in zero-padded layouts whose rows are 16-element
+// multiples, so every 16x16x16 fragment (4 consecutive inner-index elements
+// per lane, one 8-byte load) is either inside the matrix or an exact zero:
+//   B_p     per Q: [a][c], n rows x N16 columns          (symmetric B^Q)
+//   S_pq    [a][c], n_target rows x N16(n_src) columns   (target x source)
+//   T_blk   two copies: T^T [d][c] and T [c][d], n rows x N16 columns
+// The 16x16x16 accumulator keeps output row 4 g + i in register i of lane
+// group g, which is exactly the inner-index order of the next product's B
+// operand, so Y^T = X^T M^T is converted to hi/lo in registers and fed to
+// Out^T = M Y^T without leaving the VGPRs.
+#include "grouped_impl.h"
+#include "plan_internal.h"
+#include "split_internal.h"
+
+namespace dlpno {
+
+typedef short s4_t __attribute__((ext_vector_type(4)));
+typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+
+struct SplitBf16 {
+  typedef uint16_t E;
+  static __device__ __forceinline__ E cvt(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+  static __device__ __forceinline__ float back(E e) { return (float)__builtin_bit_cast(__bf16, e); }
+  static __device__ __forceinline__ f4_t mfma(uint64_t a, uint64_t b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4_t, a), __builtin_bit_cast(s4_t, b), c, 0,
+                                                     0, 0);
+  }
+};
+struct SplitF16 {
+  typedef uint16_t E;
+  static __device__ __forceinline__ E cvt(float x) { return __builtin_bit_cast(uint16_t, (_Float16)x); }
+  static __device__ __forceinline__ float back(E e) { return (float)__builtin_bit_cast(_Float16, e); }
+  static __device__ __forceinline__ f4_t mfma(uint64_t a, uint64_t b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4_t, a), __builtin_bit_cast(h4_t, b), c, 0, 0,
+                                                 0);
+  }
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc16(const uint16_t* p, uint32_t elems) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(uni(p)), (short)0, (uint32_t)uni((int32_t)(elems * 2u)),
+                                           0x00020000);
+}
+__device__ __forceinline__ uint64_t frag(__amdgpu_buffer_rsrc_t r, uint32_t off_elems) {
+  return __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(r, off_elems * 2u, 0u, 0));
+}
+
+// hi/lo of 4 FP32 values packed as two 4-element fragments
+template <typename S>
+__device__ __forceinline__ void split4(const f4_t v, float scale, uint64_t& hi, uint64_t& lo) {
+  uint64_t h = 0, l = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const float x = v[j] * scale;
+    const typename S::E eh = S::cvt(x);
+    const typename S::E el = S::cvt(x - S::back(eh));
+    h |= (uint64_t)eh << (16 * j);
+    l |= (uint64_t)el << (16 * j);
+  }
+  hi = h;
+  lo = l;
+}
+
+template <typename S>
+__device__ __forceinline__ f4_t mfma3(uint64_t ah, uint64_t al, uint64_t bh, uint64_t bl, f4_t c) {
+  c = S::mfma(ah, bh, c);
+  c = S::mfma(ah, bl, c);
+  c = S::mfma(al, bh, c);
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// ladder item (same schedule as the FP64 kernel; NT inner tiles of 16)
+// ---------------------------------------------------------------------------
+template <typename S, int NT, int NB, int NTA, int TA0>
+__device__ __forceinline__ void split_ladder_item(const SplitArgs& A, const Item& it) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const PairDev& Pg = A.pairs[it.pair];
+  const int n = uni(Pg.n);
+  const int blk0 = uni(Pg.blk0);
+  const int n16 = 16 * NT;
+  const uint32_t slice = (uint32_t)n * (uint32_t)n16;
+  const int64_t boff = uni(A.pair_boff[it.pair]);
+  const float bs = A.pair_bscale ? __builtin_bit_cast(float, uni(__builtin_bit_cast(int32_t, A.pair_bscale[it.pair]))) : 1.f;
+
+  // amplitude fragments (T^T layout): Af[b][td][kt] = T^T[16 td + r][16 kt + 4 g .. +3]
+  uint64_t Ah[NB][NT][NT], Alo[NB][NT][NT];
+  float unscale[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const int blk = blk0 + it.bslot0 + b;
+    const int64_t toff = uni(A.blk_toff[blk]);
+    const float ts = A.blk_tscale ? __builtin_bit_cast(float, uni(__builtin_bit_cast(int32_t, A.blk_tscale[blk]))) : 1.f;
+    unscale[b] = 1.f / (ts * bs * bs);
+    const __amdgpu_buffer_rsrc_t rh = rsrc16(A.Tt_hi + toff, slice);
+    const __amdgpu_buffer_rsrc_t rl = rsrc16(A.Tt_lo + toff, slice);
+#pragma unroll
+    for (int td = 0; td < NT; ++td)
+#pragma unroll
+      for (int kt = 0; kt < NT; ++kt) {
+        const uint32_t o = (uint32_t)((16 * td + r) * n16 + 16 * kt + 4 * g);
+        Ah[b][td][kt] = frag(rh, o);
+        Alo[b][td][kt] = frag(rl, o);
+      }
+  }
+  f4_t acc[NB][NT][NTA];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int u = 0; u < NTA; ++u) acc[b][t][u] = f4_t{0, 0, 0, 0};
+
+  // B^Q fragments: M[t][kt] = B^Q[16 t + r][16 kt + 4 g .. +3]
+  auto loadM = [&](uint64_t (&Mh)[NT][NT], uint64_t (&Ml)[NT][NT], int Q) {
+    const __amdgpu_buffer_rsrc_t rh = rsrc16(A.B_hi + boff + (size_t)Q * slice, slice);
+    const __amdgpu_buffer_rsrc_t rl = rsrc16(A.B_lo + boff + (size_t)Q * slice, slice);
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int kt = 0; kt < NT; ++kt) {
+        const uint32_t o = (uint32_t)((16 * t + r) * n16 + 16 * kt + 4 * g);
+        Mh[t][kt] = frag(rh, o);
+        Ml[t][kt] = frag(rl, o);
+      }
+  };
+  auto compute = [&](const uint64_t (&Mh)[NT][NT], const uint64_t (&Ml)[NT][NT]) {
+#pragma unroll
+    for (int td = 0; td < NT; ++td) {
+      f4_t d1[NB][NTA];
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int u = 0; u < NTA; ++u) {
+          f4_t c = f4_t{0, 0, 0, 0};
+#pragma unroll
+          for (int kt = 0; kt < NT; ++kt) c = mfma3<S>(Ah[b][td][kt], Alo[b][td][kt], Mh[TA0 + u][kt], Ml[TA0 + u][kt], c);
+          d1[b][u] = c;
+        }
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int u = 0; u < NTA; ++u) {
+          uint64_t yh, yl;
+          split4<S>(d1[b][u], 1.f, yh, yl);
+#pragma unroll
+          for (int tb = 0; tb < NT; ++tb) acc[b][tb][u] = mfma3<S>(Mh[tb][td], Ml[tb][td], yh, yl, acc[b][tb][u]);
+        }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  };
+  uint64_t M0h[NT][NT], M0l[NT][NT], M1h[NT][NT], M1l[NT][NT];
+  loadM(M0h, M0l, it.lo);
+  for (int Q = it.lo; Q < it.hi; Q += 2) {
+    if (Q + 1 < it.hi) loadM(M1h, M1l, Q + 1);
+    compute(M0h, M0l);
+    if (Q + 1 >= it.hi) break;
+    if (Q + 2 < it.hi) loadM(M0h, M0l, Q + 2);
+    compute(M1h, M1l);
+  }
+  const int64_t nn = (int64_t)n * n;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    double* dst = A.ws + uni(A.blocks[blk0 + it.bslot0 + b].off_ws) + (int64_t)it.slot * nn;
+#pragma unroll
+    for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+      for (int u = 0; u < NTA; ++u) {
+        const int a = 16 * (TA0 + u) + r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int bb = 16 * tb + 4 * g + i;
+          if (a < n && bb < n) dst[bb * n + a] = (double)acc[b][tb][u][i] * (double)unscale[b];
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// projection item: per coupling S fragments, per term source fragments
+// ---------------------------------------------------------------------------
+template <typename S, int NT, int NB>
+__device__ __forceinline__ void split_proj_item(const SplitArgs& A, const Item& it) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+  const PairDev& Pg = A.pairs[it.pair];
+  const int n = uni(Pg.n);
+  const int blk0 = uni(Pg.blk0);
+  float tscale[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+    tscale[b] = A.blk_tscale
+                    ? __builtin_bit_cast(float, uni(__builtin_bit_cast(int32_t, A.blk_tscale[blk0 + it.bslot0 + b])))
+                    : 1.f;
+  f4_t acc[NB][NT][NT];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) acc[b][t][u] = f4_t{0, 0, 0, 0};
+
+  for (int e = it.lo; e < it.hi; ++e) {
+    const int nq = uni(A.cpl[e].nsrc);
+    const int NQ = (nq + 15) >> 4;
+    const int nq16 = 16 * NQ;
+    const int64_t soff = uni(A.cpl_soff[e]);
+    const __amdgpu_buffer_rsrc_t sh = rsrc16(A.S_hi + soff, (uint32_t)(n * nq16));
+    const __amdgpu_buffer_rsrc_t sl = rsrc16(A.S_lo + soff, (uint32_t)(n * nq16));
+    // S_{p,q} fragments: M[t][kt] = S[16 t + r][16 kt + 4 g .. +3]
+    uint64_t Mh[NT][4], Ml[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt) {
+        if (kt < NQ) {
+          const uint32_t o = (uint32_t)((16 * t + r) * nq16 + 16 * kt + 4 * g);
+          Mh[t][kt] = frag(sh, o);
+          Ml[t][kt] = frag(sl, o);
+        } else {
+          Mh[t][kt] = 0;
+          Ml[t][kt] = 0;
+        }
+      }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const TermDev& tg = A.terms[(int64_t)e * 4 + it.bslot0 + b];
+      const int64_t src_off = uni(tg.src_off);
+      if (src_off < 0) continue;
+      const int sblk = uni(tg.src_blk);
+      const int trans = uni(tg.trans);
+      const float w = (float)uni(tg.w);
+      const float qs = A.blk_tscale ? __builtin_bit_cast(float, uni(__builtin_bit_cast(int32_t, A.blk_tscale[sblk]))) : 1.f;
+      // X^T fragments: X = T_q (take the T^T copy) or X = T_q^T (take the T copy)
+      const int64_t toff = uni(A.blk_toff[sblk]);
+      const uint16_t* xh = trans ? A.T_hi : A.Tt_hi;
+      const uint16_t* xl = trans ? A.T_lo : A.Tt_lo;
+      const __amdgpu_buffer_rsrc_t xrh = rsrc16(xh + toff, (uint32_t)(nq * nq16));
+      const __amdgpu_buffer_rsrc_t xrl = rsrc16(xl + toff, (uint32_t)(nq * nq16));
+      // rescale Y to the target block's scale with the Fock weight folded in
+      const float ysc = -w * tscale[b] / qs;
+#pragma unroll
+      for (int td = 0; td < 4; ++td) {
+        if (td < NQ) {
+          uint64_t Xh[4], Xl[4];
+#pragma unroll
+          for (int kt = 0; kt < 4; ++kt) {
+            if (kt < NQ) {
+              const uint32_t o = (uint32_t)((16 * td + r) * nq16 + 16 * kt + 4 * g);
+              Xh[kt] = frag(xrh, o);
+              Xl[kt] = frag(xrl, o);
+            } else {
+              Xh[kt] = 0;
+              Xl[kt] = 0;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < NT; ++u) {
+            f4_t c = f4_t{0, 0, 0, 0};
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt)
+              if (kt < NQ) c = mfma3<S>(Xh[kt], Xl[kt], Mh[u][kt], Ml[u][kt], c);
+            uint64_t yh, yl;
+            split4<S>(c, ysc, yh, yl);
+#pragma unroll
+            for (int tb = 0; tb < NT; ++tb) acc[b][tb][u] = mfma3<S>(Mh[tb][td], Ml[tb][td], yh, yl, acc[b][tb][u]);
+          }
+        }
+      }
+    }
+  }
+  const int64_t nn = (int64_t)n * n;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    double* dst = A.ws + uni(A.blocks[blk0 + it.bslot0 + b].off_ws) + (int64_t)it.slot * nn;
+    const double us = 1.0 / (double)tscale[b];
+#pragma unroll
+    for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const int a = 16 * u + r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int bb = 16 * tb + 4 * g + i;
+          if (a < n && bb < n) dst[bb * n + a] = (double)acc[b][tb][u][i] * us;
+        }
+      }
+  }
+}
+
+template <typename S>
+__device__ __forceinline__ void split_run_item(const SplitArgs& A, const Item& it) {
+  if (it.kind == ITEM_LADDER) {
+    switch (it.variant) {
+      case 0: split_ladder_item<S, 1, 4, 1, 0>(A, it); break;
+      case 1: split_ladder_item<S, 1, 2, 1, 0>(A, it); break;
+      case 2: split_ladder_item<S, 1, 1, 1, 0>(A, it); break;
+      case 3: split_ladder_item<S, 2, 4, 2, 0>(A, it); break;
+      case 4: split_ladder_item<S, 2, 2, 2, 0>(A, it); break;
+      case 5: split_ladder_item<S, 2, 1, 2, 0>(A, it); break;
+      case 6:
+        if (it.ta0 == 0) split_ladder_item<S, 2, 4, 1, 0>(A, it);
+        else split_ladder_item<S, 2, 4, 1, 1>(A, it);
+        break;
+      case 7: split_ladder_item<S, 3, 1, 3, 0>(A, it); break;
+      case 8:
+        if (it.ta0 == 0) split_ladder_item<S, 4, 1, 2, 0>(A, it);
+        else split_ladder_item<S, 4, 1, 2, 2>(A, it);
+        break;
+      default: break;
+    }
+  } else {
+    switch (it.variant) {
+      case 0: split_proj_item<S, 1, 4>(A, it); break;
+      case 1: split_proj_item<S, 1, 2>(A, it); break;
+      case 2: split_proj_item<S, 1, 1>(A, it); break;
+      case 3: split_proj_item<S, 2, 4>(A, it); break;
+      case 4: split_proj_item<S, 2, 2>(A, it); break;
+      case 5: split_proj_item<S, 2, 1>(A, it); break;
+      case 6: split_proj_item<S, 3, 2>(A, it); break;
+      case 7: split_proj_item<S, 3, 1>(A, it); break;
+      case 8: split_proj_item<S, 4, 1>(A, it); break;
+      default: break;
+    }
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(256) void split_grouped_kernel(SplitArgs A) {
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    int idx = 0;
+    if (lane == 0) idx = atomicAdd(A.counter, 1);
+    idx = __builtin_amdgcn_readfirstlane(idx);
+    if (idx >= A.n_items) break;
+    const Item& ig = A.items[idx];
+    Item it;
+    it.kind = uni(ig.kind);
+    it.variant = uni(ig.variant);
+    it.pair = uni(ig.pair);
+    it.bslot0 = uni(ig.bslot0);
+    it.slot = uni(ig.slot);
+    it.ta0 = uni(ig.ta0);
+    it.lo = uni(ig.lo);
+    it.hi = uni(ig.hi);
+    split_run_item<S>(A, it);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// conversions
+// ---------------------------------------------------------------------------
+template <typename S>
+__device__ __forceinline__ void split_d(double x, uint16_t& h, uint16_t& l) {
+  const typename S::E eh = S::cvt((float)x);
+  const typename S::E el = S::cvt((float)(x - (double)S::back(eh)));
+  h = eh;
+  l = el;
+}
+
+__device__ __forceinline__ float pow2_scale(double amax) {
+  // power of two s with amax * s in [0.5, 1); 1 when amax is zero
+  if (!(amax > 0.0)) return 1.f;
+  int e;
+  (void)frexp(amax, &e);
+  return ldexpf(1.f, -e);
+}
+
+__device__ __forceinline__ double block_max(double v) {
+  __shared__ double sm[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = v;
+  __syncthreads();
+  v = fmax(fmax(sm[0], sm[1]), fmax(sm[2], sm[3]));
+  __syncthreads();
+  return v;
+}
+
+// B_p (FP64 [Q][a][c]) -> padded split copy, one workgroup per pair
+template <typename S>
+__global__ __launch_bounds__(256) void split_B_kernel(const PairDev* pairs, const double* B, const int64_t* boff,
+                                                      float* bscale, uint16_t* hi, uint16_t* lo, int scaled) {
+  const PairDev P = pairs[blockIdx.x];
+  if (P.nblk == 0) return;
+  const int n = P.n, n16 = 16 * ((n + 15) / 16);
+  const int64_t total = (int64_t)P.m * n * n;
+  const double* src = B + P.off_B;
+  float sc = 1.f;
+  if (scaled) {
+    double mx = 0.0;
+    for (int64_t x = threadIdx.x; x < total; x += 256) mx = fmax(mx, fabs(src[x]));
+    sc = pow2_scale(block_max(mx));
+    if (threadIdx.x == 0) bscale[blockIdx.x] = sc;
+  }
+  const int64_t tot16 = (int64_t)P.m * n * n16;
+  for (int64_t x = threadIdx.x; x < tot16; x += 256) {
+    const int64_t q = x / ((int64_t)n * n16);
+    const int rem = (int)(x - q * n * n16);
+    const int a = rem / n16, c = rem - a * n16;
+    uint16_t h = 0, l = 0;
+    if (c < n) split_d<S>(src[(q * n + a) * n + c] * (double)sc, h, l);
+    hi[boff[blockIdx.x] + x] = h;
+    lo[boff[blockIdx.x] + x] = l;
+  }
+}
+
+// S of coupling e (FP64 [c][a], n_src x n_tgt) -> [a][c] padded split copy
+template <typename S>
+__global__ __launch_bounds__(256) void split_S_kernel(const PairDev* pairs, const int64_t* rowptr_target,
+                                                      const CplDev* cpl, const double* Sd, const int64_t* soff,
+                                                      int64_t ncpl, uint16_t* hi, uint16_t* lo) {
+  for (int64_t e = blockIdx.x; e < ncpl; e += gridDim.x) {
+    const int p = (int)rowptr_target[e];
+    const int n = pairs[p].n, nq = cpl[e].nsrc, nq16 = 16 * ((nq + 15) / 16);
+    const double* W = Sd + cpl[e].off_S;
+    for (int x = threadIdx.x; x < n * nq16; x += 256) {
+      const int a = x / nq16, c = x - a * nq16;
+      uint16_t h = 0, l = 0;
+      if (c < nq) split_d<S>(W[c * n + a], h, l);
+      hi[soff[e] + x] = h;
+      lo[soff[e] + x] = l;
+    }
+  }
+}
+
+// amplitudes (FP64 T layout) -> split T^T and T copies, one workgroup per block
+template <typename S>
+__global__ __launch_bounds__(256) void split_T_kernel(const BlockDev* blocks, const double* T, const int64_t* toff,
+                                                      float* tscale, uint16_t* tt_hi, uint16_t* tt_lo,
+                                                      uint16_t* t_hi, uint16_t* t_lo, int scaled) {
+  const BlockDev bk = blocks[blockIdx.x];
+  const int n = bk.n, n16 = 16 * ((n + 15) / 16);
+  const double* src = T + bk.off_T;
+  float sc = 1.f;
+  if (scaled) {
+    double mx = 0.0;
+    for (int x = threadIdx.x; x < n * n; x += 256) mx = fmax(mx, fabs(src[x]));
+    sc = pow2_scale(block_max(mx));
+    if (threadIdx.x == 0) tscale[blockIdx.x] = sc;
+  }
+  const int64_t o = toff[blockIdx.x];
+  for (int x = threadIdx.x; x < n * n16; x += 256) {
+    const int row = x / n16, col = x - row * n16;
+    uint16_t h = 0, l = 0, h2 = 0, l2 = 0;
+    if (col < n) {
+      split_d<S>(src[col * n + row] * (double)sc, h, l);    // T^T[row][col] = T[col][row]
+      split_d<S>(src[row * n + col] * (double)sc, h2, l2);  // T[row][col]
+    }
+    tt_hi[o + x] = h;
+    tt_lo[o + x] = l;
+    t_hi[o + x] = h2;
+    t_lo[o + x] = l2;
+  }
+}
+
+hipError_t launch_split_grouped(const SplitArgs& a, bool fp16, int workers, hipStream_t s) {
+  if (fp16) hipLaunchKernelGGL(split_grouped_kernel<SplitF16>, dim3(workers), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(split_grouped_kernel<SplitBf16>, dim3(workers), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_B(const PairDev* pairs, int npairs, const double* B, const int64_t* boff, float* bscale,
+                          uint16_t* hi, uint16_t* lo, bool fp16, hipStream_t s) {
+  if (npairs == 0) return hipSuccess;
+  if (fp16) hipLaunchKernelGGL(split_B_kernel<SplitF16>, dim3(npairs), dim3(256), 0, s, pairs, B, boff, bscale, hi, lo, 1);
+  else hipLaunchKernelGGL(split_B_kernel<SplitBf16>, dim3(npairs), dim3(256), 0, s, pairs, B, boff, bscale, hi, lo, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_S(const PairDev* pairs, const int64_t* cpl_target, const CplDev* cpl, const double* S,
+                          const int64_t* soff, int64_t ncpl, uint16_t* hi, uint16_t* lo, bool fp16, hipStream_t s) {
+  if (ncpl == 0) return hipSuccess;
+  const int grid = (int)std::min<int64_t>(ncpl, 65536);
+  if (fp16) hipLaunchKernelGGL(split_S_kernel<SplitF16>, dim3(grid), dim3(256), 0, s, pairs, cpl_target, cpl, S, soff, ncpl, hi, lo);
+  else hipLaunchKernelGGL(split_S_kernel<SplitBf16>, dim3(grid), dim3(256), 0, s, pairs, cpl_target, cpl, S, soff, ncpl, hi, lo);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_T(const BlockDev* blocks, int nblocks, const double* T, const int64_t* toff, float* tscale,
+                          uint16_t* tt_hi, uint16_t* tt_lo, uint16_t* t_hi, uint16_t* t_lo, bool fp16, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  if (fp16) hipLaunchKernelGGL(split_T_kernel<SplitF16>, dim3(nblocks), dim3(256), 0, s, blocks, T, toff, tscale, tt_hi, tt_lo, t_hi, t_lo, 1);
+  else hipLaunchKernelGGL(split_T_kernel<SplitBf16>, dim3(nblocks), dim3(256), 0, s, blocks, T, toff, tscale, tt_hi, tt_lo, t_hi, t_lo, 0);
+  return hipGetLastError();
+}
+
+}  // namespace dlpno
