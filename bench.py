@@ -94,6 +94,10 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=400)
+    ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision / refinement leg")
+    ap.add_argument("--mixed-precision", default="bf16x2", choices=["bf16x2", "fp16x2", "fp32"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (the pair sharding across GPUs is a design "
@@ -111,6 +115,12 @@ def main():
         print("[bench %.1fs] %s" % (time.perf_counter() - t_setup, msg), file=sys.stderr, flush=True)
 
     t_setup = time.perf_counter()
+    if args.copy_calibration:
+        x = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
     prob = build_problem(args.workload)
     log("workload %s: %d pairs, %d couplings" % (args.workload, prob.n_pairs, prob.n_couplings))
     dev = device_fields(prob)
@@ -182,10 +192,65 @@ def main():
         "setup_s": round(setup_s, 1),
     }
     log("grouped kernel %.3f ms/launch" % kern_ms)
+    if not args.no_mixed:
+        out["mixed"] = mixed_leg(prob, dev, plan, eps_a, eps_b, args, flops, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, n_pairs=args.cpu_pairs)
     plan.close()
     print(json.dumps(out), flush=True)
+
+
+def mixed_leg(prob, dev, plan64, eps_a, eps_b, args, flops, log):
+    """Split-precision grouped kernel throughput, and the refined mixed solve
+    against the converged FP64 solve (time and energy error)."""
+    import numpy as np
+    import torch
+
+    from paper_2008_03237_amd import Plan
+    # FP64 reference: iterate to max|R| < 1e-9 (DIIS), timed
+    plan64.reset()
+    T64 = torch.zeros(max(prob.n_T, 1), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n64 = 0
+    while n64 < 60:
+        _, e64, et64, r64 = plan64.iterate(2, T64)
+        n64 += 2
+        if float(r64.cpu()[0]) < 1e-9:
+            break
+    torch.cuda.synchronize()
+    t64 = time.perf_counter() - t0
+    mp = Plan(prob, dev["B"], dev["S"], dev["K"], eps_a, eps_b, precision=args.mixed_precision)
+    Tm = torch.zeros_like(T64)
+    mp.solve_mixed(1, 1, Tm)              # warm-up (split conversions, code objects)
+    Tm.zero_()
+    mp.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, em, etm, rm = mp.solve_mixed(3, 12, Tm)
+    torch.cuda.synchronize()
+    tm = time.perf_counter() - t0
+    # split grouped kernel alone (HIP events inside the library)
+    mp.set_profiling(True)
+    for _ in range(3):
+        mp.residual(Tm)
+    ms, cnt = mp.phase_times()
+    mp.set_profiling(False)
+    k_ms = ms[0] / max(cnt[0], 1)
+    conv_ms = ms[4] / max(cnt[4], 1)
+    e64n = e64.cpu().numpy().reshape(-1, 4).sum(1)
+    emn = em.cpu().numpy().reshape(-1, 4).sum(1)
+    res = {"precision": args.mixed_precision, "refinements": 3, "inner_iterations": 12,
+           "kernel_ms": round(k_ms, 3), "split_T_ms": round(conv_ms, 3),
+           "achieved_tflops": round(flops / (k_ms / 1e3) / 1e12, 3),
+           "mixed_solve_s": round(tm, 3), "fp64_solve_s": round(t64, 3), "fp64_iterations": n64,
+           "energy_fp64": float(et64.cpu()[0]), "energy_mixed": float(etm.cpu()[0]),
+           "total_energy_error": abs(float(etm.cpu()[0]) - float(et64.cpu()[0])),
+           "max_pair_energy_error": float(np.max(np.abs(emn - e64n))),
+           "max_abs_R_mixed": float(rm.cpu()[0])}
+    log("mixed leg: %s" % res)
+    mp.close()
+    return res
 
 
 def kernel_source_sha():
