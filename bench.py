@@ -96,6 +96,8 @@ def main():
     ap.add_argument("--cpu-pairs", type=int, default=400)
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision / refinement leg")
     ap.add_argument("--mixed-precision", default="bf16x2", choices=["bf16x2", "fp16x2", "fp32"])
+    ap.add_argument("--mixed-outer", type=int, default=3, help="FP64 refinement steps")
+    ap.add_argument("--mixed-inner", type=int, default=6, help="low-precision iterations per refinement step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -227,7 +229,7 @@ def mixed_leg(prob, dev, plan64, eps_a, eps_b, args, flops, log):
     mp.reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, em, etm, rm = mp.solve_mixed(3, 12, Tm)
+    _, em, etm, rm = mp.solve_mixed(args.mixed_outer, args.mixed_inner, Tm)
     torch.cuda.synchronize()
     tm = time.perf_counter() - t0
     # split grouped kernel alone (HIP events inside the library)
@@ -240,7 +242,7 @@ def mixed_leg(prob, dev, plan64, eps_a, eps_b, args, flops, log):
     conv_ms = ms[4] / max(cnt[4], 1)
     e64n = e64.cpu().numpy().reshape(-1, 4).sum(1)
     emn = em.cpu().numpy().reshape(-1, 4).sum(1)
-    res = {"precision": args.mixed_precision, "refinements": 3, "inner_iterations": 12,
+    res = {"precision": args.mixed_precision, "refinements": args.mixed_outer, "inner_iterations": args.mixed_inner,
            "kernel_ms": round(k_ms, 3), "split_T_ms": round(conv_ms, 3),
            "achieved_tflops": round(flops / (k_ms / 1e3) / 1e12, 3),
            "mixed_solve_s": round(tm, 3), "fp64_solve_s": round(t64, 3), "fp64_iterations": n64,

@@ -108,7 +108,7 @@ constexpr int kLdsWaveWords = 72 * 64;
 // Ladder item: pair p, NB consecutive blocks, a-tiles TA0..TA0+NTA-1,
 // Q in [lo, hi).  Partial Out^T[b][a] of sum_Q B^Q T B^Q^T.
 // The inner (k) dimension runs over S4 = 4 (NT - 1) + R steps of 4, R in
-// {2, 4}: n is padded to a multiple of 8, and with every trip count known at
+// 1..4: n is padded to a multiple of 4, and with every trip count known at
 // compile time one Q slice is a single basic block that the scheduler can
 // interleave (stage 1 of every block is issued before the stage 2 that reads
 // it).  REG keeps the X-form operands in VGPRs instead of the LDS slab.
@@ -351,11 +351,15 @@ __device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& i
   }
 }
 
-// k-step class of the pair: R = 2 when n mod 16 is in 1..8, else 4
+// k-steps of 4 in the last 16-wide tile of the pair: R = ceil((n mod 16) / 4), 1..4
 #define DLPNO_LADDER(NT, NB, NTA, TA0, REG)                                      \
   do {                                                                             \
-    if (rk == 2) ladder_item<F, NT, NB, NTA, TA0, 2, REG>(A, it, lds);             \
-    else ladder_item<F, NT, NB, NTA, TA0, 4, REG>(A, it, lds);                     \
+    switch (rk) {                                                                  \
+      case 1: ladder_item<F, NT, NB, NTA, TA0, 1, REG>(A, it, lds); break;         \
+      case 2: ladder_item<F, NT, NB, NTA, TA0, 2, REG>(A, it, lds); break;         \
+      case 3: ladder_item<F, NT, NB, NTA, TA0, 3, REG>(A, it, lds); break;         \
+      default: ladder_item<F, NT, NB, NTA, TA0, 4, REG>(A, it, lds); break;        \
+    }                                                                              \
   } while (0)
 
 template <typename F>
@@ -363,7 +367,7 @@ __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it
   if (it.kind == ITEM_LADDER) {
     const int n = uni(A.pairs[it.pair].n);
     const int rem = n - 16 * ((n - 1) >> 4);     // 1..16 PNOs in the last tile
-    const int rk = rem <= 8 ? 2 : 4;
+    const int rk = (rem + 3) >> 2;
     switch (it.variant) {
       case 0: DLPNO_LADDER(1, 4, 1, 0, true); break;
       case 1: DLPNO_LADDER(1, 2, 1, 0, true); break;

@@ -1,8 +1,8 @@
 // Split-precision (BF16x2 / FP16x2) ladder and projection contractions.
 //
 // Every operand x is carried as hi + lo with hi = round(x), lo = round(x - hi)
-// in BF16 or FP16, and a product as hi*hi + hi*lo + lo*hi on the 16x16x16
-// MFMA with FP32 accumulation (the lo*lo term is below the FP32 accumulation
+// in BF16 or FP16, and a product as hi*hi + hi*lo + lo*hi on the 16x16x32
+// MFMA (two 16-wide inner tiles per instruction) with FP32 accumulation (the lo*lo term is below the FP32 accumulation
 // error).  This keeps about 16 (BF16) or 22 (FP16) significant bits per
 // operand; the FP64 refinement driver (mixed.hip) recovers full accuracy.
 // FP16 needs power-of-two scaling: per pair for B, per block for the
@@ -14,10 +14,14 @@
 //   B_p     per Q: [a][c], n rows x N16 columns          (symmetric B^Q)
 //   S_pq    [a][c], n_target rows x N16(n_src) columns   (target x source)
 //   T_blk   two copies: T^T [d][c] and T [c][d], n rows x N16 columns
-// The 16x16x16 accumulator keeps output row 4 g + i in register i of lane
-// group g, which is exactly the inner-index order of the next product's B
-// operand, so Y^T = X^T M^T is converted to hi/lo in registers and fed to
-// Out^T = M Y^T without leaving the VGPRs.
+// The accumulator keeps output row 4 g + i in register i of lane group g,
+// which is exactly the inner-index order of a 4-element fragment of the next
+// product's B operand, so Y^T = X^T M^T is converted to hi/lo in registers and
+// fed to Out^T = M Y^T without leaving the VGPRs; two d-tiles make one K = 32
+// operand.  Only the K = 32 shape is used: on gfx950 the K = 16 form takes the
+// same time per instruction, and chaining the two shapes on one accumulator is
+// emitted without the wait states it needs (measured: wrong sums), so odd
+// tiles are padded with zero fragments instead.
 #include "grouped_impl.h"
 #include "plan_internal.h"
 #include "split_internal.h"
@@ -26,6 +30,9 @@ namespace dlpno {
 
 typedef short s4_t __attribute__((ext_vector_type(4)));
 typedef _Float16 h4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 b8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 h8_t __attribute__((ext_vector_type(8)));
+typedef unsigned long long u2_t __attribute__((ext_vector_type(2)));
 
 struct SplitBf16 {
   typedef uint16_t E;
@@ -35,6 +42,11 @@ struct SplitBf16 {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(s4_t, a), __builtin_bit_cast(s4_t, b), c, 0,
                                                      0, 0);
   }
+  // K = 32 from two K = 16 fragments (the same element order in both operands)
+  static __device__ __forceinline__ f4_t mfma32(uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8_t, u2_t{a0, a1}),
+                                                   __builtin_bit_cast(b8_t, u2_t{b0, b1}), c, 0, 0, 0);
+  }
 };
 struct SplitF16 {
   typedef uint16_t E;
@@ -43,6 +55,10 @@ struct SplitF16 {
   static __device__ __forceinline__ f4_t mfma(uint64_t a, uint64_t b, f4_t c) {
     return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(h4_t, a), __builtin_bit_cast(h4_t, b), c, 0, 0,
                                                  0);
+  }
+  static __device__ __forceinline__ f4_t mfma32(uint64_t a0, uint64_t a1, uint64_t b0, uint64_t b1, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8_t, u2_t{a0, a1}),
+                                                  __builtin_bit_cast(h8_t, u2_t{b0, b1}), c, 0, 0, 0);
   }
 };
 
@@ -75,6 +91,15 @@ __device__ __forceinline__ f4_t mfma3(uint64_t ah, uint64_t al, uint64_t bh, uin
   c = S::mfma(ah, bh, c);
   c = S::mfma(ah, bl, c);
   c = S::mfma(al, bh, c);
+  return c;
+}
+// two adjacent 16-wide inner tiles as one K = 32 product (hi*hi + hi*lo + lo*hi)
+template <typename S>
+__device__ __forceinline__ f4_t mfma3x2(uint64_t ah0, uint64_t ah1, uint64_t al0, uint64_t al1, uint64_t bh0,
+                                        uint64_t bh1, uint64_t bl0, uint64_t bl1, f4_t c) {
+  c = S::mfma32(ah0, ah1, bh0, bh1, c);
+  c = S::mfma32(ah0, ah1, bl0, bl1, c);
+  c = S::mfma32(al0, al1, bh0, bh1, c);
   return c;
 }
 
@@ -121,52 +146,87 @@ __device__ __forceinline__ void split_ladder_item(const SplitArgs& A, const Item
 #pragma unroll
       for (int u = 0; u < NTA; ++u) acc[b][t][u] = f4_t{0, 0, 0, 0};
 
-  // B^Q fragments: M[t][kt] = B^Q[16 t + r][16 kt + 4 g .. +3]
-  auto loadM = [&](uint64_t (&Mh)[NT][NT], uint64_t (&Ml)[NT][NT], int Q) {
-    const __amdgpu_buffer_rsrc_t rh = rsrc16(A.B_hi + boff + (size_t)Q * slice, slice);
-    const __amdgpu_buffer_rsrc_t rl = rsrc16(A.B_lo + boff + (size_t)Q * slice, slice);
+  // B^Q fragments: M[t][kt] = B^Q[16 t + r][16 kt + 4 g .. +3].  One slice is
+  // only a few hundred cycles of MFMA work here, so QB slices are loaded per
+  // batch and the next batch is in flight while the current one is used.
+  constexpr int QB = NT == 1 ? 8 : NT == 2 ? 4 : NT == 3 ? 2 : 1;
+  auto loadM = [&](uint64_t (&Mh)[QB][NT][NT], uint64_t (&Ml)[QB][NT][NT], int Q0) {
 #pragma unroll
-    for (int t = 0; t < NT; ++t)
+    for (int q = 0; q < QB; ++q) {
+      // slices past the item's range read as zeros (empty resource)
+      const bool in = Q0 + q < it.hi;
+      const __amdgpu_buffer_rsrc_t rh = rsrc16(A.B_hi + boff + (size_t)(in ? Q0 + q : 0) * slice, in ? slice : 0u);
+      const __amdgpu_buffer_rsrc_t rl = rsrc16(A.B_lo + boff + (size_t)(in ? Q0 + q : 0) * slice, in ? slice : 0u);
 #pragma unroll
-      for (int kt = 0; kt < NT; ++kt) {
-        const uint32_t o = (uint32_t)((16 * t + r) * n16 + 16 * kt + 4 * g);
-        Mh[t][kt] = frag(rh, o);
-        Ml[t][kt] = frag(rl, o);
-      }
+      for (int t = 0; t < NT; ++t)
+#pragma unroll
+        for (int kt = 0; kt < NT; ++kt) {
+          const uint32_t o = (uint32_t)((16 * t + r) * n16 + 16 * kt + 4 * g);
+          Mh[q][t][kt] = frag(rh, o);
+          Ml[q][t][kt] = frag(rl, o);
+        }
+    }
+  };
+  // stage 1 for d-tile td: Y^T[d][a] over the inner index in K = 32 pairs of tiles
+  auto stage1 = [&](const uint64_t (&Mh)[NT][NT], const uint64_t (&Ml)[NT][NT], int b, int td, int u) -> f4_t {
+    f4_t c = f4_t{0, 0, 0, 0};
+#pragma unroll
+    for (int kp = 0; kp + 1 < NT; kp += 2)
+      c = mfma3x2<S>(Ah[b][td][kp], Ah[b][td][kp + 1], Alo[b][td][kp], Alo[b][td][kp + 1], Mh[TA0 + u][kp],
+                     Mh[TA0 + u][kp + 1], Ml[TA0 + u][kp], Ml[TA0 + u][kp + 1], c);
+    if constexpr (NT % 2 == 1)   // odd tail: K = 32 with a zero upper half (never mix MFMA shapes on one accumulator)
+      c = mfma3x2<S>(Ah[b][td][NT - 1], 0, Alo[b][td][NT - 1], 0, Mh[TA0 + u][NT - 1], 0, Ml[TA0 + u][NT - 1], 0, c);
+    return c;
   };
   auto compute = [&](const uint64_t (&Mh)[NT][NT], const uint64_t (&Ml)[NT][NT]) {
+    // d-tiles in pairs: the two stage-1 tiles form one K = 32 operand of stage 2
 #pragma unroll
-    for (int td = 0; td < NT; ++td) {
-      f4_t d1[NB][NTA];
+    for (int tp = 0; tp + 1 < NT; tp += 2) {
+      uint64_t yh[NB][NTA][2], yl[NB][NTA][2];
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
-        for (int u = 0; u < NTA; ++u) {
-          f4_t c = f4_t{0, 0, 0, 0};
+        for (int u = 0; u < NTA; ++u)
 #pragma unroll
-          for (int kt = 0; kt < NT; ++kt) c = mfma3<S>(Ah[b][td][kt], Alo[b][td][kt], Mh[TA0 + u][kt], Ml[TA0 + u][kt], c);
-          d1[b][u] = c;
-        }
+          for (int h = 0; h < 2; ++h) split4<S>(stage1(Mh, Ml, b, tp + h, u), 1.f, yh[b][u][h], yl[b][u][h]);
+#pragma unroll
+      for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int u = 0; u < NTA; ++u)
+#pragma unroll
+          for (int tb = 0; tb < NT; ++tb)
+            acc[b][tb][u] = mfma3x2<S>(Mh[tb][tp], Mh[tb][tp + 1], Ml[tb][tp], Ml[tb][tp + 1], yh[b][u][0],
+                                       yh[b][u][1], yl[b][u][0], yl[b][u][1], acc[b][tb][u]);
+    }
+    if constexpr (NT % 2 == 1) {
+      constexpr int td = NT - 1;
 #pragma unroll
       for (int b = 0; b < NB; ++b)
 #pragma unroll
         for (int u = 0; u < NTA; ++u) {
           uint64_t yh, yl;
-          split4<S>(d1[b][u], 1.f, yh, yl);
+          split4<S>(stage1(Mh, Ml, b, td, u), 1.f, yh, yl);
 #pragma unroll
-          for (int tb = 0; tb < NT; ++tb) acc[b][tb][u] = mfma3<S>(Mh[tb][td], Ml[tb][td], yh, yl, acc[b][tb][u]);
+          for (int tb = 0; tb < NT; ++tb)
+            acc[b][tb][u] = mfma3x2<S>(Mh[tb][td], 0, Ml[tb][td], 0, yh, 0, yl, 0, acc[b][tb][u]);
         }
+    }
+  };
+  auto compute_batch = [&](const uint64_t (&Mh)[QB][NT][NT], const uint64_t (&Ml)[QB][NT][NT], int Q0) {
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+      if (Q0 + q < it.hi) compute(Mh[q], Ml[q]);
       __builtin_amdgcn_sched_barrier(0);
     }
   };
-  uint64_t M0h[NT][NT], M0l[NT][NT], M1h[NT][NT], M1l[NT][NT];
+  uint64_t M0h[QB][NT][NT], M0l[QB][NT][NT], M1h[QB][NT][NT], M1l[QB][NT][NT];
   loadM(M0h, M0l, it.lo);
-  for (int Q = it.lo; Q < it.hi; Q += 2) {
-    if (Q + 1 < it.hi) loadM(M1h, M1l, Q + 1);
-    compute(M0h, M0l);
-    if (Q + 1 >= it.hi) break;
-    if (Q + 2 < it.hi) loadM(M0h, M0l, Q + 2);
-    compute(M1h, M1l);
+  for (int Q = it.lo; Q < it.hi; Q += 2 * QB) {
+    if (Q + QB < it.hi) loadM(M1h, M1l, Q + QB);
+    compute_batch(M0h, M0l, Q);
+    if (Q + QB >= it.hi) break;
+    if (Q + 2 * QB < it.hi) loadM(M0h, M0l, Q + 2 * QB);
+    compute_batch(M1h, M1l, Q + QB);
   }
   const int64_t nn = (int64_t)n * n;
 #pragma unroll
@@ -249,32 +309,44 @@ __device__ __forceinline__ void split_proj_item(const SplitArgs& A, const Item& 
       const __amdgpu_buffer_rsrc_t xrl = rsrc16(xl + toff, (uint32_t)(nq * nq16));
       // rescale Y to the target block's scale with the Fock weight folded in
       const float ysc = -w * tscale[b] / qs;
+      // source d-tiles in pairs (one K = 32 operand of stage 2); every product
+      // is a K = 32 MFMA, absent tiles are zero fragments
 #pragma unroll
-      for (int td = 0; td < 4; ++td) {
-        if (td < NQ) {
-          uint64_t Xh[4], Xl[4];
+      for (int tp = 0; tp < 4; tp += 2) {
+        if (tp < NQ) {
+          uint64_t yh[NT][2], yl[NT][2];
 #pragma unroll
-          for (int kt = 0; kt < 4; ++kt) {
-            if (kt < NQ) {
-              const uint32_t o = (uint32_t)((16 * td + r) * nq16 + 16 * kt + 4 * g);
-              Xh[kt] = frag(xrh, o);
-              Xl[kt] = frag(xrl, o);
-            } else {
-              Xh[kt] = 0;
-              Xl[kt] = 0;
+          for (int h = 0; h < 2; ++h) {
+            const int td = tp + h;
+            uint64_t Xh[4], Xl[4];
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) {
+              if (td < NQ && kt < NQ) {
+                const uint32_t o = (uint32_t)((16 * td + r) * nq16 + 16 * kt + 4 * g);
+                Xh[kt] = frag(xrh, o);
+                Xl[kt] = frag(xrl, o);
+              } else {
+                Xh[kt] = 0;
+                Xl[kt] = 0;
+              }
+            }
+#pragma unroll
+            for (int u = 0; u < NT; ++u) {
+              f4_t c = f4_t{0, 0, 0, 0};
+#pragma unroll
+              for (int kp = 0; kp < 4; kp += 2)
+                if (kp < NQ)
+                  c = mfma3x2<S>(Xh[kp], Xh[kp + 1], Xl[kp], Xl[kp + 1], Mh[u][kp], Mh[u][kp + 1], Ml[u][kp],
+                                 Ml[u][kp + 1], c);
+              split4<S>(c, ysc, yh[u][h], yl[u][h]);
             }
           }
 #pragma unroll
-          for (int u = 0; u < NT; ++u) {
-            f4_t c = f4_t{0, 0, 0, 0};
+          for (int u = 0; u < NT; ++u)
 #pragma unroll
-            for (int kt = 0; kt < 4; ++kt)
-              if (kt < NQ) c = mfma3<S>(Xh[kt], Xl[kt], Mh[u][kt], Ml[u][kt], c);
-            uint64_t yh, yl;
-            split4<S>(c, ysc, yh, yl);
-#pragma unroll
-            for (int tb = 0; tb < NT; ++tb) acc[b][tb][u] = mfma3<S>(Mh[tb][td], Ml[tb][td], yh, yl, acc[b][tb][u]);
-          }
+            for (int tb = 0; tb < NT; ++tb)
+              acc[b][tb][u] = mfma3x2<S>(Mh[tb][tp], Mh[tb][tp + 1], Ml[tb][tp], Ml[tb][tp + 1], yh[u][0], yh[u][1],
+                                         yl[u][0], yl[u][1], acc[b][tb][u]);
         }
       }
     }
