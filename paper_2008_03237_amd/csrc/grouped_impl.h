@@ -230,14 +230,19 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
 
 // ---------------------------------------------------------------------------
 // Projection item: target pair p (NT tiles), NB consecutive blocks, couplings
-// [lo, hi).  Per coupling: M = S_{p,q}; per target block the term
-// -w S_{p,q} op(T_q) S_{p,q}^T.  The source dimension n_q varies per
-// coupling; it is processed in 16-wide chunks (uniform branches per chunk),
-// the padded rows and columns being zeros returned by the range-checked loads.
+// [lo, hi) whose source pairs all have NQ tiles of 16.  Per coupling:
+// M = S_{p,q}; per target block the term -w S_{p,q} op(T_q) S_{p,q}^T.  The
+// source dimension is padded to 16 (zeros from the range-checked loads); with
+// NQ fixed at compile time a coupling is one straight-line block.  A block
+// without a term for this coupling runs with weight 0 and an empty operand
+// range, which keeps the code branch-free.
 // ---------------------------------------------------------------------------
-template <typename F, int NT, int NB>
+template <typename F, int NT, int NB, int NQ>
 __device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
   typedef typename Mfma<F>::V V;
+  constexpr int S16 = 4 * NQ;                 // k-steps of 4 over the padded source index
+  constexpr int SL = NQ * S16;                // LDS slots per term
+  constexpr bool BATCH = NB * SL <= kLdsWaveWords / 64;
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4, pr = Mfma<F>::perm(r);
   const PairDev& Pg = A.pairs[it.pair];
@@ -256,79 +261,63 @@ __device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& i
   for (int e = it.lo; e < it.hi; ++e) {
     const int nq = uni(A.cpl[e].nsrc);
     const int64_t off_S = uni(A.cpl[e].off_S);
-    const int C16 = (nq + 15) >> 4;        // 16-wide chunks of the source index
     // M-form: M[t][s] = S_{p,q}[16t + r][4s + g] = W[(4s + g) n + 16t + r], W = [c][a]
     const __amdgpu_buffer_rsrc_t sr = rsrc(A.S + off_S, (uint32_t)(nq * n));
     const uint32_t mbase = (uint32_t)(g * n + r);
-    F M[NT][16];
+    F M[NT][S16];
 #pragma unroll
-    for (int cc = 0; cc < 4; ++cc) {
-      if (cc < C16) {
+    for (int s = 0; s < S16; ++s)
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-          for (int t = 0; t < NT; ++t)
-            M[t][4 * cc + s4] = Mfma<F>::load(sr, mbase + (uint32_t)(4 * (4 * cc + s4) * n + 16 * t));
-      } else {
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4)
-#pragma unroll
-          for (int t = 0; t < NT; ++t) M[t][4 * cc + s4] = F(0);
-      }
-    }
+      for (int t = 0; t < NT; ++t) M[t][s] = Mfma<F>::load(sr, mbase + (uint32_t)(4 * s * n + 16 * t));
 
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
+    auto load_x = [&](int b, int base_slot) {
       const TermDev& tg = A.terms[(int64_t)e * 4 + it.bslot0 + b];
       const int64_t src_off = uni(tg.src_off);
-      if (src_off < 0) continue;
+      const bool valid = src_off >= 0;
       const int trans = uni(tg.trans);
-      const F mw = F(-uni(tg.w));
-      const __amdgpu_buffer_rsrc_t xr = rsrc(A.T + src_off, (uint32_t)(nq * nq));
-      // X-form of -w op(T_q) into the LDS slab: Al[td][s] = X[4s + g][16 td + perm(r)]
+      const F mw = valid ? F(-uni(tg.w)) : F(0);
+      const __amdgpu_buffer_rsrc_t xr = rsrc(A.T + (valid ? src_off : 0), valid ? (uint32_t)(nq * nq) : 0u);
+      // Al[td][s] = X[4s + g][16 td + perm(r)], X = -w T_q or -w T_q^T
       const uint32_t base = trans ? (uint32_t)(pr * nq + g) : (uint32_t)(g * nq + pr);
       const uint32_t step_s = trans ? 4u : (uint32_t)(4 * nq);
       const uint32_t step_t = trans ? (uint32_t)(16 * nq) : 16u;
 #pragma unroll
-      for (int td = 0; td < 4; ++td) {
-        if (td < C16) {
+      for (int td = 0; td < NQ; ++td)
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc) {
-            if (cc < C16) {
+        for (int s = 0; s < S16; ++s)
+          Al[(base_slot + td * S16 + s) * 64 + lane] =
+              mw * Mfma<F>::load(xr, base + (uint32_t)s * step_s + (uint32_t)td * step_t);
+    };
+    auto compute_x = [&](int b, int base_slot) {
 #pragma unroll
-              for (int s4 = 0; s4 < 4; ++s4) {
-                const int s = 4 * cc + s4;
-                Al[(td * 16 + s) * 64 + lane] = mw * Mfma<F>::load(xr, base + (uint32_t)s * step_s + (uint32_t)td * step_t);
-              }
-            }
-          }
+      for (int td = 0; td < NQ; ++td) {
+        V d1[NT];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) d1[u] = V{0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < S16; ++s) {
+          const F av = Al[(base_slot + td * S16 + s) * 64 + lane];
+#pragma unroll
+          for (int u = 0; u < NT; ++u) d1[u] = Mfma<F>::op(av, M[u][s], d1[u]);
         }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
       }
+    };
+    if constexpr (BATCH) {
 #pragma unroll
-      for (int td = 0; td < 4; ++td) {
-        if (td < C16) {
-          V d1[NT];
+      for (int b = 0; b < NB; ++b) load_x(b, b * SL);
 #pragma unroll
-          for (int u = 0; u < NT; ++u) d1[u] = V{0, 0, 0, 0};
+      for (int b = 0; b < NB; ++b) compute_x(b, b * SL);
+    } else {
 #pragma unroll
-          for (int cc = 0; cc < 4; ++cc) {
-            if (cc < C16) {
-#pragma unroll
-              for (int s4 = 0; s4 < 4; ++s4) {
-                const int s = 4 * cc + s4;
-                const F av = Al[(td * 16 + s) * 64 + lane];
-#pragma unroll
-                for (int u = 0; u < NT; ++u) d1[u] = Mfma<F>::op(av, M[u][s], d1[u]);
-              }
-            }
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int tb = 0; tb < NT; ++tb)
-#pragma unroll
-              for (int u = 0; u < NT; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
-        }
+      for (int b = 0; b < NB; ++b) {
+        load_x(b, 0);
+        compute_x(b, 0);
       }
     }
   }
@@ -387,18 +376,25 @@ __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it
       default: break;
     }
   } else {
+    // variant = 4 * (tile variant) + (source tiles - 1)
+#define DLPNO_PROJ(V, NT, NB)                                                        \
+  case 4 * V + 0: proj_item<F, NT, NB, 1>(A, it, lds); break;                        \
+  case 4 * V + 1: proj_item<F, NT, NB, 2>(A, it, lds); break;                        \
+  case 4 * V + 2: proj_item<F, NT, NB, 3>(A, it, lds); break;                        \
+  case 4 * V + 3: proj_item<F, NT, NB, 4>(A, it, lds); break;
     switch (it.variant) {
-      case 0: proj_item<F, 1, 4>(A, it, lds); break;
-      case 1: proj_item<F, 1, 2>(A, it, lds); break;
-      case 2: proj_item<F, 1, 1>(A, it, lds); break;
-      case 3: proj_item<F, 2, 4>(A, it, lds); break;
-      case 4: proj_item<F, 2, 2>(A, it, lds); break;
-      case 5: proj_item<F, 2, 1>(A, it, lds); break;
-      case 6: proj_item<F, 3, 2>(A, it, lds); break;
-      case 7: proj_item<F, 3, 1>(A, it, lds); break;
-      case 8: proj_item<F, 4, 1>(A, it, lds); break;
+      DLPNO_PROJ(0, 1, 4)
+      DLPNO_PROJ(1, 1, 2)
+      DLPNO_PROJ(2, 1, 1)
+      DLPNO_PROJ(3, 2, 4)
+      DLPNO_PROJ(4, 2, 2)
+      DLPNO_PROJ(5, 2, 1)
+      DLPNO_PROJ(6, 3, 2)
+      DLPNO_PROJ(7, 3, 1)
+      DLPNO_PROJ(8, 4, 1)
       default: break;
     }
+#undef DLPNO_PROJ
   }
 }
 #undef DLPNO_LADDER

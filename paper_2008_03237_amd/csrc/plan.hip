@@ -176,14 +176,16 @@ dlpno_status build_schedule(dlpno_plan* P) {
     if (e1 > e0) {
       const int pv = P->tune.proj_variant[nt - 1];
       const ProjVariant U = kProjVariants[pv];
-      // chunk the coupling list by cost
+      // chunk the coupling list by cost, never across a change of the source
+      // tile count (one compiled body per count)
       std::vector<std::pair<int64_t, int64_t>> ranges;
       double acc = 0.0;
       int64_t start = e0;
       for (int64_t e = e0; e < e1; ++e) {
         const int nq = P->cpl_h[e].nsrc;
-        acc += (double)U.nb * (nt * ((nq + 15) / 16) + nt * nt) * ((nq + 3) / 4);
-        if (acc >= target && e + 1 < e1) {
+        acc += (double)U.nb * (nt * ((nq + 15) / 16) + nt * nt) * 4 * ((nq + 15) / 16);
+        const bool cls_end = e + 1 < e1 && (P->cpl_h[e + 1].nsrc + 15) / 16 != (nq + 15) / 16;
+        if ((acc >= target || cls_end) && e + 1 < e1) {
           ranges.push_back({start, e + 1});
           start = e + 1;
           acc = 0.0;
@@ -193,16 +195,14 @@ dlpno_status build_schedule(dlpno_plan* P) {
       nP[p] = (int)ranges.size();
       for (size_t c = 0; c < ranges.size(); ++c) {
         double cost = 0.0;
-        for (int64_t e = ranges[c].first; e < ranges[c].second; ++e) {
-          const int nq = P->cpl_h[e].nsrc;
-          cost += (nt * ((nq + 15) / 16) + nt * nt) * ((nq + 3) / 4);
-        }
+        const int cq = (P->cpl_h[ranges[c].first].nsrc + 15) / 16;
+        for (int64_t e = ranges[c].first; e < ranges[c].second; ++e) cost += (nt * cq + nt * nt) * 4 * cq;
         for (int b0 = 0; b0 < pr.nblk;) {
           const int v = pick_proj(nt, std::min(U.nb, pr.nblk - b0));
           if (v < 0) return fail(DLPNO_ERR_INVALID_ARG, "no projection tile variant for this block group");
           Item it{};
           it.kind = ITEM_PROJ;
-          it.variant = v;
+          it.variant = v * 4 + (cq - 1);
           it.pair = p;
           it.bslot0 = b0;
           it.slot = nL[p] + (int)c;
@@ -465,6 +465,26 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
         P->flops_proj += 2.0 * pd.n * (double)nq * (pd.n + nq);
         ++P->n_terms;
       }
+    }
+  }
+  // device tables: within each target row, couplings ordered by the tile
+  // count of the source pair (stable), so projection items are homogeneous
+  for (int p = 0; p < npairs; ++p) {
+    const int64_t e0 = P->rowptr_h[p], e1 = P->rowptr_h[p + 1];
+    std::vector<int64_t> ord;
+    for (int64_t e = e0; e < e1; ++e) ord.push_back(e);
+    std::stable_sort(ord.begin(), ord.end(), [&](int64_t x, int64_t y) {
+      return (P->cpl_h[x].nsrc + 15) / 16 < (P->cpl_h[y].nsrc + 15) / 16;
+    });
+    std::vector<CplDev> c2;
+    std::vector<TermDev> t2;
+    for (int64_t e : ord) {
+      c2.push_back(P->cpl_h[e]);
+      for (int b = 0; b < 4; ++b) t2.push_back(P->terms_h[(size_t)e * 4 + b]);
+    }
+    for (int64_t k = 0; k < (int64_t)ord.size(); ++k) {
+      P->cpl_h[e0 + k] = c2[k];
+      for (int b = 0; b < 4; ++b) P->terms_h[(size_t)(e0 + k) * 4 + b] = t2[(size_t)k * 4 + b];
     }
   }
   // ---- device ----

@@ -392,7 +392,7 @@ __device__ __forceinline__ void split_run_item(const SplitArgs& A, const Item& i
       default: break;
     }
   } else {
-    switch (it.variant) {
+    switch (it.variant >> 2) {     // variant = 4 * (tile variant) + (source tiles - 1)
       case 0: split_proj_item<S, 1, 4>(A, it); break;
       case 1: split_proj_item<S, 1, 2>(A, it); break;
       case 2: split_proj_item<S, 1, 1>(A, it); break;
