@@ -4,7 +4,9 @@
 // and projection variant of that class on the plan's own workload (the other
 // classes keep their current choice), then the queue granularity, and keeps
 // the fastest.  Timings are HIP events around the grouped kernel on the
-// caller's stream, best of three launches.
+// caller's stream, best of three launches; a candidate replaces the current
+// choice only when it is faster by more than kMinGain, so that run-to-run
+// timing noise does not flip the schedule between otherwise equal runs.
 #include "plan_internal.h"
 
 #include <algorithm>
@@ -12,6 +14,8 @@
 #include <string>
 
 using namespace dlpno;
+
+static constexpr float kMinGain = 0.005f;
 
 static float time_grouped(dlpno_plan* P, const double* T, hipStream_t s, int reps) {
   hipEvent_t a, b;
@@ -68,7 +72,7 @@ extern "C" dlpno_status dlpno_autotune(dlpno_plan* P, const double* T, double* R
       const float t = time_grouped(P, T, s, 3);
       snprintf(buf, sizeof buf, "  ladder nt=%d variant %d: %.3f ms\n", nt, v, t);
       log += buf;
-      if (t > 0 && t < best) best = t;
+      if (t > 0 && t < best * (1.f - kMinGain)) best = t;
       else P->tune.ladder_variant[nt - 1] = keep;
     }
     for (int v = 0; v < kNumProjVariants; ++v) {
@@ -79,7 +83,7 @@ extern "C" dlpno_status dlpno_autotune(dlpno_plan* P, const double* T, double* R
       const float t = time_grouped(P, T, s, 3);
       snprintf(buf, sizeof buf, "  projection nt=%d variant %d: %.3f ms\n", nt, v, t);
       log += buf;
-      if (t > 0 && t < best) best = t;
+      if (t > 0 && t < best * (1.f - kMinGain)) best = t;
       else P->tune.proj_variant[nt - 1] = keep;
     }
   }
@@ -92,7 +96,7 @@ extern "C" dlpno_status dlpno_autotune(dlpno_plan* P, const double* T, double* R
     const float t = time_grouped(P, T, s, 3);
     snprintf(buf, sizeof buf, "  items/wave %.0f: %.3f ms\n", x, t);
     log += buf;
-    if (t > 0 && t < best) best = t;
+    if (t > 0 && t < best * (1.f - kMinGain)) best = t;
     else P->tune.items_per_wave = keep;
   }
   if ((st = apply(P, s)) != DLPNO_OK) return st;
