@@ -43,6 +43,8 @@
 #pragma once
 #include "internal.h"
 
+#include <type_traits>
+
 namespace dlpno {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
@@ -77,6 +79,58 @@ struct Mfma<float> {
   static __device__ __forceinline__ int perm(int r) { return ((r & 3) << 2) | (r >> 2); }
   static __device__ __forceinline__ int orow(int g, int i) { return 4 * g + i; }
 };
+
+// FP64 row strips.  The four-block 4x4x4 FP64 MFMA (lane 16 g + 4 b + v:
+// A[m = v][k = g], B[k = g][n = v], D[m = g][n = v] of block b) does a quarter
+// of the work of the 16x16x4 one in less than a quarter of its time on
+// gfx950.  Given the 16x16x4 B operand register (k in g, 16 columns in r =
+// 4 b + v) and an A operand whose four blocks all hold rows 4 j .. 4 j + 3 of
+// the 16x16x4 A operand, it returns rows 4 j .. 4 j + 3 of the 16x16x4 product
+// in one register laid out like register j of the 16x16x4 accumulator (row
+// 4 j + g, column r).  Strips made only of padded rows are not issued, so the
+// row dimensions of both sandwich stages are padded to 4 instead of 16.  The
+// instruction has no operand broadcast for FP64, so the replicated A operand
+// is built with DPP row shifts (bcast_strip) or read from LDS with a
+// lane-permuted address (strip_lane).
+template <typename F>
+struct Strips : std::false_type {};
+template <>
+struct Strips<double> : std::true_type {};
+__device__ __forceinline__ double mfma_strip(double a, double b, double c) {
+  return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
+}
+// lane of a 16x16x4 operand register that holds what lane `lane` needs as the
+// A operand of strip j: same g and v, block j
+__device__ __forceinline__ int strip_lane(int lane, int j) { return (lane & 0x33) | (j << 2); }
+// every block of every row of 16 lanes receives block J of that row:
+// row_shl:n reads lane + n, row_shr:n reads lane - n (within the row); the
+// bank mask restricts each copy to one block
+template <int J, int B>
+__device__ __forceinline__ void bcast_block(int& lo, int& hi, int lo0, int hi0) {
+  if constexpr (B != J) {
+    constexpr int ctrl = B < J ? 0x100 + 4 * (J - B) : 0x110 + 4 * (B - J);
+    lo = __builtin_amdgcn_update_dpp(lo, lo0, ctrl, 0xf, 1 << B, false);
+    hi = __builtin_amdgcn_update_dpp(hi, hi0, ctrl, 0xf, 1 << B, false);
+  }
+}
+template <int J>
+__device__ __forceinline__ double bcast_strip(double x) {
+  const int lo0 = __double2loint(x), hi0 = __double2hiint(x);
+  int lo = lo0, hi = hi0;
+  bcast_block<J, 0>(lo, hi, lo0, hi0);
+  bcast_block<J, 1>(lo, hi, lo0, hi0);
+  bcast_block<J, 2>(lo, hi, lo0, hi0);
+  bcast_block<J, 3>(lo, hi, lo0, hi0);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double bcast_strip(double x, int j) {
+  switch (j) {
+    case 0: return bcast_strip<0>(x);
+    case 1: return bcast_strip<1>(x);
+    case 2: return bcast_strip<2>(x);
+    default: return bcast_strip<3>(x);
+  }
+}
 
 // Wave-uniform copies of descriptor fields.  Descriptors are read with vector
 // loads (the kernel also writes memory, so they cannot go through the scalar
@@ -125,6 +179,11 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
   const int64_t off_B = uni(Pg.off_B);
   const uint32_t nn = (uint32_t)n * (uint32_t)n;
   F* Al = reinterpret_cast<F*>(lds + (size_t)(threadIdx.x >> 6) * kLdsWaveWords);
+  // FP64 with a partial last tile (R < 4 k-steps in it): the last d-tile of
+  // stage 1 and the last b-tile of stage 2 run as R row strips; the X operands
+  // of that d-tile are then also kept in the LDS slab, where the strips read
+  // them at permuted lanes
+  constexpr bool STRIPS = Strips<F>::value && R < 4;
   F Ar[REG ? NB : 1][REG ? NT : 1][REG ? S4 : 1];
 
   // X-form operands of the NB amplitude blocks, once per item
@@ -139,13 +198,15 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
       for (int s = 0; s < S4; ++s) {
         const F v = Mfma<F>::load(tr, base + (uint32_t)(4 * s * n + 16 * td));
         if constexpr (REG) Ar[b][td][s] = v;
-        else Al[((b * NT + td) * S4 + s) * 64 + lane] = v;
+        if (!REG || (STRIPS && td == NT - 1)) Al[((b * NT + td) * S4 + s) * 64 + lane] = v;
       }
   }
   auto aop = [&](int b, int td, int s) -> F {
     if constexpr (REG) return Ar[b][td][s];
     else return Al[((b * NT + td) * S4 + s) * 64 + lane];
   };
+  // A operand of row strip i of the last d-tile: block i of the X operand
+  auto aop_strip = [&](int b, int s, int i) -> F { return Al[((b * NT + NT - 1) * S4 + s) * 64 + strip_lane(lane, i)]; };
 
   V acc[NB][NT][NTA];
 #pragma unroll
@@ -177,9 +238,19 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
         for (int u = 0; u < NTA; ++u) d1[b][u] = V{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < S4; ++s) {
-          const F av = aop(b, td, s);
+          if (STRIPS && td == NT - 1) {
+            // strip i = k-step 4 td + i of stage 2; only the R strips with PNO rows
 #pragma unroll
-          for (int u = 0; u < NTA; ++u) d1[b][u] = Mfma<F>::op(av, M[TA0 + u][s], d1[b][u]);
+            for (int i = 0; i < R; ++i) {
+              const F av = aop_strip(b, s, i);
+#pragma unroll
+              for (int u = 0; u < NTA; ++u) d1[b][u][i] = mfma_strip(av, M[TA0 + u][s], d1[b][u][i]);
+            }
+          } else {
+            const F av = aop(b, td, s);
+#pragma unroll
+            for (int u = 0; u < NTA; ++u) d1[b][u] = Mfma<F>::op(av, M[TA0 + u][s], d1[b][u]);
+          }
         }
       }
       // stage 2: Out^T[b][a] += sum_d B^Q[b][d] Y^T[d][a] over this d-tile
@@ -189,10 +260,22 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
 #pragma unroll
           for (int b = 0; b < NB; ++b)
 #pragma unroll
-            for (int tb = 0; tb < NT; ++tb)
+            for (int tb = 0; tb < (STRIPS ? NT - 1 : NT); ++tb)
 #pragma unroll
               for (int u = 0; u < NTA; ++u)
                 acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[b][u][i], acc[b][tb][u]);
+          if constexpr (STRIPS) {
+            // last b-tile: output strip j holds rows 16 (NT - 1) + 4 j + g
+#pragma unroll
+            for (int j = 0; j < R; ++j) {
+              const F mv = bcast_strip(M[NT - 1][4 * td + i], j);
+#pragma unroll
+              for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int u = 0; u < NTA; ++u)
+                  acc[b][NT - 1][u][j] = mfma_strip(mv, d1[b][u][i], acc[b][NT - 1][u][j]);
+            }
+          }
         }
       }
       // keep each d-tile in its own scheduling region (bounded live ranges)

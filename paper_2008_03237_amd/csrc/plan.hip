@@ -89,7 +89,15 @@ dlpno_status upload(T** p, const std::vector<T>& h, const char* what, hipStream_
 // ---------------------------------------------------------------------------
 namespace dlpno {
 
-int ladder_mfma_per_q(int nt, int nta, int s4) { return 2 * nt * nta * s4; }
+// Work of one ladder item per auxiliary function and block, in 16x16x4 MFMA
+// times: both stages issue nt x nta x s4 of them.  In FP64 a partial last
+// tile (r = s4 - 4 (nt - 1) < 4 k-steps in it) runs as r row strips of the
+// four-block 4x4x4 MFMA, each about 0.22 of a 16x16x4 instruction.
+double ladder_mfma_per_q(int nt, int nta, int s4, bool strips) {
+  const int r = s4 - 4 * (nt - 1);
+  const double last = strips && r < 4 ? 0.22 * r : 1.0;
+  return 2.0 * nta * s4 * (nt - 1 + last);
+}
 
 // largest compiled variant with this tile shape handling at most maxnb blocks
 int pick_ladder(int nt, int nta, int maxnb) {
@@ -117,6 +125,7 @@ int pick_proj(int nt, int maxnb) {
 
 dlpno_status build_schedule(dlpno_plan* P) {
   const int npairs = P->n_pairs;
+  const bool strips = P->opt.precision == DLPNO_FP64;
   std::vector<int> nL(npairs, 0), nP(npairs, 0);
   struct Cand { Item it; double cost; };
   std::vector<Cand> cand;
@@ -126,7 +135,7 @@ dlpno_status build_schedule(dlpno_plan* P) {
     const PairDev& pr = P->pairs_h[p];
     if (pr.nblk == 0) continue;
     const int nt = (pr.n + 15) / 16, s4 = (pr.n + 3) / 4;
-    total += (double)pr.m * pr.nblk * ladder_mfma_per_q(nt, nt, s4);
+    total += (double)pr.m * pr.nblk * ladder_mfma_per_q(nt, nt, s4, strips);
     for (int64_t e = P->rowptr_h[p]; e < P->rowptr_h[p + 1]; ++e) {
       const int nq = P->cpl_h[e].nsrc;
       const int ntq = (nq + 15) / 16, s4q = (nq + 3) / 4;
@@ -146,7 +155,7 @@ dlpno_status build_schedule(dlpno_plan* P) {
     // tile shape for the remainder
     const int lv = P->tune.ladder_variant[nt - 1];
     const LadderVariant V = kLadderVariants[lv];
-    const double per_q = (double)V.nb * ladder_mfma_per_q(V.nt, V.nta, s4);
+    const double per_q = (double)V.nb * ladder_mfma_per_q(V.nt, V.nta, s4, strips);
     int chunks = (int)std::ceil(per_q * pr.m / target);
     chunks = std::max(1, std::min(chunks, pr.m));
     nL[p] = chunks;
@@ -166,7 +175,7 @@ dlpno_status build_schedule(dlpno_plan* P) {
           it.ta0 = ta0;
           it.lo = lo;
           it.hi = hi;
-          cand.push_back({it, (double)(hi - lo) * W.nb * ladder_mfma_per_q(W.nt, W.nta, s4)});
+          cand.push_back({it, (double)(hi - lo) * W.nb * ladder_mfma_per_q(W.nt, W.nta, s4, strips)});
         }
         b0 += W.nb;
       }
