@@ -194,8 +194,10 @@ dlpno_status dlpno_autotune(dlpno_plan* plan, const double* T, double* R, void* 
 /* Kernel timing: when enabled, residual/iterate record HIP events around the
  * phases on the call's stream (graphs are bypassed) and dlpno_phase_times
  * returns the accumulated milliseconds and launch counts of:
- *   0 grouped ladder+projection kernel, 1 finish/update, 2 energy reduction,
- *   3 DIIS, 4 precision conversion. */
+ *   0 grouped kernel over the ladder items, 1 finish/update, 2 energy
+ *   reduction, 3 DIIS, 4 precision conversion, 5 grouped kernel over the
+ *   projection items (in the split precisions one launch covers both kinds
+ *   and is counted under 0). */
 dlpno_status dlpno_set_profiling(dlpno_plan* plan, int32_t enable);
 dlpno_status dlpno_phase_times(const dlpno_plan* plan, double* ms, int64_t* launches, int32_t n);
 

@@ -3,8 +3,9 @@
 
 namespace dlpno {
 
-hipError_t launch_grouped_f64(const GroupedArgs<double>& a, int workers, hipStream_t s) {
-  hipLaunchKernelGGL(grouped_kernel<double>, dim3(workers), dim3(256), 0, s, a);
+hipError_t launch_grouped_f64(const GroupedArgs<double>& a, int kind, int workers, hipStream_t s) {
+  if (kind == ITEM_LADDER) hipLaunchKernelGGL((grouped_kernel<double, ITEM_LADDER>), dim3(workers), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL((grouped_kernel<double, ITEM_PROJ>), dim3(workers), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -321,7 +321,7 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
 // range, which keeps the code branch-free.
 // ---------------------------------------------------------------------------
 template <typename F, int NT, int NB, int NQ>
-__device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
+__device__ __forceinline__ void proj_item_direct(const GroupedArgs<F>& A, const Item& it, double* lds) {
   typedef typename Mfma<F>::V V;
   constexpr int S16 = 4 * NQ;                 // k-steps of 4 over the padded source index
   constexpr int SL = NQ * S16;                // LDS slots per term
@@ -423,6 +423,170 @@ __device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& i
   }
 }
 
+// Pipelined projection item: the same contractions as proj_item_direct, with
+// the loads of the next (coupling, block) unit issued before the current unit
+// is contracted, so that one wave per SIMD hides its own memory latency.
+// Per coupling the descriptors of the coupling after next are read, the
+// next coupling's S operand is loaded into Mn during the last block, and the
+// source amplitudes of the next unit are loaded into Xn; Xn is weighted and
+// written to the LDS slab at the start of its unit.
+template <typename F, int NT, int NB, int NQ>
+__device__ __forceinline__ void proj_item_pipelined(const GroupedArgs<F>& A, const Item& it, double* lds) {
+  typedef typename Mfma<F>::V V;
+  constexpr int S16 = 4 * NQ;
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4, pr = Mfma<F>::perm(r);
+  const PairDev& Pg = A.pairs[it.pair];
+  const int n = uni(Pg.n);
+  const int blk0 = uni(Pg.blk0);
+  F* Al = reinterpret_cast<F*>(lds + (size_t)(threadIdx.x >> 6) * kLdsWaveWords);
+  const uint32_t mbase = (uint32_t)(g * n + r);
+
+  // Descriptors of one coupling packed in one VGPR: lane l holds dword l of
+  // the coupling record (lanes 0..3) followed by its four term records (lanes
+  // 4..27); fields are read with readlane where they are used.
+  static_assert(sizeof(CplDev) == 16 && sizeof(TermDev) == 24, "descriptor layout");
+  auto load_desc = [&](int e) -> int32_t {
+    const int32_t* cw = reinterpret_cast<const int32_t*>(A.cpl + e);
+    const int32_t* tw = reinterpret_cast<const int32_t*>(A.terms + (int64_t)e * 4);
+    int32_t v = 0;
+    if (lane < 4) v = cw[lane];
+    else if (lane < 28) v = tw[lane - 4];
+    return v;
+  };
+  auto rd32 = [](int32_t d, int k) -> int32_t { return __builtin_amdgcn_readlane(d, k); };
+  auto rd64 = [](int32_t d, int k) -> int64_t {
+    return (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane(d, k + 1) << 32) |
+                     (uint32_t)__builtin_amdgcn_readlane(d, k));
+  };
+  const int tb0 = 4 + 6 * it.bslot0;            // dword of the item's first term
+  auto d_nq = [&](int32_t d) { return rd32(d, 1); };
+  auto d_offS = [&](int32_t d) { return rd64(d, 2); };
+  auto d_src = [&](int32_t d, int b) { return rd64(d, tb0 + 6 * b); };
+  auto d_w = [&](int32_t d, int b) { return __builtin_bit_cast(double, rd64(d, tb0 + 6 * b + 2)); };
+  auto d_trans = [&](int32_t d, int b) { return rd32(d, tb0 + 6 * b + 4); };
+
+  // M-form of S_{p,q}: M[t][s] = W[(4s + g) n + 16t + r], W = [c][a]; an
+  // empty resource (live = false) makes every load return 0
+  auto load_M = [&](F (&M)[NT][S16], int32_t d, bool live) {
+    const int nq = d_nq(d);
+    const __amdgpu_buffer_rsrc_t sr = rsrc(A.S + d_offS(d), live ? (uint32_t)(nq * n) : 0u);
+#pragma unroll
+    for (int s = 0; s < S16; ++s)
+#pragma unroll
+      for (int t = 0; t < NT; ++t) M[t][s] = Mfma<F>::load(sr, mbase + (uint32_t)(4 * s * n + 16 * t));
+  };
+  // X-form of the source block of term b: X[4s + g][16 td + perm(r)], X = T_q or T_q^T
+  auto load_X = [&](F (&X)[NQ][S16], int32_t d, int b, bool live) {
+    const int64_t src = d_src(d, b);
+    const bool valid = live && src >= 0;
+    const int nq = d_nq(d);
+    const __amdgpu_buffer_rsrc_t xr = rsrc(A.T + (valid ? src : 0), valid ? (uint32_t)(nq * nq) : 0u);
+    const int trans = d_trans(d, b);
+    const uint32_t base = trans ? (uint32_t)(pr * nq + g) : (uint32_t)(g * nq + pr);
+    const uint32_t step_s = trans ? 4u : (uint32_t)(4 * nq);
+    const uint32_t step_t = trans ? (uint32_t)(16 * nq) : 16u;
+#pragma unroll
+    for (int td = 0; td < NQ; ++td)
+#pragma unroll
+      for (int s = 0; s < S16; ++s) X[td][s] = Mfma<F>::load(xr, base + (uint32_t)s * step_s + (uint32_t)td * step_t);
+  };
+  // residual gets -w S X S^T; a block without a term for this coupling gets weight 0
+  auto store_X = [&](const F (&X)[NQ][S16], int32_t d, int b) {
+    const F mw = d_src(d, b) >= 0 ? F(-d_w(d, b)) : F(0);
+#pragma unroll
+    for (int td = 0; td < NQ; ++td)
+#pragma unroll
+      for (int s = 0; s < S16; ++s) Al[(td * S16 + s) * 64 + lane] = mw * X[td][s];
+  };
+
+  V acc[NB][NT][NT];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) acc[b][t][u] = V{0, 0, 0, 0};
+
+  auto compute = [&](const F (&M)[NT][S16], int b) {
+#pragma unroll
+    for (int td = 0; td < NQ; ++td) {
+      V d1[NT];
+#pragma unroll
+      for (int u = 0; u < NT; ++u) d1[u] = V{0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < S16; ++s) {
+        const F av = Al[(td * S16 + s) * 64 + lane];
+#pragma unroll
+        for (int u = 0; u < NT; ++u) d1[u] = Mfma<F>::op(av, M[u][s], d1[u]);
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+          for (int u = 0; u < NT; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
+    }
+  };
+
+  // prologue: descriptors of the first two couplings, operands of the first unit
+  const int last = it.hi - 1;
+  int32_t dc = load_desc(it.lo);
+  int32_t dn = load_desc(it.lo + 1 <= last ? it.lo + 1 : last);
+  F M[NT][S16], Mn[NT][S16], Xn[NQ][S16];
+  load_M(M, dc, true);
+  load_X(Xn, dc, 0, true);
+  for (int e = it.lo; e <= last; ++e) {
+    const bool more = e < last;
+    const int32_t dnn = load_desc(e + 2 <= last ? e + 2 : last);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      store_X(Xn, dc, b);
+      if (b + 1 < NB) {
+        load_X(Xn, dc, b + 1, true);
+      } else {
+        load_M(Mn, dn, more);
+        load_X(Xn, dn, 0, more);
+      }
+      compute(M, b);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int s = 0; s < S16; ++s) M[t][s] = Mn[t][s];
+    dc = dn;
+    dn = dnn;
+  }
+
+  const int64_t nn = (int64_t)n * n;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    double* dst = A.ws + uni(A.blocks[blk0 + it.bslot0 + b].off_ws) + (int64_t)it.slot * nn;
+#pragma unroll
+    for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+      for (int u = 0; u < NT; ++u) {
+        const int a = 16 * u + r;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int bb = 16 * tb + Mfma<F>::orow(g, i);
+          if (a < n && bb < n) dst[bb * n + a] = (double)acc[b][tb][u][i];
+        }
+      }
+  }
+}
+
+// Projection item: pipelined where its registers (accumulators, two S
+// operands, one block of source amplitudes, the stage-1 product; counted in
+// operands) fit without spilling, direct otherwise.
+template <typename F, int NT, int NB, int NQ>
+__device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
+  constexpr int kRegs = 4 * NB * NT * NT + 2 * NT * 4 * NQ + 4 * NQ * NQ + 4 * NT;
+  if constexpr (kRegs <= 170) proj_item_pipelined<F, NT, NB, NQ>(A, it, lds);
+  else proj_item_direct<F, NT, NB, NQ>(A, it, lds);
+}
+
 // k-steps of 4 in the last 16-wide tile of the pair: R = ceil((n mod 16) / 4), 1..4
 #define DLPNO_LADDER(NT, NB, NTA, TA0, REG)                                      \
   do {                                                                             \
@@ -434,9 +598,9 @@ __device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& i
     }                                                                              \
   } while (0)
 
-template <typename F>
+template <typename F, int KIND>
 __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
-  if (it.kind == ITEM_LADDER) {
+  if constexpr (KIND == ITEM_LADDER) {
     const int n = uni(A.pairs[it.pair].n);
     const int rem = n - 16 * ((n - 1) >> 4);     // 1..16 PNOs in the last tile
     const int rk = (rem + 3) >> 2;
@@ -472,7 +636,11 @@ __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it
       DLPNO_PROJ(3, 2, 4)
       DLPNO_PROJ(4, 2, 2)
       DLPNO_PROJ(5, 2, 1)
-      DLPNO_PROJ(6, 3, 2)
+      // three target tiles, two blocks: up to three source tiles (the
+      // schedule gives four-tile sources one block per item)
+      case 4 * 6 + 0: proj_item<F, 3, 2, 1>(A, it, lds); break;
+      case 4 * 6 + 1: proj_item<F, 3, 2, 2>(A, it, lds); break;
+      case 4 * 6 + 2: proj_item<F, 3, 2, 3>(A, it, lds); break;
       DLPNO_PROJ(7, 3, 1)
       DLPNO_PROJ(8, 4, 1)
       default: break;
@@ -482,7 +650,9 @@ __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it
 }
 #undef DLPNO_LADDER
 
-template <typename F>
+// One launch processes the items of one kind (KIND), so that the ladder and
+// projection bodies are register-allocated separately.
+template <typename F, int KIND>
 __global__ __launch_bounds__(256) void grouped_kernel(GroupedArgs<F> A) {
   __shared__ double lds[4 * kLdsWaveWords];
   const int lane = threadIdx.x & 63;
@@ -501,7 +671,7 @@ __global__ __launch_bounds__(256) void grouped_kernel(GroupedArgs<F> A) {
     it.ta0 = uni(ig.ta0);
     it.lo = uni(ig.lo);
     it.hi = uni(ig.hi);
-    run_item<F>(A, it, lds);
+    run_item<F, KIND>(A, it, lds);
   }
 }
 

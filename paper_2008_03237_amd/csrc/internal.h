@@ -79,8 +79,9 @@ struct GroupedArgs {
 };
 
 // kernels.hip
-hipError_t launch_grouped_f64(const GroupedArgs<double>& a, int workers, hipStream_t s);
-hipError_t launch_grouped_f32(const GroupedArgs<float>& a, int workers, hipStream_t s);
+// kind: ITEM_LADDER or ITEM_PROJ; every item of `a` must be of that kind
+hipError_t launch_grouped_f64(const GroupedArgs<double>& a, int kind, int workers, hipStream_t s);
+hipError_t launch_grouped_f32(const GroupedArgs<float>& a, int kind, int workers, hipStream_t s);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);
 
 // elementwise.hip

@@ -206,8 +206,11 @@ dlpno_status build_schedule(dlpno_plan* P) {
         double cost = 0.0;
         const int cq = (P->cpl_h[ranges[c].first].nsrc + 15) / 16;
         for (int64_t e = ranges[c].first; e < ranges[c].second; ++e) cost += (nt * cq + nt * nt) * 4 * cq;
+        // three target tiles with four source tiles: one block per item (two
+        // blocks' accumulators and operands do not fit the registers)
+        const int nbmax = nt == 3 && cq == 4 ? 1 : U.nb;
         for (int b0 = 0; b0 < pr.nblk;) {
-          const int v = pick_proj(nt, std::min(U.nb, pr.nblk - b0));
+          const int v = pick_proj(nt, std::min(nbmax, pr.nblk - b0));
           if (v < 0) return fail(DLPNO_ERR_INVALID_ARG, "no projection tile variant for this block group");
           Item it{};
           it.kind = ITEM_PROJ;
@@ -237,15 +240,22 @@ dlpno_status build_schedule(dlpno_plan* P) {
     }
   }
   P->ws_elems = ws;
-  // longest first; ties by pair for a deterministic order
-  std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) { return a.cost > b.cost; });
+  // ladder items, then projection items (one queue and one launch each);
+  // longest first within a kind, ties by pair for a deterministic order
+  std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) {
+    if (a.it.kind != b.it.kind) return a.it.kind == ITEM_LADDER;
+    return a.cost > b.cost;
+  });
   P->items_h.clear();
   P->items_h.reserve(cand.size());
   double maxc = 0.0;
+  int nl = 0;
   for (auto& c : cand) {
     P->items_h.push_back(c.it);
     maxc = std::max(maxc, c.cost);
+    nl += c.it.kind == ITEM_LADDER;
   }
+  P->n_ladder_items = nl;
   P->max_item_mfma = maxc;
   return DLPNO_OK;
 }
@@ -655,24 +665,38 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec) 
       return e;
     phase_end(P, s);
   }
-  if ((e = launch_zero_i32(P->d_counter, 1, s)) != hipSuccess) return e;
-  phase_begin(P, 0, s);
-  if (prec == DLPNO_FP32) {
-    GroupedArgs<float> a{P->d_items, (int32_t)P->items_h.size(), P->d_counter, P->d_pairs, P->d_blocks,
-                         P->d_cpl, P->d_terms, P->B32, P->S32, P->T32, P->d_ws};
-    e = launch_grouped_f32(a, P->workers, s);
-  } else if (is_split(prec)) {
+  if ((e = launch_zero_i32(P->d_counter, 2, s)) != hipSuccess) return e;
+  const int32_t nl = P->n_ladder_items, np = (int32_t)P->items_h.size() - nl;
+  if (is_split(prec)) {
+    phase_begin(P, 0, s);
     SplitArgs a{P->d_items, (int32_t)P->items_h.size(), P->d_counter, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
                 P->d_pair_boff, P->d_pair_bscale, P->d_blk_toff, P->d_blk_tscale, P->d_cpl_soff, P->Bs_hi, P->Bs_lo,
                 P->Ss_hi, P->Ss_lo, P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo, P->d_ws};
     e = launch_split_grouped(a, prec == DLPNO_FP16X2, P->workers, s);
-  } else {
-    GroupedArgs<double> a{P->d_items, (int32_t)P->items_h.size(), P->d_counter, P->d_pairs, P->d_blocks,
-                          P->d_cpl, P->d_terms, P->in.B, P->in.S, T, P->d_ws};
-    e = launch_grouped_f64(a, P->workers, s);
+    phase_end(P, s);
+    return e;
   }
-  phase_end(P, s);
-  return e;
+  // ladder items, then projection items: each kind in its own launch of the
+  // persistent kernel (own queue head), so that each is register-allocated alone
+  for (int kind = ITEM_LADDER; kind <= ITEM_PROJ; ++kind) {
+    const int32_t cnt = kind == ITEM_LADDER ? nl : np;
+    if (cnt == 0) continue;
+    const Item* items = P->d_items + (kind == ITEM_LADDER ? 0 : nl);
+    int32_t* counter = P->d_counter + kind;
+    phase_begin(P, kind == ITEM_LADDER ? 0 : 5, s);
+    if (prec == DLPNO_FP32) {
+      GroupedArgs<float> a{items, cnt, counter, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
+                           P->B32, P->S32, P->T32, P->d_ws};
+      e = launch_grouped_f32(a, kind, P->workers, s);
+    } else {
+      GroupedArgs<double> a{items, cnt, counter, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
+                            P->in.B, P->in.S, T, P->d_ws};
+      e = launch_grouped_f64(a, kind, P->workers, s);
+    }
+    phase_end(P, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 FinishArgs finish_args(dlpno_plan* P, const double* T) {

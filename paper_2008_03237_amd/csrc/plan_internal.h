@@ -14,7 +14,7 @@ namespace dlpno {
 
 constexpr int kHistCap = 4096;   // iterations kept in the device history
 constexpr int kDiisParts = 1024; // workgroups of the DIIS dot-product kernel
-constexpr int kPhases = 5;
+constexpr int kPhases = 6;
 
 // schedule choices (set by defaults or the autotuner)
 struct Tuning {
@@ -44,7 +44,8 @@ struct dlpno_plan {
   std::vector<dlpno::CplDev> cpl_h;
   std::vector<dlpno::TermDev> terms_h;
   std::vector<int64_t> rowptr_h;
-  std::vector<dlpno::Item> items_h;
+  std::vector<dlpno::Item> items_h;     // ladder items first, then projection items
+  int32_t n_ladder_items = 0;
   dlpno::Tuning tune;
   double flops_ladder = 0.0, flops_proj = 0.0, total_mfma = 0.0, max_item_mfma = 0.0;
   int64_t ws_elems = 0;
@@ -95,8 +96,8 @@ struct dlpno_plan {
   bool profiling = false;
   std::vector<hipEvent_t> events;
   std::vector<dlpno::PendingEvent> pending;
-  double phase_ms[dlpno::kPhases] = {0, 0, 0, 0, 0};
-  int64_t phase_n[dlpno::kPhases] = {0, 0, 0, 0, 0};
+  double phase_ms[dlpno::kPhases] = {};
+  int64_t phase_n[dlpno::kPhases] = {};
   std::string info;
 };
 
