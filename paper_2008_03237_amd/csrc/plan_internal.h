@@ -19,7 +19,7 @@ constexpr int kPhases = 6;
 // schedule choices (set by defaults or the autotuner)
 struct Tuning {
   int ladder_variant[4] = {0, 3, 7, 8};   // by tiles of 16 PNOs (1..4)
-  int proj_variant[4] = {0, 3, 6, 8};
+  int proj_variant[4] = {0, 4, 7, 8};
   double items_per_wave = 6.0;            // target items per wavefront of the queue
   double min_item_mfma = 2048.0;          // smallest item worth scheduling alone
 };
