@@ -124,8 +124,17 @@ typedef struct {
   int32_t diis_start;   /* first extrapolation once this many are stored (>= 2) */
   int32_t n_workers;    /* persistent workgroups (0 = 2 per compute unit) */
   int32_t chunk_flops;  /* log2 of the target work per scheduled item (0 = default) */
-  int32_t flags;        /* reserved, 0 */
+  int32_t flags;        /* DLPNO_FLAG_* bits, 0 = defaults */
 } dlpno_options;
+
+/* Same-spin (AA, BB) amplitude blocks are antisymmetric in the two virtual
+ * indices (Sec. II.A), and so are their ladder and projection contributions:
+ * by default only the tiles on and below the diagonal of those contributions
+ * are computed and the others are their negated transposes.  With this flag
+ * every tile is computed, so the residual is the plain linear map also for
+ * amplitudes that lack the antisymmetry.  Vector-Jacobian products always
+ * compute every tile. */
+#define DLPNO_FLAG_GENERAL_T 1
 
 typedef struct dlpno_plan dlpno_plan;   /* opaque, owned by the library */
 
@@ -137,7 +146,9 @@ dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno_inputs* in
                                const dlpno_options* opts, void* stream, dlpno_plan** out);
 dlpno_status dlpno_plan_destroy(dlpno_plan* plan);
 
-/* R = residual(T) for every stored block.  T, R: device, n_T doubles. */
+/* R = residual(T) for every stored block.  T, R: device, n_T doubles.  The
+ * same-spin blocks of T must be antisymmetric unless the plan was created
+ * with DLPNO_FLAG_GENERAL_T. */
 dlpno_status dlpno_residual(dlpno_plan* plan, const double* T, double* R, void* stream);
 
 /* T_out = T - R / D; e_pair[4 p + c] = energy of block c (0 AA, 1 BB, 2 AB,

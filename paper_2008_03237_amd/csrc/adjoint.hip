@@ -156,7 +156,7 @@ extern "C" dlpno_status dlpno_residual_vjp(dlpno_plan* P, const double* T, const
   if (!P || ((!T || !G || !dT) && P->n_T > 0)) return fail(DLPNO_ERR_INVALID_ARG, "NULL plan or buffer");
   hipStream_t s = (hipStream_t)stream;
   // dT = D o G + (ladder + projection)(G)
-  if (run_grouped(P, G, s) != hipSuccess) return fail(DLPNO_ERR_HIP, "vjp launch failed");
+  if (run_grouped(P, G, s, -1, true) != hipSuccess) return fail(DLPNO_ERR_HIP, "vjp launch failed");
   FinishArgs f = finish_args(P, G);
   f.R = dT;
   f.with_driver = 0;

@@ -158,6 +158,34 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const F* p, uint32_t elem
 // the projection (4 * 16 operands).
 constexpr int kLdsWaveWords = 72 * 64;
 
+// Partial sums of one block into its workspace slot: acc[tb][u] holds the
+// Out^T tile with rows in b-tile tb and columns in a-tile ta0 + u (row b,
+// column a stored at b n + a, coalesced over r).  mirror: the block's result
+// is antisymmetric; tiles above the diagonal (tb < ta) were not computed and
+// are written as the negated transpose of the tile below it, by whichever item
+// owns that tile's a-tile.
+template <typename F, int NT, int NU, typename V>
+__device__ __forceinline__ void store_tiles(double* dst, int n, int ta0, const V (&acc)[NT][NU], bool mirror) {
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+      const int ta = ta0 + u;
+      if (mirror && tb < ta) continue;
+      const int a = 16 * ta + r;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int bb = 16 * tb + Mfma<F>::orow(g, i);
+        if (a < n && bb < n) {
+          dst[bb * n + a] = (double)acc[tb][u][i];
+          if (mirror && tb > ta) dst[a * n + bb] = -(double)acc[tb][u][i];
+        }
+      }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Ladder item: pair p, NB consecutive blocks, a-tiles TA0..TA0+NTA-1,
 // Q in [lo, hi).  Partial Out^T[b][a] of sum_Q B^Q T B^Q^T.
@@ -167,7 +195,7 @@ constexpr int kLdsWaveWords = 72 * 64;
 // interleave (stage 1 of every block is issued before the stage 2 that reads
 // it).  REG keeps the X-form operands in VGPRs instead of the LDS slab.
 // ---------------------------------------------------------------------------
-template <typename F, int NT, int NB, int NTA, int TA0, int R, bool REG>
+template <typename F, int NT, int NB, int NTA, int TA0, int R, bool REG, int MASK>
 __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
   typedef typename Mfma<F>::V V;
   constexpr int S4 = 4 * (NT - 1) + R;
@@ -215,6 +243,9 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int u = 0; u < NTA; ++u) acc[b][t][u] = V{0, 0, 0, 0};
+  // bit b of MASK: block b is antisymmetric (same spin), stage 2 only for
+  // tiles with tb >= ta
+  auto mir = [](int b) { return ((MASK >> b) & 1) != 0; };
 
   // M-form of B^Q: M[t][s] = B^Q[4s + g][16t + r] = B^Q[16t + r][4s + g] (symmetric)
   const F* Bp = A.B + off_B;
@@ -258,12 +289,21 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
       for (int i = 0; i < 4; ++i) {
         if (4 * td + i < S4) {
 #pragma unroll
-          for (int b = 0; b < NB; ++b)
+          for (int b = 0; b < NB; ++b) {
+            if (mir(b)) {
 #pragma unroll
-            for (int tb = 0; tb < (STRIPS ? NT - 1 : NT); ++tb)
+              for (int tb = 0; tb < (STRIPS ? NT - 1 : NT); ++tb)
 #pragma unroll
-              for (int u = 0; u < NTA; ++u)
-                acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[b][u][i], acc[b][tb][u]);
+                for (int u = 0; u < NTA; ++u)
+                  if (tb >= TA0 + u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[b][u][i], acc[b][tb][u]);
+            } else {
+#pragma unroll
+              for (int tb = 0; tb < (STRIPS ? NT - 1 : NT); ++tb)
+#pragma unroll
+                for (int u = 0; u < NTA; ++u)
+                  acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[b][u][i], acc[b][tb][u]);
+            }
+          }
           if constexpr (STRIPS) {
             // last b-tile: output strip j holds rows 16 (NT - 1) + 4 j + g
 #pragma unroll
@@ -293,21 +333,10 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
     compute(M1);
   }
 
-  // partial slot stored as Out^T[b][a] (row b, column a): coalesced over r
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     double* dst = A.ws + uni(A.blocks[blk0 + it.bslot0 + b].off_ws) + (int64_t)it.slot * nn;
-#pragma unroll
-    for (int tb = 0; tb < NT; ++tb)
-#pragma unroll
-      for (int u = 0; u < NTA; ++u) {
-        const int a = 16 * (TA0 + u) + r;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int bb = 16 * tb + Mfma<F>::orow(g, i);
-          if (a < n && bb < n) dst[bb * n + a] = (double)acc[b][tb][u][i];
-        }
-      }
+    store_tiles<F>(dst, n, TA0, acc[b], mir(b));
   }
 }
 
@@ -320,7 +349,7 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
 // without a term for this coupling runs with weight 0 and an empty operand
 // range, which keeps the code branch-free.
 // ---------------------------------------------------------------------------
-template <typename F, int NT, int NB, int NQ>
+template <typename F, int NT, int NB, int NQ, int MASK>
 __device__ __forceinline__ void proj_item_direct(const GroupedArgs<F>& A, const Item& it, double* lds) {
   typedef typename Mfma<F>::V V;
   constexpr int S16 = 4 * NQ;                 // k-steps of 4 over the padded source index
@@ -340,6 +369,9 @@ __device__ __forceinline__ void proj_item_direct(const GroupedArgs<F>& A, const 
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int u = 0; u < NT; ++u) acc[b][t][u] = V{0, 0, 0, 0};
+  // bit b of MASK: target block b is antisymmetric (its sources are same-spin
+  // blocks too), so stage 2 runs only for tiles with tb >= ta
+  auto mir = [](int b) { return ((MASK >> b) & 1) != 0; };
 
   for (int e = it.lo; e < it.hi; ++e) {
     const int nq = uni(A.cpl[e].nsrc);
@@ -383,12 +415,21 @@ __device__ __forceinline__ void proj_item_direct(const GroupedArgs<F>& A, const 
 #pragma unroll
           for (int u = 0; u < NT; ++u) d1[u] = Mfma<F>::op(av, M[u][s], d1[u]);
         }
+        if (mir(b)) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+          for (int i = 0; i < 4; ++i)
 #pragma unroll
-          for (int tb = 0; tb < NT; ++tb)
+            for (int tb = 0; tb < NT; ++tb)
 #pragma unroll
-            for (int u = 0; u < NT; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
+              for (int u = 0; u <= tb; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+              for (int u = 0; u < NT; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
+        }
       }
     };
     if constexpr (BATCH) {
@@ -409,17 +450,7 @@ __device__ __forceinline__ void proj_item_direct(const GroupedArgs<F>& A, const 
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     double* dst = A.ws + uni(A.blocks[blk0 + it.bslot0 + b].off_ws) + (int64_t)it.slot * nn;
-#pragma unroll
-    for (int tb = 0; tb < NT; ++tb)
-#pragma unroll
-      for (int u = 0; u < NT; ++u) {
-        const int a = 16 * u + r;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int bb = 16 * tb + Mfma<F>::orow(g, i);
-          if (a < n && bb < n) dst[bb * n + a] = (double)acc[b][tb][u][i];
-        }
-      }
+    store_tiles<F>(dst, n, 0, acc[b], mir(b));
   }
 }
 
@@ -430,7 +461,7 @@ __device__ __forceinline__ void proj_item_direct(const GroupedArgs<F>& A, const 
 // next coupling's S operand is loaded into Mn during the last block, and the
 // source amplitudes of the next unit are loaded into Xn; Xn is weighted and
 // written to the LDS slab at the start of its unit.
-template <typename F, int NT, int NB, int NQ>
+template <typename F, int NT, int NB, int NQ, int MASK>
 __device__ __forceinline__ void proj_item_pipelined(const GroupedArgs<F>& A, const Item& it, double* lds) {
   typedef typename Mfma<F>::V V;
   constexpr int S16 = 4 * NQ;
@@ -507,6 +538,9 @@ __device__ __forceinline__ void proj_item_pipelined(const GroupedArgs<F>& A, con
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int u = 0; u < NT; ++u) acc[b][t][u] = V{0, 0, 0, 0};
+  // bit b of MASK: target block b is antisymmetric (its sources are same-spin
+  // blocks too), so stage 2 runs only for tiles with tb >= ta
+  auto mir = [](int b) { return ((MASK >> b) & 1) != 0; };
 
   auto compute = [&](const F (&M)[NT][S16], int b) {
 #pragma unroll
@@ -520,12 +554,21 @@ __device__ __forceinline__ void proj_item_pipelined(const GroupedArgs<F>& A, con
 #pragma unroll
         for (int u = 0; u < NT; ++u) d1[u] = Mfma<F>::op(av, M[u][s], d1[u]);
       }
+      if (mir(b)) {
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int tb = 0; tb < NT; ++tb)
+          for (int tb = 0; tb < NT; ++tb)
 #pragma unroll
-          for (int u = 0; u < NT; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
+            for (int u = 0; u <= tb; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
+      } else {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int tb = 0; tb < NT; ++tb)
+#pragma unroll
+            for (int u = 0; u < NT; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
+      }
     }
   };
 
@@ -563,38 +606,58 @@ __device__ __forceinline__ void proj_item_pipelined(const GroupedArgs<F>& A, con
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     double* dst = A.ws + uni(A.blocks[blk0 + it.bslot0 + b].off_ws) + (int64_t)it.slot * nn;
-#pragma unroll
-    for (int tb = 0; tb < NT; ++tb)
-#pragma unroll
-      for (int u = 0; u < NT; ++u) {
-        const int a = 16 * u + r;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int bb = 16 * tb + Mfma<F>::orow(g, i);
-          if (a < n && bb < n) dst[bb * n + a] = (double)acc[b][tb][u][i];
-        }
-      }
+    store_tiles<F>(dst, n, 0, acc[b], mir(b));
   }
 }
 
 // Projection item: pipelined where its registers (accumulators, two S
 // operands, one block of source amplitudes, the stage-1 product; counted in
 // operands) fit without spilling, direct otherwise.
+template <typename F, int NT, int NB, int NQ, int MASK>
+__device__ __forceinline__ void proj_item_m(const GroupedArgs<F>& A, const Item& it, double* lds) {
+  constexpr int kRegs = 4 * NB * NT * NT + 2 * NT * 4 * NQ + 4 * NQ * NQ + 4 * NT;
+  if constexpr (kRegs <= 170) proj_item_pipelined<F, NT, NB, NQ, MASK>(A, it, lds);
+  else proj_item_direct<F, NT, NB, NQ, MASK>(A, it, lds);
+}
+// The antisymmetry pattern of the item's blocks selects a compiled body (see
+// ladder_masked).
 template <typename F, int NT, int NB, int NQ>
 __device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
-  constexpr int kRegs = 4 * NB * NT * NT + 2 * NT * 4 * NQ + 4 * NQ * NQ + 4 * NT;
-  if constexpr (kRegs <= 170) proj_item_pipelined<F, NT, NB, NQ>(A, it, lds);
-  else proj_item_direct<F, NT, NB, NQ>(A, it, lds);
+  int mask = 0;
+  if (A.anti != 0) {
+    const int blk0 = uni(A.pairs[it.pair].blk0);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) mask |= (uni(A.blocks[blk0 + it.bslot0 + b].anti) != 0 ? 1 : 0) << b;
+  }
+  constexpr int kMirror = NB == 4 ? 3 : (1 << NB) - 1;
+  if (mask == kMirror) proj_item_m<F, NT, NB, NQ, kMirror>(A, it, lds);
+  else proj_item_m<F, NT, NB, NQ, 0>(A, it, lds);
+}
+
+// The antisymmetry pattern of the item's blocks selects a compiled body: for
+// four blocks (AA, BB, AB, BA) the first two, otherwise all of them; any
+// other pattern computes every tile.
+template <typename F, int NT, int NB, int NTA, int TA0, int R, bool REG>
+__device__ __forceinline__ void ladder_masked(const GroupedArgs<F>& A, const Item& it, double* lds) {
+  int mask = 0;
+  if (A.anti != 0) {
+    const int blk0 = uni(A.pairs[it.pair].blk0);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) mask |= (uni(A.blocks[blk0 + it.bslot0 + b].anti) != 0 ? 1 : 0) << b;
+  }
+  constexpr int kMirror = NB == 4 ? 3 : (1 << NB) - 1;
+  if (mask == kMirror) ladder_item<F, NT, NB, NTA, TA0, R, REG, kMirror>(A, it, lds);
+  else ladder_item<F, NT, NB, NTA, TA0, R, REG, 0>(A, it, lds);
 }
 
 // k-steps of 4 in the last 16-wide tile of the pair: R = ceil((n mod 16) / 4), 1..4
 #define DLPNO_LADDER(NT, NB, NTA, TA0, REG)                                      \
   do {                                                                             \
     switch (rk) {                                                                  \
-      case 1: ladder_item<F, NT, NB, NTA, TA0, 1, REG>(A, it, lds); break;         \
-      case 2: ladder_item<F, NT, NB, NTA, TA0, 2, REG>(A, it, lds); break;         \
-      case 3: ladder_item<F, NT, NB, NTA, TA0, 3, REG>(A, it, lds); break;         \
-      default: ladder_item<F, NT, NB, NTA, TA0, 4, REG>(A, it, lds); break;        \
+      case 1: ladder_masked<F, NT, NB, NTA, TA0, 1, REG>(A, it, lds); break;       \
+      case 2: ladder_masked<F, NT, NB, NTA, TA0, 2, REG>(A, it, lds); break;       \
+      case 3: ladder_masked<F, NT, NB, NTA, TA0, 3, REG>(A, it, lds); break;       \
+      default: ladder_masked<F, NT, NB, NTA, TA0, 4, REG>(A, it, lds); break;      \
     }                                                                              \
   } while (0)
 

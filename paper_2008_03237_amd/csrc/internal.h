@@ -76,6 +76,11 @@ struct GroupedArgs {
   const F* S;
   const F* T;
   double* ws;
+  // 1: same-spin blocks hold antisymmetric amplitudes, so their ladder and
+  // projection contributions are antisymmetric too; only the tiles on and
+  // below the diagonal are computed and the others are stored mirrored.
+  // 0 (vector-Jacobian products, whose cotangents are general): all tiles.
+  int32_t anti;
 };
 
 // kernels.hip

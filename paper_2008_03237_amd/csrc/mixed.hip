@@ -21,11 +21,14 @@ using namespace dlpno;
   } while (0)
 
 // FP64 residual r = R(T); energies and max |r| of the Jacobi-updated T are
-// recorded in the history (the updated amplitudes go to `scratch`)
+// recorded in the history (the updated amplitudes go to `scratch`).  Every
+// tile is computed: the low-precision corrections added to T carry rounding
+// that is not antisymmetric in the same-spin blocks, and the refinement
+// needs the true residual of that T.
 static hipError_t fp64_residual(dlpno_plan* P, const double* T, double* r, double* scratch, double* e_pair,
                                 double* e_total, double* rmax, bool in_place, hipStream_t s) {
   hipError_t e;
-  if ((e = run_grouped(P, T, s, DLPNO_FP64)) != hipSuccess) return e;
+  if ((e = run_grouped(P, T, s, DLPNO_FP64, true)) != hipSuccess) return e;
   FinishArgs f = finish_args(P, T);
   f.R = r;
   f.T_new = in_place ? const_cast<double*>(T) : scratch;

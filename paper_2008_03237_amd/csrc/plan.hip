@@ -326,6 +326,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if (opt.precision < DLPNO_FP64 || opt.precision > DLPNO_FP16X2)
     return fail(DLPNO_ERR_INVALID_ARG, "unknown precision");
   if (opt.diis_max < 0 || opt.diis_max > 8) return fail(DLPNO_ERR_INVALID_ARG, "diis_max must be in 0..8");
+  if ((opt.flags & ~DLPNO_FLAG_GENERAL_T) != 0) return fail(DLPNO_ERR_INVALID_ARG, "unknown option flag");
   if (opt.diis_max > 0 && (opt.diis_start < 1 || opt.diis_start > opt.diis_max))
     return fail(DLPNO_ERR_INVALID_ARG, "diis_start must be in 1..diis_max");
   for (int k = 0; k < n_occ; ++k)
@@ -650,7 +651,7 @@ bool is_split(int prec) { return prec == DLPNO_BF16X2 || prec == DLPNO_FP16X2; }
 
 // grouped kernel over amplitudes T (FP64 buffer given by the caller) in the
 // plan's precision, or in `prec` when given (FP64 residuals of a split plan)
-hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec) {
+hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, bool general) {
   hipError_t e;
   if (P->items_h.empty()) return hipSuccess;
   if (prec < 0) prec = P->opt.precision;
@@ -676,6 +677,7 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec) 
     phase_end(P, s);
     return e;
   }
+  general = general || (P->opt.flags & DLPNO_FLAG_GENERAL_T) != 0;
   // ladder items, then projection items: each kind in its own launch of the
   // persistent kernel (own queue head), so that each is register-allocated alone
   for (int kind = ITEM_LADDER; kind <= ITEM_PROJ; ++kind) {
@@ -686,11 +688,11 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec) 
     phase_begin(P, kind == ITEM_LADDER ? 0 : 5, s);
     if (prec == DLPNO_FP32) {
       GroupedArgs<float> a{items, cnt, counter, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
-                           P->B32, P->S32, P->T32, P->d_ws};
+                           P->B32, P->S32, P->T32, P->d_ws, general ? 0 : 1};
       e = launch_grouped_f32(a, kind, P->workers, s);
     } else {
       GroupedArgs<double> a{items, cnt, counter, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
-                            P->in.B, P->in.S, T, P->d_ws};
+                            P->in.B, P->in.S, T, P->d_ws, general ? 0 : 1};
       e = launch_grouped_f64(a, kind, P->workers, s);
     }
     phase_end(P, s);

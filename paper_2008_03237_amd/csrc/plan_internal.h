@@ -106,7 +106,9 @@ namespace dlpno {
 dlpno_status fail(dlpno_status s, const std::string& msg);
 dlpno_status build_schedule(dlpno_plan* P);
 dlpno_status upload_schedule(dlpno_plan* P, hipStream_t s);
-hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec = -1);
+// general: the amplitudes may lack the antisymmetry of same-spin blocks
+// (cotangents of the vector-Jacobian product), so every tile is computed
+hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec = -1, bool general = false);
 FinishArgs finish_args(dlpno_plan* P, const double* T);
 hipError_t enqueue_iteration(dlpno_plan* P, double* T, double* R, double* e_pair, double* e_total, double* rmax,
                              hipStream_t s, const double* drv = nullptr, int prec = -1, bool record = true);

@@ -8,6 +8,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 
 FP64, FP32, BF16X2, FP16X2 = 0, 1, 2, 3
 _PREC = {"fp64": FP64, "fp32": FP32, "bf16x2": BF16X2, "fp16x2": FP16X2}
+FLAG_GENERAL_T = 1     # same-spin amplitude blocks need not be antisymmetric
 
 
 class DlpnoError(RuntimeError):
@@ -117,10 +118,12 @@ class Plan:
     blocks, off_B, off_T, off_K, off_eps, cpl_rowptr, cpl_src, cpl_k, cpl_side,
     cpl_off_S, f_a, f_b, n_B, n_T, n_K, n_S and eps sizes), e.g. a
     workload.Problem.  B, S, K, eps_a, eps_b: device tensors (kept referenced).
+    The same-spin blocks of the amplitudes passed to residual/iterate must be
+    antisymmetric (as physical amplitudes are) unless general_T is set.
     """
 
     def __init__(self, desc, B, S, K, eps_a, eps_b, precision="fp64", diis_max=8, diis_start=3, n_workers=0,
-                 items_per_wave=0):
+                 items_per_wave=0, general_T=False):
         import torch
         L = lib()
         P = len(desc.pi)
@@ -147,7 +150,7 @@ class Plan:
         inp = Inputs(B.data_ptr(), S.data_ptr() if S is not None else None, K.data_ptr(), eps_a.data_ptr(),
                      eps_b.data_ptr())
         prec = _PREC[precision] if isinstance(precision, str) else int(precision)
-        opt = Options(prec, diis_max, diis_start, n_workers, int(items_per_wave), 0)
+        opt = Options(prec, diis_max, diis_start, n_workers, int(items_per_wave), FLAG_GENERAL_T if general_T else 0)
         self.precision = prec
         self.n_T, self.n_B, self.n_pairs = int(desc.n_T), int(desc.n_B), P
         self._h = C.c_void_p()

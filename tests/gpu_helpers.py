@@ -19,6 +19,21 @@ def device_problem(prob, precision="fp64", diis_max=8, diis_start=3, T_random=Tr
     return plan, dev
 
 
+def antisymmetrize_same_spin(prob, flat):
+    """Replace every same-spin (AA, BB) block of a flat amplitude-shaped device
+    vector by its antisymmetric part (the physical amplitude space)."""
+    somo = prob.is_somo.astype(bool)
+    for p in range(prob.n_pairs):
+        n = int(prob.npno[p])
+        o = int(prob.off_T[p])
+        for name in oracle.stored_blocks(int(prob.pi[p]), int(prob.pj[p]), somo):
+            if name in ("AA", "BB"):
+                blk = flat[o:o + n * n].view(n, n)
+                blk.copy_((blk - blk.t()) / 2)
+            o += n * n
+    return flat
+
+
 def oracle_inputs(prob, full=True):
     if full:
         return oracle.Inputs.from_problem(prob, B=prob.materialize("B"), K=prob.materialize("K"),

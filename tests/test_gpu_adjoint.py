@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 from oracle.model import unpack_T
-from tests.gpu_helpers import device_problem, oracle_inputs, compare_blocks
+from tests.gpu_helpers import antisymmetrize_same_spin, compare_blocks, device_problem, oracle_inputs
 from workload import build_problem
 
 pytestmark = pytest.mark.gpu
@@ -57,13 +57,21 @@ def test_fp32_residual_close_to_fp64_oracle():
     plan.close()
 
 
-def test_dot_product_identity_on_device():
-    # <G, J dT> = <J^T G, dT> with J the residual's linear part (FP64, mini chain)
+@pytest.mark.parametrize("general", [False, True])
+def test_dot_product_identity_on_device(general):
+    # <G, J dT> = <J^T G, dT> with J the residual's linear part (FP64, mini
+    # chain).  Default plans take antisymmetric same-spin blocks (dT in that
+    # space, G general); general_T plans take any dT.
+    from paper_2008_03237_amd import Plan
     prob = build_problem("chain", n_occ=24, band=6, somos=(7, 16))
-    plan, dev = device_problem(prob)
+    plan0, dev = device_problem(prob)
+    plan = Plan(prob, dev["B"], dev["S"], dev["K"], plan0._dev[3], plan0._dev[4], general_T=general)
+    plan0.close()
     rng = np.random.default_rng(8)
     G = torch.from_numpy(rng.standard_normal(prob.n_T)).cuda()
     X = torch.from_numpy(rng.standard_normal(prob.n_T)).cuda()
+    if not general:
+        X = antisymmetrize_same_spin(prob, X)
     zero = torch.zeros_like(X)
     # only elements of stored blocks: the alignment gaps between pairs are never written
     mask = torch.zeros(prob.n_T, dtype=torch.float64, device="cuda")
@@ -107,6 +115,8 @@ def test_autograd_lagrangian_central_differences_50_pairs(precision):
         o, nb = int(prob.off_T[p]), int(nblk[p])
         sz = nb * int(prob.npno[p]) ** 2
         dTdir[o:o + sz] = torch.from_numpy(rng.standard_normal(sz)).cuda()
+    antisymmetrize_same_spin(prob, dTdir)            # a direction in the amplitude space
+    for p in pick:
         m, n = int(prob.naux[p]), int(prob.npno[p])
         o, sz = int(prob.off_B[p]), m * n * n
         d = rng.standard_normal((m, n, n))

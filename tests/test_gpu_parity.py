@@ -56,6 +56,37 @@ def test_residual_update_energy_parity(cfg):
     plan.close()
 
 
+@pytest.mark.parametrize("general", [False, True])
+def test_general_amplitudes_flag(general):
+    """Same-spin blocks are taken antisymmetric by default (only the lower
+    tiles of their contributions are computed, the upper ones mirrored);
+    with general_T every tile is computed.  Residuals of a random T whose
+    same-spin blocks are antisymmetric (default) or not (general_T) vs the
+    oracle's plain formula."""
+    from paper_2008_03237_amd import Plan
+    prob = build_problem("chain", n_occ=24, band=6, somos=(7, 16))
+    plan0, dev = device_problem(prob)
+    plan = Plan(prob, dev["B"], dev["S"], dev["K"], plan0._dev[3], plan0._dev[4], general_T=general)
+    plan0.close()
+    rng = np.random.default_rng(31)
+    Th = rng.standard_normal(prob.n_T) * 1e-2
+    if not general:
+        somo = prob.is_somo.astype(bool)
+        for p in range(prob.n_pairs):
+            n, o = int(prob.npno[p]), int(prob.off_T[p])
+            for name in oracle.stored_blocks(int(prob.pi[p]), int(prob.pj[p]), somo):
+                if name in ("AA", "BB"):
+                    blk = Th[o:o + n * n].reshape(n, n)
+                    Th[o:o + n * n] = ((blk - blk.T) / 2).ravel()
+                o += n * n
+    R = plan.residual(torch.from_numpy(Th).cuda())
+    torch.cuda.synchronize()
+    inp = oracle_inputs(prob)
+    Ro = oracle.residual_os(inp, unpack_T(prob, Th))
+    compare_blocks(prob, R.cpu().numpy(), Ro, rel=1e-12)
+    plan.close()
+
+
 def test_tile_classes_all_present_in_mini():
     prob = build_problem("chain", n_occ=24, band=6, somos=(7, 16))
     nt = set(((prob.npno + 15) // 16).tolist())
