@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 
 
-def cpu_baseline(prob, n_pairs=400, seed=99):
+def cpu_baseline(prob, n_pairs=1200, seed=99):
     """Time the FP64 oracle on a contiguous window of pairs of the workload
     (inputs regenerated from the seeded counters beforehand, not timed)."""
     import concurrent.futures as cf
@@ -95,7 +95,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pairs", type=int, default=400)
+    ap.add_argument("--cpu-pairs", type=int, default=1200)
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision / refinement leg")
     ap.add_argument("--mixed-precision", default="bf16x2", choices=["bf16x2", "fp16x2", "fp32"])
     ap.add_argument("--mixed-outer", type=int, default=3, help="FP64 refinement steps")
