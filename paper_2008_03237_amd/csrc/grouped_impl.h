@@ -542,7 +542,10 @@ __device__ __forceinline__ void proj_item_pipelined(const GroupedArgs<F>& A, con
   // blocks too), so stage 2 runs only for tiles with tb >= ta
   auto mir = [](int b) { return ((MASK >> b) & 1) != 0; };
 
-  auto compute = [&](const F (&M)[NT][S16], int b) {
+  // One unit's contractions.  nq4: k-steps of 4 over the source's PNOs; the
+  // k-steps of the last 16-wide source tile past it (zero operands) are
+  // skipped by wave-uniform branches.
+  auto compute = [&](const F (&M)[NT][S16], int b, int nq4) {
 #pragma unroll
     for (int td = 0; td < NQ; ++td) {
       V d1[NT];
@@ -550,24 +553,19 @@ __device__ __forceinline__ void proj_item_pipelined(const GroupedArgs<F>& A, con
       for (int u = 0; u < NT; ++u) d1[u] = V{0, 0, 0, 0};
 #pragma unroll
       for (int s = 0; s < S16; ++s) {
+        if (s > 4 * (NQ - 1) && s >= nq4) continue;
         const F av = Al[(td * S16 + s) * 64 + lane];
 #pragma unroll
         for (int u = 0; u < NT; ++u) d1[u] = Mfma<F>::op(av, M[u][s], d1[u]);
       }
-      if (mir(b)) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i) {
+        if (4 * td + i > 4 * (NQ - 1) && 4 * td + i >= nq4) continue;
 #pragma unroll
-          for (int tb = 0; tb < NT; ++tb)
+        for (int tb = 0; tb < NT; ++tb)
 #pragma unroll
-            for (int u = 0; u <= tb; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int tb = 0; tb < NT; ++tb)
-#pragma unroll
-            for (int u = 0; u < NT; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
+          for (int u = 0; u < NT; ++u)
+            if (!mir(b) || u <= tb) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
       }
     }
   };
@@ -582,6 +580,7 @@ __device__ __forceinline__ void proj_item_pipelined(const GroupedArgs<F>& A, con
   for (int e = it.lo; e <= last; ++e) {
     const bool more = e < last;
     const int32_t dnn = load_desc(e + 2 <= last ? e + 2 : last);
+    const int nq4 = (d_nq(dc) + 3) >> 2;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       store_X(Xn, dc, b);
@@ -591,7 +590,7 @@ __device__ __forceinline__ void proj_item_pipelined(const GroupedArgs<F>& A, con
         load_M(Mn, dn, more);
         load_X(Xn, dn, 0, more);
       }
-      compute(M, b);
+      compute(M, b, nq4);
       __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
