@@ -403,6 +403,8 @@ __device__ __forceinline__ void proj_item_direct(const GroupedArgs<F>& A, const 
           Al[(base_slot + td * S16 + s) * 64 + lane] =
               mw * Mfma<F>::load(xr, base + (uint32_t)s * step_s + (uint32_t)td * step_t);
     };
+    // k-steps of the last source tile past the source's PNOs are skipped
+    const int nq4 = (nq + 3) >> 2;
     auto compute_x = [&](int b, int base_slot) {
 #pragma unroll
       for (int td = 0; td < NQ; ++td) {
@@ -411,24 +413,19 @@ __device__ __forceinline__ void proj_item_direct(const GroupedArgs<F>& A, const 
         for (int u = 0; u < NT; ++u) d1[u] = V{0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < S16; ++s) {
+          if (s > 4 * (NQ - 1) && s >= nq4) continue;
           const F av = Al[(base_slot + td * S16 + s) * 64 + lane];
 #pragma unroll
           for (int u = 0; u < NT; ++u) d1[u] = Mfma<F>::op(av, M[u][s], d1[u]);
         }
-        if (mir(b)) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < 4; ++i) {
+          if (4 * td + i > 4 * (NQ - 1) && 4 * td + i >= nq4) continue;
 #pragma unroll
-            for (int tb = 0; tb < NT; ++tb)
+          for (int tb = 0; tb < NT; ++tb)
 #pragma unroll
-              for (int u = 0; u <= tb; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
-        } else {
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int tb = 0; tb < NT; ++tb)
-#pragma unroll
-              for (int u = 0; u < NT; ++u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
+            for (int u = 0; u < NT; ++u)
+              if (!mir(b) || u <= tb) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[u][i], acc[b][tb][u]);
         }
       }
     };

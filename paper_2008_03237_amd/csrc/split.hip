@@ -72,6 +72,25 @@ __device__ __forceinline__ uint64_t frag(__amdgpu_buffer_rsrc_t r, uint32_t off_
 
 // hi/lo of 4 FP32 values packed as two 4-element fragments
 template <typename S>
+__device__ __forceinline__ void split4(const f4_t v, float scale, uint64_t& hi, uint64_t& lo);
+// BF16: packed conversions of element pairs (round to nearest even); a BF16
+// value back in FP32 is its bits shifted into the high half
+typedef __bf16 b2_t __attribute__((ext_vector_type(2)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
+template <>
+__device__ __forceinline__ void split4<SplitBf16>(const f4_t v, float scale, uint64_t& hi, uint64_t& lo) {
+  uint32_t h[2], l[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const float x0 = v[2 * j] * scale, x1 = v[2 * j + 1] * scale;
+    h[j] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2_t{x0, x1}, b2_t));
+    const float b0 = __builtin_bit_cast(float, h[j] << 16), b1 = __builtin_bit_cast(float, h[j] & 0xffff0000u);
+    l[j] = __builtin_bit_cast(uint32_t, __builtin_convertvector(f2_t{x0 - b0, x1 - b1}, b2_t));
+  }
+  hi = ((uint64_t)h[1] << 32) | h[0];
+  lo = ((uint64_t)l[1] << 32) | l[0];
+}
+template <typename S>
 __device__ __forceinline__ void split4(const f4_t v, float scale, uint64_t& hi, uint64_t& lo) {
   uint64_t h = 0, l = 0;
 #pragma unroll
