@@ -204,3 +204,38 @@ def test_graph_replay_matches_eager():
     assert np.array_equal(E_graph, E_eager)
     assert torch.equal(T1.view(torch.int64), T2.view(torch.int64))
     plan.close()
+
+
+@pytest.mark.parametrize("n", [1, 4, 5, 16, 17, 33, 48, 49, 64])
+def test_every_tile_remainder_against_oracle(n):
+    """Fixed PNO count n per pair: one, two, three and four tiles of 16 with
+    every remainder of k-steps (row strips for R < 4, full tiles for R = 4),
+    same-spin mirroring, and SOMO-SOMO pairs with one block next to diagonal
+    SOMO pairs with none (SOMOs 3 and 5 within the band)."""
+    prob = build_problem("chain", n_occ=10, band=3, somos=(3, 5), npno=("fixed", n), naux=("uniform", 40, 90))
+    print("case n =", n, prob.n_pairs, "pairs", prob.n_couplings, "couplings", flush=True)
+    assert (prob.n_blocks() == 0).any() and (prob.n_blocks() == 1).any()
+    plan, dev = device_problem(prob)
+    R = plan.residual(dev["T"])
+    torch.cuda.synchronize()
+    inp = oracle_inputs(prob)
+    Ro = oracle.residual_os(inp, unpack_T(prob, prob.materialize("T")))
+    compare_blocks(prob, R.cpu().numpy(), Ro, rel=1e-12)
+    plan.close()
+
+
+def test_diagonal_pairs_only_no_couplings():
+    """Band 0: only diagonal pairs, no projection terms (an empty projection
+    queue), one block per DOMO pair and none per SOMO pair."""
+    prob = build_problem("chain", n_occ=8, band=0, somos=(2, 5), naux=("uniform", 40, 90))
+    assert prob.n_couplings == 0
+    plan, dev = device_problem(prob)
+    R = plan.residual(dev["T"])
+    Tn, e_pair, e_tot = plan.update(dev["T"], R)
+    torch.cuda.synchronize()
+    inp = oracle_inputs(prob)
+    T, Ro, Tno, eo = _oracle_step(prob, inp, prob.materialize("T"))
+    compare_blocks(prob, R.cpu().numpy(), Ro, rel=1e-12)
+    compare_blocks(prob, Tn.cpu().numpy(), Tno, rel=1e-12)
+    assert abs(float(e_tot.cpu()[0]) - sum(eo.values())) <= 1e-10
+    plan.close()
