@@ -122,7 +122,7 @@ typedef struct {
   dlpno_precision precision;
   int32_t diis_max;     /* vectors kept by DIIS, 0 = plain Jacobi, at most 8 */
   int32_t diis_start;   /* first extrapolation once this many are stored (>= 2) */
-  int32_t n_workers;    /* persistent workgroups (0 = 2 per compute unit) */
+  int32_t n_workers;    /* persistent workgroups (0 = one per compute unit) */
   int32_t chunk_flops;  /* log2 of the target work per scheduled item (0 = default) */
   int32_t flags;        /* DLPNO_FLAG_* bits, 0 = defaults */
 } dlpno_options;
@@ -187,7 +187,10 @@ dlpno_status dlpno_residual_vjp(dlpno_plan* plan, const double* T, const double*
 /* Mixed-precision solve (plan precision BF16X2, FP16X2 or FP32): n_outer
  * refinement steps, each computing the FP64 residual r = R(T) and then
  * n_inner low-precision Jacobi+DIIS iterations on the correction equation
- * (D + A) delta = -r, T += delta.  T in/out (device).  Synchronous. */
+ * (D + A) delta = -r, T += delta.  Unless the plan has DLPNO_FLAG_GENERAL_T,
+ * the same-spin blocks of T are replaced by their antisymmetric part on entry
+ * and after every step (removing the rounding of the low-precision
+ * corrections).  T in/out (device).  Synchronous. */
 dlpno_status dlpno_solve_mixed(dlpno_plan* plan, int32_t n_outer, int32_t n_inner, double* T,
                                double* R, double* e_pair, double* e_total, double* max_abs_R,
                                void* stream);
@@ -207,8 +210,7 @@ dlpno_status dlpno_autotune(dlpno_plan* plan, const double* T, double* R, void* 
  * returns the accumulated milliseconds and launch counts of:
  *   0 grouped kernel over the ladder items, 1 finish/update, 2 energy
  *   reduction, 3 DIIS, 4 precision conversion, 5 grouped kernel over the
- *   projection items (in the split precisions one launch covers both kinds
- *   and is counted under 0). */
+ *   projection items. */
 dlpno_status dlpno_set_profiling(dlpno_plan* plan, int32_t enable);
 dlpno_status dlpno_phase_times(const dlpno_plan* plan, double* ms, int64_t* launches, int32_t n);
 

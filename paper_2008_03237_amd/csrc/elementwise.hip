@@ -346,6 +346,26 @@ __global__ void axpy_kernel(double* y, const double* x, double a, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
     y[i] += a * x[i];
 }
+// Same-spin blocks onto their antisymmetric part: T <- (T - T^T) / 2.  One
+// workgroup per block; each thread owns the element pairs (a, b), a < b, it
+// updates, so no two threads touch the same element.
+__global__ void antisym_kernel(const BlockDev* blocks, double* T) {
+  const BlockDev& bk = blocks[blockIdx.x];
+  if (!bk.anti) return;
+  const int n = bk.n;
+  double* X = T + bk.off_T;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int a = idx / n, b = idx % n;
+    if (a > b) continue;
+    if (a == b) {
+      X[idx] = 0.0;
+    } else {
+      const double v = 0.5 * (X[a * n + b] - X[b * n + a]);
+      X[a * n + b] = v;
+      X[b * n + a] = -v;
+    }
+  }
+}
 __global__ void fill_kernel(double* y, double v, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) y[i] = v;
 }
@@ -401,6 +421,11 @@ hipError_t launch_convert_f32(const double* src, float* dst, int64_t n, hipStrea
 }
 hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(axpy_kernel, dim3(grid_for(n)), dim3(256), 0, s, y, x, a, n);
+  return hipGetLastError();
+}
+hipError_t launch_antisymmetrize(const BlockDev* blocks, int n_blocks, double* T, hipStream_t s) {
+  if (n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(antisym_kernel, dim3(n_blocks), dim3(256), 0, s, blocks, T);
   return hipGetLastError();
 }
 hipError_t launch_copy(double* y, const double* x, int64_t n, hipStream_t s) {

@@ -165,7 +165,8 @@ constexpr int kLdsWaveWords = 72 * 64;
 // are written as the negated transpose of the tile below it, by whichever item
 // owns that tile's a-tile.
 template <typename F, int NT, int NU, typename V>
-__device__ __forceinline__ void store_tiles(double* dst, int n, int ta0, const V (&acc)[NT][NU], bool mirror) {
+__device__ __forceinline__ void store_tiles(double* dst, int n, int ta0, const V (&acc)[NT][NU], bool mirror,
+                                            double scale = 1.0) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -179,8 +180,9 @@ __device__ __forceinline__ void store_tiles(double* dst, int n, int ta0, const V
       for (int i = 0; i < 4; ++i) {
         const int bb = 16 * tb + Mfma<F>::orow(g, i);
         if (a < n && bb < n) {
-          dst[bb * n + a] = (double)acc[tb][u][i];
-          if (mirror && tb > ta) dst[a * n + bb] = -(double)acc[tb][u][i];
+          const double v = (double)acc[tb][u][i] * scale;
+          dst[bb * n + a] = v;
+          if (mirror && tb > ta) dst[a * n + bb] = -v;
         }
       }
     }

@@ -166,6 +166,8 @@ hipError_t launch_diis_reset(DiisState* st, int max, int start, hipStream_t s);
 hipError_t launch_convert_f32(const double* src, float* dst, int64_t n, hipStream_t s);
 hipError_t launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t s);
 hipError_t launch_copy(double* y, const double* x, int64_t n, hipStream_t s);
+// same-spin (anti) blocks of T replaced by their antisymmetric part
+hipError_t launch_antisymmetrize(const BlockDev* blocks, int n_blocks, double* T, hipStream_t s);
 hipError_t launch_fill(double* y, double v, int64_t n, hipStream_t s);
 
 }  // namespace dlpno

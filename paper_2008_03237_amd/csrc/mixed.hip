@@ -21,14 +21,13 @@ using namespace dlpno;
   } while (0)
 
 // FP64 residual r = R(T); energies and max |r| of the Jacobi-updated T are
-// recorded in the history (the updated amplitudes go to `scratch`).  Every
-// tile is computed: the low-precision corrections added to T carry rounding
-// that is not antisymmetric in the same-spin blocks, and the refinement
-// needs the true residual of that T.
+// recorded in the history (the updated amplitudes go to `scratch`).  T's
+// same-spin blocks are antisymmetric here (projected after every correction)
+// unless the plan takes general amplitudes.
 static hipError_t fp64_residual(dlpno_plan* P, const double* T, double* r, double* scratch, double* e_pair,
                                 double* e_total, double* rmax, bool in_place, hipStream_t s) {
   hipError_t e;
-  if ((e = run_grouped(P, T, s, DLPNO_FP64, true)) != hipSuccess) return e;
+  if ((e = run_grouped(P, T, s, DLPNO_FP64)) != hipSuccess) return e;
   FinishArgs f = finish_args(P, T);
   f.R = r;
   f.T_new = in_place ? const_cast<double*>(T) : scratch;
@@ -67,6 +66,11 @@ extern "C" dlpno_status dlpno_solve_mixed(dlpno_plan* P, int32_t n_outer, int32_
       return fail(DLPNO_ERR_OOM, "mixed solve workspace");
     }
   }
+  // The low-precision corrections carry rounding that is not antisymmetric in
+  // the same-spin blocks; T is projected back onto the amplitude space (where
+  // the FP64 residual mirrors those blocks) at the start and after each step.
+  const bool project = (P->opt.flags & DLPNO_FLAG_GENERAL_T) == 0;
+  if (project) MIXCK(launch_antisymmetrize(P->d_blocks, P->n_blocks, T, s));
   for (int o = 0; o < n_outer; ++o) {
     MIXCK(fp64_residual(P, T, P->d_mix_r, P->d_mix_delta, nullptr, nullptr, nullptr, false, s));
     MIXCK(launch_fill(P->d_mix_delta, 0.0, P->n_T, s));
@@ -74,6 +78,7 @@ extern "C" dlpno_status dlpno_solve_mixed(dlpno_plan* P, int32_t n_outer, int32_
     for (int k = 0; k < n_inner; ++k)
       MIXCK(enqueue_iteration(P, P->d_mix_delta, R, nullptr, nullptr, nullptr, s, P->d_mix_r, -1, false));
     MIXCK(launch_axpy(T, P->d_mix_delta, 1.0, P->n_T, s));
+    if (project) MIXCK(launch_antisymmetrize(P->d_blocks, P->n_blocks, T, s));
   }
   MIXCK(fp64_residual(P, T, R, nullptr, e_pair, e_total, max_abs_R, true, s));
   P->host_iter += n_outer + 1;

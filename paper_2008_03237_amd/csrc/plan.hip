@@ -667,17 +667,23 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
     phase_end(P, s);
   }
   if ((e = launch_zero_i32(P->d_counter, 2, s)) != hipSuccess) return e;
+  general = general || (P->opt.flags & DLPNO_FLAG_GENERAL_T) != 0;
   const int32_t nl = P->n_ladder_items, np = (int32_t)P->items_h.size() - nl;
   if (is_split(prec)) {
-    phase_begin(P, 0, s);
-    SplitArgs a{P->d_items, (int32_t)P->items_h.size(), P->d_counter, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
-                P->d_pair_boff, P->d_pair_bscale, P->d_blk_toff, P->d_blk_tscale, P->d_cpl_soff, P->Bs_hi, P->Bs_lo,
-                P->Ss_hi, P->Ss_lo, P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo, P->d_ws};
-    e = launch_split_grouped(a, prec == DLPNO_FP16X2, P->workers, s);
-    phase_end(P, s);
-    return e;
+    for (int kind = ITEM_LADDER; kind <= ITEM_PROJ; ++kind) {
+      const int32_t cnt = kind == ITEM_LADDER ? nl : np;
+      if (cnt == 0) continue;
+      SplitArgs a{P->d_items + (kind == ITEM_LADDER ? 0 : nl), cnt, P->d_counter + kind, P->d_pairs, P->d_blocks,
+                  P->d_cpl, P->d_terms, P->d_pair_boff, P->d_pair_bscale, P->d_blk_toff, P->d_blk_tscale,
+                  P->d_cpl_soff, P->Bs_hi, P->Bs_lo, P->Ss_hi, P->Ss_lo, P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo,
+                  P->d_ws, general ? 0 : 1};
+      phase_begin(P, kind == ITEM_LADDER ? 0 : 5, s);
+      e = launch_split_grouped(a, kind, prec == DLPNO_FP16X2, P->workers, s);
+      phase_end(P, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
-  general = general || (P->opt.flags & DLPNO_FLAG_GENERAL_T) != 0;
   // ladder items, then projection items: each kind in its own launch of the
   // persistent kernel (own queue head), so that each is register-allocated alone
   for (int kind = ITEM_LADDER; kind <= ITEM_PROJ; ++kind) {

@@ -125,8 +125,10 @@ __device__ __forceinline__ f4_t mfma3x2(uint64_t ah0, uint64_t ah1, uint64_t al0
 // ---------------------------------------------------------------------------
 // ladder item (same schedule as the FP64 kernel; NT inner tiles of 16)
 // ---------------------------------------------------------------------------
-template <typename S, int NT, int NB, int NTA, int TA0>
+template <typename S, int NT, int NB, int NTA, int TA0, int MASK>
 __device__ __forceinline__ void split_ladder_item(const SplitArgs& A, const Item& it) {
+  // bit b of MASK: block b antisymmetric, stage 2 only for tiles with tb >= ta
+  auto mir = [](int b) { return ((MASK >> b) & 1) != 0; };
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
   const PairDev& Pg = A.pairs[it.pair];
@@ -214,8 +216,9 @@ __device__ __forceinline__ void split_ladder_item(const SplitArgs& A, const Item
         for (int u = 0; u < NTA; ++u)
 #pragma unroll
           for (int tb = 0; tb < NT; ++tb)
-            acc[b][tb][u] = mfma3x2<S>(Mh[tb][tp], Mh[tb][tp + 1], Ml[tb][tp], Ml[tb][tp + 1], yh[b][u][0],
-                                       yh[b][u][1], yl[b][u][0], yl[b][u][1], acc[b][tb][u]);
+            if (!mir(b) || tb >= TA0 + u)
+              acc[b][tb][u] = mfma3x2<S>(Mh[tb][tp], Mh[tb][tp + 1], Ml[tb][tp], Ml[tb][tp + 1], yh[b][u][0],
+                                         yh[b][u][1], yl[b][u][0], yl[b][u][1], acc[b][tb][u]);
     }
     if constexpr (NT % 2 == 1) {
       constexpr int td = NT - 1;
@@ -227,7 +230,8 @@ __device__ __forceinline__ void split_ladder_item(const SplitArgs& A, const Item
           split4<S>(stage1(Mh, Ml, b, td, u), 1.f, yh, yl);
 #pragma unroll
           for (int tb = 0; tb < NT; ++tb)
-            acc[b][tb][u] = mfma3x2<S>(Mh[tb][td], 0, Ml[tb][td], 0, yh, 0, yl, 0, acc[b][tb][u]);
+            if (!mir(b) || tb >= TA0 + u)
+              acc[b][tb][u] = mfma3x2<S>(Mh[tb][td], 0, Ml[tb][td], 0, yh, 0, yl, 0, acc[b][tb][u]);
         }
     }
   };
@@ -251,25 +255,17 @@ __device__ __forceinline__ void split_ladder_item(const SplitArgs& A, const Item
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     double* dst = A.ws + uni(A.blocks[blk0 + it.bslot0 + b].off_ws) + (int64_t)it.slot * nn;
-#pragma unroll
-    for (int tb = 0; tb < NT; ++tb)
-#pragma unroll
-      for (int u = 0; u < NTA; ++u) {
-        const int a = 16 * (TA0 + u) + r;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int bb = 16 * tb + 4 * g + i;
-          if (a < n && bb < n) dst[bb * n + a] = (double)acc[b][tb][u][i] * (double)unscale[b];
-        }
-      }
+    // FP32 accumulator layout: row 4 g + i
+    store_tiles<float>(dst, n, TA0, acc[b], mir(b), (double)unscale[b]);
   }
 }
 
 // ---------------------------------------------------------------------------
 // projection item: per coupling S fragments, per term source fragments
 // ---------------------------------------------------------------------------
-template <typename S, int NT, int NB>
+template <typename S, int NT, int NB, int MASK>
 __device__ __forceinline__ void split_proj_item(const SplitArgs& A, const Item& it) {
+  auto mir = [](int b) { return ((MASK >> b) & 1) != 0; };
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
   const PairDev& Pg = A.pairs[it.pair];
@@ -364,8 +360,9 @@ __device__ __forceinline__ void split_proj_item(const SplitArgs& A, const Item& 
           for (int u = 0; u < NT; ++u)
 #pragma unroll
             for (int tb = 0; tb < NT; ++tb)
-              acc[b][tb][u] = mfma3x2<S>(Mh[tb][tp], Mh[tb][tp + 1], Ml[tb][tp], Ml[tb][tp + 1], yh[u][0], yh[u][1],
-                                         yl[u][0], yl[u][1], acc[b][tb][u]);
+              if (!mir(b) || tb >= u)
+                acc[b][tb][u] = mfma3x2<S>(Mh[tb][tp], Mh[tb][tp + 1], Ml[tb][tp], Ml[tb][tp + 1], yh[u][0],
+                                           yh[u][1], yl[u][0], yl[u][1], acc[b][tb][u]);
         }
       }
     }
@@ -374,60 +371,75 @@ __device__ __forceinline__ void split_proj_item(const SplitArgs& A, const Item& 
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     double* dst = A.ws + uni(A.blocks[blk0 + it.bslot0 + b].off_ws) + (int64_t)it.slot * nn;
-    const double us = 1.0 / (double)tscale[b];
-#pragma unroll
-    for (int tb = 0; tb < NT; ++tb)
-#pragma unroll
-      for (int u = 0; u < NT; ++u) {
-        const int a = 16 * u + r;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int bb = 16 * tb + 4 * g + i;
-          if (a < n && bb < n) dst[bb * n + a] = (double)acc[b][tb][u][i] * us;
-        }
-      }
+    store_tiles<float>(dst, n, 0, acc[b], mir(b), 1.0 / (double)tscale[b]);
   }
 }
 
-template <typename S>
+// the antisymmetry pattern of the item's blocks selects a compiled body (as
+// in the FP64 kernel: four blocks AA, BB, AB, BA mirror the first two)
+__device__ __forceinline__ int split_mask(const SplitArgs& A, const Item& it, int nb) {
+  if (A.anti == 0) return 0;
+  const int blk0 = uni(A.pairs[it.pair].blk0);
+  int mask = 0;
+  for (int b = 0; b < nb; ++b) mask |= (uni(A.blocks[blk0 + it.bslot0 + b].anti) != 0 ? 1 : 0) << b;
+  const int mirror = nb == 4 ? 3 : (1 << nb) - 1;
+  return mask == mirror ? mirror : 0;
+}
+template <typename S, int NT, int NB, int NTA, int TA0>
+__device__ __forceinline__ void split_ladder_masked(const SplitArgs& A, const Item& it) {
+  constexpr int kMirror = NB == 4 ? 3 : (1 << NB) - 1;
+  if (split_mask(A, it, NB) == kMirror) split_ladder_item<S, NT, NB, NTA, TA0, kMirror>(A, it);
+  else split_ladder_item<S, NT, NB, NTA, TA0, 0>(A, it);
+}
+template <typename S, int NT, int NB>
+__device__ __forceinline__ void split_proj_masked(const SplitArgs& A, const Item& it) {
+  constexpr int kMirror = NB == 4 ? 3 : (1 << NB) - 1;
+  if (split_mask(A, it, NB) == kMirror) split_proj_item<S, NT, NB, kMirror>(A, it);
+  else split_proj_item<S, NT, NB, 0>(A, it);
+}
+
+template <typename S, int KIND>
 __device__ __forceinline__ void split_run_item(const SplitArgs& A, const Item& it) {
-  if (it.kind == ITEM_LADDER) {
+  if constexpr (KIND == ITEM_LADDER) {
     switch (it.variant) {
-      case 0: split_ladder_item<S, 1, 4, 1, 0>(A, it); break;
-      case 1: split_ladder_item<S, 1, 2, 1, 0>(A, it); break;
-      case 2: split_ladder_item<S, 1, 1, 1, 0>(A, it); break;
-      case 3: split_ladder_item<S, 2, 4, 2, 0>(A, it); break;
-      case 4: split_ladder_item<S, 2, 2, 2, 0>(A, it); break;
-      case 5: split_ladder_item<S, 2, 1, 2, 0>(A, it); break;
+      case 0: split_ladder_masked<S, 1, 4, 1, 0>(A, it); break;
+      case 1: split_ladder_masked<S, 1, 2, 1, 0>(A, it); break;
+      case 2: split_ladder_masked<S, 1, 1, 1, 0>(A, it); break;
+      case 3: split_ladder_masked<S, 2, 4, 2, 0>(A, it); break;
+      case 4: split_ladder_masked<S, 2, 2, 2, 0>(A, it); break;
+      case 5: split_ladder_masked<S, 2, 1, 2, 0>(A, it); break;
       case 6:
-        if (it.ta0 == 0) split_ladder_item<S, 2, 4, 1, 0>(A, it);
-        else split_ladder_item<S, 2, 4, 1, 1>(A, it);
+        if (it.ta0 == 0) split_ladder_masked<S, 2, 4, 1, 0>(A, it);
+        else split_ladder_masked<S, 2, 4, 1, 1>(A, it);
         break;
-      case 7: split_ladder_item<S, 3, 1, 3, 0>(A, it); break;
+      case 7: split_ladder_masked<S, 3, 1, 3, 0>(A, it); break;
       case 8:
-        if (it.ta0 == 0) split_ladder_item<S, 4, 1, 2, 0>(A, it);
-        else split_ladder_item<S, 4, 1, 2, 2>(A, it);
+        if (it.ta0 == 0) split_ladder_masked<S, 4, 1, 2, 0>(A, it);
+        else split_ladder_masked<S, 4, 1, 2, 2>(A, it);
         break;
       default: break;
     }
   } else {
     switch (it.variant >> 2) {     // variant = 4 * (tile variant) + (source tiles - 1)
-      case 0: split_proj_item<S, 1, 4>(A, it); break;
-      case 1: split_proj_item<S, 1, 2>(A, it); break;
-      case 2: split_proj_item<S, 1, 1>(A, it); break;
-      case 3: split_proj_item<S, 2, 4>(A, it); break;
-      case 4: split_proj_item<S, 2, 2>(A, it); break;
-      case 5: split_proj_item<S, 2, 1>(A, it); break;
-      case 6: split_proj_item<S, 3, 2>(A, it); break;
-      case 7: split_proj_item<S, 3, 1>(A, it); break;
-      case 8: split_proj_item<S, 4, 1>(A, it); break;
+      case 0: split_proj_masked<S, 1, 4>(A, it); break;
+      case 1: split_proj_masked<S, 1, 2>(A, it); break;
+      case 2: split_proj_masked<S, 1, 1>(A, it); break;
+      case 3: split_proj_masked<S, 2, 4>(A, it); break;
+      case 4: split_proj_masked<S, 2, 2>(A, it); break;
+      case 5: split_proj_masked<S, 2, 1>(A, it); break;
+      case 6: split_proj_masked<S, 3, 2>(A, it); break;
+      case 7: split_proj_masked<S, 3, 1>(A, it); break;
+      case 8: split_proj_masked<S, 4, 1>(A, it); break;
       default: break;
     }
   }
 }
 
-template <typename S>
-__global__ __launch_bounds__(256) void split_grouped_kernel(SplitArgs A) {
+// one launch per item kind (separate register allocation), as in the FP64
+// kernel; the projection launch fits two waves per SIMD (it uses no LDS and
+// fewer than 256 registers per lane), which hides more of its load latency
+template <typename S, int KIND>
+__global__ __launch_bounds__(256, KIND == ITEM_PROJ ? 2 : 1) void split_grouped_kernel(SplitArgs A) {
   const int lane = threadIdx.x & 63;
   for (;;) {
     int idx = 0;
@@ -444,7 +456,7 @@ __global__ __launch_bounds__(256) void split_grouped_kernel(SplitArgs A) {
     it.ta0 = uni(ig.ta0);
     it.lo = uni(ig.lo);
     it.hi = uni(ig.hi);
-    split_run_item<S>(A, it);
+    split_run_item<S, KIND>(A, it);
   }
 }
 
@@ -555,9 +567,14 @@ __global__ __launch_bounds__(256) void split_T_kernel(const BlockDev* blocks, co
   }
 }
 
-hipError_t launch_split_grouped(const SplitArgs& a, bool fp16, int workers, hipStream_t s) {
-  if (fp16) hipLaunchKernelGGL(split_grouped_kernel<SplitF16>, dim3(workers), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(split_grouped_kernel<SplitBf16>, dim3(workers), dim3(256), 0, s, a);
+hipError_t launch_split_grouped(const SplitArgs& a, int kind, bool fp16, int workers, hipStream_t s) {
+  if (kind == ITEM_LADDER) {
+    if (fp16) hipLaunchKernelGGL((split_grouped_kernel<SplitF16, ITEM_LADDER>), dim3(workers), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((split_grouped_kernel<SplitBf16, ITEM_LADDER>), dim3(workers), dim3(256), 0, s, a);
+  } else {
+    if (fp16) hipLaunchKernelGGL((split_grouped_kernel<SplitF16, ITEM_PROJ>), dim3(2 * workers), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((split_grouped_kernel<SplitBf16, ITEM_PROJ>), dim3(2 * workers), dim3(256), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -26,9 +26,11 @@ struct SplitArgs {
   const uint16_t* T_hi;       // amplitudes, plain copy [c][d]
   const uint16_t* T_lo;
   double* ws;
+  int32_t anti;               // same-spin blocks antisymmetric (see GroupedArgs::anti)
 };
 
-hipError_t launch_split_grouped(const SplitArgs& a, bool fp16, int workers, hipStream_t s);
+// kind: ITEM_LADDER or ITEM_PROJ; every item of `a` must be of that kind
+hipError_t launch_split_grouped(const SplitArgs& a, int kind, bool fp16, int workers, hipStream_t s);
 hipError_t launch_split_B(const PairDev* pairs, int npairs, const double* B, const int64_t* boff, float* bscale,
                           uint16_t* hi, uint16_t* lo, bool fp16, hipStream_t s);
 hipError_t launch_split_S(const PairDev* pairs, const int64_t* cpl_target, const CplDev* cpl, const double* S,
