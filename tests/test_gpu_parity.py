@@ -239,3 +239,35 @@ def test_diagonal_pairs_only_no_couplings():
     compare_blocks(prob, Tn.cpu().numpy(), Tno, rel=1e-12)
     assert abs(float(e_tot.cpu()[0]) - sum(eo.values())) <= 1e-10
     plan.close()
+
+
+def test_flop_count_profiling_and_autotune():
+    """dlpno_flop_count against the formula over the oracle's own term list;
+    phase timers count one launch per kind; the autotuner's schedule keeps
+    the residual at parity."""
+    prob = build_problem("chain", n_occ=24, band=6, somos=(7, 16))
+    plan, dev = device_problem(prob)
+    inp = oracle_inputs(prob)
+    T = unpack_T(prob, prob.materialize("T"))
+    somo = prob.is_somo.astype(bool)
+    lad = proj = 0.0
+    for p in range(prob.n_pairs):
+        n, m = int(prob.npno[p]), int(prob.naux[p])
+        for name in oracle.stored_blocks(int(prob.pi[p]), int(prob.pj[p]), somo):
+            lad += 4.0 * m * n ** 3
+            for (w, q, S, src) in oracle.model.projection_terms(inp, T, p, name):
+                nq = int(prob.npno[q])
+                proj += 2.0 * n * nq * (n + nq)
+    fl_l, fl_p = plan.flop_count()
+    assert (fl_l, fl_p) == (lad, proj)
+    plan.set_profiling(True)
+    plan.residual(dev["T"])
+    ms, cnt = plan.phase_times()
+    plan.set_profiling(False)
+    assert cnt[0] == 1 and cnt[5] == 1 and cnt[1] == 1 and ms[0] > 0 and ms[5] > 0
+    plan.autotune(dev["T"])
+    assert "autotune best" in plan.info()
+    R = plan.residual(dev["T"])
+    torch.cuda.synchronize()
+    compare_blocks(prob, R.cpu().numpy(), oracle.residual_os(inp, T), rel=1e-12)
+    plan.close()
