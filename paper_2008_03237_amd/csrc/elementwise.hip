@@ -58,6 +58,15 @@ __global__ __launch_bounds__(kEwThreads) void finish_kernel(FinishArgs a) {
     Tn = a.ring_vecs + o;
     err = a.ring_errs + o;
   }
+  // The partial slots hold Out^T (row b, column a): they are summed with
+  // coalesced reads into LDS and read back transposed (n <= 64).
+  __shared__ double part[64 * 64];
+  for (int idx = threadIdx.x; idx < nn; idx += kEwThreads) {
+    double v = 0.0;
+    for (int sl = 0; sl < bk.nslot; ++sl) v += ws[(int64_t)sl * nn + idx];
+    part[idx] = v;
+  }
+  __syncthreads();
   double esum = 0.0, rmax = 0.0;
   bool bad = false;
   for (int idx = threadIdx.x; idx < nn; idx += kEwThreads) {
@@ -70,7 +79,7 @@ __global__ __launch_bounds__(kEwThreads) void finish_kernel(FinishArgs a) {
       if (bk.anti) kk -= K[y * n + x];
     }
     double r = (a.drv ? a.drv[bk.off_T + idx] : kk) + D * t;
-    for (int sl = 0; sl < bk.nslot; ++sl) r += ws[(int64_t)sl * nn + y * n + x];   // slots hold Out^T
+    r += part[y * n + x];
     if (!isfinite(r)) bad = true;
     rmax = fmax(rmax, fabs(r));
     if (a.R) a.R[bk.off_T + idx] = r;
@@ -238,12 +247,24 @@ __device__ void sym_eigs(double* A, int n, double* ev) {
 // Gram update, bordered system [[<e_i,e_j>, -1], [-1, 0]] c = [0, -1] solved by
 // Gaussian elimination with partial pivoting; oldest vectors are dropped while
 // the matrix's 2-norm condition number exceeds 1e14.
-__global__ void diis_solve_kernel(DiisState* st, const double* partial, int nparts) {
+__global__ __launch_bounds__(256) void diis_solve_kernel(DiisState* st, const double* partial, int nparts) {
   const int cnt0 = st->count, head = st->head, mx = st->max;
-  // new Gram row (fixed-order sum over parts)
+  // new Gram row: the parts summed by 256 threads (thread t takes parts t,
+  // t + 256, ...), then a fixed-order reduction over the threads
+  __shared__ double lw[8][4];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    double v = 0.0;
+    if (k < cnt0)
+      for (int p = threadIdx.x; p < nparts; p += 256) v += partial[(int64_t)p * 8 + k];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) lw[k][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  // the small bordered solve on one thread
   for (int k = 0; k < cnt0; ++k) {
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += partial[(int64_t)p * 8 + k];
+    const double s = ((lw[k][0] + lw[k][1]) + lw[k][2]) + lw[k][3];
     const int slot = (head - k + mx) % mx;
     st->gram[head][slot] = s;
     st->gram[slot][head] = s;
@@ -408,7 +429,7 @@ hipError_t launch_diis_dots(const double* errs, int64_t n, DiisState* st, double
   return hipGetLastError();
 }
 hipError_t launch_diis_solve(DiisState* st, const double* partial, int nparts, hipStream_t s) {
-  hipLaunchKernelGGL(diis_solve_kernel, dim3(1), dim3(1), 0, s, st, partial, nparts);
+  hipLaunchKernelGGL(diis_solve_kernel, dim3(1), dim3(256), 0, s, st, partial, nparts);
   return hipGetLastError();
 }
 hipError_t launch_diis_extrap(const double* vecs, int64_t n, const DiisState* st, double* T, hipStream_t s) {
