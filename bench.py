@@ -286,14 +286,23 @@ def schedule_line(plan):
     return ""
 
 
+def _code_only(text):
+    """C++ source without comments and blank-line/indent differences."""
+    import re
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.strip() for line in text.splitlines() if line.strip())
+
+
 def kernel_source_sha():
-    """Hash of the grouped kernel's sources and of its schedule builder: the HBM
-    traffic record is used only while it describes this code."""
+    """Hash of the grouped kernel's sources and of its schedule builder,
+    comments left out: the HBM traffic record is used only while it describes
+    this code."""
     import hashlib
     h = hashlib.sha256()
     for f in ("grouped_impl.h", "grouped_f64.hip", "grouped_f32.hip", "internal.h", "plan.hip", "plan_internal.h"):
-        with open(os.path.join(ROOT, "paper_2008_03237_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2008_03237_amd", "csrc", f)) as fh:
+            h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

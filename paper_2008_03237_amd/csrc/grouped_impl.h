@@ -1,6 +1,8 @@
 // Persistent grouped kernel: every DF ladder and PNO-overlap projection
 // contraction of one residual evaluation, over all pairs of uneven PNO and
-// auxiliary sizes, in one launch.
+// auxiliary sizes.  Ladder items and projection items run as two launches of
+// the same persistent kernel (KIND), each with its own queue, so that each
+// body is register-allocated alone.
 //
 // Both contractions have the "sandwich" form  Out = M X M^T  summed over a
 // list of (M, X) pairs:
@@ -26,14 +28,22 @@
 // which register i again holds rows 4 i + g.  Either way register i of the
 // first product is exactly k-step i of the second.
 // K-steps of 4 beyond the inner dimension are skipped, so only the M and N
-// tile edges are padded to 16.  Operands are read with raw buffer loads whose
-// resource covers exactly one matrix: reads past its end return zero, and the
-// remaining padded reads land inside the same matrix, are finite, and only
-// reach rows or columns that are multiplied by those zeros or never stored.
+// tile edges are padded to 16; in FP64 the partial last ladder tile runs as
+// row strips of 4 (see mfma_strip).  Operands are read with raw buffer loads
+// whose resource covers exactly one matrix: reads past its end return zero,
+// and the remaining padded reads land inside the same matrix, are finite, and
+// only reach rows or columns that are multiplied by those zeros or never
+// stored.
+//
+// Same-spin blocks hold antisymmetric amplitudes, so their contributions are
+// antisymmetric: a compile-time block mask limits stage 2 to the tiles on and
+// below the diagonal, and store_tiles writes the others mirrored.
 //
 // The X-form operands live in a per-wave LDS slab (one 8-byte slot per lane
-// and operand, conflict free); the M operands of B^Q are double-buffered in
-// VGPRs so the next slice is in flight while the current one is contracted.
+// and operand, conflict free) or, for small tiles, in VGPRs; the M operands of
+// B^Q are double-buffered in VGPRs so the next slice is in flight while the
+// current one is contracted.  Projection items are software-pipelined one
+// (coupling, block) unit ahead.
 //
 // Work items come from a queue ordered longest-first; every wave pops items
 // with one atomic increment until the queue is empty (the exit condition every
