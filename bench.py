@@ -264,6 +264,24 @@ def mixed_leg(prob, dev, plan64, eps_a, eps_b, args, flops, log):
     conv_ms = ms[4] / max(cnt[4], 1)
     e64n = e64.cpu().numpy().reshape(-1, 4).sum(1)
     emn = em.cpu().numpy().reshape(-1, 4).sum(1)
+    # inner only: the low-precision residuals iterated (FP64 update, energies
+    # and DIIS) with no FP64 refinement, until max|R| stops falling
+    Ti = torch.zeros_like(T64)
+    mp.reset()
+    best, n_in = None, 0
+    while n_in < 40:
+        _, ei, eti, ri = mp.iterate(2, Ti)
+        n_in += 2
+        r_now = float(ri.cpu()[0])
+        if best is not None and r_now >= 0.5 * best:
+            break
+        best = r_now if best is None else min(best, r_now)
+    ein = ei.cpu().numpy().reshape(-1, 4).sum(1)
+    # split B and S (hi and lo halves, rows padded to 16) read by one split launch
+    n16 = 16 * ((prob.npno.astype(np.int64) + 15) // 16)
+    split_B = float((prob.naux.astype(np.int64) * prob.npno * n16 * prob.n_blocks().clip(0, 1)).sum()) * 2 * 2
+    tgt = np.repeat(np.arange(prob.n_pairs), np.diff(prob.cpl_rowptr))
+    split_S = float((prob.npno[tgt].astype(np.int64) * n16[prob.cpl_src]).sum()) * 2 * 2
     res = {"precision": args.mixed_precision, "refinements": args.mixed_outer, "inner_iterations": args.mixed_inner,
            "kernel_ms": round(k_ms, 3), "ladder_ms": round(k_lad, 3), "projection_ms": round(k_proj, 3),
            "split_T_ms": round(conv_ms, 3),
@@ -272,7 +290,12 @@ def mixed_leg(prob, dev, plan64, eps_a, eps_b, args, flops, log):
            "energy_fp64": float(et64.cpu()[0]), "energy_mixed": float(etm.cpu()[0]),
            "total_energy_error": abs(float(etm.cpu()[0]) - float(et64.cpu()[0])),
            "max_pair_energy_error": float(np.max(np.abs(emn - e64n))),
-           "max_abs_R_mixed": float(rm.cpu()[0])}
+           "max_abs_R_mixed": float(rm.cpu()[0]),
+           "inner_only": {"iterations": n_in, "max_abs_R": r_now,
+                          "total_energy_error": abs(float(eti.cpu()[0]) - float(et64.cpu()[0])),
+                          "max_pair_energy_error": float(np.max(np.abs(ein - e64n)))},
+           "split_bytes_per_launch": split_B + split_S,
+           "hbm_frac": round((split_B + split_S) / (k_ms / 1e3) / 8e12, 4)}
     log("mixed leg: %s" % res)
     mp.close()
     return res
