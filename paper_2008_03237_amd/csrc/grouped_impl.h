@@ -726,12 +726,10 @@ __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it
 template <typename F, int KIND>
 __global__ __launch_bounds__(256) void grouped_kernel(GroupedArgs<F> A) {
   __shared__ double lds[4 * kLdsWaveWords];
-  const int lane = threadIdx.x & 63;
+  int q = blockIdx.x % kQueues, left = kQueues;
   for (;;) {
-    int idx = 0;
-    if (lane == 0) idx = atomicAdd(A.counter, 1);
-    idx = __builtin_amdgcn_readfirstlane(idx);
-    if (idx >= A.n_items) break;
+    const int idx = next_item(A.q, q, left);
+    if (idx < 0) break;
     const Item& ig = A.items[idx];
     Item it;
     it.kind = uni(ig.kind);

@@ -51,6 +51,34 @@ struct Item {
   int32_t lo, hi;                // Q range (ladder) or coupling range (projection)
 };
 
+// Work queues of one launch, one per XCD.  The items of one pair and one Q or
+// coupling range (one partial slot) read the same B^Q or S slices; the
+// schedule puts them in the same queue, so that they run on one XCD at about
+// the same time and the repeated reads hit that XCD's L2.
+constexpr int kQueues = 8;
+struct WorkQueues {
+  int32_t off[kQueues + 1];      // queue k holds items [off[k], off[k+1])
+  int32_t* counter;              // kQueues heads, zeroed before each launch
+};
+
+// Pops the calling wave's next item, or returns -1 once every queue is empty.
+// Workgroups are dispatched to the eight XCDs round-robin by workgroup index,
+// so a workgroup starts on queue blockIdx.x % kQueues, the one of its own
+// XCD.  A wave drains that queue, then the following ones in turn; a failed
+// pop moves it on for good, so every wave ends after at most kQueues failed
+// pops and every item is taken exactly once.
+__device__ __forceinline__ int next_item(const WorkQueues& Q, int& q, int& left) {
+  while (left > 0) {
+    int idx = 0;
+    if ((threadIdx.x & 63) == 0) idx = atomicAdd(Q.counter + q, 1);
+    idx = __builtin_amdgcn_readfirstlane(idx) + Q.off[q];
+    if (idx < Q.off[q + 1]) return idx;
+    q = q + 1 == kQueues ? 0 : q + 1;
+    --left;
+  }
+  return -1;
+}
+
 // Tile variants compiled into the grouped kernel.
 // Ladder: (NT tiles of 16 per PNO index, NB blocks per item, NTA a-tiles per item).
 struct LadderVariant { int nt, nb, nta; };
@@ -66,8 +94,7 @@ constexpr ProjVariant kProjVariants[kNumProjVariants] = {
 template <typename F>
 struct GroupedArgs {
   const Item* items;
-  int32_t n_items;
-  int32_t* counter;              // work-queue head, zeroed before each launch
+  WorkQueues q;
   const PairDev* pairs;
   const BlockDev* blocks;
   const CplDev* cpl;

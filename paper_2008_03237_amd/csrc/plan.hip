@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <unordered_map>
 #include <utility>
 #include <vector>
 
@@ -246,14 +247,40 @@ dlpno_status build_schedule(dlpno_plan* P) {
     if (a.it.kind != b.it.kind) return a.it.kind == ITEM_LADDER;
     return a.cost > b.cost;
   });
+  // One queue per XCD.  The items of one (pair, slot) read the same B^Q or S
+  // slices and go to one queue; groups are dealt out in that order to the
+  // least-loaded queue, and each queue keeps the longest-first order.
   P->items_h.clear();
   P->items_h.reserve(cand.size());
   double maxc = 0.0;
   int nl = 0;
-  for (auto& c : cand) {
-    P->items_h.push_back(c.it);
-    maxc = std::max(maxc, c.cost);
-    nl += c.it.kind == ITEM_LADDER;
+  for (int kind = ITEM_LADDER; kind <= ITEM_PROJ; ++kind) {
+    std::vector<std::vector<Item>> qs(kQueues);
+    double load[kQueues] = {};
+    std::unordered_map<int64_t, int> group_q;
+    for (const Cand& c : cand) {
+      if (c.it.kind != kind) continue;
+      const int64_t key = ((int64_t)c.it.pair << 32) | (uint32_t)c.it.slot;
+      auto g = group_q.find(key);
+      int q = 0;
+      if (g != group_q.end()) {
+        q = g->second;
+      } else {
+        for (int k = 1; k < kQueues; ++k)
+          if (load[k] < load[q]) q = k;
+        group_q.emplace(key, q);
+      }
+      qs[q].push_back(c.it);
+      load[q] += c.cost;
+      maxc = std::max(maxc, c.cost);
+    }
+    const int32_t base = (int32_t)P->items_h.size();
+    for (int k = 0; k < kQueues; ++k) {
+      P->qoff[kind][k] = (int32_t)P->items_h.size() - base;
+      P->items_h.insert(P->items_h.end(), qs[k].begin(), qs[k].end());
+    }
+    P->qoff[kind][kQueues] = (int32_t)P->items_h.size() - base;
+    if (kind == ITEM_LADDER) nl = P->qoff[kind][kQueues];
   }
   P->n_ladder_items = nl;
   P->max_item_mfma = maxc;
@@ -522,7 +549,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if ((st = upload(&P->d_cpl, P->cpl_h, "coupling table", s)) != DLPNO_OK) return destroy_fail(st);
   if ((st = upload(&P->d_terms, P->terms_h, "term table", s)) != DLPNO_OK) return destroy_fail(st);
   if ((st = upload_schedule(P, s)) != DLPNO_OK) return destroy_fail(st);
-  if ((st = dev_alloc(&P->d_counter, 4, "queue counter")) != DLPNO_OK) return destroy_fail(st);
+  if ((st = dev_alloc(&P->d_counter, 2 * kQueues, "queue heads")) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_e_block, std::max(1, nblk_total), "block energies")) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_rmax_block, std::max(1, nblk_total), "block residual maxima")) != DLPNO_OK)
     return destroy_fail(st);
@@ -649,6 +676,14 @@ void phase_collect(dlpno_plan* P) {
 
 bool is_split(int prec) { return prec == DLPNO_BF16X2 || prec == DLPNO_FP16X2; }
 
+// the work queues of one kind's launch
+WorkQueues queues(const dlpno_plan* P, int kind) {
+  WorkQueues q{};
+  for (int k = 0; k <= kQueues; ++k) q.off[k] = P->qoff[kind][k];
+  q.counter = P->d_counter + kind * kQueues;
+  return q;
+}
+
 // grouped kernel over amplitudes T (FP64 buffer given by the caller) in the
 // plan's precision, or in `prec` when given (FP64 residuals of a split plan)
 hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, bool general) {
@@ -666,14 +701,14 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
       return e;
     phase_end(P, s);
   }
-  if ((e = launch_zero_i32(P->d_counter, 2, s)) != hipSuccess) return e;
+  if ((e = launch_zero_i32(P->d_counter, 2 * kQueues, s)) != hipSuccess) return e;
   general = general || (P->opt.flags & DLPNO_FLAG_GENERAL_T) != 0;
   const int32_t nl = P->n_ladder_items, np = (int32_t)P->items_h.size() - nl;
   if (is_split(prec)) {
     for (int kind = ITEM_LADDER; kind <= ITEM_PROJ; ++kind) {
       const int32_t cnt = kind == ITEM_LADDER ? nl : np;
       if (cnt == 0) continue;
-      SplitArgs a{P->d_items + (kind == ITEM_LADDER ? 0 : nl), cnt, P->d_counter + kind, P->d_pairs, P->d_blocks,
+      SplitArgs a{P->d_items + (kind == ITEM_LADDER ? 0 : nl), queues(P, kind), P->d_pairs, P->d_blocks,
                   P->d_cpl, P->d_terms, P->d_pair_boff, P->d_pair_bscale, P->d_blk_toff, P->d_blk_tscale,
                   P->d_cpl_soff, P->Bs_hi, P->Bs_lo, P->Ss_hi, P->Ss_lo, P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo,
                   P->d_ws, general ? 0 : 1};
@@ -685,19 +720,19 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
     return hipSuccess;
   }
   // ladder items, then projection items: each kind in its own launch of the
-  // persistent kernel (own queue head), so that each is register-allocated alone
+  // persistent kernel (own queues), so that each is register-allocated alone
   for (int kind = ITEM_LADDER; kind <= ITEM_PROJ; ++kind) {
     const int32_t cnt = kind == ITEM_LADDER ? nl : np;
     if (cnt == 0) continue;
     const Item* items = P->d_items + (kind == ITEM_LADDER ? 0 : nl);
-    int32_t* counter = P->d_counter + kind;
+    const WorkQueues wq = queues(P, kind);
     phase_begin(P, kind == ITEM_LADDER ? 0 : 5, s);
     if (prec == DLPNO_FP32) {
-      GroupedArgs<float> a{items, cnt, counter, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
+      GroupedArgs<float> a{items, wq, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
                            P->B32, P->S32, P->T32, P->d_ws, general ? 0 : 1};
       e = launch_grouped_f32(a, kind, P->workers, s);
     } else {
-      GroupedArgs<double> a{items, cnt, counter, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
+      GroupedArgs<double> a{items, wq, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
                             P->in.B, P->in.S, T, P->d_ws, general ? 0 : 1};
       e = launch_grouped_f64(a, kind, P->workers, s);
     }

@@ -46,6 +46,9 @@ struct dlpno_plan {
   std::vector<int64_t> rowptr_h;
   std::vector<dlpno::Item> items_h;     // ladder items first, then projection items
   int32_t n_ladder_items = 0;
+  // per kind: queue k holds items [qoff[kind][k], qoff[kind][k+1]) counted
+  // from the kind's first item
+  int32_t qoff[2][dlpno::kQueues + 1] = {};
   dlpno::Tuning tune;
   double flops_ladder = 0.0, flops_proj = 0.0, total_mfma = 0.0, max_item_mfma = 0.0;
   int64_t ws_elems = 0;
@@ -55,7 +58,7 @@ struct dlpno_plan {
   dlpno::CplDev* d_cpl = nullptr;
   dlpno::TermDev* d_terms = nullptr;
   dlpno::Item* d_items = nullptr;
-  int32_t* d_counter = nullptr;
+  int32_t* d_counter = nullptr;        // queue heads: kQueues per kind
   double* d_ws = nullptr;
   double* d_e_block = nullptr;
   double* d_rmax_block = nullptr;

@@ -440,12 +440,10 @@ __device__ __forceinline__ void split_run_item(const SplitArgs& A, const Item& i
 // fewer than 256 registers per lane), which hides more of its load latency
 template <typename S, int KIND>
 __global__ __launch_bounds__(256, KIND == ITEM_PROJ ? 2 : 1) void split_grouped_kernel(SplitArgs A) {
-  const int lane = threadIdx.x & 63;
+  int q = blockIdx.x % kQueues, left = kQueues;
   for (;;) {
-    int idx = 0;
-    if (lane == 0) idx = atomicAdd(A.counter, 1);
-    idx = __builtin_amdgcn_readfirstlane(idx);
-    if (idx >= A.n_items) break;
+    const int idx = next_item(A.q, q, left);
+    if (idx < 0) break;
     const Item& ig = A.items[idx];
     Item it;
     it.kind = uni(ig.kind);

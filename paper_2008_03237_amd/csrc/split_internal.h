@@ -6,8 +6,7 @@ namespace dlpno {
 
 struct SplitArgs {
   const Item* items;
-  int32_t n_items;
-  int32_t* counter;
+  WorkQueues q;
   const PairDev* pairs;
   const BlockDev* blocks;
   const CplDev* cpl;

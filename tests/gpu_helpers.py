@@ -5,7 +5,7 @@ import oracle
 from oracle.model import unpack_T
 
 
-def device_problem(prob, precision="fp64", diis_max=8, diis_start=3, T_random=True):
+def device_problem(prob, precision="fp64", diis_max=8, diis_start=3, T_random=True, **plan_options):
     import torch
     from paper_2008_03237_amd import Plan
     from workload.gpu import device_fields
@@ -13,7 +13,7 @@ def device_problem(prob, precision="fp64", diis_max=8, diis_start=3, T_random=Tr
     eps_a = torch.from_numpy(prob.eps_a).cuda()
     eps_b = torch.from_numpy(prob.eps_b).cuda()
     plan = Plan(prob, dev["B"], dev["S"], dev["K"], eps_a, eps_b, precision=precision, diis_max=diis_max,
-                diis_start=diis_start)
+                diis_start=diis_start, **plan_options)
     if not T_random:
         dev["T"].zero_()
     return plan, dev
