@@ -167,6 +167,9 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const F* p, uint32_t elem
 // are the 3-tile, 2-block ladder variant (2 * 3 * 12 operands of 64 lanes) and
 // the projection (4 * 16 operands).
 constexpr int kLdsWaveWords = 72 * 64;
+// ... and for the launch at two waves per SIMD (two workgroups per CU): the
+// 3-tile one-block ladder variant (3 * 12 operands)
+constexpr int kLdsWaveWords2 = 40 * 64;
 
 // Partial sums of one block into its workspace slot: acc[tb][u] holds the
 // Out^T tile with rows in b-tile tb and columns in a-tile ta0 + u (row b,
@@ -207,10 +210,12 @@ __device__ __forceinline__ void store_tiles(double* dst, int n, int ta0, const V
 // interleave (stage 1 of every block is issued before the stage 2 that reads
 // it).  REG keeps the X-form operands in VGPRs instead of the LDS slab.
 // ---------------------------------------------------------------------------
-template <typename F, int NT, int NB, int NTA, int TA0, int R, bool REG, int MASK>
+template <typename F, int NT, int NB, int NTA, int TA0, int R, bool REG, int MASK, bool W2>
 __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
   typedef typename Mfma<F>::V V;
   constexpr int S4 = 4 * (NT - 1) + R;
+  constexpr int LW = W2 ? kLdsWaveWords2 : kLdsWaveWords;
+  static_assert(NB * NT * S4 * 64 <= LW, "X slab exceeds the wave's LDS");
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4, pr = Mfma<F>::perm(r);
   const PairDev& Pg = A.pairs[it.pair];
@@ -218,7 +223,7 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
   const int blk0 = uni(Pg.blk0);
   const int64_t off_B = uni(Pg.off_B);
   const uint32_t nn = (uint32_t)n * (uint32_t)n;
-  F* Al = reinterpret_cast<F*>(lds + (size_t)(threadIdx.x >> 6) * kLdsWaveWords);
+  F* Al = reinterpret_cast<F*>(lds + (size_t)(threadIdx.x >> 6) * LW);
   // FP64 with a partial last tile (R < 4 k-steps in it): the last d-tile of
   // stage 1 and the last b-tile of stage 2 run as R row strips; the X operands
   // of that d-tile are then also kept in the LDS slab, where the strips read
@@ -335,14 +340,23 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
     }
   };
 
-  F M0[NT][S4], M1[NT][S4];
-  loadM(M0, it.lo);
-  for (int Q = it.lo; Q < it.hi; Q += 2) {
-    if (Q + 1 < it.hi) loadM(M1, Q + 1);
-    compute(M0);
-    if (Q + 1 >= it.hi) break;
-    if (Q + 2 < it.hi) loadM(M0, Q + 2);
-    compute(M1);
+  if constexpr (W2) {
+    // two waves per SIMD: one B^Q buffer; the other wave covers the loads
+    F M0[NT][S4];
+    for (int Q = it.lo; Q < it.hi; ++Q) {
+      loadM(M0, Q);
+      compute(M0);
+    }
+  } else {
+    F M0[NT][S4], M1[NT][S4];
+    loadM(M0, it.lo);
+    for (int Q = it.lo; Q < it.hi; Q += 2) {
+      if (Q + 1 < it.hi) loadM(M1, Q + 1);
+      compute(M0);
+      if (Q + 1 >= it.hi) break;
+      if (Q + 2 < it.hi) loadM(M0, Q + 2);
+      compute(M1);
+    }
   }
 
 #pragma unroll
@@ -645,7 +659,7 @@ __device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& i
 // The antisymmetry pattern of the item's blocks selects a compiled body: for
 // four blocks (AA, BB, AB, BA) the first two, otherwise all of them; any
 // other pattern computes every tile.
-template <typename F, int NT, int NB, int NTA, int TA0, int R, bool REG>
+template <typename F, int NT, int NB, int NTA, int TA0, int R, bool REG, bool W2>
 __device__ __forceinline__ void ladder_masked(const GroupedArgs<F>& A, const Item& it, double* lds) {
   int mask = 0;
   if (A.anti != 0) {
@@ -654,20 +668,21 @@ __device__ __forceinline__ void ladder_masked(const GroupedArgs<F>& A, const Ite
     for (int b = 0; b < NB; ++b) mask |= (uni(A.blocks[blk0 + it.bslot0 + b].anti) != 0 ? 1 : 0) << b;
   }
   constexpr int kMirror = NB == 4 ? 3 : (1 << NB) - 1;
-  if (mask == kMirror) ladder_item<F, NT, NB, NTA, TA0, R, REG, kMirror>(A, it, lds);
-  else ladder_item<F, NT, NB, NTA, TA0, R, REG, 0>(A, it, lds);
+  if (mask == kMirror) ladder_item<F, NT, NB, NTA, TA0, R, REG, kMirror, W2>(A, it, lds);
+  else ladder_item<F, NT, NB, NTA, TA0, R, REG, 0, W2>(A, it, lds);
 }
 
 // k-steps of 4 in the last 16-wide tile of the pair: R = ceil((n mod 16) / 4), 1..4
-#define DLPNO_LADDER(NT, NB, NTA, TA0, REG)                                      \
+#define DLPNO_LADDER_W(NT, NB, NTA, TA0, REG, W2)                                 \
   do {                                                                             \
     switch (rk) {                                                                  \
-      case 1: ladder_masked<F, NT, NB, NTA, TA0, 1, REG>(A, it, lds); break;       \
-      case 2: ladder_masked<F, NT, NB, NTA, TA0, 2, REG>(A, it, lds); break;       \
-      case 3: ladder_masked<F, NT, NB, NTA, TA0, 3, REG>(A, it, lds); break;       \
-      default: ladder_masked<F, NT, NB, NTA, TA0, 4, REG>(A, it, lds); break;      \
+      case 1: ladder_masked<F, NT, NB, NTA, TA0, 1, REG, W2>(A, it, lds); break;   \
+      case 2: ladder_masked<F, NT, NB, NTA, TA0, 2, REG, W2>(A, it, lds); break;   \
+      case 3: ladder_masked<F, NT, NB, NTA, TA0, 3, REG, W2>(A, it, lds); break;   \
+      default: ladder_masked<F, NT, NB, NTA, TA0, 4, REG, W2>(A, it, lds); break;  \
     }                                                                              \
   } while (0)
+#define DLPNO_LADDER(NT, NB, NTA, TA0, REG) DLPNO_LADDER_W(NT, NB, NTA, TA0, REG, false)
 
 template <typename F, int KIND>
 __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
@@ -691,6 +706,21 @@ __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it
         if (it.ta0 == 0) DLPNO_LADDER(4, 1, 2, 0, false);
         else DLPNO_LADDER(4, 1, 2, 2, false);
         break;
+      default: break;
+    }
+  } else if constexpr (KIND == ITEM_LADDER2) {
+    // items of at most three tiles at two waves per SIMD: variants whose X
+    // operands fit the smaller LDS slab or the smaller register budget
+    const int n = uni(A.pairs[it.pair].n);
+    const int rem = n - 16 * ((n - 1) >> 4);
+    const int rk = (rem + 3) >> 2;
+    switch (it.variant) {
+      case 0: DLPNO_LADDER_W(1, 4, 1, 0, true, true); break;
+      case 1: DLPNO_LADDER_W(1, 2, 1, 0, true, true); break;
+      case 2: DLPNO_LADDER_W(1, 1, 1, 0, true, true); break;
+      case 4: DLPNO_LADDER_W(2, 2, 2, 0, false, true); break;
+      case 5: DLPNO_LADDER_W(2, 1, 2, 0, false, true); break;
+      case 7: DLPNO_LADDER_W(3, 1, 3, 0, false, true); break;
       default: break;
     }
   } else {
@@ -720,12 +750,13 @@ __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it
   }
 }
 #undef DLPNO_LADDER
+#undef DLPNO_LADDER_W
 
 // One launch processes the items of one kind (KIND), so that the ladder and
 // projection bodies are register-allocated separately.
 template <typename F, int KIND>
-__global__ __launch_bounds__(256) void grouped_kernel(GroupedArgs<F> A) {
-  __shared__ double lds[4 * kLdsWaveWords];
+__global__ __launch_bounds__(256, KIND == ITEM_LADDER2 ? 2 : 1) void grouped_kernel(GroupedArgs<F> A) {
+  __shared__ double lds[4 * (KIND == ITEM_LADDER2 ? kLdsWaveWords2 : kLdsWaveWords)];
   int q = blockIdx.x % kQueues, left = kQueues;
   for (;;) {
     const int idx = next_item(A.q, q, left);

@@ -38,7 +38,12 @@ struct TermDev {
   int32_t src_blk;               // global index of the source block
 };
 
-enum ItemKind { ITEM_LADDER = 0, ITEM_PROJ = 1 };
+// ITEM_LADDER2: ladder items of an FP64 plan run by the launch at two waves
+// per SIMD (at most three tiles of 16 PNOs and the variants below).
+enum ItemKind { ITEM_LADDER = 0, ITEM_PROJ = 1, ITEM_LADDER2 = 2 };
+constexpr int kKinds = 3;
+// launch order of the kinds within one residual
+constexpr int kKindOrder[kKinds] = {ITEM_LADDER2, ITEM_LADDER, ITEM_PROJ};
 
 // One scheduled unit of the grouped kernel.
 struct Item {
@@ -86,6 +91,9 @@ struct ProjVariant { int nt, nb; };
 constexpr int kNumLadderVariants = 9;
 constexpr LadderVariant kLadderVariants[kNumLadderVariants] = {
     {1, 4, 1}, {1, 2, 1}, {1, 1, 1}, {2, 4, 2}, {2, 2, 2}, {2, 1, 2}, {2, 4, 1}, {3, 1, 3}, {4, 1, 2}};
+// ladder variants compiled into the two-wave launch: their X operands fit a
+// 40-operand LDS slab (or registers) and their registers fit 256 per lane
+constexpr bool kLadderTwoWave[kNumLadderVariants] = {true, true, true, false, true, true, false, true, false};
 constexpr int kNumProjVariants = 9;
 constexpr ProjVariant kProjVariants[kNumProjVariants] = {
     {1, 4}, {1, 2}, {1, 1}, {2, 4}, {2, 2}, {2, 1}, {3, 2}, {3, 1}, {4, 1}};
@@ -111,7 +119,8 @@ struct GroupedArgs {
 };
 
 // kernels.hip
-// kind: ITEM_LADDER or ITEM_PROJ; every item of `a` must be of that kind
+// kind: ITEM_LADDER, ITEM_LADDER2 (FP64 only) or ITEM_PROJ; every item of
+// `a` must be of that kind
 hipError_t launch_grouped_f64(const GroupedArgs<double>& a, int kind, int workers, hipStream_t s);
 hipError_t launch_grouped_f32(const GroupedArgs<float>& a, int kind, int workers, hipStream_t s);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);

@@ -127,6 +127,7 @@ int pick_proj(int nt, int maxnb) {
 dlpno_status build_schedule(dlpno_plan* P) {
   const int npairs = P->n_pairs;
   const bool strips = P->opt.precision == DLPNO_FP64;
+  const bool two_wave = P->opt.precision == DLPNO_FP64 && P->tune.two_wave;
   std::vector<int> nL(npairs, 0), nP(npairs, 0);
   struct Cand { Item it; double cost; };
   std::vector<Cand> cand;
@@ -168,7 +169,7 @@ dlpno_status build_schedule(dlpno_plan* P) {
         const LadderVariant W = kLadderVariants[v];
         for (int ta0 = 0; ta0 < nt; ta0 += W.nta) {
           Item it{};
-          it.kind = ITEM_LADDER;
+          it.kind = two_wave && kLadderTwoWave[v] ? ITEM_LADDER2 : ITEM_LADDER;
           it.variant = v;
           it.pair = p;
           it.bslot0 = b0;
@@ -241,10 +242,12 @@ dlpno_status build_schedule(dlpno_plan* P) {
     }
   }
   P->ws_elems = ws;
-  // ladder items, then projection items (one queue and one launch each);
+  // items by kind in launch order (one set of queues and one launch each);
   // longest first within a kind, ties by pair for a deterministic order
-  std::stable_sort(cand.begin(), cand.end(), [](const Cand& a, const Cand& b) {
-    if (a.it.kind != b.it.kind) return a.it.kind == ITEM_LADDER;
+  int rank[kKinds];
+  for (int k = 0; k < kKinds; ++k) rank[kKindOrder[k]] = k;
+  std::stable_sort(cand.begin(), cand.end(), [&](const Cand& a, const Cand& b) {
+    if (a.it.kind != b.it.kind) return rank[a.it.kind] < rank[b.it.kind];
     return a.cost > b.cost;
   });
   // One queue per XCD.  The items of one (pair, slot) read the same B^Q or S
@@ -253,8 +256,7 @@ dlpno_status build_schedule(dlpno_plan* P) {
   P->items_h.clear();
   P->items_h.reserve(cand.size());
   double maxc = 0.0;
-  int nl = 0;
-  for (int kind = ITEM_LADDER; kind <= ITEM_PROJ; ++kind) {
+  for (int kind : kKindOrder) {
     std::vector<std::vector<Item>> qs(kQueues);
     double load[kQueues] = {};
     std::unordered_map<int64_t, int> group_q;
@@ -280,9 +282,9 @@ dlpno_status build_schedule(dlpno_plan* P) {
       P->items_h.insert(P->items_h.end(), qs[k].begin(), qs[k].end());
     }
     P->qoff[kind][kQueues] = (int32_t)P->items_h.size() - base;
-    if (kind == ITEM_LADDER) nl = P->qoff[kind][kQueues];
+    P->kind_begin[kind] = base;
+    P->kind_count[kind] = P->qoff[kind][kQueues];
   }
-  P->n_ladder_items = nl;
   P->max_item_mfma = maxc;
   return DLPNO_OK;
 }
@@ -310,20 +312,19 @@ dlpno_status dlpno::upload_schedule(dlpno_plan* P, hipStream_t s) {
 
 std::string dlpno::describe(const dlpno_plan* P) {
   char buf[1024];
-  int nl = 0, np = 0;
-  for (auto& it : P->items_h) (it.kind == ITEM_LADDER ? nl : np)++;
   std::string s;
   snprintf(buf, sizeof buf,
-           "pairs=%d blocks=%d couplings=%lld terms=%lld precision=%d workers=%d items=%zu (ladder %d, "
-           "projection %d) max_item/total=%.2e workspace=%.3f GB\n",
+           "pairs=%d blocks=%d couplings=%lld terms=%lld precision=%d workers=%d items=%zu (ladder %d, ladder at two "
+           "waves per SIMD %d, projection %d) max_item/total=%.2e workspace=%.3f GB\n",
            P->n_pairs, P->n_blocks, (long long)P->n_cpl, (long long)P->n_terms, (int)P->opt.precision, P->workers,
-           P->items_h.size(), nl, np, P->total_mfma > 0 ? P->max_item_mfma / P->total_mfma : 0.0,
-           P->ws_elems * 8.0 / 1e9);
+           P->items_h.size(), P->kind_count[ITEM_LADDER], P->kind_count[ITEM_LADDER2], P->kind_count[ITEM_PROJ],
+           P->total_mfma > 0 ? P->max_item_mfma / P->total_mfma : 0.0, P->ws_elems * 8.0 / 1e9);
   s += buf;
-  snprintf(buf, sizeof buf, "ladder variants by tiles: %d %d %d %d; projection: %d %d %d %d; items/wave %.1f\n",
+  snprintf(buf, sizeof buf,
+           "ladder variants by tiles: %d %d %d %d%s; projection: %d %d %d %d; items/wave %.1f\n",
            P->tune.ladder_variant[0], P->tune.ladder_variant[1], P->tune.ladder_variant[2], P->tune.ladder_variant[3],
-           P->tune.proj_variant[0], P->tune.proj_variant[1], P->tune.proj_variant[2], P->tune.proj_variant[3],
-           P->tune.items_per_wave);
+           P->kind_count[ITEM_LADDER2] > 0 ? " (two-wave launch)" : "", P->tune.proj_variant[0],
+           P->tune.proj_variant[1], P->tune.proj_variant[2], P->tune.proj_variant[3], P->tune.items_per_wave);
   s += buf;
   snprintf(buf, sizeof buf, "flops/residual: ladder %.4e projection %.4e\n", P->flops_ladder, P->flops_proj);
   s += buf;
@@ -543,13 +544,16 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   P->num_cu = prop.multiProcessorCount;
   P->workers = opt.n_workers > 0 ? opt.n_workers : P->num_cu;
   if (opt.chunk_flops > 0) P->tune.items_per_wave = std::max(1.0, (double)opt.chunk_flops);
+  // FP64: two-tile pairs two blocks per item, in the two-wave ladder launch
+  // (the four-block variant's X operands do not fit its LDS slab)
+  if (opt.precision == DLPNO_FP64) P->tune.ladder_variant[1] = 4;
   dlpno_status st;
   if ((st = build_schedule(P)) != DLPNO_OK) return destroy_fail(st);
   if ((st = upload(&P->d_pairs, P->pairs_h, "pair table", s)) != DLPNO_OK) return destroy_fail(st);
   if ((st = upload(&P->d_cpl, P->cpl_h, "coupling table", s)) != DLPNO_OK) return destroy_fail(st);
   if ((st = upload(&P->d_terms, P->terms_h, "term table", s)) != DLPNO_OK) return destroy_fail(st);
   if ((st = upload_schedule(P, s)) != DLPNO_OK) return destroy_fail(st);
-  if ((st = dev_alloc(&P->d_counter, 2 * kQueues, "queue heads")) != DLPNO_OK) return destroy_fail(st);
+  if ((st = dev_alloc(&P->d_counter, kKinds * kQueues, "queue heads")) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_e_block, std::max(1, nblk_total), "block energies")) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_rmax_block, std::max(1, nblk_total), "block residual maxima")) != DLPNO_OK)
     return destroy_fail(st);
@@ -701,14 +705,12 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
       return e;
     phase_end(P, s);
   }
-  if ((e = launch_zero_i32(P->d_counter, 2 * kQueues, s)) != hipSuccess) return e;
+  if ((e = launch_zero_i32(P->d_counter, kKinds * kQueues, s)) != hipSuccess) return e;
   general = general || (P->opt.flags & DLPNO_FLAG_GENERAL_T) != 0;
-  const int32_t nl = P->n_ladder_items, np = (int32_t)P->items_h.size() - nl;
   if (is_split(prec)) {
-    for (int kind = ITEM_LADDER; kind <= ITEM_PROJ; ++kind) {
-      const int32_t cnt = kind == ITEM_LADDER ? nl : np;
-      if (cnt == 0) continue;
-      SplitArgs a{P->d_items + (kind == ITEM_LADDER ? 0 : nl), queues(P, kind), P->d_pairs, P->d_blocks,
+    for (int kind : {ITEM_LADDER, ITEM_PROJ}) {
+      if (P->kind_count[kind] == 0) continue;
+      SplitArgs a{P->d_items + P->kind_begin[kind], queues(P, kind), P->d_pairs, P->d_blocks,
                   P->d_cpl, P->d_terms, P->d_pair_boff, P->d_pair_bscale, P->d_blk_toff, P->d_blk_tscale,
                   P->d_cpl_soff, P->Bs_hi, P->Bs_lo, P->Ss_hi, P->Ss_lo, P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo,
                   P->d_ws, general ? 0 : 1};
@@ -719,14 +721,14 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
     }
     return hipSuccess;
   }
-  // ladder items, then projection items: each kind in its own launch of the
-  // persistent kernel (own queues), so that each is register-allocated alone
-  for (int kind = ITEM_LADDER; kind <= ITEM_PROJ; ++kind) {
-    const int32_t cnt = kind == ITEM_LADDER ? nl : np;
-    if (cnt == 0) continue;
-    const Item* items = P->d_items + (kind == ITEM_LADDER ? 0 : nl);
+  // each kind in its own launch of the persistent kernel (own queues), so
+  // that each is register-allocated alone; the two-wave ladder launch exists
+  // in FP64 plans only
+  for (int kind : kKindOrder) {
+    if (P->kind_count[kind] == 0) continue;
+    const Item* items = P->d_items + P->kind_begin[kind];
     const WorkQueues wq = queues(P, kind);
-    phase_begin(P, kind == ITEM_LADDER ? 0 : 5, s);
+    phase_begin(P, kind == ITEM_LADDER ? 0 : kind == ITEM_LADDER2 ? 6 : 5, s);
     if (prec == DLPNO_FP32) {
       GroupedArgs<float> a{items, wq, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
                            P->B32, P->S32, P->T32, P->d_ws, general ? 0 : 1};

@@ -14,13 +14,14 @@ namespace dlpno {
 
 constexpr int kHistCap = 4096;   // iterations kept in the device history
 constexpr int kDiisParts = 1024; // workgroups of the DIIS dot-product kernel
-constexpr int kPhases = 6;
+constexpr int kPhases = 7;
 
 // schedule choices (set by defaults or the autotuner)
 struct Tuning {
-  int ladder_variant[4] = {0, 3, 7, 8};   // by tiles of 16 PNOs (1..4)
+  int ladder_variant[4] = {0, 3, 7, 8};   // by tiles of 16 PNOs (1..4); FP64 plans start from 0 4 7 8
   int proj_variant[4] = {0, 4, 7, 8};
   double items_per_wave = 6.0;            // target items per wavefront of the queue
+  bool two_wave = true;                   // FP64: ladder variants of kLadderTwoWave at two waves per SIMD
   double min_item_mfma = 2048.0;          // smallest item worth scheduling alone
 };
 
@@ -44,11 +45,11 @@ struct dlpno_plan {
   std::vector<dlpno::CplDev> cpl_h;
   std::vector<dlpno::TermDev> terms_h;
   std::vector<int64_t> rowptr_h;
-  std::vector<dlpno::Item> items_h;     // ladder items first, then projection items
-  int32_t n_ladder_items = 0;
+  std::vector<dlpno::Item> items_h;     // items by kind, in launch order (kKindOrder)
+  int32_t kind_begin[dlpno::kKinds] = {}, kind_count[dlpno::kKinds] = {};
   // per kind: queue k holds items [qoff[kind][k], qoff[kind][k+1]) counted
   // from the kind's first item
-  int32_t qoff[2][dlpno::kQueues + 1] = {};
+  int32_t qoff[dlpno::kKinds][dlpno::kQueues + 1] = {};
   dlpno::Tuning tune;
   double flops_ladder = 0.0, flops_proj = 0.0, total_mfma = 0.0, max_item_mfma = 0.0;
   int64_t ws_elems = 0;

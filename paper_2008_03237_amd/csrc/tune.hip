@@ -87,6 +87,15 @@ extern "C" dlpno_status dlpno_autotune(dlpno_plan* P, const double* T, double* R
       else P->tune.proj_variant[nt - 1] = keep;
     }
   }
+  if (P->opt.precision == DLPNO_FP64) {
+    P->tune.two_wave = !P->tune.two_wave;
+    if ((st = apply(P, s)) != DLPNO_OK) return st;
+    const float t = time_grouped(P, T, s, 3);
+    snprintf(buf, sizeof buf, "  two-wave ladder launch %s: %.3f ms\n", P->tune.two_wave ? "on" : "off", t);
+    log += buf;
+    if (t > 0 && t < best * (1.f - kMinGain)) best = t;
+    else P->tune.two_wave = !P->tune.two_wave;
+  }
   const double ipw[] = {2.0, 4.0, 6.0, 10.0, 16.0};
   for (double x : ipw) {
     if (x == P->tune.items_per_wave) continue;

@@ -233,9 +233,9 @@ class Plan:
         _check(lib().dlpno_set_profiling(self._h, 1 if on else 0))
 
     def phase_times(self):
-        ms = (C.c_double * 6)()
-        n = (C.c_int64 * 6)()
-        _check(lib().dlpno_phase_times(self._h, ms, n, 6))
+        ms = (C.c_double * 7)()
+        n = (C.c_int64 * 7)()
+        _check(lib().dlpno_phase_times(self._h, ms, n, 7))
         return list(ms), list(n)
 
     def info(self):
