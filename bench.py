@@ -166,13 +166,15 @@ def main():
     torch.cuda.synchronize()
     ms_graph = (time.perf_counter() - t0) / max(args.steps, 1) * 1e3
 
-    # dominant kernel: the grouped kernel over the ladder items, in two
+    # dominant kernel: the grouped kernel over the ladder items, in up to three
     # launches per residual (phase 6: pairs of at most three PNO tiles at two
-    # waves per SIMD; phase 0: the rest at one); its projection launch
-    # (phase 5) is reported beside it
+    # waves per SIMD; phase 7: four-tile pairs, one workgroup per item, two
+    # waves per SIMD; phase 0: anything else, one wave per SIMD); its
+    # projection launch (phase 5) is reported beside it
     lad1_ms = ms[0] / max(cnt[0], 1)
     lad2_ms = ms[6] / max(cnt[6], 1)
-    kern_ms = lad1_ms + lad2_ms
+    lad4_ms = ms[7] / max(cnt[7], 1)
+    kern_ms = lad1_ms + lad2_ms + lad4_ms
     proj_ms = ms[5] / max(cnt[5], 1)
     achieved = fl_ladder / (kern_ms / 1e3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
@@ -206,8 +208,9 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,
                      "kernel": "grouped_kernel<%s, ladder items>" % ("double" if args.precision == "fp64" else "float"),
-                     "kernel_ms": round(kern_ms, 3), "residuals": int(max(cnt[0], cnt[6])),
-                     "launch_ms": {"two_waves_per_simd": round(lad2_ms, 3), "one_wave_per_simd": round(lad1_ms, 3)},
+                     "kernel_ms": round(kern_ms, 3), "residuals": int(max(cnt[0], cnt[6], cnt[7])),
+                     "launch_ms": {"two_waves_per_simd": round(lad2_ms, 3), "cooperative": round(lad4_ms, 3),
+                                   "one_wave_per_simd": round(lad1_ms, 3)},
                      "flops_per_launch": fl_ladder, "schedule": schedule},
         "projection_kernel": {"kernel": "grouped_kernel<%s, projection items>" % (
                                   "double" if args.precision == "fp64" else "float"),
@@ -218,8 +221,8 @@ def main():
         "energy_last": float(E_hist[-1]) if len(E_hist) else None,
         "setup_s": round(setup_s, 1),
     }
-    log("grouped kernel: ladder %.3f ms (two-wave launch %.3f, one-wave launch %.3f), projection %.3f ms per residual"
-        % (kern_ms, lad2_ms, lad1_ms, proj_ms))
+    log("grouped kernel: ladder %.3f ms (two-wave launch %.3f, cooperative %.3f, one-wave %.3f), projection %.3f ms "
+        "per residual" % (kern_ms, lad2_ms, lad4_ms, lad1_ms, proj_ms))
     if not args.no_mixed:
         out["mixed"] = mixed_leg(prob, dev, plan, eps_a, eps_b, args, flops, log)
     if not args.no_cpu_baseline:

@@ -1,8 +1,12 @@
 // Persistent grouped kernel: every DF ladder and PNO-overlap projection
 // contraction of one residual evaluation, over all pairs of uneven PNO and
-// auxiliary sizes.  Ladder items and projection items run as two launches of
-// the same persistent kernel (KIND), each with its own queue, so that each
-// body is register-allocated alone.
+// auxiliary sizes.  Ladder items and projection items run as separate
+// launches of the same persistent kernel (KIND), each with its own queues, so
+// that each body is register-allocated alone.  In FP64 the ladder items of
+// pairs with at most three PNO tiles run at two waves per SIMD (one B^Q
+// buffer, a smaller LDS slab), and those of four-tile pairs in a cooperative
+// launch, also at two waves per SIMD, in which a whole workgroup takes one
+// item of two blocks and each pair of waves shares one block's X slab.
 //
 // Both contractions have the "sandwich" form  Out = M X M^T  summed over a
 // list of (M, X) pairs:
@@ -40,14 +44,15 @@
 // below the diagonal, and store_tiles writes the others mirrored.
 //
 // The X-form operands live in a per-wave LDS slab (one 8-byte slot per lane
-// and operand, conflict free) or, for small tiles, in VGPRs; the M operands of
-// B^Q are double-buffered in VGPRs so the next slice is in flight while the
-// current one is contracted.  Projection items are software-pipelined one
-// (coupling, block) unit ahead.
+// and operand, conflict free) or, for small tiles, in VGPRs; at one wave per
+// SIMD the M operands of B^Q are double-buffered in VGPRs so the next slice is
+// in flight while the current one is contracted.  Projection items are
+// software-pipelined one (coupling, block) unit ahead.
 //
-// Work items come from a queue ordered longest-first; every wave pops items
-// with one atomic increment until the queue is empty (the exit condition every
-// wave reaches).  Each item writes its partial sums to a private workspace
+// Work items come from one queue per XCD, each ordered longest-first (see
+// next_item); every wave (cooperative launch: every workgroup) pops items with
+// one atomic increment until all queues are empty, the exit condition every
+// wave reaches.  Each item writes its partial sums to a private workspace
 // slot; the finishing kernel adds the slots in a fixed order, so results are
 // bitwise reproducible.
 #pragma once
@@ -170,23 +175,26 @@ constexpr int kLdsWaveWords = 72 * 64;
 // ... and for the launch at two waves per SIMD (two workgroups per CU): the
 // 3-tile one-block ladder variant (3 * 12 operands)
 constexpr int kLdsWaveWords2 = 40 * 64;
+// ... and per pair of waves in the cooperative four-tile launch (two
+// workgroups per CU, two slabs each): 4 * 16 operands
+constexpr int kCoopSlabWords = 64 * 64;
 
 // Partial sums of one block into its workspace slot: acc[tb][u] holds the
-// Out^T tile with rows in b-tile tb and columns in a-tile ta0 + u (row b,
+// Out^T tile with rows in b-tile tb and columns in a-tile ta0 + u dta (row b,
 // column a stored at b n + a, coalesced over r).  mirror: the block's result
 // is antisymmetric; tiles above the diagonal (tb < ta) were not computed and
 // are written as the negated transpose of the tile below it, by whichever item
 // owns that tile's a-tile.
 template <typename F, int NT, int NU, typename V>
 __device__ __forceinline__ void store_tiles(double* dst, int n, int ta0, const V (&acc)[NT][NU], bool mirror,
-                                            double scale = 1.0) {
+                                            double scale = 1.0, int dta = 1) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int tb = 0; tb < NT; ++tb)
 #pragma unroll
     for (int u = 0; u < NU; ++u) {
-      const int ta = ta0 + u;
+      const int ta = ta0 + u * dta;
       if (mirror && tb < ta) continue;
       const int a = 16 * ta + r;
 #pragma unroll
@@ -202,20 +210,29 @@ __device__ __forceinline__ void store_tiles(double* dst, int n, int ta0, const V
 }
 
 // ---------------------------------------------------------------------------
-// Ladder item: pair p, NB consecutive blocks, a-tiles TA0..TA0+NTA-1,
-// Q in [lo, hi).  Partial Out^T[b][a] of sum_Q B^Q T B^Q^T.
+// Ladder item: pair p, NB consecutive blocks, a-tiles TA0 + u DTA for
+// u < NTA, Q in [lo, hi).  Partial Out^T[b][a] of sum_Q B^Q T B^Q^T.
 // The inner (k) dimension runs over S4 = 4 (NT - 1) + R steps of 4, R in
 // 1..4: n is padded to a multiple of 4, and with every trip count known at
 // compile time one Q slice is a single basic block that the scheduler can
 // interleave (stage 1 of every block is issued before the stage 2 that reads
 // it).  REG keeps the X-form operands in VGPRs instead of the LDS slab.
+// W2: the launch runs two waves per SIMD (one B^Q buffer, smaller slab).
+// COOP: one wave's share of a cooperative item (see ladder_coop).
 // ---------------------------------------------------------------------------
-template <typename F, int NT, int NB, int NTA, int TA0, int R, bool REG, int MASK, bool W2>
+template <typename F, int NT, int NB, int NTA, int TA0, int R, bool REG, int MASK, bool W2, int DTA = 1,
+          bool COOP = false>
 __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
   typedef typename Mfma<F>::V V;
   constexpr int S4 = 4 * (NT - 1) + R;
-  constexpr int LW = W2 ? kLdsWaveWords2 : kLdsWaveWords;
+  constexpr int LW = COOP ? kCoopSlabWords : W2 ? kLdsWaveWords2 : kLdsWaveWords;
   static_assert(NB * NT * S4 * 64 <= LW, "X slab exceeds the wave's LDS");
+  // a-tile of accumulator column u
+  auto ta = [](int u) { return TA0 + u * DTA; };
+  // cooperative items: waves 2h and 2h + 1 take block h of the item and
+  // share its X slab (both write it whole, with the same values)
+  const int wave = threadIdx.x >> 6;
+  const int bslot0 = it.bslot0 + (COOP ? (wave >> 1) : 0);
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4, pr = Mfma<F>::perm(r);
   const PairDev& Pg = A.pairs[it.pair];
@@ -223,7 +240,7 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
   const int blk0 = uni(Pg.blk0);
   const int64_t off_B = uni(Pg.off_B);
   const uint32_t nn = (uint32_t)n * (uint32_t)n;
-  F* Al = reinterpret_cast<F*>(lds + (size_t)(threadIdx.x >> 6) * LW);
+  F* Al = reinterpret_cast<F*>(lds + (size_t)(COOP ? (wave >> 1) : wave) * LW);
   // FP64 with a partial last tile (R < 4 k-steps in it): the last d-tile of
   // stage 1 and the last b-tile of stage 2 run as R row strips; the X operands
   // of that d-tile are then also kept in the LDS slab, where the strips read
@@ -234,7 +251,7 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
   // X-form operands of the NB amplitude blocks, once per item
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    const int64_t off_T = uni(A.blocks[blk0 + it.bslot0 + b].off_T);
+    const int64_t off_T = uni(A.blocks[blk0 + bslot0 + b].off_T);
     const __amdgpu_buffer_rsrc_t tr = rsrc(A.T + off_T, nn);
     const uint32_t base = (uint32_t)(g * n + pr);
 #pragma unroll
@@ -292,12 +309,12 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
             for (int i = 0; i < R; ++i) {
               const F av = aop_strip(b, s, i);
 #pragma unroll
-              for (int u = 0; u < NTA; ++u) d1[b][u][i] = mfma_strip(av, M[TA0 + u][s], d1[b][u][i]);
+              for (int u = 0; u < NTA; ++u) d1[b][u][i] = mfma_strip(av, M[ta(u)][s], d1[b][u][i]);
             }
           } else {
             const F av = aop(b, td, s);
 #pragma unroll
-            for (int u = 0; u < NTA; ++u) d1[b][u] = Mfma<F>::op(av, M[TA0 + u][s], d1[b][u]);
+            for (int u = 0; u < NTA; ++u) d1[b][u] = Mfma<F>::op(av, M[ta(u)][s], d1[b][u]);
           }
         }
       }
@@ -312,7 +329,7 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
               for (int tb = 0; tb < (STRIPS ? NT - 1 : NT); ++tb)
 #pragma unroll
                 for (int u = 0; u < NTA; ++u)
-                  if (tb >= TA0 + u) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[b][u][i], acc[b][tb][u]);
+                  if (tb >= ta(u)) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[b][u][i], acc[b][tb][u]);
             } else {
 #pragma unroll
               for (int tb = 0; tb < (STRIPS ? NT - 1 : NT); ++tb)
@@ -361,8 +378,8 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
 
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
-    double* dst = A.ws + uni(A.blocks[blk0 + it.bslot0 + b].off_ws) + (int64_t)it.slot * nn;
-    store_tiles<F>(dst, n, TA0, acc[b], mir(b));
+    double* dst = A.ws + uni(A.blocks[blk0 + bslot0 + b].off_ws) + (int64_t)it.slot * nn;
+    store_tiles<F>(dst, n, TA0, acc[b], mir(b), 1.0, DTA);
   }
 }
 
@@ -752,6 +769,39 @@ __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it
 #undef DLPNO_LADDER
 #undef DLPNO_LADDER_W
 
+// Cooperative four-tile ladder item, run by one workgroup: the item has nbi
+// (1 or 2) blocks; waves 2h and 2h + 1 take block h, two a-tiles each: {0, 3}
+// and {1, 2} when the block is antisymmetric (five stage-2 tiles each), {0, 1}
+// and {2, 3} otherwise.  Waves without a block go straight to the next
+// barrier of the launch loop.
+template <typename F, int R>
+__device__ __forceinline__ void ladder_coop(const GroupedArgs<F>& A, const Item& it, int nbi, double* lds) {
+  const int wave = threadIdx.x >> 6, h = wave >> 1, odd = wave & 1;
+  if (h >= nbi) return;
+  const int blk0 = uni(A.pairs[it.pair].blk0);
+  const bool mirror = A.anti != 0 && uni(A.blocks[blk0 + it.bslot0 + h].anti) != 0;
+  if (mirror) {
+    if (odd) ladder_item<F, 4, 1, 2, 1, R, false, 1, true, 1, true>(A, it, lds);
+    else ladder_item<F, 4, 1, 2, 0, R, false, 1, true, 3, true>(A, it, lds);
+  } else {
+    if (odd) ladder_item<F, 4, 1, 2, 2, R, false, 0, true, 1, true>(A, it, lds);
+    else ladder_item<F, 4, 1, 2, 0, R, false, 0, true, 1, true>(A, it, lds);
+  }
+}
+
+__device__ __forceinline__ Item read_item(const Item& ig) {
+  Item it;
+  it.kind = uni(ig.kind);
+  it.variant = uni(ig.variant);
+  it.pair = uni(ig.pair);
+  it.bslot0 = uni(ig.bslot0);
+  it.slot = uni(ig.slot);
+  it.ta0 = uni(ig.ta0);
+  it.lo = uni(ig.lo);
+  it.hi = uni(ig.hi);
+  return it;
+}
+
 // One launch processes the items of one kind (KIND), so that the ladder and
 // projection bodies are register-allocated separately.
 template <typename F, int KIND>
@@ -761,17 +811,38 @@ __global__ __launch_bounds__(256, KIND == ITEM_LADDER2 ? 2 : 1) void grouped_ker
   for (;;) {
     const int idx = next_item(A.q, q, left);
     if (idx < 0) break;
-    const Item& ig = A.items[idx];
-    Item it;
-    it.kind = uni(ig.kind);
-    it.variant = uni(ig.variant);
-    it.pair = uni(ig.pair);
-    it.bslot0 = uni(ig.bslot0);
-    it.slot = uni(ig.slot);
-    it.ta0 = uni(ig.ta0);
-    it.lo = uni(ig.lo);
-    it.hi = uni(ig.hi);
-    run_item<F, KIND>(A, it, lds);
+    run_item<F, KIND>(A, read_item(A.items[idx]), lds);
+  }
+}
+
+// Cooperative launch over the four-tile ladder items (ITEM_LADDER4), two
+// workgroups per CU.  Wave 0 pops an item for its workgroup and passes it on
+// through LDS between two barriers; every wave passes both barriers of every
+// round, and all leave the loop in the same round.
+template <typename F>
+__global__ __launch_bounds__(256, 2) void grouped_coop_kernel(GroupedArgs<F> A) {
+  __shared__ double lds[2 * kCoopSlabWords];
+  __shared__ int32_t next;
+  int q = blockIdx.x % kQueues, left = kQueues;
+  for (;;) {
+    __syncthreads();                     // the previous item's slabs are free
+    if (threadIdx.x < 64) {
+      const int i = next_item(A.q, q, left);
+      if (threadIdx.x == 0) next = i;
+    }
+    __syncthreads();
+    const int idx = __builtin_amdgcn_readfirstlane(next);
+    if (idx < 0) break;
+    const Item it = read_item(A.items[idx]);
+    const int n = uni(A.pairs[it.pair].n);
+    const int rk = (n - 16 * ((n - 1) >> 4) + 3) >> 2;
+    const int nbi = it.variant == kLadderCoopPair ? 2 : 1;
+    switch (rk) {
+      case 1: ladder_coop<F, 1>(A, it, nbi, lds); break;
+      case 2: ladder_coop<F, 2>(A, it, nbi, lds); break;
+      case 3: ladder_coop<F, 3>(A, it, nbi, lds); break;
+      default: ladder_coop<F, 4>(A, it, nbi, lds); break;
+    }
   }
 }
 

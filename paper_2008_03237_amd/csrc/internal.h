@@ -40,10 +40,12 @@ struct TermDev {
 
 // ITEM_LADDER2: ladder items of an FP64 plan run by the launch at two waves
 // per SIMD (at most three tiles of 16 PNOs and the variants below).
-enum ItemKind { ITEM_LADDER = 0, ITEM_PROJ = 1, ITEM_LADDER2 = 2 };
-constexpr int kKinds = 3;
+// ITEM_LADDER4: four-tile ladder items of an FP64 plan, each run by a whole
+// workgroup (cooperative variants below), also at two waves per SIMD.
+enum ItemKind { ITEM_LADDER = 0, ITEM_PROJ = 1, ITEM_LADDER2 = 2, ITEM_LADDER4 = 3 };
+constexpr int kKinds = 4;
 // launch order of the kinds within one residual
-constexpr int kKindOrder[kKinds] = {ITEM_LADDER2, ITEM_LADDER, ITEM_PROJ};
+constexpr int kKindOrder[kKinds] = {ITEM_LADDER2, ITEM_LADDER4, ITEM_LADDER, ITEM_PROJ};
 
 // One scheduled unit of the grouped kernel.
 struct Item {
@@ -88,12 +90,19 @@ __device__ __forceinline__ int next_item(const WorkQueues& Q, int& q, int& left)
 // Ladder: (NT tiles of 16 per PNO index, NB blocks per item, NTA a-tiles per item).
 struct LadderVariant { int nt, nb, nta; };
 struct ProjVariant { int nt, nb; };
-constexpr int kNumLadderVariants = 9;
+constexpr int kNumLadderVariants = 11;
 constexpr LadderVariant kLadderVariants[kNumLadderVariants] = {
-    {1, 4, 1}, {1, 2, 1}, {1, 1, 1}, {2, 4, 2}, {2, 2, 2}, {2, 1, 2}, {2, 4, 1}, {3, 1, 3}, {4, 1, 2}};
+    {1, 4, 1}, {1, 2, 1}, {1, 1, 1}, {2, 4, 2}, {2, 2, 2}, {2, 1, 2}, {2, 4, 1}, {3, 1, 3}, {4, 1, 2},
+    {4, 2, 4}, {4, 1, 4}};
+// the cooperative variants (FP64 only): a workgroup per item of two blocks
+// (kLadderCoopPair) or one
+constexpr int kLadderCoopPair = 9, kLadderCoopOne = 10;
+constexpr bool kLadderCoop[kNumLadderVariants] = {false, false, false, false, false, false, false, false, false,
+                                                  true, true};
 // ladder variants compiled into the two-wave launch: their X operands fit a
 // 40-operand LDS slab (or registers) and their registers fit 256 per lane
-constexpr bool kLadderTwoWave[kNumLadderVariants] = {true, true, true, false, true, true, false, true, false};
+constexpr bool kLadderTwoWave[kNumLadderVariants] = {true, true, true, false, true, true, false, true, false,
+                                                     false, false};
 constexpr int kNumProjVariants = 9;
 constexpr ProjVariant kProjVariants[kNumProjVariants] = {
     {1, 4}, {1, 2}, {1, 1}, {2, 4}, {2, 2}, {2, 1}, {3, 2}, {3, 1}, {4, 1}};

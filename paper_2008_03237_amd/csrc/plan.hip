@@ -155,9 +155,12 @@ dlpno_status build_schedule(dlpno_plan* P) {
     const int nt = (pr.n + 15) / 16, s4 = (pr.n + 3) / 4;
     // ladder: block groups of the tuned variant, smaller variants of the same
     // tile shape for the remainder
-    const int lv = P->tune.ladder_variant[nt - 1];
+    // the cooperative variants run in a two-wave FP64 launch only
+    int lv = P->tune.ladder_variant[nt - 1];
+    if (kLadderCoop[lv] && !two_wave) lv = 8;
     const LadderVariant V = kLadderVariants[lv];
-    const double per_q = (double)V.nb * ladder_mfma_per_q(V.nt, V.nta, s4, strips);
+    // work per wave: a cooperative item is shared by the workgroup's 4 waves
+    const double per_q = (double)V.nb * ladder_mfma_per_q(V.nt, V.nta, s4, strips) / (kLadderCoop[lv] ? 4.0 : 1.0);
     int chunks = (int)std::ceil(per_q * pr.m / target);
     chunks = std::max(1, std::min(chunks, pr.m));
     nL[p] = chunks;
@@ -169,7 +172,7 @@ dlpno_status build_schedule(dlpno_plan* P) {
         const LadderVariant W = kLadderVariants[v];
         for (int ta0 = 0; ta0 < nt; ta0 += W.nta) {
           Item it{};
-          it.kind = two_wave && kLadderTwoWave[v] ? ITEM_LADDER2 : ITEM_LADDER;
+          it.kind = kLadderCoop[v] ? ITEM_LADDER4 : two_wave && kLadderTwoWave[v] ? ITEM_LADDER2 : ITEM_LADDER;
           it.variant = v;
           it.pair = p;
           it.bslot0 = b0;
@@ -177,7 +180,8 @@ dlpno_status build_schedule(dlpno_plan* P) {
           it.ta0 = ta0;
           it.lo = lo;
           it.hi = hi;
-          cand.push_back({it, (double)(hi - lo) * W.nb * ladder_mfma_per_q(W.nt, W.nta, s4, strips)});
+          cand.push_back({it, (double)(hi - lo) * W.nb * ladder_mfma_per_q(W.nt, W.nta, s4, strips) /
+                                  (kLadderCoop[v] ? 4.0 : 1.0)});
         }
         b0 += W.nb;
       }
@@ -315,9 +319,10 @@ std::string dlpno::describe(const dlpno_plan* P) {
   std::string s;
   snprintf(buf, sizeof buf,
            "pairs=%d blocks=%d couplings=%lld terms=%lld precision=%d workers=%d items=%zu (ladder %d, ladder at two "
-           "waves per SIMD %d, projection %d) max_item/total=%.2e workspace=%.3f GB\n",
+           "waves per SIMD %d, cooperative ladder %d, projection %d) max_item/total=%.2e workspace=%.3f GB\n",
            P->n_pairs, P->n_blocks, (long long)P->n_cpl, (long long)P->n_terms, (int)P->opt.precision, P->workers,
-           P->items_h.size(), P->kind_count[ITEM_LADDER], P->kind_count[ITEM_LADDER2], P->kind_count[ITEM_PROJ],
+           P->items_h.size(), P->kind_count[ITEM_LADDER], P->kind_count[ITEM_LADDER2], P->kind_count[ITEM_LADDER4],
+           P->kind_count[ITEM_PROJ],
            P->total_mfma > 0 ? P->max_item_mfma / P->total_mfma : 0.0, P->ws_elems * 8.0 / 1e9);
   s += buf;
   snprintf(buf, sizeof buf,
@@ -546,7 +551,11 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if (opt.chunk_flops > 0) P->tune.items_per_wave = std::max(1.0, (double)opt.chunk_flops);
   // FP64: two-tile pairs two blocks per item, in the two-wave ladder launch
   // (the four-block variant's X operands do not fit its LDS slab)
-  if (opt.precision == DLPNO_FP64) P->tune.ladder_variant[1] = 4;
+  // and four-tile pairs two blocks per cooperative workgroup item
+  if (opt.precision == DLPNO_FP64) {
+    P->tune.ladder_variant[1] = 4;
+    P->tune.ladder_variant[3] = kLadderCoopPair;
+  }
   dlpno_status st;
   if ((st = build_schedule(P)) != DLPNO_OK) return destroy_fail(st);
   if ((st = upload(&P->d_pairs, P->pairs_h, "pair table", s)) != DLPNO_OK) return destroy_fail(st);
@@ -728,7 +737,7 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
     if (P->kind_count[kind] == 0) continue;
     const Item* items = P->d_items + P->kind_begin[kind];
     const WorkQueues wq = queues(P, kind);
-    phase_begin(P, kind == ITEM_LADDER ? 0 : kind == ITEM_LADDER2 ? 6 : 5, s);
+    phase_begin(P, kind == ITEM_LADDER ? 0 : kind == ITEM_LADDER2 ? 6 : kind == ITEM_LADDER4 ? 7 : 5, s);
     if (prec == DLPNO_FP32) {
       GroupedArgs<float> a{items, wq, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
                            P->B32, P->S32, P->T32, P->d_ws, general ? 0 : 1};

@@ -66,6 +66,8 @@ extern "C" dlpno_status dlpno_autotune(dlpno_plan* P, const double* T, double* R
     if (!present[nt - 1]) continue;
     for (int v = 0; v < kNumLadderVariants; ++v) {
       if (kLadderVariants[v].nt != nt || v == P->tune.ladder_variant[nt - 1]) continue;
+      // cooperative items: FP64 only; the one-block form serves remainders
+      if (kLadderCoop[v] && (P->opt.precision != DLPNO_FP64 || v == kLadderCoopOne)) continue;
       const int keep = P->tune.ladder_variant[nt - 1];
       P->tune.ladder_variant[nt - 1] = v;
       if ((st = apply(P, s)) != DLPNO_OK) return st;
