@@ -284,15 +284,22 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
   // M-form of B^Q: M[t][s] = B^Q[4s + g][16t + r] = B^Q[16t + r][4s + g] (symmetric)
   const F* Bp = A.B + off_B;
   const uint32_t mbase = (uint32_t)(g * n + r);
-  auto loadM = [&](F (&M)[NT][S4], int Q) {
+  // k-steps [s0, s1) of every tile of the M-form of slice Q
+  auto loadM_steps = [&](F (&M)[NT][S4], int Q, int s0, int s1) {
     const __amdgpu_buffer_rsrc_t br = rsrc(Bp + (size_t)Q * nn, nn);
 #pragma unroll
-    for (int s = 0; s < S4; ++s)
+    for (int s = s0; s < s1; ++s)
 #pragma unroll
       for (int t = 0; t < NT; ++t) M[t][s] = Mfma<F>::load(br, mbase + (uint32_t)(4 * s * n + 16 * t));
   };
+  auto loadM = [&](F (&M)[NT][S4], int Q) { loadM_steps(M, Q, 0, S4); };
 
-  auto compute = [&](const F (&M)[NT][S4]) {
+  // W2 (one B^Q buffer): once the last d-tile's stage 1 has run, k-steps
+  // s < 4 (NT - 1) of M are dead (that d-tile's stage 2 reads only the steps
+  // above); they are reloaded there from slice q_next, so most of the next
+  // slice is in flight while this one finishes.  Not in cooperative items,
+  // whose registers are full without it.
+  auto compute = [&](F (&M)[NT][S4], int q_next) {
 #pragma unroll
     for (int td = 0; td < NT; ++td) {
       V d1[NB][NTA];
@@ -317,6 +324,9 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
             for (int u = 0; u < NTA; ++u) d1[b][u] = Mfma<F>::op(av, M[ta(u)][s], d1[b][u]);
           }
         }
+      }
+      if constexpr (W2 && !COOP && NT > 1) {
+        if (td == NT - 1) loadM_steps(M, q_next, 0, 4 * (NT - 1));
       }
       // stage 2: Out^T[b][a] += sum_d B^Q[b][d] Y^T[d][a] over this d-tile
 #pragma unroll
@@ -358,21 +368,32 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
   };
 
   if constexpr (W2) {
-    // two waves per SIMD: one B^Q buffer; the other wave covers the loads
+    // two waves per SIMD: one B^Q buffer, most of the next slice loaded in
+    // the last d-tile (the last slice reloads itself there, harmlessly); the
+    // other wave covers the rest of the latency
     F M0[NT][S4];
-    for (int Q = it.lo; Q < it.hi; ++Q) {
-      loadM(M0, Q);
-      compute(M0);
+    if constexpr (COOP || NT == 1) {
+      for (int Q = it.lo; Q < it.hi; ++Q) {
+        loadM(M0, Q);
+        compute(M0, Q);
+      }
+    } else {
+      loadM(M0, it.lo);
+      for (int Q = it.lo; Q < it.hi; ++Q) {
+        const int qn = Q + 1 < it.hi ? Q + 1 : Q;
+        compute(M0, qn);
+        loadM_steps(M0, qn, 4 * (NT - 1), S4);
+      }
     }
   } else {
     F M0[NT][S4], M1[NT][S4];
     loadM(M0, it.lo);
     for (int Q = it.lo; Q < it.hi; Q += 2) {
       if (Q + 1 < it.hi) loadM(M1, Q + 1);
-      compute(M0);
+      compute(M0, 0);
       if (Q + 1 >= it.hi) break;
       if (Q + 2 < it.hi) loadM(M0, Q + 2);
-      compute(M1);
+      compute(M1, 0);
     }
   }
 
