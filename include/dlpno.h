@@ -213,7 +213,8 @@ dlpno_status dlpno_autotune(dlpno_plan* plan, const double* T, double* R, void* 
  *   projection items, 6 grouped kernel over the ladder items run at two
  *   waves per SIMD (FP64 plans: pairs of at most 48 PNOs), 7 cooperative
  *   ladder launch (FP64 plans: pairs of 49 to 64 PNOs, one workgroup per
- *   item). */
+ *   item), 8 projection items run at two waves per SIMD (FP64 plans: target
+ *   and source pairs of at most 48 PNOs). */
 dlpno_status dlpno_set_profiling(dlpno_plan* plan, int32_t enable);
 dlpno_status dlpno_phase_times(const dlpno_plan* plan, double* ms, int64_t* launches, int32_t n);
 

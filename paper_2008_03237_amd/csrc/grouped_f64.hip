@@ -7,6 +7,7 @@ hipError_t launch_grouped_f64(const GroupedArgs<double>& a, int kind, int worker
   if (kind == ITEM_LADDER) hipLaunchKernelGGL((grouped_kernel<double, ITEM_LADDER>), dim3(workers), dim3(256), 0, s, a);
   else if (kind == ITEM_LADDER2) hipLaunchKernelGGL((grouped_kernel<double, ITEM_LADDER2>), dim3(2 * workers), dim3(256), 0, s, a);
   else if (kind == ITEM_LADDER4) hipLaunchKernelGGL((grouped_coop_kernel<double>), dim3(2 * workers), dim3(256), 0, s, a);
+  else if (kind == ITEM_PROJ2) hipLaunchKernelGGL((grouped_kernel<double, ITEM_PROJ2>), dim3(2 * workers), dim3(256), 0, s, a);
   else hipLaunchKernelGGL((grouped_kernel<double, ITEM_PROJ>), dim3(workers), dim3(256), 0, s, a);
   return hipGetLastError();
 }

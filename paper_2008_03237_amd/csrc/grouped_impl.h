@@ -413,18 +413,20 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
 // without a term for this coupling runs with weight 0 and an empty operand
 // range, which keeps the code branch-free.
 // ---------------------------------------------------------------------------
-template <typename F, int NT, int NB, int NQ, int MASK>
+template <typename F, int NT, int NB, int NQ, int MASK, bool W2 = false>
 __device__ __forceinline__ void proj_item_direct(const GroupedArgs<F>& A, const Item& it, double* lds) {
   typedef typename Mfma<F>::V V;
   constexpr int S16 = 4 * NQ;                 // k-steps of 4 over the padded source index
   constexpr int SL = NQ * S16;                // LDS slots per term
-  constexpr bool BATCH = NB * SL <= kLdsWaveWords / 64;
+  constexpr int LW = W2 ? kLdsWaveWords2 : kLdsWaveWords;
+  static_assert(SL * 64 <= LW, "source operands exceed the wave's LDS");
+  constexpr bool BATCH = NB * SL <= LW / 64;
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4, pr = Mfma<F>::perm(r);
   const PairDev& Pg = A.pairs[it.pair];
   const int n = uni(Pg.n);
   const int blk0 = uni(Pg.blk0);
-  F* Al = reinterpret_cast<F*>(lds + (size_t)(threadIdx.x >> 6) * kLdsWaveWords);
+  F* Al = reinterpret_cast<F*>(lds + (size_t)(threadIdx.x >> 6) * LW);
 
   V acc[NB][NT][NT];
 #pragma unroll
@@ -673,15 +675,18 @@ __device__ __forceinline__ void proj_item_pipelined(const GroupedArgs<F>& A, con
 // Projection item: pipelined where its registers (accumulators, two S
 // operands, one block of source amplitudes, the stage-1 product; counted in
 // operands) fit without spilling, direct otherwise.
-template <typename F, int NT, int NB, int NQ, int MASK>
+// At two waves per SIMD (W2) the direct form: the other wave covers its
+// latency, and the pipelined form's registers would not fit.
+template <typename F, int NT, int NB, int NQ, int MASK, bool W2>
 __device__ __forceinline__ void proj_item_m(const GroupedArgs<F>& A, const Item& it, double* lds) {
   constexpr int kRegs = 4 * NB * NT * NT + 2 * NT * 4 * NQ + 4 * NQ * NQ + 4 * NT;
-  if constexpr (kRegs <= 170) proj_item_pipelined<F, NT, NB, NQ, MASK>(A, it, lds);
+  if constexpr (W2) proj_item_direct<F, NT, NB, NQ, MASK, true>(A, it, lds);
+  else if constexpr (kRegs <= 170) proj_item_pipelined<F, NT, NB, NQ, MASK>(A, it, lds);
   else proj_item_direct<F, NT, NB, NQ, MASK>(A, it, lds);
 }
 // The antisymmetry pattern of the item's blocks selects a compiled body (see
 // ladder_masked).
-template <typename F, int NT, int NB, int NQ>
+template <typename F, int NT, int NB, int NQ, bool W2 = false>
 __device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& it, double* lds) {
   int mask = 0;
   if (A.anti != 0) {
@@ -690,8 +695,8 @@ __device__ __forceinline__ void proj_item(const GroupedArgs<F>& A, const Item& i
     for (int b = 0; b < NB; ++b) mask |= (uni(A.blocks[blk0 + it.bslot0 + b].anti) != 0 ? 1 : 0) << b;
   }
   constexpr int kMirror = NB == 4 ? 3 : (1 << NB) - 1;
-  if (mask == kMirror) proj_item_m<F, NT, NB, NQ, kMirror>(A, it, lds);
-  else proj_item_m<F, NT, NB, NQ, 0>(A, it, lds);
+  if (mask == kMirror) proj_item_m<F, NT, NB, NQ, kMirror, W2>(A, it, lds);
+  else proj_item_m<F, NT, NB, NQ, 0, W2>(A, it, lds);
 }
 
 // The antisymmetry pattern of the item's blocks selects a compiled body: for
@@ -761,6 +766,23 @@ __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it
       case 7: DLPNO_LADDER_W(3, 1, 3, 0, false, true); break;
       default: break;
     }
+  } else if constexpr (KIND == ITEM_PROJ2) {
+    // projection items at two waves per SIMD: target and sources of at most
+    // three tiles, variants whose registers fit 256 per lane
+#define DLPNO_PROJ2(V, NT, NB)                                                       \
+  case 4 * V + 0: proj_item<F, NT, NB, 1, true>(A, it, lds); break;                  \
+  case 4 * V + 1: proj_item<F, NT, NB, 2, true>(A, it, lds); break;                  \
+  case 4 * V + 2: proj_item<F, NT, NB, 3, true>(A, it, lds); break;
+    switch (it.variant) {
+      DLPNO_PROJ2(0, 1, 4)
+      DLPNO_PROJ2(1, 1, 2)
+      DLPNO_PROJ2(2, 1, 1)
+      DLPNO_PROJ2(4, 2, 2)
+      DLPNO_PROJ2(5, 2, 1)
+      DLPNO_PROJ2(7, 3, 1)
+      default: break;
+    }
+#undef DLPNO_PROJ2
   } else {
     // variant = 4 * (tile variant) + (source tiles - 1)
 #define DLPNO_PROJ(V, NT, NB)                                                        \
@@ -826,8 +848,9 @@ __device__ __forceinline__ Item read_item(const Item& ig) {
 // One launch processes the items of one kind (KIND), so that the ladder and
 // projection bodies are register-allocated separately.
 template <typename F, int KIND>
-__global__ __launch_bounds__(256, KIND == ITEM_LADDER2 ? 2 : 1) void grouped_kernel(GroupedArgs<F> A) {
-  __shared__ double lds[4 * (KIND == ITEM_LADDER2 ? kLdsWaveWords2 : kLdsWaveWords)];
+__global__ __launch_bounds__(256, KIND == ITEM_LADDER2 || KIND == ITEM_PROJ2 ? 2 : 1) void grouped_kernel(
+    GroupedArgs<F> A) {
+  __shared__ double lds[4 * (KIND == ITEM_LADDER2 || KIND == ITEM_PROJ2 ? kLdsWaveWords2 : kLdsWaveWords)];
   int q = blockIdx.x % kQueues, left = kQueues;
   for (;;) {
     const int idx = next_item(A.q, q, left);

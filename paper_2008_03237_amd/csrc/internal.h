@@ -42,10 +42,12 @@ struct TermDev {
 // per SIMD (at most three tiles of 16 PNOs and the variants below).
 // ITEM_LADDER4: four-tile ladder items of an FP64 plan, each run by a whole
 // workgroup (cooperative variants below), also at two waves per SIMD.
-enum ItemKind { ITEM_LADDER = 0, ITEM_PROJ = 1, ITEM_LADDER2 = 2, ITEM_LADDER4 = 3 };
-constexpr int kKinds = 4;
+// ITEM_PROJ2: projection items of an FP64 plan with targets and sources of
+// at most three tiles (variants of kProjTwoWave), at two waves per SIMD.
+enum ItemKind { ITEM_LADDER = 0, ITEM_PROJ = 1, ITEM_LADDER2 = 2, ITEM_LADDER4 = 3, ITEM_PROJ2 = 4 };
+constexpr int kKinds = 5;
 // launch order of the kinds within one residual
-constexpr int kKindOrder[kKinds] = {ITEM_LADDER2, ITEM_LADDER4, ITEM_LADDER, ITEM_PROJ};
+constexpr int kKindOrder[kKinds] = {ITEM_LADDER2, ITEM_LADDER4, ITEM_LADDER, ITEM_PROJ2, ITEM_PROJ};
 
 // One scheduled unit of the grouped kernel.
 struct Item {
@@ -106,6 +108,9 @@ constexpr bool kLadderTwoWave[kNumLadderVariants] = {true, true, true, false, tr
 constexpr int kNumProjVariants = 9;
 constexpr ProjVariant kProjVariants[kNumProjVariants] = {
     {1, 4}, {1, 2}, {1, 1}, {2, 4}, {2, 2}, {2, 1}, {3, 2}, {3, 1}, {4, 1}};
+// projection variants compiled into the two-wave launch (sources of at most
+// three tiles): their accumulators and S operands fit 256 registers per lane
+constexpr bool kProjTwoWave[kNumProjVariants] = {true, true, true, false, true, true, false, true, false};
 
 // Arguments of the grouped kernel (templated on the operand type).
 template <typename F>

@@ -219,7 +219,7 @@ dlpno_status build_schedule(dlpno_plan* P) {
           const int v = pick_proj(nt, std::min(nbmax, pr.nblk - b0));
           if (v < 0) return fail(DLPNO_ERR_INVALID_ARG, "no projection tile variant for this block group");
           Item it{};
-          it.kind = ITEM_PROJ;
+          it.kind = two_wave && kProjTwoWave[v] && cq <= 3 ? ITEM_PROJ2 : ITEM_PROJ;
           it.variant = v * 4 + (cq - 1);
           it.pair = p;
           it.bslot0 = b0;
@@ -319,10 +319,11 @@ std::string dlpno::describe(const dlpno_plan* P) {
   std::string s;
   snprintf(buf, sizeof buf,
            "pairs=%d blocks=%d couplings=%lld terms=%lld precision=%d workers=%d items=%zu (ladder %d, ladder at two "
-           "waves per SIMD %d, cooperative ladder %d, projection %d) max_item/total=%.2e workspace=%.3f GB\n",
+           "waves per SIMD %d, cooperative ladder %d, projection %d, projection at two waves per SIMD %d) "
+           "max_item/total=%.2e workspace=%.3f GB\n",
            P->n_pairs, P->n_blocks, (long long)P->n_cpl, (long long)P->n_terms, (int)P->opt.precision, P->workers,
            P->items_h.size(), P->kind_count[ITEM_LADDER], P->kind_count[ITEM_LADDER2], P->kind_count[ITEM_LADDER4],
-           P->kind_count[ITEM_PROJ],
+           P->kind_count[ITEM_PROJ], P->kind_count[ITEM_PROJ2],
            P->total_mfma > 0 ? P->max_item_mfma / P->total_mfma : 0.0, P->ws_elems * 8.0 / 1e9);
   s += buf;
   snprintf(buf, sizeof buf,
@@ -737,7 +738,12 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
     if (P->kind_count[kind] == 0) continue;
     const Item* items = P->d_items + P->kind_begin[kind];
     const WorkQueues wq = queues(P, kind);
-    phase_begin(P, kind == ITEM_LADDER ? 0 : kind == ITEM_LADDER2 ? 6 : kind == ITEM_LADDER4 ? 7 : 5, s);
+    const int phase = kind == ITEM_LADDER    ? 0
+                      : kind == ITEM_LADDER2 ? 6
+                      : kind == ITEM_LADDER4 ? 7
+                      : kind == ITEM_PROJ2   ? 8
+                                             : 5;
+    phase_begin(P, phase, s);
     if (prec == DLPNO_FP32) {
       GroupedArgs<float> a{items, wq, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
                            P->B32, P->S32, P->T32, P->d_ws, general ? 0 : 1};

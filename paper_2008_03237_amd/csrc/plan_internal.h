@@ -14,14 +14,14 @@ namespace dlpno {
 
 constexpr int kHistCap = 4096;   // iterations kept in the device history
 constexpr int kDiisParts = 1024; // workgroups of the DIIS dot-product kernel
-constexpr int kPhases = 8;
+constexpr int kPhases = 9;
 
 // schedule choices (set by defaults or the autotuner)
 struct Tuning {
   int ladder_variant[4] = {0, 3, 7, 8};   // by tiles of 16 PNOs (1..4); FP64 plans start from 0 4 7 9
   int proj_variant[4] = {0, 4, 7, 8};
   double items_per_wave = 6.0;            // target items per wavefront of the queue
-  bool two_wave = true;                   // FP64: the two-wave ladder launches (kLadderTwoWave, kLadderCoop)
+  bool two_wave = true;                   // FP64: the two-wave launches (kLadderTwoWave, kLadderCoop, kProjTwoWave)
   double min_item_mfma = 2048.0;          // smallest item worth scheduling alone
 };
 

@@ -233,9 +233,9 @@ class Plan:
         _check(lib().dlpno_set_profiling(self._h, 1 if on else 0))
 
     def phase_times(self):
-        ms = (C.c_double * 8)()
-        n = (C.c_int64 * 8)()
-        _check(lib().dlpno_phase_times(self._h, ms, n, 8))
+        ms = (C.c_double * 9)()
+        n = (C.c_int64 * 9)()
+        _check(lib().dlpno_phase_times(self._h, ms, n, 9))
         return list(ms), list(n)
 
     def info(self):

@@ -294,9 +294,10 @@ def test_flop_count_profiling_and_autotune():
     ms, cnt = plan.phase_times()
     plan.set_profiling(False)
     # the mini chain has pairs of 1..4 tiles: the two-wave and cooperative
-    # ladder launches run (the one-wave ladder launch only for leftovers)
-    assert cnt[6] == 1 and cnt[7] == 1 and cnt[5] == 1 and cnt[1] == 1 and cnt[0] <= 1
-    assert ms[5] > 0 and ms[6] > 0 and ms[7] > 0
+    # ladder launches and both projection launches run (the one-wave ladder
+    # launch only for leftovers)
+    assert cnt[6] == 1 and cnt[7] == 1 and cnt[5] == 1 and cnt[8] == 1 and cnt[1] == 1 and cnt[0] <= 1
+    assert ms[5] > 0 and ms[6] > 0 and ms[7] > 0 and ms[8] > 0
     plan.autotune(dev["T"])
     assert "autotune best" in plan.info()
     R = plan.residual(dev["T"])
