@@ -100,6 +100,18 @@ double ladder_mfma_per_q(int nt, int nta, int s4, bool strips) {
   return 2.0 * nta * s4 * (nt - 1 + last);
 }
 
+// The same for one block and the a-tiles ta0 + u dta (u < nta), with stage 2
+// limited to the tiles tb >= ta of an antisymmetric block (mirror).
+double ladder_block_mfma_per_q(int nt, int ta0, int nta, int dta, int s4, bool strips, bool mirror) {
+  const int r = s4 - 4 * (nt - 1);
+  const double last = strips && r < 4 ? 0.22 * r : 1.0;
+  double st2 = 0.0;
+  for (int u = 0; u < nta; ++u)
+    for (int tb = 0; tb < nt; ++tb)
+      if (!mirror || tb >= ta0 + u * dta) st2 += tb == nt - 1 ? last : 1.0;
+  return s4 * (nta * (nt - 1 + last) + st2);
+}
+
 // largest compiled variant with this tile shape handling at most maxnb blocks
 int pick_ladder(int nt, int nta, int maxnb) {
   int best = -1;
@@ -180,8 +192,15 @@ dlpno_status build_schedule(dlpno_plan* P) {
           it.ta0 = ta0;
           it.lo = lo;
           it.hi = hi;
-          cand.push_back({it, (double)(hi - lo) * W.nb * ladder_mfma_per_q(W.nt, W.nta, s4, strips) /
-                                  (kLadderCoop[v] ? 4.0 : 1.0)});
+          // duration: the blocks' work, antisymmetric ones with stage 2 halved;
+          // a cooperative item takes as long as its slower block over two waves
+          double cost = 0.0;
+          for (int b = 0; b < W.nb; ++b) {
+            const bool mirror = !(P->opt.flags & DLPNO_FLAG_GENERAL_T) && P->blocks_h[pr.blk0 + b0 + b].anti != 0;
+            const double c = ladder_block_mfma_per_q(W.nt, ta0, W.nta, 1, s4, strips, mirror);
+            cost = kLadderCoop[v] ? std::max(cost, c / 2.0) : cost + c;
+          }
+          cand.push_back({it, (double)(hi - lo) * cost});
         }
         b0 += W.nb;
       }
