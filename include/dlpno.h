@@ -122,8 +122,11 @@ typedef struct {
   dlpno_precision precision;
   int32_t diis_max;     /* vectors kept by DIIS, 0 = plain Jacobi, at most 8 */
   int32_t diis_start;   /* first extrapolation once this many are stored (>= 2) */
-  int32_t n_workers;    /* persistent workgroups (0 = one per compute unit) */
-  int32_t chunk_flops;  /* log2 of the target work per scheduled item (0 = default) */
+  int32_t n_workers;    /* persistent workgroups of the one-wave launches (0 = one per
+                           compute unit); the two-wave launches use twice as many */
+  int32_t items_per_wave; /* items per wavefront the schedule aims at: the work is
+                           cut into about n_workers * 4 * items_per_wave items
+                           (0 = default, 6; the autotuner may change it) */
   int32_t flags;        /* DLPNO_FLAG_* bits, 0 = defaults */
 } dlpno_options;
 

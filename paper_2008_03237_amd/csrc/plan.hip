@@ -568,7 +568,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   HIPCK(hipGetDeviceProperties(&prop, dev));
   P->num_cu = prop.multiProcessorCount;
   P->workers = opt.n_workers > 0 ? opt.n_workers : P->num_cu;
-  if (opt.chunk_flops > 0) P->tune.items_per_wave = std::max(1.0, (double)opt.chunk_flops);
+  if (opt.items_per_wave > 0) P->tune.items_per_wave = (double)opt.items_per_wave;
   // FP64: two-tile pairs two blocks per item, in the two-wave ladder launch
   // (the four-block variant's X operands do not fit its LDS slab)
   // and four-tile pairs two blocks per cooperative workgroup item

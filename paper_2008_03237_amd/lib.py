@@ -42,7 +42,7 @@ class Inputs(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int32), ("diis_max", C.c_int32), ("diis_start", C.c_int32),
-                ("n_workers", C.c_int32), ("chunk_flops", C.c_int32), ("flags", C.c_int32)]
+                ("n_workers", C.c_int32), ("items_per_wave", C.c_int32), ("flags", C.c_int32)]
 
 
 PAIR_DTYPE = np.dtype([("i", "<i4"), ("j", "<i4"), ("npno", "<i4"), ("naux", "<i4"), ("blocks", "<u4"),
