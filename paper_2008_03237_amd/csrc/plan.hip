@@ -167,7 +167,8 @@ dlpno_status build_schedule(dlpno_plan* P) {
     const int nt = (pr.n + 15) / 16, s4 = (pr.n + 3) / 4;
     // ladder: block groups of the tuned variant, smaller variants of the same
     // tile shape for the remainder
-    // the cooperative variants run in a two-wave FP64 launch only
+    // the cooperative variants run in a two-wave FP64 launch only; elsewhere
+    // four-tile pairs take the one-wave variant 8
     int lv = P->tune.ladder_variant[nt - 1];
     if (kLadderCoop[lv] && !two_wave) lv = 8;
     const LadderVariant V = kLadderVariants[lv];
@@ -192,8 +193,9 @@ dlpno_status build_schedule(dlpno_plan* P) {
           it.ta0 = ta0;
           it.lo = lo;
           it.hi = hi;
-          // duration: the blocks' work, antisymmetric ones with stage 2 halved;
-          // a cooperative item takes as long as its slower block over two waves
+          // duration: the blocks' work, counting for an antisymmetric block only
+          // the stage-2 tiles it computes; a cooperative item takes as long as
+          // its slower block, shared by two waves
           double cost = 0.0;
           for (int b = 0; b < W.nb; ++b) {
             const bool mirror = !(P->opt.flags & DLPNO_FLAG_GENERAL_T) && P->blocks_h[pr.blk0 + b0 + b].anti != 0;
@@ -569,9 +571,9 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   P->num_cu = prop.multiProcessorCount;
   P->workers = opt.n_workers > 0 ? opt.n_workers : P->num_cu;
   if (opt.items_per_wave > 0) P->tune.items_per_wave = (double)opt.items_per_wave;
-  // FP64: two-tile pairs two blocks per item, in the two-wave ladder launch
-  // (the four-block variant's X operands do not fit its LDS slab)
-  // and four-tile pairs two blocks per cooperative workgroup item
+  // FP64 defaults: two-tile pairs take two blocks per item, so that they run
+  // in the two-wave ladder launch (the four-block variant's X operands do not
+  // fit its LDS slab); four-tile pairs take cooperative items of two blocks
   if (opt.precision == DLPNO_FP64) {
     P->tune.ladder_variant[1] = 4;
     P->tune.ladder_variant[3] = kLadderCoopPair;
