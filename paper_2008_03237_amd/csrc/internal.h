@@ -132,9 +132,9 @@ struct GroupedArgs {
   int32_t anti;
 };
 
-// kernels.hip
-// kind: ITEM_LADDER, ITEM_LADDER2 (FP64 only) or ITEM_PROJ; every item of
-// `a` must be of that kind
+// grouped_f64.hip, grouped_f32.hip
+// kind: ITEM_LADDER or ITEM_PROJ, and in FP64 also ITEM_LADDER2, ITEM_LADDER4
+// or ITEM_PROJ2; every item of `a` must be of that kind
 hipError_t launch_grouped_f64(const GroupedArgs<double>& a, int kind, int workers, hipStream_t s);
 hipError_t launch_grouped_f32(const GroupedArgs<float>& a, int kind, int workers, hipStream_t s);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);
