@@ -33,9 +33,13 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
   diis               converges to the dense-solve fixed point
   vjp                finite differences (exact for this bilinear Lagrangian)
                      and the dot-product (adjoint) identity
+  f12.f12_energy     spin-adapted prefactors from the cusp amplitudes on
+                     explicit spin functions, rank-one closed forms of the two
+                     contractions, enumeration of the spin-orbital pairs
 """
 from .model import (Inputs, stored_blocks, residual_os, residual_cs, jacobi,  # noqa: F401
                     pair_energies, pair_energies_cs, denominators, t_lookup)
 from .spinorbital import residual_spinorbital  # noqa: F401
 from .solver import DIIS, solve, dense_solution, apply_operator  # noqa: F401
 from .adjoint import vjp  # noqa: F401
+from . import f12  # noqa: F401

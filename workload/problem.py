@@ -35,7 +35,11 @@ BLOCK_BITS = {"AA": 1, "BB": 2, "AB": 4, "BA": 8}
 BLOCK_SPINS = {"AA": (0, 0), "BB": (1, 1), "AB": (0, 1), "BA": (1, 0)}
 
 # Philox field ids (fourth counter word)
-F_NPNO, F_NAUX, F_B, F_T, F_K, F_EPS, F_FDIAG, F_FOFF, F_S, F_QR = range(1, 11)
+F_NPNO, F_NAUX, F_B, F_T, F_K, F_EPS, F_FDIAG, F_FOFF, F_S, F_QR, F_W, F_F12 = range(1, 13)
+
+# F12 inputs (synthetic): W = V + C per stored block, in the amplitude layout,
+# and six scalars per block (V, V', B1..B4, see Problem.f12_scalars)
+SIGMA_W = 0.05
 
 # segment generation modes (see segment_values)
 MODE_PLAIN, MODE_SYM, MODE_ANTI, MODE_TRANS = 0, 1, 2, 3
@@ -134,8 +138,8 @@ class Problem:
 
     # ---------------- materialisation of the large fields ----------------
     def materialize(self, what):
-        """Full flat array of 'B', 'T', 'K' or 'S' (host memory; small problems)."""
-        size = {"B": self.n_B, "T": self.n_T, "K": self.n_K, "S": self.n_S}[what]
+        """Full flat array of 'B', 'T', 'K', 'S' or 'W' (host memory; small problems)."""
+        size = {"B": self.n_B, "T": self.n_T, "K": self.n_K, "S": self.n_S, "W": self.n_T}[what]
         if what == "S" and self.S_host is not None:
             return self.S_host.copy()
         out = np.zeros(size, dtype=np.float64)
@@ -148,6 +152,20 @@ class Problem:
         """B_p as an (m, n, n) array regenerated from its counters."""
         seg = self.segs["B"][p]
         return segment_values(self.seed, seg).reshape(seg["layers"], seg["rows"], seg["cols"])
+
+    def f12_scalars(self):
+        """Six synthetic F12 scalars per stored block, in block order (pairs in
+        order, blocks AA, BB, AB, BA within a pair): the geminal diagonal
+        V (negative, about -0.02), its exchange counterpart V' (opposite spin),
+        and four B-tilde values (positive, about 0.02).  float64 [n_blocks, 6]."""
+        nb = int(self.n_blocks().sum())
+        idx = (np.arange(nb, dtype=np.uint64)[:, None] * np.uint64(8) + np.arange(6, dtype=np.uint64)[None, :])
+        z = philox.normals(self.seed, F_F12, 0, idx)
+        out = np.empty((nb, 6))
+        out[:, 0] = -0.02 * (1.0 + 0.25 * z[:, 0])
+        out[:, 1] = 0.005 * z[:, 1]
+        out[:, 2:] = 0.02 * (1.0 + 0.25 * z[:, 2:])
+        return out
 
     def segment(self, what, idx):
         seg = self.segs[what][idx]
@@ -330,8 +348,11 @@ def build_problem(name="tiny", **override):
                        1, int(npno[p]), int(npno[p]), 0, sT / np.sqrt(2.0) if same else sT))
             o += int(npno[p]) ** 2
     segT = np.array(tl, dtype=SEG_DTYPE)
+    # F12 input W = V + C: general (no symmetry), same layout as the amplitudes
+    segW = segT.copy()
+    segW["field"], segW["mode"], segW["scale"] = F_W, MODE_PLAIN, SIGMA_W
 
-    segs = {"B": segB, "K": segK, "T": segT}
+    segs = {"B": segB, "K": segK, "T": segT, "W": segW}
     S_host = None
     if cfg["S"] == "qr60":
         # orthonormal PNO bases over a shared 60-dimensional virtual space
