@@ -160,6 +160,24 @@ dlpno_status dlpno_residual(dlpno_plan* plan, const double* T, double* R, void* 
 dlpno_status dlpno_update(dlpno_plan* plan, const double* T, const double* R, double* T_out,
                           double* e_pair, double* e_total, void* stream);
 
+/* Second-order F12 correction with the (converged) amplitudes T (Sec. II.A:
+ * Eq. "Vtilde" without its singles terms, and the spin-adapted pair energies
+ * that follow Eq. "F12 energy").  For every stored block, in that block's
+ * electron order:
+ *   V~  = V  + 1/2 sum_ab W_ab T_ab      (direct geminal)
+ *   V~x = V' + 1/2 sum_ab W_ba T_ab      (exchanged geminal)
+ *   same spin:     eps = 1/2 V~ + 1/16 B1
+ *   opposite spin: eps = 3/4 V~ + 1/4 V~x + 9/64 B1 + 3/64 B2 + 3/64 B3 + 1/64 B4
+ * T, W: device, n_T doubles in the amplitude layout (W = V + C over the
+ * pair's PNOs); scalars: device, 6 doubles per stored block in block order
+ * (pairs in order, blocks AA, BB, AB, BA): V, V', B1, B2, B3, B4 (V' and
+ * B2..B4 unused for same spin).  e_pair: 4 n_pairs doubles, by block code,
+ * 0 for absent blocks; *e_total = their sum in a fixed order.  Device
+ * pointers, caller-owned; asynchronous on stream.  NULL buffers with
+ * nonzero sizes give DLPNO_ERR_INVALID_ARG. */
+dlpno_status dlpno_f12_energy(dlpno_plan* plan, const double* T, const double* W, const double* scalars,
+                              double* e_pair, double* e_total, void* stream);
+
 /* n_iter iterations of: R = residual(T); T' = T - R/D; energies of T';
  * DIIS on (T', T' - T) (when enabled); T <- extrapolated T'.  One hipGraph per
  * iteration, replayed.  T is in/out; R, e_pair, e_total, max_abs_R receive

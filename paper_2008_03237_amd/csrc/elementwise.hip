@@ -25,6 +25,21 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // block-wide sum/max over 256 threads in a fixed order
+// two sums over the workgroup (kEwThreads), fixed order
+__device__ __forceinline__ void block_sum2(double& s, double& t) {
+  __shared__ double ls[4], lt[4];
+  s = wave_sum(s);
+  t = wave_sum(t);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    ls[w] = s;
+    lt[w] = t;
+  }
+  __syncthreads();
+  s = ((ls[0] + ls[1]) + ls[2]) + ls[3];
+  t = ((lt[0] + lt[1]) + lt[2]) + lt[3];
+}
+
 __device__ __forceinline__ void block_sum_max(double& s, double& m) {
   __shared__ double ls[4], lm[4];
   s = wave_sum(s);
@@ -95,6 +110,43 @@ __global__ __launch_bounds__(kEwThreads) void finish_kernel(FinishArgs a) {
   if (threadIdx.x == 0) {
     if (a.e_block) a.e_block[blk] = bk.w * esum;
     if (a.rmax_block) a.rmax_block[blk] = rmax;
+  }
+}
+
+// Second-order F12 pair energy of every stored block with the converged
+// amplitudes (Sec. II.A: Eq. "Vtilde" without the singles terms, and the
+// spin-adapted pair energies that follow Eq. "F12 energy").  Per block:
+//   d = <W, T>, x = <W^T, T>        (W = (V + C)^{ij}_{ab} in the block's order)
+//   V~ = V + d / 2, V~x = V' + x / 2 (direct and exchanged geminal)
+//   same spin:     eps = V~ / 2 + B1 / 16
+//   opposite spin: eps = 3/4 V~ + 1/4 V~x + (9 B1 + 3 B2 + 3 B3 + B4) / 64
+// One workgroup per block; T is staged in LDS so that both contractions read
+// W and T with coalesced loads.  The sums use a fixed order.
+__global__ __launch_bounds__(kEwThreads) void f12_kernel(F12Args a) {
+  const int blk = blockIdx.x;
+  const BlockDev bk = a.blocks[blk];
+  const int n = bk.n;
+  const int nn = n * n;
+  const double* T = a.T + bk.off_T;
+  const double* W = a.W + bk.off_T;
+  __shared__ double tl[64 * 64];
+  for (int idx = threadIdx.x; idx < nn; idx += kEwThreads) tl[idx] = T[idx];
+  __syncthreads();
+  double d = 0.0, x = 0.0;
+  for (int idx = threadIdx.x; idx < nn; idx += kEwThreads) {
+    const int r = idx / n, c = idx - r * n;
+    const double w = W[idx];
+    d += w * tl[idx];
+    x += w * tl[c * n + r];
+  }
+  block_sum2(d, x);
+  if (threadIdx.x == 0) {
+    const double* sc = a.scal + 6 * (int64_t)blk;
+    const double vt = sc[0] + 0.5 * d, vtx = sc[1] + 0.5 * x;
+    double e;
+    if (bk.s1 == bk.s2) e = 0.5 * vt + sc[2] / 16.0;
+    else e = 0.75 * vt + 0.25 * vtx + (9.0 * sc[2] + 3.0 * sc[3] + 3.0 * sc[4] + sc[5]) / 64.0;
+    a.e_block[blk] = e;
   }
 }
 
@@ -404,6 +456,11 @@ static int grid_for(int64_t n) {
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
   if (a.n_blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(finish_kernel, dim3(a.n_blocks), dim3(kEwThreads), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_f12(const F12Args& a, hipStream_t s) {
+  if (a.n_blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(f12_kernel, dim3(a.n_blocks), dim3(kEwThreads), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_update(const UpdateArgs& a, hipStream_t s) {

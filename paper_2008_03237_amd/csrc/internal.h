@@ -188,6 +188,17 @@ struct UpdateArgs {         // Jacobi from a given residual
 };
 hipError_t launch_update(const UpdateArgs& a, hipStream_t s);
 
+// F12 pair energies of every stored block (elementwise.hip, f12_kernel)
+struct F12Args {
+  const BlockDev* blocks;
+  int32_t n_blocks;
+  const double* T;         // converged amplitudes
+  const double* W;         // (V + C) per block, amplitude layout
+  const double* scal;      // [n_blocks][6]: V, V', B1..B4
+  double* e_block;         // [n_blocks] out
+};
+hipError_t launch_f12(const F12Args& a, hipStream_t s);
+
 struct ReduceArgs {
   const PairDev* pairs;
   const BlockDev* blocks;

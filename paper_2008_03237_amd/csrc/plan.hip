@@ -586,6 +586,8 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if ((st = upload_schedule(P, s)) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_counter, kKinds * kQueues, "queue heads")) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_e_block, std::max(1, nblk_total), "block energies")) != DLPNO_OK) return destroy_fail(st);
+  if ((st = dev_alloc(&P->d_f12_block, std::max(1, nblk_total), "F12 block energies")) != DLPNO_OK)
+    return destroy_fail(st);
   if ((st = dev_alloc(&P->d_rmax_block, std::max(1, nblk_total), "block residual maxima")) != DLPNO_OK)
     return destroy_fail(st);
   if ((st = dev_alloc(&P->d_nonfinite, 4, "non-finite flag")) != DLPNO_OK) return destroy_fail(st);
@@ -668,7 +670,7 @@ extern "C" dlpno_status dlpno_plan_destroy(dlpno_plan* P) {
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   for (auto& ev : P->events) (void)hipEventDestroy(ev);
   void* ptrs[] = {P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms, P->d_items, P->d_counter, P->d_ws,
-                  P->d_e_block, P->d_rmax_block, P->d_nonfinite, P->d_hist, P->d_diis, P->d_scalars,
+                  P->d_e_block, P->d_f12_block, P->d_rmax_block, P->d_nonfinite, P->d_hist, P->d_diis, P->d_scalars,
                   P->d_diis_partial, P->d_ring_vecs, P->d_ring_errs, P->B32, P->S32, P->T32,
                   P->d_vjp_items, P->d_mixed, P->G32, P->d_pair_boff, P->d_blk_toff, P->d_cpl_soff,
                   P->d_cpl_target, P->d_pair_bscale, P->d_blk_tscale, P->Bs_hi, P->Bs_lo, P->Ss_hi, P->Ss_lo,
@@ -874,6 +876,26 @@ extern "C" dlpno_status dlpno_update(dlpno_plan* P, const double* T, const doubl
   ra.n_blocks = P->n_blocks;
   ra.n_pairs = P->n_pairs;
   ra.e_block = P->d_e_block;
+  ra.rmax_block = nullptr;
+  ra.e_pair = e_pair;
+  ra.e_total = e_total;
+  HIPCK(launch_reduce(ra, s));
+  return DLPNO_OK;
+}
+
+extern "C" dlpno_status dlpno_f12_energy(dlpno_plan* P, const double* T, const double* W, const double* scalars,
+                                         double* e_pair, double* e_total, void* stream) {
+  if (!P || ((!T || !W) && P->n_T > 0) || (!scalars && P->n_blocks > 0))
+    return fail(DLPNO_ERR_INVALID_ARG, "NULL plan or buffer");
+  hipStream_t s = (hipStream_t)stream;
+  F12Args f{P->d_blocks, P->n_blocks, T, W, scalars, P->d_f12_block};
+  HIPCK(launch_f12(f, s));
+  ReduceArgs ra{};
+  ra.pairs = P->d_pairs;
+  ra.blocks = P->d_blocks;
+  ra.n_blocks = P->n_blocks;
+  ra.n_pairs = P->n_pairs;
+  ra.e_block = P->d_f12_block;
   ra.rmax_block = nullptr;
   ra.e_pair = e_pair;
   ra.e_total = e_total;

@@ -62,6 +62,7 @@ struct dlpno_plan {
   int32_t* d_counter = nullptr;        // queue heads: kQueues per kind
   double* d_ws = nullptr;
   double* d_e_block = nullptr;
+  double* d_f12_block = nullptr;        // F12 pair energy per block
   double* d_rmax_block = nullptr;
   int32_t* d_nonfinite = nullptr;
   int32_t* d_hist_iter = nullptr;   // iterations recorded in the history

@@ -71,6 +71,7 @@ def lib():
         "dlpno_plan_destroy": [vp],
         "dlpno_residual": [vp, vp, vp, vp],
         "dlpno_update": [vp, vp, vp, vp, vp, vp, vp],
+        "dlpno_f12_energy": [vp, vp, vp, vp, vp, vp, vp],
         "dlpno_iterate": [vp, i32, vp, vp, vp, vp, vp, vp],
         "dlpno_reset": [vp, vp],
         "dlpno_residual_vjp": [vp, vp, vp, vp, vp, vp],
@@ -153,6 +154,7 @@ class Plan:
         opt = Options(prec, diis_max, diis_start, n_workers, int(items_per_wave), FLAG_GENERAL_T if general_T else 0)
         self.precision = prec
         self.n_T, self.n_B, self.n_pairs = int(desc.n_T), int(desc.n_B), P
+        self.n_blocks = int(sum(bin(int(b)).count("1") for b in desc.blocks))
         self._h = C.c_void_p()
         _check(L.dlpno_plan_create(C.byref(prob), C.byref(inp), C.byref(opt), _stream(), C.byref(self._h)))
 
@@ -183,6 +185,21 @@ class Plan:
         e_tot = self._new(1)
         _check(lib().dlpno_update(self._h, _ptr(T), _ptr(R), _ptr(T_out), _ptr(e_pair), _ptr(e_tot), _stream()))
         return T_out, e_pair, e_tot
+
+    def f12_energy(self, T, W, scalars, e_pair=None, e_total=None):
+        """F12 pair energies with amplitudes T: W (amplitude layout) and
+        scalars ([n_blocks, 6]: V, V', B1..B4) are device float64 tensors."""
+        e_pair = self._new(4 * self.n_pairs) if e_pair is None else e_pair
+        e_total = self._new(1) if e_total is None else e_total
+        import torch
+        for t in (T, W, scalars):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("T, W and scalars must be contiguous float64 CUDA tensors")
+        if T.numel() < self.n_T or W.numel() < self.n_T or scalars.numel() < 6 * self.n_blocks:
+            raise ValueError("T and W need n_T doubles, scalars 6 per stored block")
+        _check(lib().dlpno_f12_energy(self._h, _ptr(T), _ptr(W), _ptr(scalars), _ptr(e_pair), _ptr(e_total),
+                                      _stream()))
+        return e_pair, e_total
 
     def iterate(self, n, T, R=None, e_pair=None, e_total=None, rmax=None):
         R = self._new(self.n_T) if R is None else R

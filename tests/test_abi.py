@@ -90,3 +90,10 @@ def test_status_strings():
     L = lib()
     for s in range(-8, 1):
         assert L.dlpno_status_string(s)
+
+
+def test_f12_energy_rejects_a_null_plan():
+    from paper_2008_03237_amd.lib import lib
+    L = lib()
+    st = L.dlpno_f12_energy(None, None, None, None, None, None, None)
+    assert st != 0 and "NULL" in L.dlpno_last_error().decode()
