@@ -97,6 +97,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pairs", type=int, default=1200)
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision / refinement leg")
+    ap.add_argument("--no-f12", action="store_true", help="skip the F12-correction leg")
     ap.add_argument("--mixed-precision", default="bf16x2", choices=["bf16x2", "fp16x2", "fp32"])
     ap.add_argument("--mixed-outer", type=int, default=2, help="FP64 refinement steps")
     ap.add_argument("--mixed-inner", type=int, default=6, help="low-precision iterations per refinement step")
@@ -228,12 +229,44 @@ def main():
     }
     log("grouped kernel: ladder %.3f ms (two-wave launch %.3f, cooperative %.3f, one-wave %.3f), projection %.3f ms "
         "(two-wave %.3f, one-wave %.3f) per residual" % (kern_ms, lad2_ms, lad4_ms, lad1_ms, proj_ms, proj2_ms, proj1_ms))
+    if not args.no_f12:
+        out["f12"] = f12_leg(prob, plan, T, log)
     if not args.no_mixed:
         out["mixed"] = mixed_leg(prob, dev, plan, eps_a, eps_b, args, flops, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, n_pairs=args.cpu_pairs)
     plan.close()
     print(json.dumps(out), flush=True)
+
+
+def f12_leg(prob, plan, T, log):
+    """The F12 correction (V-tilde contraction and spin-adapted pair energies)
+    with the amplitudes the timed iterations left, on synthetic W = V + C and
+    F12 scalars: HIP-event time of dlpno_f12_energy (block kernel and the
+    pair/total reduction) and its algorithmic HBM bytes, T and W once."""
+    import torch
+    from workload.gpu import device_fields
+    W = device_fields(prob, fields=("W",))["W"]
+    scal = torch.from_numpy(prob.f12_scalars()).cuda()
+    e_pair, e_tot = plan.f12_energy(T, W, scal)
+    torch.cuda.synchronize()
+    reps = 20
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        plan.f12_energy(T, W, scal, e_pair, e_tot)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    nblk = int(prob.n_blocks().sum())
+    nbytes = 2 * 8 * prob.n_T + 8 * 6 * nblk + 8 * (nblk + 4 * prob.n_pairs + 1)
+    res = {"kernels": "f12_kernel + reduce_parts_kernel + reduce_final_kernel", "ms": round(ms, 4), "algorithmic_bytes": nbytes,
+           "achieved_GBps": round(nbytes / (ms / 1e3) / 1e9, 1),
+           "hbm_frac": round(nbytes / (ms / 1e3) / 1e9 / 8000.0, 4),
+           "energy_f12": float(e_tot.cpu()[0]), "amplitudes": "after the timed iterations"}
+    log("f12 leg: %s" % res)
+    del W
+    return res
 
 
 def mixed_leg(prob, dev, plan64, eps_a, eps_b, args, flops, log):

@@ -130,14 +130,28 @@ __global__ __launch_bounds__(kEwThreads) void f12_kernel(F12Args a) {
   const double* T = a.T + bk.off_T;
   const double* W = a.W + bk.off_T;
   __shared__ double tl[64 * 64];
-  for (int idx = threadIdx.x; idx < nn; idx += kEwThreads) tl[idx] = T[idx];
+  // W is loaded into registers while T goes to LDS: one round of latency
+  constexpr int kPer = 64 * 64 / kEwThreads;
+  double w[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int idx = threadIdx.x + k * kEwThreads;
+    w[k] = 0.0;
+    if (idx < nn) {
+      tl[idx] = T[idx];
+      w[k] = W[idx];
+    }
+  }
   __syncthreads();
   double d = 0.0, x = 0.0;
-  for (int idx = threadIdx.x; idx < nn; idx += kEwThreads) {
-    const int r = idx / n, c = idx - r * n;
-    const double w = W[idx];
-    d += w * tl[idx];
-    x += w * tl[c * n + r];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const int idx = threadIdx.x + k * kEwThreads;
+    if (idx < nn) {
+      const int r = idx / n, c = idx - r * n;
+      d += w[k] * tl[idx];
+      x += w[k] * tl[c * n + r];
+    }
   }
   block_sum2(d, x);
   if (threadIdx.x == 0) {
@@ -173,43 +187,48 @@ __global__ __launch_bounds__(kEwThreads) void update_kernel(UpdateArgs a) {
   if (threadIdx.x == 0) a.e_block[blk] = bk.w * esum;
 }
 
-// pair energies, total energy, max |R|, iteration history (one workgroup)
-__global__ __launch_bounds__(1024) void reduce_kernel(ReduceArgs a) {
-  __shared__ double ls[16], lm[16];
+// pair energies, total energy, max |R|, iteration history.  Stage 1:
+// kReduceParts workgroups, each summing (and taking the maximum of) a fixed
+// contiguous range of blocks, and writing the pair energies of a grid-stride
+// share of the pairs; stage 2: one wave combines the partial results.  Both
+// stages use a fixed order, so the results do not depend on timing.
+__global__ __launch_bounds__(kEwThreads) void reduce_parts_kernel(ReduceArgs a) {
+  const int g = blockIdx.x;
+  const int chunk = (a.n_blocks + kReduceParts - 1) / kReduceParts;
+  const int b0 = g * chunk, b1 = min(a.n_blocks, b0 + chunk);
   double s = 0.0, m = 0.0;
-  for (int b = threadIdx.x; b < a.n_blocks; b += 1024) {
+  for (int b = b0 + threadIdx.x; b < b1; b += kEwThreads) {
     s += a.e_block[b];
     if (a.rmax_block) m = fmax(m, a.rmax_block[b]);
   }
   if (a.e_pair) {
-    for (int p = threadIdx.x; p < a.n_pairs; p += 1024) {
+    for (int p = g * kEwThreads + threadIdx.x; p < a.n_pairs; p += kReduceParts * kEwThreads) {
       const PairDev P = a.pairs[p];
       double e[4] = {0.0, 0.0, 0.0, 0.0};
       for (int k = 0; k < P.nblk; ++k) e[a.blocks[P.blk0 + k].code] = a.e_block[P.blk0 + k];
       for (int c = 0; c < 4; ++c) a.e_pair[4 * (int64_t)p + c] = e[c];
     }
   }
+  block_sum_max(s, m);
+  if (threadIdx.x == 0) {
+    a.partial[g] = s;
+    a.partial[kReduceParts + g] = m;
+  }
+}
+
+__global__ __launch_bounds__(64) void reduce_final_kernel(ReduceArgs a) {
+  static_assert(kReduceParts == 64, "one partial per lane");
+  double s = a.partial[threadIdx.x], m = a.partial[kReduceParts + threadIdx.x];
   s = wave_sum(s);
   m = wave_max(m);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    ls[w] = s;
-    lm[w] = m;
-  }
-  __syncthreads();
   if (threadIdx.x == 0) {
-    double tot = 0.0, mx = 0.0;
-    for (int k = 0; k < 16; ++k) {
-      tot += ls[k];
-      mx = fmax(mx, lm[k]);
-    }
-    if (a.e_total) *a.e_total = tot;
-    if (a.rmax) *a.rmax = mx;
+    if (a.e_total) *a.e_total = s;
+    if (a.rmax) *a.rmax = m;
     if (a.iter) {
       const int it = *a.iter;
       if (a.hist && it < a.hist_cap) {
-        a.hist[2 * it] = tot;
-        a.hist[2 * it + 1] = mx;
+        a.hist[2 * it] = s;
+        a.hist[2 * it + 1] = m;
       }
       *a.iter = it + 1;
     }
@@ -312,9 +331,13 @@ __global__ __launch_bounds__(256) void diis_solve_kernel(DiisState* st, const do
     v = wave_sum(v);
     if ((threadIdx.x & 63) == 0) lw[k][threadIdx.x >> 6] = v;
   }
+  // the small bordered solve runs on one thread with its arrays in LDS:
+  // as private arrays with run-time indices they lived in scratch memory,
+  // whose latency made this kernel take 0.7 ms
+  __shared__ double M[81], E[81], rhs[9], x[9], ev[9];
+  __shared__ int sl[8];
   __syncthreads();
   if (threadIdx.x != 0) return;
-  // the small bordered solve on one thread
   for (int k = 0; k < cnt0; ++k) {
     const double s = ((lw[k][0] + lw[k][1]) + lw[k][2]) + lw[k][3];
     const int slot = (head - k + mx) % mx;
@@ -329,10 +352,8 @@ __global__ __launch_bounds__(256) void diis_solve_kernel(DiisState* st, const do
   int cnt = cnt0;
   for (;;) {
     // slots oldest -> newest
-    int sl[8];
     for (int k = 0; k < cnt; ++k) sl[k] = (head - (cnt - 1 - k) + mx) % mx;
     const int N = cnt + 1;
-    double M[81], E[81], rhs[9];
     for (int a = 0; a < N; ++a) {
       for (int b = 0; b < N; ++b) {
         double v;
@@ -345,7 +366,6 @@ __global__ __launch_bounds__(256) void diis_solve_kernel(DiisState* st, const do
       rhs[a] = (a == cnt) ? -1.0 : 0.0;
     }
     if (cnt > 1) {
-      double ev[9];
       sym_eigs(E, N, ev);
       double amax = 0.0, amin = 1e308;
       for (int k = 0; k < N; ++k) {
@@ -379,7 +399,6 @@ __global__ __launch_bounds__(256) void diis_solve_kernel(DiisState* st, const do
         rhs[rr] -= f * rhs[c];
       }
     }
-    double x[9];
     for (int c = N - 1; c >= 0; --c) {
       double s = rhs[c];
       for (int k = c + 1; k < N; ++k) s -= M[c * 9 + k] * x[k];
@@ -469,7 +488,9 @@ hipError_t launch_update(const UpdateArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, a);
+  if (!a.partial) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(reduce_parts_kernel, dim3(kReduceParts), dim3(kEwThreads), 0, s, a);
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_diis_reset(DiisState* st, int max, int start, hipStream_t s) {

@@ -212,7 +212,9 @@ struct ReduceArgs {
   double* hist;            // per-iteration history [cap][2], indexed by *iter (may be null)
   int32_t* iter;           // device iteration counter (may be null)
   int32_t hist_cap;
+  double* partial;         // [2 kReduceParts] scratch of the two-stage reduction
 };
+constexpr int kReduceParts = 64;
 hipError_t launch_reduce(const ReduceArgs& a, hipStream_t s);
 
 hipError_t launch_diis_slot(DiisState* st, hipStream_t s);          // advance head before finish

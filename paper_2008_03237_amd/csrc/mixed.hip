@@ -33,6 +33,7 @@ static hipError_t fp64_residual(dlpno_plan* P, const double* T, double* r, doubl
   f.T_new = in_place ? const_cast<double*>(T) : scratch;
   if ((e = launch_finish(f, s)) != hipSuccess) return e;
   ReduceArgs ra{};
+  ra.partial = P->d_red_partial;
   ra.pairs = P->d_pairs;
   ra.blocks = P->d_blocks;
   ra.n_blocks = P->n_blocks;

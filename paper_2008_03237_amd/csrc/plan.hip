@@ -588,6 +588,8 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if ((st = dev_alloc(&P->d_e_block, std::max(1, nblk_total), "block energies")) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_f12_block, std::max(1, nblk_total), "F12 block energies")) != DLPNO_OK)
     return destroy_fail(st);
+  if ((st = dev_alloc(&P->d_red_partial, 2 * kReduceParts, "reduction scratch")) != DLPNO_OK)
+    return destroy_fail(st);
   if ((st = dev_alloc(&P->d_rmax_block, std::max(1, nblk_total), "block residual maxima")) != DLPNO_OK)
     return destroy_fail(st);
   if ((st = dev_alloc(&P->d_nonfinite, 4, "non-finite flag")) != DLPNO_OK) return destroy_fail(st);
@@ -670,7 +672,7 @@ extern "C" dlpno_status dlpno_plan_destroy(dlpno_plan* P) {
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   for (auto& ev : P->events) (void)hipEventDestroy(ev);
   void* ptrs[] = {P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms, P->d_items, P->d_counter, P->d_ws,
-                  P->d_e_block, P->d_f12_block, P->d_rmax_block, P->d_nonfinite, P->d_hist, P->d_diis, P->d_scalars,
+                  P->d_e_block, P->d_f12_block, P->d_red_partial, P->d_rmax_block, P->d_nonfinite, P->d_hist, P->d_diis, P->d_scalars,
                   P->d_diis_partial, P->d_ring_vecs, P->d_ring_errs, P->B32, P->S32, P->T32,
                   P->d_vjp_items, P->d_mixed, P->G32, P->d_pair_boff, P->d_blk_toff, P->d_cpl_soff,
                   P->d_cpl_target, P->d_pair_bscale, P->d_blk_tscale, P->Bs_hi, P->Bs_lo, P->Ss_hi, P->Ss_lo,
@@ -820,6 +822,7 @@ hipError_t enqueue_iteration(dlpno_plan* P, double* T, double* R, double* e_pair
   if ((e = launch_finish(f, s)) != hipSuccess) return e;
   phase_end(P, s);
   ReduceArgs ra{};
+  ra.partial = P->d_red_partial;
   ra.pairs = P->d_pairs;
   ra.blocks = P->d_blocks;
   ra.n_blocks = P->n_blocks;
@@ -871,6 +874,7 @@ extern "C" dlpno_status dlpno_update(dlpno_plan* P, const double* T, const doubl
   UpdateArgs u{P->d_blocks, P->n_blocks, T, R, P->in.K, P->in.eps_a, P->in.eps_b, T_out, P->d_e_block};
   HIPCK(launch_update(u, s));
   ReduceArgs ra{};
+  ra.partial = P->d_red_partial;
   ra.pairs = P->d_pairs;
   ra.blocks = P->d_blocks;
   ra.n_blocks = P->n_blocks;
@@ -891,6 +895,7 @@ extern "C" dlpno_status dlpno_f12_energy(dlpno_plan* P, const double* T, const d
   F12Args f{P->d_blocks, P->n_blocks, T, W, scalars, P->d_f12_block};
   HIPCK(launch_f12(f, s));
   ReduceArgs ra{};
+  ra.partial = P->d_red_partial;
   ra.pairs = P->d_pairs;
   ra.blocks = P->d_blocks;
   ra.n_blocks = P->n_blocks;

@@ -63,6 +63,7 @@ struct dlpno_plan {
   double* d_ws = nullptr;
   double* d_e_block = nullptr;
   double* d_f12_block = nullptr;        // F12 pair energy per block
+  double* d_red_partial = nullptr;      // energy/max|R| reduction scratch, 2 kReduceParts
   double* d_rmax_block = nullptr;
   int32_t* d_nonfinite = nullptr;
   int32_t* d_hist_iter = nullptr;   // iterations recorded in the history
