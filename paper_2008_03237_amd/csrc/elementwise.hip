@@ -25,21 +25,6 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // block-wide sum/max over 256 threads in a fixed order
-// two sums over the workgroup (kEwThreads), fixed order
-__device__ __forceinline__ void block_sum2(double& s, double& t) {
-  __shared__ double ls[4], lt[4];
-  s = wave_sum(s);
-  t = wave_sum(t);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    ls[w] = s;
-    lt[w] = t;
-  }
-  __syncthreads();
-  s = ((ls[0] + ls[1]) + ls[2]) + ls[3];
-  t = ((lt[0] + lt[1]) + lt[2]) + lt[3];
-}
-
 __device__ __forceinline__ void block_sum_max(double& s, double& m) {
   __shared__ double ls[4], lm[4];
   s = wave_sum(s);
@@ -120,45 +105,33 @@ __global__ __launch_bounds__(kEwThreads) void finish_kernel(FinishArgs a) {
 //   V~ = V + d / 2, V~x = V' + x / 2 (direct and exchanged geminal)
 //   same spin:     eps = V~ / 2 + B1 / 16
 //   opposite spin: eps = 3/4 V~ + 1/4 V~x + (9 B1 + 3 B2 + 3 B3 + B4) / 64
-// One workgroup per block; T is staged in LDS so that both contractions read
-// W and T with coalesced loads.  The sums use a fixed order.
+// One wave per block (four per workgroup, no LDS, so that many blocks are in
+// flight): W and T are read coalesced, the transposed T reads hit the lines
+// the wave fetches itself.  The sums use a fixed order.
 __global__ __launch_bounds__(kEwThreads) void f12_kernel(F12Args a) {
-  const int blk = blockIdx.x;
-  const BlockDev bk = a.blocks[blk];
-  const int n = bk.n;
+  const int lane = threadIdx.x & 63;
+  const int blk = blockIdx.x * (kEwThreads / 64) + (threadIdx.x >> 6);
+  if (blk >= a.n_blocks) return;                  // whole waves; no barriers below
+  const int n = a.blocks[blk].n;
+  const int64_t off = a.blocks[blk].off_T;
+  const double* T = a.T + off;
+  const double* W = a.W + off;
   const int nn = n * n;
-  const double* T = a.T + bk.off_T;
-  const double* W = a.W + bk.off_T;
-  __shared__ double tl[64 * 64];
-  // W is loaded into registers while T goes to LDS: one round of latency
-  constexpr int kPer = 64 * 64 / kEwThreads;
-  double w[kPer];
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int idx = threadIdx.x + k * kEwThreads;
-    w[k] = 0.0;
-    if (idx < nn) {
-      tl[idx] = T[idx];
-      w[k] = W[idx];
-    }
-  }
-  __syncthreads();
   double d = 0.0, x = 0.0;
-#pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const int idx = threadIdx.x + k * kEwThreads;
-    if (idx < nn) {
-      const int r = idx / n, c = idx - r * n;
-      d += w[k] * tl[idx];
-      x += w[k] * tl[c * n + r];
-    }
+#pragma unroll 4
+  for (int idx = lane; idx < nn; idx += 64) {
+    const int r = idx / n, c = idx - r * n;
+    const double w = W[idx];
+    d += w * T[idx];
+    x += w * T[c * n + r];
   }
-  block_sum2(d, x);
-  if (threadIdx.x == 0) {
+  d = wave_sum(d);
+  x = wave_sum(x);
+  if (lane == 0) {
     const double* sc = a.scal + 6 * (int64_t)blk;
     const double vt = sc[0] + 0.5 * d, vtx = sc[1] + 0.5 * x;
     double e;
-    if (bk.s1 == bk.s2) e = 0.5 * vt + sc[2] / 16.0;
+    if (a.blocks[blk].s1 == a.blocks[blk].s2) e = 0.5 * vt + sc[2] / 16.0;
     else e = 0.75 * vt + 0.25 * vtx + (9.0 * sc[2] + 3.0 * sc[3] + 3.0 * sc[4] + sc[5]) / 64.0;
     a.e_block[blk] = e;
   }
@@ -479,7 +452,8 @@ hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {
 }
 hipError_t launch_f12(const F12Args& a, hipStream_t s) {
   if (a.n_blocks == 0) return hipSuccess;
-  hipLaunchKernelGGL(f12_kernel, dim3(a.n_blocks), dim3(kEwThreads), 0, s, a);
+  const int per = kEwThreads / 64;
+  hipLaunchKernelGGL(f12_kernel, dim3((a.n_blocks + per - 1) / per), dim3(kEwThreads), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_update(const UpdateArgs& a, hipStream_t s) {
