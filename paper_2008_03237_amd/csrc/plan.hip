@@ -136,13 +136,66 @@ int pick_proj(int nt, int maxnb) {
   return best;
 }
 
+struct Cand {
+  Item it;
+  double cost;
+};
+
+// Items by kind in launch order (one set of queues and one launch each),
+// longest first within a kind, ties by pair for a deterministic order.  One
+// queue per XCD: the items of one (pair, slot) read the same B^Q or S slices
+// and go to one queue; groups are dealt out in that order to the
+// least-loaded queue, and each queue keeps the longest-first order.
+void partition(std::vector<Cand>& cand, Schedule& S, double& maxc) {
+  int rank[kKinds];
+  for (int k = 0; k < kKinds; ++k) rank[kKindOrder[k]] = k;
+  std::stable_sort(cand.begin(), cand.end(), [&](const Cand& a, const Cand& b) {
+    if (a.it.kind != b.it.kind) return rank[a.it.kind] < rank[b.it.kind];
+    return a.cost > b.cost;
+  });
+  S.items_h.clear();
+  S.items_h.reserve(cand.size());
+  for (int kind : kKindOrder) {
+    std::vector<std::vector<Item>> qs(kQueues);
+    double load[kQueues] = {};
+    std::unordered_map<int64_t, int> group_q;
+    for (const Cand& c : cand) {
+      if (c.it.kind != kind) continue;
+      const int64_t key = ((int64_t)c.it.pair << 32) | (uint32_t)c.it.slot;
+      auto g = group_q.find(key);
+      int q = 0;
+      if (g != group_q.end()) {
+        q = g->second;
+      } else {
+        for (int k = 1; k < kQueues; ++k)
+          if (load[k] < load[q]) q = k;
+        group_q.emplace(key, q);
+      }
+      qs[q].push_back(c.it);
+      load[q] += c.cost;
+      maxc = std::max(maxc, c.cost);
+    }
+    const int32_t base = (int32_t)S.items_h.size();
+    for (int k = 0; k < kQueues; ++k) {
+      S.qoff[kind][k] = (int32_t)S.items_h.size() - base;
+      S.items_h.insert(S.items_h.end(), qs[k].begin(), qs[k].end());
+    }
+    S.qoff[kind][kQueues] = (int32_t)S.items_h.size() - base;
+    S.kind_begin[kind] = base;
+    S.kind_count[kind] = S.qoff[kind][kQueues];
+  }
+}
+
 dlpno_status build_schedule(dlpno_plan* P) {
   const int npairs = P->n_pairs;
   const bool strips = P->opt.precision == DLPNO_FP64;
   const bool two_wave = P->opt.precision == DLPNO_FP64 && P->tune.two_wave;
+  // split plans also keep FP64 items over the same slots for their FP64
+  // residuals (refinement), in the FP64 launches
+  const bool split = P->opt.precision == DLPNO_BF16X2 || P->opt.precision == DLPNO_FP16X2;
+  constexpr int kFp64Ladder[4] = {0, 4, 7, kLadderCoopPair};
   std::vector<int> nL(npairs, 0), nP(npairs, 0);
-  struct Cand { Item it; double cost; };
-  std::vector<Cand> cand;
+  std::vector<Cand> cand, cand64;
   // total work in MFMA instructions, to size the items
   double total = 0.0;
   for (int p = 0; p < npairs; ++p) {
@@ -177,15 +230,17 @@ dlpno_status build_schedule(dlpno_plan* P) {
     int chunks = (int)std::ceil(per_q * pr.m / target);
     chunks = std::max(1, std::min(chunks, pr.m));
     nL[p] = chunks;
-    for (int c = 0; c < chunks; ++c) {
-      const int lo = (int)((int64_t)pr.m * c / chunks), hi = (int)((int64_t)pr.m * (c + 1) / chunks);
+    // the items of ladder slot c (Q in [lo, hi)) with variant lvx; tw: the
+    // FP64 two-wave launches are in use, stx: FP64 row strips
+    auto emit_ladder = [&](std::vector<Cand>& out, int lvx, bool tw, bool stx, int c, int lo, int hi) -> bool {
+      const LadderVariant VX = kLadderVariants[lvx];
       for (int b0 = 0; b0 < pr.nblk;) {
-        const int v = pick_ladder(nt, V.nta, std::min(V.nb, pr.nblk - b0));
-        if (v < 0) return fail(DLPNO_ERR_INVALID_ARG, "no ladder tile variant for this block group");
+        const int v = pick_ladder(nt, VX.nta, std::min(VX.nb, pr.nblk - b0));
+        if (v < 0) return false;
         const LadderVariant W = kLadderVariants[v];
         for (int ta0 = 0; ta0 < nt; ta0 += W.nta) {
           Item it{};
-          it.kind = kLadderCoop[v] ? ITEM_LADDER4 : two_wave && kLadderTwoWave[v] ? ITEM_LADDER2 : ITEM_LADDER;
+          it.kind = kLadderCoop[v] ? ITEM_LADDER4 : tw && kLadderTwoWave[v] ? ITEM_LADDER2 : ITEM_LADDER;
           it.variant = v;
           it.pair = p;
           it.bslot0 = b0;
@@ -199,13 +254,20 @@ dlpno_status build_schedule(dlpno_plan* P) {
           double cost = 0.0;
           for (int b = 0; b < W.nb; ++b) {
             const bool mirror = !(P->opt.flags & DLPNO_FLAG_GENERAL_T) && P->blocks_h[pr.blk0 + b0 + b].anti != 0;
-            const double c = ladder_block_mfma_per_q(W.nt, ta0, W.nta, 1, s4, strips, mirror);
-            cost = kLadderCoop[v] ? std::max(cost, c / 2.0) : cost + c;
+            const double cb = ladder_block_mfma_per_q(W.nt, ta0, W.nta, 1, s4, stx, mirror);
+            cost = kLadderCoop[v] ? std::max(cost, cb / 2.0) : cost + cb;
           }
-          cand.push_back({it, (double)(hi - lo) * cost});
+          out.push_back({it, (double)(hi - lo) * cost});
         }
         b0 += W.nb;
       }
+      return true;
+    };
+    for (int c = 0; c < chunks; ++c) {
+      const int lo = (int)((int64_t)pr.m * c / chunks), hi = (int)((int64_t)pr.m * (c + 1) / chunks);
+      if (!emit_ladder(cand, lv, two_wave, strips, c, lo, hi) ||
+          (split && !emit_ladder(cand64, kFp64Ladder[nt - 1], true, true, c, lo, hi)))
+        return fail(DLPNO_ERR_INVALID_ARG, "no ladder tile variant for this block group");
     }
     // projection
     const int64_t e0 = P->rowptr_h[p], e1 = P->rowptr_h[p + 1];
@@ -236,20 +298,23 @@ dlpno_status build_schedule(dlpno_plan* P) {
         // three target tiles with four source tiles: one block per item (two
         // blocks' accumulators and operands do not fit the registers)
         const int nbmax = nt == 3 && cq == 4 ? 1 : U.nb;
-        for (int b0 = 0; b0 < pr.nblk;) {
-          const int v = pick_proj(nt, std::min(nbmax, pr.nblk - b0));
-          if (v < 0) return fail(DLPNO_ERR_INVALID_ARG, "no projection tile variant for this block group");
-          Item it{};
-          it.kind = two_wave && kProjTwoWave[v] && cq <= 3 ? ITEM_PROJ2 : ITEM_PROJ;
-          it.variant = v * 4 + (cq - 1);
-          it.pair = p;
-          it.bslot0 = b0;
-          it.slot = nL[p] + (int)c;
-          it.ta0 = 0;
-          it.lo = (int)ranges[c].first;
-          it.hi = (int)ranges[c].second;
-          cand.push_back({it, cost * kProjVariants[v].nb});
-          b0 += kProjVariants[v].nb;
+        for (int pass = 0; pass < (split ? 2 : 1); ++pass) {
+          const bool tw = pass == 1 || two_wave;
+          for (int b0 = 0; b0 < pr.nblk;) {
+            const int v = pick_proj(nt, std::min(nbmax, pr.nblk - b0));
+            if (v < 0) return fail(DLPNO_ERR_INVALID_ARG, "no projection tile variant for this block group");
+            Item it{};
+            it.kind = tw && kProjTwoWave[v] && cq <= 3 ? ITEM_PROJ2 : ITEM_PROJ;
+            it.variant = v * 4 + (cq - 1);
+            it.pair = p;
+            it.bslot0 = b0;
+            it.slot = nL[p] + (int)c;
+            it.ta0 = 0;
+            it.lo = (int)ranges[c].first;
+            it.hi = (int)ranges[c].second;
+            (pass == 0 ? cand : cand64).push_back({it, cost * kProjVariants[v].nb});
+            b0 += kProjVariants[v].nb;
+          }
         }
       }
     }
@@ -267,49 +332,11 @@ dlpno_status build_schedule(dlpno_plan* P) {
     }
   }
   P->ws_elems = ws;
-  // items by kind in launch order (one set of queues and one launch each);
-  // longest first within a kind, ties by pair for a deterministic order
-  int rank[kKinds];
-  for (int k = 0; k < kKinds; ++k) rank[kKindOrder[k]] = k;
-  std::stable_sort(cand.begin(), cand.end(), [&](const Cand& a, const Cand& b) {
-    if (a.it.kind != b.it.kind) return rank[a.it.kind] < rank[b.it.kind];
-    return a.cost > b.cost;
-  });
-  // One queue per XCD.  The items of one (pair, slot) read the same B^Q or S
-  // slices and go to one queue; groups are dealt out in that order to the
-  // least-loaded queue, and each queue keeps the longest-first order.
-  P->items_h.clear();
-  P->items_h.reserve(cand.size());
   double maxc = 0.0;
-  for (int kind : kKindOrder) {
-    std::vector<std::vector<Item>> qs(kQueues);
-    double load[kQueues] = {};
-    std::unordered_map<int64_t, int> group_q;
-    for (const Cand& c : cand) {
-      if (c.it.kind != kind) continue;
-      const int64_t key = ((int64_t)c.it.pair << 32) | (uint32_t)c.it.slot;
-      auto g = group_q.find(key);
-      int q = 0;
-      if (g != group_q.end()) {
-        q = g->second;
-      } else {
-        for (int k = 1; k < kQueues; ++k)
-          if (load[k] < load[q]) q = k;
-        group_q.emplace(key, q);
-      }
-      qs[q].push_back(c.it);
-      load[q] += c.cost;
-      maxc = std::max(maxc, c.cost);
-    }
-    const int32_t base = (int32_t)P->items_h.size();
-    for (int k = 0; k < kQueues; ++k) {
-      P->qoff[kind][k] = (int32_t)P->items_h.size() - base;
-      P->items_h.insert(P->items_h.end(), qs[k].begin(), qs[k].end());
-    }
-    P->qoff[kind][kQueues] = (int32_t)P->items_h.size() - base;
-    P->kind_begin[kind] = base;
-    P->kind_count[kind] = P->qoff[kind][kQueues];
-  }
+  partition(cand, P->sched, maxc);
+  double unused = 0.0;
+  P->sched64.items_h.clear();
+  if (split) partition(cand64, P->sched64, unused);
   P->max_item_mfma = maxc;
   return DLPNO_OK;
 }
@@ -320,14 +347,17 @@ dlpno_status build_schedule(dlpno_plan* P) {
 // device state (re)allocation for the schedule
 // ---------------------------------------------------------------------------
 dlpno_status dlpno::upload_schedule(dlpno_plan* P, hipStream_t s) {
-  if (P->d_items) (void)hipFree(P->d_items);
+  if (P->sched.d_items) (void)hipFree(P->sched.d_items);
+  if (P->sched64.d_items) (void)hipFree(P->sched64.d_items);
   if (P->d_blocks) (void)hipFree(P->d_blocks);
   if (P->d_ws) (void)hipFree(P->d_ws);
-  P->d_items = nullptr;
+  P->sched.d_items = nullptr;
+  P->sched64.d_items = nullptr;
   P->d_blocks = nullptr;
   P->d_ws = nullptr;
   dlpno_status st;
-  if ((st = upload(&P->d_items, P->items_h, "work items", s)) != DLPNO_OK) return st;
+  if ((st = upload(&P->sched.d_items, P->sched.items_h, "work items", s)) != DLPNO_OK) return st;
+  if ((st = upload(&P->sched64.d_items, P->sched64.items_h, "FP64 work items", s)) != DLPNO_OK) return st;
   if ((st = upload(&P->d_blocks, P->blocks_h, "block table", s)) != DLPNO_OK) return st;
   if ((st = dev_alloc(&P->d_ws, (size_t)std::max<int64_t>(P->ws_elems, 1), "partial-sum workspace")) != DLPNO_OK)
     return st;
@@ -343,16 +373,20 @@ std::string dlpno::describe(const dlpno_plan* P) {
            "waves per SIMD %d, cooperative ladder %d, projection %d, projection at two waves per SIMD %d) "
            "max_item/total=%.2e workspace=%.3f GB\n",
            P->n_pairs, P->n_blocks, (long long)P->n_cpl, (long long)P->n_terms, (int)P->opt.precision, P->workers,
-           P->items_h.size(), P->kind_count[ITEM_LADDER], P->kind_count[ITEM_LADDER2], P->kind_count[ITEM_LADDER4],
-           P->kind_count[ITEM_PROJ], P->kind_count[ITEM_PROJ2],
+           P->sched.items_h.size(), P->sched.kind_count[ITEM_LADDER], P->sched.kind_count[ITEM_LADDER2],
+           P->sched.kind_count[ITEM_LADDER4], P->sched.kind_count[ITEM_PROJ], P->sched.kind_count[ITEM_PROJ2],
            P->total_mfma > 0 ? P->max_item_mfma / P->total_mfma : 0.0, P->ws_elems * 8.0 / 1e9);
   s += buf;
   snprintf(buf, sizeof buf,
            "ladder variants by tiles: %d %d %d %d%s; projection: %d %d %d %d; items/wave %.1f\n",
            P->tune.ladder_variant[0], P->tune.ladder_variant[1], P->tune.ladder_variant[2], P->tune.ladder_variant[3],
-           P->kind_count[ITEM_LADDER2] > 0 ? " (two-wave launch)" : "", P->tune.proj_variant[0],
+           P->sched.kind_count[ITEM_LADDER2] > 0 ? " (two-wave launch)" : "", P->tune.proj_variant[0],
            P->tune.proj_variant[1], P->tune.proj_variant[2], P->tune.proj_variant[3], P->tune.items_per_wave);
   s += buf;
+  if (!P->sched64.items_h.empty()) {
+    snprintf(buf, sizeof buf, "FP64 items for refinement residuals: %zu\n", P->sched64.items_h.size());
+    s += buf;
+  }
   snprintf(buf, sizeof buf, "flops/residual: ladder %.4e projection %.4e\n", P->flops_ladder, P->flops_proj);
   s += buf;
   return s;
@@ -671,7 +705,7 @@ extern "C" dlpno_status dlpno_plan_destroy(dlpno_plan* P) {
   if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
   if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   for (auto& ev : P->events) (void)hipEventDestroy(ev);
-  void* ptrs[] = {P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms, P->d_items, P->d_counter, P->d_ws,
+  void* ptrs[] = {P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms, P->sched.d_items, P->sched64.d_items, P->d_counter, P->d_ws,
                   P->d_e_block, P->d_f12_block, P->d_red_partial, P->d_rmax_block, P->d_nonfinite, P->d_hist, P->d_diis, P->d_scalars,
                   P->d_diis_partial, P->d_ring_vecs, P->d_ring_errs, P->B32, P->S32, P->T32,
                   P->d_vjp_items, P->d_mixed, P->G32, P->d_pair_boff, P->d_blk_toff, P->d_cpl_soff,
@@ -716,9 +750,9 @@ void phase_collect(dlpno_plan* P) {
 bool is_split(int prec) { return prec == DLPNO_BF16X2 || prec == DLPNO_FP16X2; }
 
 // the work queues of one kind's launch
-WorkQueues queues(const dlpno_plan* P, int kind) {
+WorkQueues queues(const dlpno_plan* P, const Schedule& S, int kind) {
   WorkQueues q{};
-  for (int k = 0; k <= kQueues; ++k) q.off[k] = P->qoff[kind][k];
+  for (int k = 0; k <= kQueues; ++k) q.off[k] = S.qoff[kind][k];
   q.counter = P->d_counter + kind * kQueues;
   return q;
 }
@@ -727,7 +761,7 @@ WorkQueues queues(const dlpno_plan* P, int kind) {
 // plan's precision, or in `prec` when given (FP64 residuals of a split plan)
 hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, bool general) {
   hipError_t e;
-  if (P->items_h.empty()) return hipSuccess;
+  if (P->sched.items_h.empty()) return hipSuccess;
   if (prec < 0) prec = P->opt.precision;
   if (prec == DLPNO_FP32) {
     phase_begin(P, 4, s);
@@ -744,8 +778,8 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
   general = general || (P->opt.flags & DLPNO_FLAG_GENERAL_T) != 0;
   if (is_split(prec)) {
     for (int kind : {ITEM_LADDER, ITEM_PROJ}) {
-      if (P->kind_count[kind] == 0) continue;
-      SplitArgs a{P->d_items + P->kind_begin[kind], queues(P, kind), P->d_pairs, P->d_blocks,
+      if (P->sched.kind_count[kind] == 0) continue;
+      SplitArgs a{P->sched.d_items + P->sched.kind_begin[kind], queues(P, P->sched, kind), P->d_pairs, P->d_blocks,
                   P->d_cpl, P->d_terms, P->d_pair_boff, P->d_pair_bscale, P->d_blk_toff, P->d_blk_tscale,
                   P->d_cpl_soff, P->Bs_hi, P->Bs_lo, P->Ss_hi, P->Ss_lo, P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo,
                   P->d_ws, general ? 0 : 1};
@@ -759,10 +793,12 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
   // each kind in its own launch of the persistent kernel (own queues), so
   // that each is register-allocated alone; the two-wave ladder launch exists
   // in FP64 plans only
+  // FP64 residuals of a split plan run its FP64 schedule (same slots)
+  const Schedule& S = prec == DLPNO_FP64 && !P->sched64.items_h.empty() ? P->sched64 : P->sched;
   for (int kind : kKindOrder) {
-    if (P->kind_count[kind] == 0) continue;
-    const Item* items = P->d_items + P->kind_begin[kind];
-    const WorkQueues wq = queues(P, kind);
+    if (S.kind_count[kind] == 0) continue;
+    const Item* items = S.d_items + S.kind_begin[kind];
+    const WorkQueues wq = queues(P, S, kind);
     const int phase = kind == ITEM_LADDER    ? 0
                       : kind == ITEM_LADDER2 ? 6
                       : kind == ITEM_LADDER4 ? 7

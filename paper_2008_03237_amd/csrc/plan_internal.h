@@ -25,6 +25,16 @@ struct Tuning {
   double min_item_mfma = 2048.0;          // smallest item worth scheduling alone
 };
 
+// One list of work items with its per-kind queues.
+struct Schedule {
+  std::vector<Item> items_h;            // items by kind, in launch order (kKindOrder)
+  int32_t kind_begin[kKinds] = {}, kind_count[kKinds] = {};
+  // per kind: queue k holds items [qoff[kind][k], qoff[kind][k+1]) counted
+  // from the kind's first item
+  int32_t qoff[kKinds][kQueues + 1] = {};
+  Item* d_items = nullptr;
+};
+
 struct PendingEvent {
   int phase;
   hipEvent_t start, stop;
@@ -45,11 +55,8 @@ struct dlpno_plan {
   std::vector<dlpno::CplDev> cpl_h;
   std::vector<dlpno::TermDev> terms_h;
   std::vector<int64_t> rowptr_h;
-  std::vector<dlpno::Item> items_h;     // items by kind, in launch order (kKindOrder)
-  int32_t kind_begin[dlpno::kKinds] = {}, kind_count[dlpno::kKinds] = {};
-  // per kind: queue k holds items [qoff[kind][k], qoff[kind][k+1]) counted
-  // from the kind's first item
-  int32_t qoff[dlpno::kKinds][dlpno::kQueues + 1] = {};
+  dlpno::Schedule sched;                // the plan's precision
+  dlpno::Schedule sched64;              // split plans: FP64 items over the same slots (refinement residuals)
   dlpno::Tuning tune;
   double flops_ladder = 0.0, flops_proj = 0.0, total_mfma = 0.0, max_item_mfma = 0.0;
   int64_t ws_elems = 0;
@@ -58,7 +65,6 @@ struct dlpno_plan {
   dlpno::BlockDev* d_blocks = nullptr;
   dlpno::CplDev* d_cpl = nullptr;
   dlpno::TermDev* d_terms = nullptr;
-  dlpno::Item* d_items = nullptr;
   int32_t* d_counter = nullptr;        // queue heads: kQueues per kind
   double* d_ws = nullptr;
   double* d_e_block = nullptr;
