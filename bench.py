@@ -105,8 +105,8 @@ def main():
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (the pair sharding across GPUs is a design "
-              "note, not implemented); use --gpus 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only (sharding the pairs across GPUs is not implemented); "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

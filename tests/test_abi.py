@@ -97,3 +97,11 @@ def test_f12_energy_rejects_a_null_plan():
     L = lib()
     st = L.dlpno_f12_energy(None, None, None, None, None, None, None)
     assert st != 0 and "NULL" in L.dlpno_last_error().decode()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
