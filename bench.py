@@ -24,21 +24,29 @@ sys.path.insert(0, ROOT)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 
 
-def cpu_baseline(prob, n_pairs=1200, seed=99):
+def cpu_baseline(prob, n_pairs=400, seed=99, repeats=3):
     """Time the FP64 oracle on a contiguous window of pairs of the workload
-    (inputs regenerated from the seeded counters beforehand, not timed)."""
+    (inputs regenerated from the seeded counters beforehand, not timed);
+    median of `repeats` runs.  The flop count is the algorithmic one of the
+    terms the oracle applies (ladder 4 m n^3 per block, projection
+    2 n_p n_q (n_p + n_q) per applied term)."""
     import concurrent.futures as cf
 
     import numpy as np
 
     import oracle
+    from oracle.model import projection_terms
     from workload.problem import segment_values
 
+    blas, threads = "unknown", os.cpu_count() or 1
     try:
         from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        info = [d for d in threadpool_info() if d.get("user_api") == "blas"]
+        if info:
+            blas = "%s %s" % (info[0].get("internal_api", "?"), info[0].get("version", ""))
+            threads = max(d.get("num_threads", 1) for d in info)
     except Exception:
-        cores = os.cpu_count() or 1
+        pass
     P = prob.n_pairs
     rng = np.random.default_rng(seed)
     start = int(rng.integers(0, max(1, P - n_pairs)))
@@ -71,19 +79,23 @@ def cpu_baseline(prob, n_pairs=1200, seed=99):
         list(ex.map(gen_pair, pick))
     flops = 0.0
     for p in pick:
-        nb = len(oracle.stored_blocks(int(prob.pi[p]), int(prob.pj[p]), somo))
-        flops += 4.0 * float(prob.naux[p]) * float(n[p]) ** 3 * nb
-        for e in range(prob.cpl_rowptr[p], prob.cpl_rowptr[p + 1]):
-            q = int(prob.cpl_src[e])
-            flops += nb * 2.0 * float(n[p]) * float(n[q]) * float(n[p] + n[q])   # upper bound: every block applies
-    t0 = time.perf_counter()
-    R = oracle.residual_os(inp, T, pairs=pick)
-    Tn = oracle.jacobi(inp, {k: T[k] for k in R}, R)
-    oracle.pair_energies(inp, Tn)
-    dt = time.perf_counter() - t0
-    return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": int(cores), "kind": "oracle",
+        for name in inp.blocks(p):
+            flops += 4.0 * float(prob.naux[p]) * float(n[p]) ** 3
+            for (_, q, _, _) in projection_terms(inp, T, p, name):
+                flops += 2.0 * float(n[p]) * float(n[q]) * float(n[p] + n[q])
+    times = []
+    for _ in range(repeats):
+        t0 = time.perf_counter()
+        R = oracle.residual_os(inp, T, pairs=pick)
+        Tn = oracle.jacobi(inp, {k: T[k] for k in R}, R)
+        oracle.pair_energies(inp, Tn)
+        times.append(time.perf_counter() - t0)
+    dt = sorted(times)[len(times) // 2]
+    return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
             "sample": "%d contiguous pairs (of %d) of the same workload: residual + Jacobi + pair energies, "
-                      "%.1f s" % (len(pick), P, dt)}
+                      "median of %d runs, %.1f s each (%s)" % (len(pick), P, repeats, dt,
+                                                              ", ".join("%.1f" % t for t in times)),
+            "blas": blas, "host_cpus": os.cpu_count()}
 
 
 def main():
@@ -95,12 +107,14 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pairs", type=int, default=1200)
+    ap.add_argument("--cpu-pairs", type=int, default=400)
     ap.add_argument("--no-mixed", action="store_true", help="skip the split-precision / refinement leg")
     ap.add_argument("--no-f12", action="store_true", help="skip the F12-correction leg")
-    ap.add_argument("--mixed-precision", default="bf16x2", choices=["bf16x2", "fp16x2", "fp32"])
-    ap.add_argument("--mixed-outer", type=int, default=2, help="FP64 refinement steps")
-    ap.add_argument("--mixed-inner", type=int, default=6, help="low-precision iterations per refinement step")
+    ap.add_argument("--mixed-precisions", default="bf16x2,fp16x2",
+                    help="comma-separated split precisions of the mixed leg (bf16x2, fp16x2, fp32)")
+    ap.add_argument("--mixed-outer", type=int, default=3, help="FP64 refinement steps")
+    ap.add_argument("--mixed-inner", type=int, default=4, help="low-precision iterations per refinement step")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-path leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -231,8 +245,12 @@ def main():
         "(two-wave %.3f, one-wave %.3f) per residual" % (kern_ms, lad2_ms, lad4_ms, lad1_ms, proj_ms, proj2_ms, proj1_ms))
     if not args.no_f12:
         out["f12"] = f12_leg(prob, plan, T, log)
-    if not args.no_mixed:
-        out["mixed"] = mixed_leg(prob, dev, plan, eps_a, eps_b, args, flops, log)
+    if not (args.no_mixed and args.no_fp32) and args.precision == "fp64":
+        ref = fp64_reference(prob, plan, log)
+        if not args.no_mixed:
+            out["mixed"] = mixed_leg(prob, dev, eps_a, eps_b, args, flops, ref, log)
+        if not args.no_fp32:
+            out["fp32"] = fp32_leg(prob, dev, eps_a, eps_b, args, fl_ladder, fl_proj, ref, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, n_pairs=args.cpu_pairs)
     plan.close()
@@ -269,14 +287,10 @@ def f12_leg(prob, plan, T, log):
     return res
 
 
-def mixed_leg(prob, dev, plan64, eps_a, eps_b, args, flops, log):
-    """Split-precision grouped kernel throughput, and the refined mixed solve
-    against the converged FP64 solve (time and energy error)."""
-    import numpy as np
+def fp64_reference(prob, plan64, log):
+    """The converged FP64 solve (DIIS, from T = 0 to max|R| < 1e-9), timed:
+    the reference of the precision legs."""
     import torch
-
-    from paper_2008_03237_amd import Plan
-    # FP64 reference: iterate to max|R| < 1e-9 (DIIS), timed
     plan64.reset()
     T64 = torch.zeros(max(prob.n_T, 1), dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
@@ -289,8 +303,23 @@ def mixed_leg(prob, dev, plan64, eps_a, eps_b, args, flops, log):
             break
     torch.cuda.synchronize()
     t64 = time.perf_counter() - t0
-    mp = Plan(prob, dev["B"], dev["S"], dev["K"], eps_a, eps_b, precision=args.mixed_precision)
-    Tm = torch.zeros_like(T64)
+    ref = {"seconds": t64, "iterations": n64, "e_pair": e64.cpu().numpy().reshape(-1, 4).sum(1),
+           "energy": float(et64.cpu()[0]), "max_abs_R": float(r64.cpu()[0])}
+    log("fp64 reference solve: %d iterations, %.3f s, E = %.12f" % (n64, t64, ref["energy"]))
+    del T64
+    return ref
+
+
+def split_precision_row(prob, dev, eps_a, eps_b, precision, args, flops, ref, log):
+    """One split precision: grouped kernel throughput, the refined mixed solve
+    (args.mixed_outer FP64 refinements of args.mixed_inner low-precision
+    iterations) and the inner-only iteration, against the FP64 reference."""
+    import numpy as np
+    import torch
+
+    from paper_2008_03237_amd import Plan
+    mp = Plan(prob, dev["B"], dev["S"], dev["K"], eps_a, eps_b, precision=precision)
+    Tm = torch.zeros(max(prob.n_T, 1), dtype=torch.float64, device="cuda")
     mp.solve_mixed(1, 1, Tm)              # warm-up (split conversions, code objects)
     Tm.zero_()
     mp.reset()
@@ -309,13 +338,12 @@ def mixed_leg(prob, dev, plan64, eps_a, eps_b, args, flops, log):
     k_proj = ms[5] / max(cnt[5], 1)
     k_ms = k_lad + k_proj
     conv_ms = ms[4] / max(cnt[4], 1)
-    e64n = e64.cpu().numpy().reshape(-1, 4).sum(1)
     emn = em.cpu().numpy().reshape(-1, 4).sum(1)
     # inner only: the low-precision residuals iterated (FP64 update, energies
     # and DIIS) with no FP64 refinement, until max|R| stops falling
-    Ti = torch.zeros_like(T64)
+    Ti = torch.zeros_like(Tm)
     mp.reset()
-    best, n_in = None, 0
+    best, n_in, r_now = None, 0, None
     while n_in < 40:
         _, ei, eti, ri = mp.iterate(2, Ti)
         n_in += 2
@@ -329,23 +357,81 @@ def mixed_leg(prob, dev, plan64, eps_a, eps_b, args, flops, log):
     split_B = float((prob.naux.astype(np.int64) * prob.npno * n16 * prob.n_blocks().clip(0, 1)).sum()) * 2 * 2
     tgt = np.repeat(np.arange(prob.n_pairs), np.diff(prob.cpl_rowptr))
     split_S = float((prob.npno[tgt].astype(np.int64) * n16[prob.cpl_src]).sum()) * 2 * 2
-    res = {"precision": args.mixed_precision, "refinements": args.mixed_outer, "inner_iterations": args.mixed_inner,
+    row = {"refinements": args.mixed_outer, "inner_iterations": args.mixed_inner,
            "kernel_ms": round(k_ms, 3), "ladder_ms": round(k_lad, 3), "projection_ms": round(k_proj, 3),
            "split_T_ms": round(conv_ms, 3),
            "achieved_tflops": round(flops / (k_ms / 1e3) / 1e12, 3),
-           "mixed_solve_s": round(tm, 3), "fp64_solve_s": round(t64, 3), "fp64_iterations": n64,
-           "energy_fp64": float(et64.cpu()[0]), "energy_mixed": float(etm.cpu()[0]),
-           "total_energy_error": abs(float(etm.cpu()[0]) - float(et64.cpu()[0])),
-           "max_pair_energy_error": float(np.max(np.abs(emn - e64n))),
+           "mixed_solve_s": round(tm, 3), "vs_fp64_solve": round(tm / ref["seconds"], 3),
+           "energy_mixed": float(etm.cpu()[0]),
+           "total_energy_error": abs(float(etm.cpu()[0]) - ref["energy"]),
+           "max_pair_energy_error": float(np.max(np.abs(emn - ref["e_pair"]))),
            "max_abs_R_mixed": float(rm.cpu()[0]),
+           "gate_1e-7_pair_1e-6_total": bool(float(np.max(np.abs(emn - ref["e_pair"]))) <= 1e-7 and
+                                             abs(float(etm.cpu()[0]) - ref["energy"]) <= 1e-6),
            "inner_only": {"iterations": n_in, "max_abs_R": r_now,
-                          "total_energy_error": abs(float(eti.cpu()[0]) - float(et64.cpu()[0])),
-                          "max_pair_energy_error": float(np.max(np.abs(ein - e64n)))},
+                          "total_energy_error": abs(float(eti.cpu()[0]) - ref["energy"]),
+                          "max_pair_energy_error": float(np.max(np.abs(ein - ref["e_pair"])))},
            "split_bytes_per_launch": split_B + split_S,
            "hbm_frac": round((split_B + split_S) / (k_ms / 1e3) / 8e12, 4)}
-    log("mixed leg: %s" % res)
+    log("mixed leg %s: %s" % (precision, row))
     mp.close()
-    return res
+    del Tm, Ti
+    return row
+
+
+def mixed_leg(prob, dev, eps_a, eps_b, args, flops, ref, log):
+    """Split precisions with FP64 refinement against the converged FP64 solve."""
+    out = {"fp64_solve_s": round(ref["seconds"], 3), "fp64_iterations": ref["iterations"],
+           "energy_fp64": ref["energy"], "precisions": {}}
+    for prec in args.mixed_precisions.split(","):
+        out["precisions"][prec] = split_precision_row(prob, dev, eps_a, eps_b, prec, args, flops, ref, log)
+    return out
+
+
+def fp32_leg(prob, dev, eps_a, eps_b, args, fl_ladder, fl_proj, ref, log):
+    """The plain FP32 path (FP32 MFMA contractions, FP64 dressing, update,
+    energies and DIIS): time per iteration, the ladder launch against the
+    FP32 peak, and the energies of the FP32 iteration run until max|R| stops
+    falling, against the converged FP64 solve."""
+    import numpy as np
+    import torch
+
+    from paper_2008_03237_amd import Plan
+    p32 = Plan(prob, dev["B"], dev["S"], dev["K"], eps_a, eps_b, precision="fp32")
+    T = torch.zeros(max(prob.n_T, 1), dtype=torch.float64, device="cuda")
+    p32.iterate(2, T)
+    torch.cuda.synchronize()
+    p32.set_profiling(True)
+    t0 = time.perf_counter()
+    p32.iterate(args.steps, T)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) / max(args.steps, 1) * 1e3
+    ms, cnt = p32.phase_times()
+    p32.set_profiling(False)
+    lad = ms[0] / max(cnt[0], 1)
+    proj = ms[5] / max(cnt[5], 1)
+    T.zero_()
+    p32.reset()
+    best, n_it, r_now = None, 0, None
+    while n_it < 40:
+        _, e32, et32, r32 = p32.iterate(2, T)
+        n_it += 2
+        r_now = float(r32.cpu()[0])
+        if best is not None and r_now >= 0.5 * best:
+            break
+        best = r_now if best is None else min(best, r_now)
+    e32n = e32.cpu().numpy().reshape(-1, 4).sum(1)
+    row = {"ms_per_step": round(ms_step, 3), "value_gflops": round((fl_ladder + fl_proj) / (ms_step / 1e3) / 1e9, 2),
+           "ladder_ms": round(lad, 3), "projection_ms": round(proj, 3),
+           "ladder_tflops": round(fl_ladder / (lad / 1e3) / 1e12, 3),
+           "ladder_frac_fp32_peak": round(fl_ladder / (lad / 1e3) / 1e12 / PEAK_TFLOPS["fp32"], 4),
+           "iterations_to_stall": n_it, "max_abs_R": r_now,
+           "total_energy_error": abs(float(et32.cpu()[0]) - ref["energy"]),
+           "max_pair_energy_error": float(np.max(np.abs(e32n - ref["e_pair"])))}
+    log("fp32 leg: %s" % row)
+    p32.close()
+    del T
+    return row
 
 
 def schedule_line(plan):

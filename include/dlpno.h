@@ -23,8 +23,11 @@
  *   - host pointers are read during the call only (the plan copies them);
  *   - `stream` is a hipStream_t passed as void* (NULL = default stream);
  *   - nothing throws or aborts across the ABI: every call returns a status;
- *   - for identical inputs every result is bitwise reproducible (no floating
- *     point atomics; all reductions run in a fixed order);
+ *   - for identical inputs and an identical schedule every result is bitwise
+ *     reproducible (no floating point atomics; all reductions run in a fixed
+ *     order).  The schedule (worker count, items per wave, the autotuner's
+ *     choices) decides how the auxiliary and coupling ranges are cut into
+ *     partial sums, so plans with different schedules agree to rounding only;
  *   - a plan is not thread safe; calls on one plan must be serialised.
  */
 #ifndef DLPNO_H
@@ -151,7 +154,12 @@ dlpno_status dlpno_plan_destroy(dlpno_plan* plan);
 
 /* R = residual(T) for every stored block.  T, R: device, n_T doubles.  The
  * same-spin blocks of T must be antisymmetric unless the plan was created
- * with DLPNO_FLAG_GENERAL_T. */
+ * with DLPNO_FLAG_GENERAL_T.  Asynchronous: a non-finite residual element is
+ * reported by the next dlpno_iterate or dlpno_solve_mixed.  Every work item
+ * of the schedule is checked against the compiled kernel bodies when the
+ * plan is built (DLPNO_ERR_UNSUPPORTED there); should an item still reach a
+ * kernel without a body, the device raises a flag that those calls report as
+ * DLPNO_ERR_HIP. */
 dlpno_status dlpno_residual(dlpno_plan* plan, const double* T, double* R, void* stream);
 
 /* T_out = T - R / D; e_pair[4 p + c] = energy of block c (0 AA, 1 BB, 2 AB,
@@ -187,6 +195,17 @@ dlpno_status dlpno_f12_energy(dlpno_plan* plan, const double* T, const double* W
 dlpno_status dlpno_iterate(dlpno_plan* plan, int32_t n_iter, double* T, double* R,
                            double* e_pair, double* e_total, double* max_abs_R, void* stream);
 
+/* DIIS state after the last iteration (Pulay extrapolation of the amplitude
+ * vectors T' with errors T' - T).  The bordered system
+ *   [[G, -1], [-1, 0]] [c; -lambda] = [0; -1],  G_ab = <e_a, e_b> / max_k <e_k, e_k>,
+ * is solved for the extrapolation coefficients; while its 2-norm condition
+ * number exceeds 1e14 the oldest vector is dropped.  Outputs (host, any may be
+ * NULL): *count = vectors kept, *drops = vectors dropped since the last reset,
+ * coef[0..7] = coefficients oldest -> newest for the kept vectors (coef[count-1]
+ * = 1 and the others 0 before extrapolation starts), zeros after them.
+ * Waits for the work queued on `stream`. */
+dlpno_status dlpno_diis_state(const dlpno_plan* plan, int32_t* count, int32_t* drops, double* coef, void* stream);
+
 /* Clears the DIIS history and the iteration counter. */
 dlpno_status dlpno_reset(dlpno_plan* plan, void* stream);
 
@@ -199,9 +218,13 @@ int32_t dlpno_history(const dlpno_plan* plan, double* energy, double* max_abs_r,
  *   dB^Q_p = sum_blocks (Gbar B^Q T^T + Gbar^T B^Q T)   (general, unsymmetrised B).
  * The projection transpose is evaluated by gathering over the couplings of
  * each source pair; this requires the data the physics guarantees: f^s
- * symmetric and the S block of coupling (q <- p) the transpose of (p <- q).
+ * symmetric (to 1e-12 of its largest element), every coupling that carries a
+ * term paired with a reverse coupling (q <- p) whose S block is the transpose
+ * of (p <- q) (to 1e-12 relative).  The first call checks both (the overlap
+ * blocks on the device; synchronous that once) and keeps the result; a plan
+ * whose data violates them gets DLPNO_ERR_UNSUPPORTED from every call.
  * dT: n_T doubles; dB: n_B doubles (NULL skips it).  X^Q = B^Q T is recomputed
- * inside the kernel, never stored.  Asynchronous. */
+ * inside the kernel, never stored.  Asynchronous otherwise. */
 dlpno_status dlpno_residual_vjp(dlpno_plan* plan, const double* T, const double* Gbar,
                                 double* dT, double* dB, void* stream);
 

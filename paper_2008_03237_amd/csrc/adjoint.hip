@@ -147,6 +147,95 @@ __global__ void zero_f64_kernel(double* p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) p[i] = 0.0;
 }
 
+// One coupling and its reverse: S_e is [c][a] (rows n_src x cols n_tgt), the
+// reverse's block [a][c] must be its transpose.
+struct SPair {
+  int64_t off_e, off_r;
+  int32_t rows, cols;
+};
+
+// Sets *bad when an element of a reverse block differs from the transposed
+// element by more than 1e-12 of the larger of the two; one workgroup per pair.
+__global__ __launch_bounds__(256) void s_transpose_check_kernel(const SPair* pr, int64_t n, const double* S, int32_t* bad) {
+  for (int64_t k = blockIdx.x; k < n; k += gridDim.x) {
+    const SPair q = pr[k];
+    bool wrong = false;
+    for (int idx = threadIdx.x; idx < q.rows * q.cols; idx += 256) {
+      const int c = idx / q.cols, a = idx - c * q.cols;
+      const double x = S[q.off_e + idx], y = S[q.off_r + (int64_t)a * q.rows + c];
+      if (!(fabs(x - y) <= 1e-12 * fmax(fabs(x), fabs(y)))) wrong = true;
+    }
+    if (wrong) atomicOr(bad, 1);
+  }
+}
+
+// The transposed residual is evaluated by the forward kernels (see the top of
+// this file), which is valid when f^s is symmetric (checked at plan creation)
+// and every coupling that carries a term has a reverse coupling whose overlap
+// block is its transpose.  Checked once, at the first product; the result is
+// kept in the plan.
+static dlpno_status check_vjp_preconditions(dlpno_plan* P, hipStream_t s) {
+  if (P->vjp_checked != 0) return P->vjp_checked > 0 ? DLPNO_OK : fail(DLPNO_ERR_UNSUPPORTED, P->vjp_reason);
+  P->vjp_checked = -1;
+  if (!P->fock_symmetric) {
+    P->vjp_reason = "vector-Jacobian product: " + P->vjp_reason;
+    return fail(DLPNO_ERR_UNSUPPORTED, P->vjp_reason);
+  }
+  std::vector<SPair> pairs;
+  for (int p = 0; p < P->n_pairs; ++p) {
+    const PairDev& tp = P->pairs_h[p];
+    for (int64_t e = P->rowptr_h[p]; e < P->rowptr_h[p + 1]; ++e) {
+      bool active = false;
+      for (int b = 0; b < 4; ++b) active = active || P->terms_h[(size_t)e * 4 + b].src_off >= 0;
+      if (!active) continue;
+      const int q = P->cpl_h[e].src, k = P->cpl_k_h[e];
+      const int rep = P->cpl_side_h[e] == 0 ? tp.i : tp.j;
+      const PairDev& sq = P->pairs_h[q];
+      // reverse: target q reads p with rep replacing k (on the side where q holds k)
+      int64_t rev = -1;
+      for (int64_t f = P->rowptr_h[q]; f < P->rowptr_h[q + 1] && rev < 0; ++f) {
+        if (P->cpl_h[f].src != p || P->cpl_k_h[f] != rep) continue;
+        if ((P->cpl_side_h[f] == 0 ? sq.i : sq.j) == k) rev = f;
+      }
+      if (rev < 0) {
+        P->vjp_reason = "vector-Jacobian product: coupling " + std::to_string(e) + " (pair " + std::to_string(p) +
+                        " from pair " + std::to_string(q) + ") has no reverse coupling";
+        return fail(DLPNO_ERR_UNSUPPORTED, P->vjp_reason);
+      }
+      if (e < rev) pairs.push_back({P->cpl_h[e].off_S, P->cpl_h[rev].off_S, sq.n, tp.n});
+    }
+  }
+  if (!pairs.empty()) {
+    SPair* d_pairs = nullptr;
+    int32_t* d_bad = nullptr;
+    if (hipMalloc(&d_pairs, pairs.size() * sizeof(SPair)) != hipSuccess || hipMalloc(&d_bad, sizeof(int32_t)) != hipSuccess) {
+      if (d_pairs) (void)hipFree(d_pairs);
+      (void)hipGetLastError();
+      return fail(DLPNO_ERR_OOM, "vector-Jacobian product: overlap check buffers");
+    }
+    int32_t bad = 0;
+    hipError_t e1 = hipMemcpyAsync(d_pairs, pairs.data(), pairs.size() * sizeof(SPair), hipMemcpyHostToDevice, s);
+    if (e1 == hipSuccess) e1 = hipMemcpyAsync(d_bad, &bad, sizeof bad, hipMemcpyHostToDevice, s);
+    if (e1 == hipSuccess) {
+      const int grid = (int)std::min<size_t>(pairs.size(), 65536);
+      hipLaunchKernelGGL(s_transpose_check_kernel, dim3(grid), dim3(256), 0, s, d_pairs, (int64_t)pairs.size(),
+                         P->in.S, d_bad);
+      e1 = hipGetLastError();
+    }
+    if (e1 == hipSuccess) e1 = hipMemcpyAsync(&bad, d_bad, sizeof bad, hipMemcpyDeviceToHost, s);
+    if (e1 == hipSuccess) e1 = hipStreamSynchronize(s);
+    (void)hipFree(d_pairs);
+    (void)hipFree(d_bad);
+    if (e1 != hipSuccess) return fail(DLPNO_ERR_HIP, std::string("vector-Jacobian product: overlap check: ") + hipGetErrorString(e1));
+    if (bad) {
+      P->vjp_reason = "vector-Jacobian product: the overlap block of a reverse coupling is not the transpose of its coupling's";
+      return fail(DLPNO_ERR_UNSUPPORTED, P->vjp_reason);
+    }
+  }
+  P->vjp_checked = 1;
+  return DLPNO_OK;
+}
+
 }  // namespace dlpno
 
 using namespace dlpno;
@@ -155,6 +244,8 @@ extern "C" dlpno_status dlpno_residual_vjp(dlpno_plan* P, const double* T, const
                                            void* stream) {
   if (!P || ((!T || !G || !dT) && P->n_T > 0)) return fail(DLPNO_ERR_INVALID_ARG, "NULL plan or buffer");
   hipStream_t s = (hipStream_t)stream;
+  const dlpno_status pre = check_vjp_preconditions(P, s);
+  if (pre != DLPNO_OK) return pre;
   // dT = D o G + (ladder + projection)(G)
   if (run_grouped(P, G, s, -1, true) != hipSuccess) return fail(DLPNO_ERR_HIP, "vjp launch failed");
   FinishArgs f = finish_args(P, G);
@@ -178,7 +269,8 @@ extern "C" dlpno_status dlpno_residual_vjp(dlpno_plan* P, const double* T, const
     if (!items.empty()) {
       if (hipMalloc(&P->d_vjp_items, items.size() * sizeof(DbItem)) != hipSuccess) {
         P->d_vjp_items = nullptr;
-        return DLPNO_ERR_OOM;
+        (void)hipGetLastError();
+        return fail(DLPNO_ERR_OOM, "vector-Jacobian product: dB work items");
       }
       if (hipMemcpy(P->d_vjp_items, items.data(), items.size() * sizeof(DbItem), hipMemcpyHostToDevice) != hipSuccess)
         return fail(DLPNO_ERR_HIP, "vjp launch failed");
@@ -194,7 +286,8 @@ extern "C" dlpno_status dlpno_residual_vjp(dlpno_plan* P, const double* T, const
     if (!P->G32) {
       if (hipMalloc(&P->G32, (size_t)std::max<int64_t>(P->n_T, 1) * sizeof(float)) != hipSuccess) {
         P->G32 = nullptr;
-        return DLPNO_ERR_OOM;
+        (void)hipGetLastError();
+        return fail(DLPNO_ERR_OOM, "vector-Jacobian product: FP32 cotangent copy");
       }
     }
     if (launch_convert_f32(G, P->G32, P->n_T, s) != hipSuccess) return fail(DLPNO_ERR_HIP, "vjp launch failed");

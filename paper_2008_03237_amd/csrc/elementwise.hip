@@ -90,7 +90,7 @@ __global__ __launch_bounds__(kEwThreads) void finish_kernel(FinishArgs a) {
       esum += kk * tn;
     }
   }
-  if (bad) atomicOr(a.nonfinite, 1);
+  if (bad) atomicOr(a.nonfinite, kErrNonfinite);
   block_sum_max(esum, rmax);
   if (threadIdx.x == 0) {
     if (a.e_block) a.e_block[blk] = bk.w * esum;
@@ -215,6 +215,7 @@ __global__ void diis_reset_kernel(DiisState* st, int max, int start) {
   st->max = max;
   st->start = start;
   st->iter = 0;
+  st->drops = 0;
   for (int a = 0; a < 8; ++a) {
     st->coef[a] = 0.0;
     for (int b = 0; b < 8; ++b) st->gram[a][b] = 0.0;
@@ -288,9 +289,13 @@ __device__ void sym_eigs(double* A, int n, double* ev) {
   for (int k = 0; k < n; ++k) ev[k] = A[k * 9 + k];
 }
 
-// Gram update, bordered system [[<e_i,e_j>, -1], [-1, 0]] c = [0, -1] solved by
-// Gaussian elimination with partial pivoting; oldest vectors are dropped while
-// the matrix's 2-norm condition number exceeds 1e14.
+// Gram update, bordered system [[G, -1], [-1, 0]] c = [0, -1] with
+// G = <e_i, e_j> / max_k <e_k, e_k>, solved by Gaussian elimination with
+// partial pivoting; oldest vectors are dropped while the matrix's 2-norm
+// condition number exceeds 1e14.  The normalisation leaves c unchanged and
+// makes the test one of near linear dependence of the errors, independent of
+// their size (unnormalised, the condition number grows like 1 / |e|^2 as the
+// iteration converges).
 __global__ __launch_bounds__(256) void diis_solve_kernel(DiisState* st, const double* partial, int nparts) {
   const int cnt0 = st->count, head = st->head, mx = st->max;
   // new Gram row: the parts summed by 256 threads (thread t takes parts t,
@@ -327,10 +332,13 @@ __global__ __launch_bounds__(256) void diis_solve_kernel(DiisState* st, const do
     // slots oldest -> newest
     for (int k = 0; k < cnt; ++k) sl[k] = (head - (cnt - 1 - k) + mx) % mx;
     const int N = cnt + 1;
+    double gscale = 0.0;
+    for (int a = 0; a < cnt; ++a) gscale = fmax(gscale, st->gram[sl[a]][sl[a]]);
+    if (!(gscale > 0.0)) gscale = 1.0;
     for (int a = 0; a < N; ++a) {
       for (int b = 0; b < N; ++b) {
         double v;
-        if (a < cnt && b < cnt) v = st->gram[sl[a]][sl[b]];
+        if (a < cnt && b < cnt) v = st->gram[sl[a]][sl[b]] / gscale;
         else if (a == cnt && b == cnt) v = 0.0;
         else v = -1.0;
         M[a * 9 + b] = v;
@@ -348,6 +356,7 @@ __global__ __launch_bounds__(256) void diis_solve_kernel(DiisState* st, const do
       if (!(amin > 0.0) || amax / amin > 1e14) {
         cnt -= 1;      // drop the oldest
         st->count = cnt;
+        st->drops += 1;
         continue;
       }
     }

@@ -161,6 +161,15 @@ __device__ __forceinline__ double uni(double x) { return __builtin_bit_cast(doub
 template <typename T>
 __device__ __forceinline__ T* uni(T* p) { return reinterpret_cast<T*>(uni(reinterpret_cast<int64_t>(p))); }
 
+// An item whose (kind, variant) has no compiled body: the plan checks every
+// item against the compiled tables when it builds the schedule, so this is
+// never reached; if it were, the item's partial slot would be left stale, so
+// the wave raises kErrNoBody in the plan's status word instead of skipping
+// silently.
+__device__ __forceinline__ void no_body(int32_t* err) {
+  if ((threadIdx.x & 63) == 0 && err) atomicOr(err, kErrNoBody);
+}
+
 // raw buffer resource over [p, p + elems): out-of-range loads return 0
 template <typename F>
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const F* p, uint32_t elems) {
@@ -749,7 +758,7 @@ __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it
         if (it.ta0 == 0) DLPNO_LADDER(4, 1, 2, 0, false);
         else DLPNO_LADDER(4, 1, 2, 2, false);
         break;
-      default: break;
+      default: no_body(A.err); break;
     }
   } else if constexpr (KIND == ITEM_LADDER2) {
     // items of at most three tiles at two waves per SIMD: variants whose X
@@ -764,7 +773,7 @@ __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it
       case 4: DLPNO_LADDER_W(2, 2, 2, 0, false, true); break;
       case 5: DLPNO_LADDER_W(2, 1, 2, 0, false, true); break;
       case 7: DLPNO_LADDER_W(3, 1, 3, 0, false, true); break;
-      default: break;
+      default: no_body(A.err); break;
     }
   } else if constexpr (KIND == ITEM_PROJ2) {
     // projection items at two waves per SIMD: target and sources of at most
@@ -780,7 +789,7 @@ __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it
       DLPNO_PROJ2(4, 2, 2)
       DLPNO_PROJ2(5, 2, 1)
       DLPNO_PROJ2(7, 3, 1)
-      default: break;
+      default: no_body(A.err); break;
     }
 #undef DLPNO_PROJ2
   } else {
@@ -804,7 +813,7 @@ __device__ __forceinline__ void run_item(const GroupedArgs<F>& A, const Item& it
       case 4 * 6 + 2: proj_item<F, 3, 2, 3>(A, it, lds); break;
       DLPNO_PROJ(7, 3, 1)
       DLPNO_PROJ(8, 4, 1)
-      default: break;
+      default: no_body(A.err); break;
     }
 #undef DLPNO_PROJ
   }

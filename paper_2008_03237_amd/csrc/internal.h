@@ -130,7 +130,12 @@ struct GroupedArgs {
   // below the diagonal are computed and the others are stored mirrored.
   // 0 (vector-Jacobian products, whose cotangents are general): all tiles.
   int32_t anti;
+  int32_t* err;                  // device status word: kErrNoBody set by an item without a compiled body
 };
+
+// Bits of the device status word (the plan's non-finite flag).
+constexpr int32_t kErrNonfinite = 1;   // a residual element was NaN or Inf
+constexpr int32_t kErrNoBody = 2;      // a work item had no compiled kernel body (schedule/kernel mismatch)
 
 // grouped_f64.hip, grouped_f32.hip
 // kind: ITEM_LADDER or ITEM_PROJ, and in FP64 also ITEM_LADDER2, ITEM_LADDER4
@@ -147,7 +152,8 @@ struct DiisState {
   int32_t max;
   int32_t start;
   int32_t iter;            // iterations done (history index)
-  int32_t pad[3];
+  int32_t drops;           // vectors dropped for ill conditioning since the reset
+  int32_t pad[2];
   double gram[8][8];       // <e_a, e_b> by ring slot
   double coef[8];          // extrapolation coefficients by ring slot
 };
@@ -163,7 +169,7 @@ struct FinishArgs {
   double* T_new;           // Jacobi update out (null: no update)
   double* e_block;         // per block energy of T_new
   double* rmax_block;      // per block max |R|
-  int32_t* nonfinite;      // set to 1 when a residual element is not finite
+  int32_t* nonfinite;      // status word: kErrNonfinite set when a residual element is not finite
   int32_t with_driver;     // 0: R = D o T + partials (linear part only, used by the VJP)
   int32_t pad;
   const double* drv;       // when set, replaces the driver: R = drv + D o T + partials

@@ -83,9 +83,5 @@ extern "C" dlpno_status dlpno_solve_mixed(dlpno_plan* P, int32_t n_outer, int32_
   }
   MIXCK(fp64_residual(P, T, R, nullptr, e_pair, e_total, max_abs_R, true, s));
   P->host_iter += n_outer + 1;
-  int32_t flag = 0;
-  MIXCK(hipMemcpyAsync(&flag, P->d_nonfinite, sizeof flag, hipMemcpyDeviceToHost, s));
-  MIXCK(hipStreamSynchronize(s));
-  if (flag) return fail(DLPNO_ERR_NONFINITE, "a residual element was not finite");
-  return DLPNO_OK;
+  return read_status(P, s);
 }

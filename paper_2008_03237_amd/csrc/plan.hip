@@ -136,6 +136,30 @@ int pick_proj(int nt, int maxnb) {
   return best;
 }
 
+// Whether the kernels have a compiled body for an item of this kind and
+// variant in precision prec: mirrors the switch statements of run_item and
+// grouped_coop_kernel (grouped_impl.h) and split_run_item (split.hip).
+bool item_compiled(const Item& it, int prec) {
+  const bool fp64 = prec == DLPNO_FP64;
+  const int v = it.variant;
+  switch (it.kind) {
+    case ITEM_LADDER: return v >= 0 && v < kNumLadderVariants && !kLadderCoop[v];
+    case ITEM_LADDER2: return fp64 && v >= 0 && v < kNumLadderVariants && kLadderTwoWave[v];
+    case ITEM_LADDER4: return fp64 && (v == kLadderCoopPair || v == kLadderCoopOne);
+    case ITEM_PROJ2: {
+      const int tv = v >> 2, cq = (v & 3) + 1;
+      return fp64 && v >= 0 && tv < kNumProjVariants && kProjTwoWave[tv] && cq <= 3;
+    }
+    case ITEM_PROJ: {
+      const int tv = v >> 2, cq = (v & 3) + 1;
+      if (v < 0 || tv >= kNumProjVariants) return false;
+      // FP64/FP32: three target tiles in pairs of blocks take at most three source tiles
+      return is_split(prec) || !(tv == 6 && cq == 4);
+    }
+    default: return false;
+  }
+}
+
 struct Cand {
   Item it;
   double cost;
@@ -338,6 +362,16 @@ dlpno_status build_schedule(dlpno_plan* P) {
   P->sched64.items_h.clear();
   if (split) partition(cand64, P->sched64, unused);
   P->max_item_mfma = maxc;
+  // every item must have a compiled kernel body (an item without one would
+  // leave its partial slot stale)
+  for (const Item& it : P->sched.items_h)
+    if (!item_compiled(it, P->opt.precision))
+      return fail(DLPNO_ERR_UNSUPPORTED, "schedule item (kind " + std::to_string(it.kind) + ", variant " +
+                                             std::to_string(it.variant) + ") has no compiled kernel body");
+  for (const Item& it : P->sched64.items_h)
+    if (!item_compiled(it, DLPNO_FP64))
+      return fail(DLPNO_ERR_UNSUPPORTED, "FP64 schedule item (kind " + std::to_string(it.kind) + ", variant " +
+                                             std::to_string(it.variant) + ") has no compiled kernel body");
   return DLPNO_OK;
 }
 
@@ -505,6 +539,22 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
       ++slot;
     }
   }
+  // ---- occupied Fock symmetry (a precondition of the vector-Jacobian product) ----
+  {
+    double fmax = 0.0;
+    for (size_t x = 0; x < (size_t)n_occ * n_occ; ++x) fmax = std::max(fmax, std::max(std::fabs(prob->f_a[x]), std::fabs(prob->f_b[x])));
+    for (int a = 0; a < n_occ && P->fock_symmetric; ++a)
+      for (int b = a + 1; b < n_occ; ++b) {
+        const size_t ab = (size_t)a * n_occ + b, ba = (size_t)b * n_occ + a;
+        if (std::fabs(prob->f_a[ab] - prob->f_a[ba]) > 1e-12 * fmax ||
+            std::fabs(prob->f_b[ab] - prob->f_b[ba]) > 1e-12 * fmax) {
+          P->fock_symmetric = false;
+          P->vjp_reason = "the occupied Fock matrices are not symmetric (element " + std::to_string(a) + ", " +
+                          std::to_string(b) + ")";
+          break;
+        }
+      }
+  }
   // ---- couplings and terms ----
   P->rowptr_h.assign(prob->cpl_rowptr, prob->cpl_rowptr + npairs + 1);
   if (P->rowptr_h[0] != 0 || P->rowptr_h[npairs] != prob->n_couplings)
@@ -514,6 +564,8 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
       return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "cpl_rowptr must be non-decreasing"));
   if (prob->n_couplings > INT32_MAX) return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, "too many couplings"));
   P->cpl_h.resize(prob->n_couplings);
+  P->cpl_k_h.resize(prob->n_couplings);
+  P->cpl_side_h.resize(prob->n_couplings);
   P->terms_h.assign((size_t)prob->n_couplings * 4, TermDev{-1, 0.0, 0, -1});
   P->flops_proj = 0.0;
   P->n_terms = 0;
@@ -537,6 +589,8 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
       cd.src = c.src_pair;
       cd.nsrc = q.npno;
       cd.off_S = c.off_S;
+      P->cpl_k_h[e] = c.k;
+      P->cpl_side_h[e] = c.side;
       // terms per target block
       int slot = 0;
       for (int code = 0; code < 4; ++code) {
@@ -587,12 +641,17 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
     });
     std::vector<CplDev> c2;
     std::vector<TermDev> t2;
+    std::vector<int32_t> k2, s2;
     for (int64_t e : ord) {
       c2.push_back(P->cpl_h[e]);
+      k2.push_back(P->cpl_k_h[e]);
+      s2.push_back(P->cpl_side_h[e]);
       for (int b = 0; b < 4; ++b) t2.push_back(P->terms_h[(size_t)e * 4 + b]);
     }
     for (int64_t k = 0; k < (int64_t)ord.size(); ++k) {
       P->cpl_h[e0 + k] = c2[k];
+      P->cpl_k_h[e0 + k] = k2[k];
+      P->cpl_side_h[e0 + k] = s2[k];
       for (int b = 0; b < 4; ++b) P->terms_h[(size_t)(e0 + k) * 4 + b] = t2[(size_t)k * 4 + b];
     }
   }
@@ -749,6 +808,16 @@ void phase_collect(dlpno_plan* P) {
 
 bool is_split(int prec) { return prec == DLPNO_BF16X2 || prec == DLPNO_FP16X2; }
 
+// Waits for the stream and turns the device status word into a status.
+dlpno_status read_status(dlpno_plan* P, hipStream_t s) {
+  int32_t flag = 0;
+  HIPCK(hipMemcpyAsync(&flag, P->d_nonfinite, sizeof flag, hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  if (flag & kErrNoBody) return fail(DLPNO_ERR_HIP, "a work item had no compiled kernel body");
+  if (flag & kErrNonfinite) return fail(DLPNO_ERR_NONFINITE, "a residual element was not finite");
+  return DLPNO_OK;
+}
+
 // the work queues of one kind's launch
 WorkQueues queues(const dlpno_plan* P, const Schedule& S, int kind) {
   WorkQueues q{};
@@ -782,7 +851,7 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
       SplitArgs a{P->sched.d_items + P->sched.kind_begin[kind], queues(P, P->sched, kind), P->d_pairs, P->d_blocks,
                   P->d_cpl, P->d_terms, P->d_pair_boff, P->d_pair_bscale, P->d_blk_toff, P->d_blk_tscale,
                   P->d_cpl_soff, P->Bs_hi, P->Bs_lo, P->Ss_hi, P->Ss_lo, P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo,
-                  P->d_ws, general ? 0 : 1};
+                  P->d_ws, general ? 0 : 1, P->d_nonfinite};
       phase_begin(P, kind == ITEM_LADDER ? 0 : 5, s);
       e = launch_split_grouped(a, kind, prec == DLPNO_FP16X2, P->workers, s);
       phase_end(P, s);
@@ -807,11 +876,11 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
     phase_begin(P, phase, s);
     if (prec == DLPNO_FP32) {
       GroupedArgs<float> a{items, wq, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
-                           P->B32, P->S32, P->T32, P->d_ws, general ? 0 : 1};
+                           P->B32, P->S32, P->T32, P->d_ws, general ? 0 : 1, P->d_nonfinite};
       e = launch_grouped_f32(a, kind, P->workers, s);
     } else {
       GroupedArgs<double> a{items, wq, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
-                            P->in.B, P->in.S, T, P->d_ws, general ? 0 : 1};
+                            P->in.B, P->in.S, T, P->d_ws, general ? 0 : 1, P->d_nonfinite};
       e = launch_grouped_f64(a, kind, P->workers, s);
     }
     phase_end(P, s);
@@ -983,11 +1052,7 @@ extern "C" dlpno_status dlpno_iterate(dlpno_plan* P, int32_t n_iter, double* T, 
     for (int k = 0; k < n_iter; ++k) HIPCK(hipGraphLaunch(P->gexec, s));
   }
   P->host_iter += n_iter;
-  int32_t flag = 0;
-  HIPCK(hipMemcpyAsync(&flag, P->d_nonfinite, sizeof flag, hipMemcpyDeviceToHost, s));
-  HIPCK(hipStreamSynchronize(s));
-  if (flag) return fail(DLPNO_ERR_NONFINITE, "a residual element was not finite");
-  return DLPNO_OK;
+  return read_status(P, s);
 }
 
 extern "C" int32_t dlpno_history(const dlpno_plan* P, double* energy, double* max_abs_r, int32_t n) {
@@ -1001,6 +1066,23 @@ extern "C" int32_t dlpno_history(const dlpno_plan* P, double* energy, double* ma
     if (max_abs_r) max_abs_r[k] = h[2 * k + 1];
   }
   return m;
+}
+
+extern "C" dlpno_status dlpno_diis_state(const dlpno_plan* P, int32_t* count, int32_t* drops, double* coef,
+                                         void* stream) {
+  if (!P) return fail(DLPNO_ERR_INVALID_ARG, "NULL plan");
+  hipStream_t s = (hipStream_t)stream;
+  DiisState st;
+  HIPCK(hipMemcpyAsync(&st, P->d_diis, sizeof st, hipMemcpyDeviceToHost, s));
+  HIPCK(hipStreamSynchronize(s));
+  if (count) *count = st.count;
+  if (drops) *drops = st.drops;
+  if (coef) {
+    for (int k = 0; k < 8; ++k) coef[k] = 0.0;
+    const int mx = std::max(1, st.max);
+    for (int k = 0; k < st.count && k < 8; ++k) coef[k] = st.coef[(st.head - (st.count - 1 - k) + mx) % mx];
+  }
+  return DLPNO_OK;
 }
 
 extern "C" dlpno_status dlpno_flop_count(const dlpno_plan* P, double* ladder, double* projection) {

@@ -55,6 +55,14 @@ struct dlpno_plan {
   std::vector<dlpno::CplDev> cpl_h;
   std::vector<dlpno::TermDev> terms_h;
   std::vector<int64_t> rowptr_h;
+  std::vector<int32_t> cpl_k_h, cpl_side_h;   // k and side of each coupling (order of cpl_h)
+  // preconditions of the vector-Jacobian product (the transposed residual is
+  // evaluated by the forward kernels): symmetric occupied Fock matrices
+  // (checked at creation), a reverse for every coupling with a term and
+  // transposed overlap blocks on it (checked at the first product)
+  bool fock_symmetric = true;
+  int vjp_checked = 0;                        // 0 not yet, 1 satisfied, -1 violated
+  std::string vjp_reason;
   dlpno::Schedule sched;                // the plan's precision
   dlpno::Schedule sched64;              // split plans: FP64 items over the same slots (refinement residuals)
   dlpno::Tuning tune;
@@ -125,6 +133,7 @@ FinishArgs finish_args(dlpno_plan* P, const double* T);
 hipError_t enqueue_iteration(dlpno_plan* P, double* T, double* R, double* e_pair, double* e_total, double* rmax,
                              hipStream_t s, const double* drv = nullptr, int prec = -1, bool record = true);
 bool is_split(int prec);
+dlpno_status read_status(dlpno_plan* P, hipStream_t s);
 std::string describe(const dlpno_plan* P);
 void phase_begin(dlpno_plan* P, int ph, hipStream_t s);
 void phase_end(dlpno_plan* P, hipStream_t s);

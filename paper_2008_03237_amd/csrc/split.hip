@@ -4,9 +4,11 @@
 // in BF16 or FP16, and a product as hi*hi + hi*lo + lo*hi on the 16x16x32
 // MFMA (two 16-wide inner tiles per instruction) with FP32 accumulation (the lo*lo term is below the FP32 accumulation
 // error).  This keeps about 16 (BF16) or 22 (FP16) significant bits per
-// operand; the FP64 refinement driver (mixed.hip) recovers full accuracy.
-// FP16 needs power-of-two scaling: per pair for B, per block for the
-// amplitudes; BF16 has the FP32 exponent range and runs unscaled.
+// operand while the lo half stays a normal number; the FP64 refinement
+// driver (mixed.hip) recovers full accuracy.  FP16 needs power-of-two
+// scaling: per pair for B, per block for the amplitudes, and per projection
+// item and target block for the weighted stage-1 products; BF16 has the FP32
+// exponent range and runs unscaled.
 //
 // Split operands are stored in zero-padded layouts whose rows are 16-element
 // multiples, so every 16x16x16 fragment (4 consecutive inner-index elements
@@ -277,6 +279,38 @@ __device__ __forceinline__ void split_proj_item(const SplitArgs& A, const Item& 
     tscale[b] = A.blk_tscale
                     ? __builtin_bit_cast(float, uni(__builtin_bit_cast(int32_t, A.blk_tscale[blk0 + it.bslot0 + b])))
                     : 1.f;
+  // FP16: the stage-1 product Y of a term is split after scaling by
+  // -w tscale / qs (Fock weight, target over source block scale).  Those
+  // factors span orders of magnitude, so per target block they are first
+  // normalised by a power of two psc that puts the item's largest one in
+  // [256, 512): |Y| <= n_q * 512 < 65504 (|S| <= 1, scaled |X| <= 1), so the
+  // hi half cannot overflow, and the dominant terms keep their lo halves out
+  // of the FP16 subnormals.  The accumulator is unscaled by tscale * psc.
+  float psc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) psc[b] = 1.f;
+  if (A.blk_tscale) {
+    float wmax[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) wmax[b] = 0.f;
+    for (int e = it.lo; e < it.hi; ++e) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const TermDev& tg = A.terms[(int64_t)e * 4 + it.bslot0 + b];
+        if (uni(tg.src_off) < 0) continue;
+        const float qs = __builtin_bit_cast(float, uni(__builtin_bit_cast(int32_t, A.blk_tscale[uni(tg.src_blk)])));
+        wmax[b] = fmaxf(wmax[b], fabsf((float)uni(tg.w)) * (tscale[b] / qs));
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (wmax[b] > 0.f) {
+        int ex;
+        (void)frexpf(wmax[b], &ex);
+        psc[b] = ldexpf(1.f, min(100, max(-100, 9 - ex)));
+      }
+    }
+  }
   f4_t acc[NB][NT][NT];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
@@ -323,7 +357,8 @@ __device__ __forceinline__ void split_proj_item(const SplitArgs& A, const Item& 
       const __amdgpu_buffer_rsrc_t xrh = rsrc16(xh + toff, (uint32_t)(nq * nq16));
       const __amdgpu_buffer_rsrc_t xrl = rsrc16(xl + toff, (uint32_t)(nq * nq16));
       // rescale Y to the target block's scale with the Fock weight folded in
-      const float ysc = -w * tscale[b] / qs;
+      // (and the item's power-of-two normalisation, FP16)
+      const float ysc = -w * (tscale[b] / qs) * psc[b];
       // source d-tiles in pairs (one K = 32 operand of stage 2); every product
       // is a K = 32 MFMA, absent tiles are zero fragments
 #pragma unroll
@@ -371,7 +406,7 @@ __device__ __forceinline__ void split_proj_item(const SplitArgs& A, const Item& 
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     double* dst = A.ws + uni(A.blocks[blk0 + it.bslot0 + b].off_ws) + (int64_t)it.slot * nn;
-    store_tiles<float>(dst, n, 0, acc[b], mir(b), 1.0 / (double)tscale[b]);
+    store_tiles<float>(dst, n, 0, acc[b], mir(b), 1.0 / ((double)tscale[b] * (double)psc[b]));
   }
 }
 
@@ -417,7 +452,7 @@ __device__ __forceinline__ void split_run_item(const SplitArgs& A, const Item& i
         if (it.ta0 == 0) split_ladder_masked<S, 4, 1, 2, 0>(A, it);
         else split_ladder_masked<S, 4, 1, 2, 2>(A, it);
         break;
-      default: break;
+      default: no_body(A.err); break;
     }
   } else {
     switch (it.variant >> 2) {     // variant = 4 * (tile variant) + (source tiles - 1)
@@ -430,7 +465,7 @@ __device__ __forceinline__ void split_run_item(const SplitArgs& A, const Item& i
       case 6: split_proj_masked<S, 3, 2>(A, it); break;
       case 7: split_proj_masked<S, 3, 1>(A, it); break;
       case 8: split_proj_masked<S, 4, 1>(A, it); break;
-      default: break;
+      default: no_body(A.err); break;
     }
   }
 }

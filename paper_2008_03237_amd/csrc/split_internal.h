@@ -26,6 +26,7 @@ struct SplitArgs {
   const uint16_t* T_lo;
   double* ws;
   int32_t anti;               // same-spin blocks antisymmetric (see GroupedArgs::anti)
+  int32_t* err;               // device status word (see kErrNoBody)
 };
 
 // kind: ITEM_LADDER or ITEM_PROJ; every item of `a` must be of that kind

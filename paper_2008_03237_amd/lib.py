@@ -77,6 +77,7 @@ def lib():
         "dlpno_residual_vjp": [vp, vp, vp, vp, vp, vp],
         "dlpno_solve_mixed": [vp, i32, i32, vp, vp, vp, vp, vp, vp],
         "dlpno_flop_count": [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+        "dlpno_diis_state": [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double), vp],
         "dlpno_autotune": [vp, vp, vp, vp],
         "dlpno_set_profiling": [vp, i32],
         "dlpno_phase_times": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32],
@@ -236,6 +237,13 @@ class Plan:
         _check(lib().dlpno_solve_mixed(self._h, int(n_outer), int(n_inner), _ptr(T), _ptr(R), _ptr(e_pair),
                                        _ptr(e_total), _ptr(rmax), _stream()))
         return R, e_pair, e_total, rmax
+
+    def diis_state(self):
+        """(vectors kept, vectors dropped since the reset, coefficients oldest -> newest)."""
+        cnt, drops = C.c_int32(), C.c_int32()
+        coef = (C.c_double * 8)()
+        _check(lib().dlpno_diis_state(self._h, C.byref(cnt), C.byref(drops), coef, _stream()))
+        return cnt.value, drops.value, np.array(coef[:cnt.value])
 
     def flop_count(self):
         a, b = C.c_double(), C.c_double()

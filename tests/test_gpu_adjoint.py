@@ -142,3 +142,41 @@ def test_autograd_lagrangian_central_differences_50_pairs(precision):
     assert abs(fd_B - an_B) <= tol * abs(an_B)
     for x in (pp, pm, fp, plan):
         x.close()
+
+
+def test_vjp_refuses_data_without_the_adjoint_symmetries():
+    """The VJP evaluates the transposed residual with the forward kernels, which
+    needs symmetric occupied Fock matrices and transposed overlap blocks on
+    reverse couplings.  Data without them: the forward residual still runs,
+    the product is refused (DLPNO_ERR_UNSUPPORTED) instead of being silently
+    wrong; the same data made consistent again is accepted."""
+    from paper_2008_03237_amd import DlpnoError, Plan
+    prob = build_problem("chain", n_occ=12, band=3, somos=(4, 8), npno=("fixed", 10), naux=("fixed", 30))
+    plan, dev = device_problem(prob)
+    G = torch.ones_like(dev["T"])
+    plan.vjp(dev["T"], G)                                  # consistent data: accepted
+    plan.close()
+    # a non-symmetric beta Fock matrix
+    fb = prob.f_b.copy()
+    fb[2, 3] += 1e-3
+    prob_f = build_problem("chain", n_occ=12, band=3, somos=(4, 8), npno=("fixed", 10), naux=("fixed", 30))
+    prob_f.f_b = fb
+    eps_a, eps_b = torch.from_numpy(prob.eps_a).cuda(), torch.from_numpy(prob.eps_b).cuda()
+    pf = Plan(prob_f, dev["B"], dev["S"], dev["K"], eps_a, eps_b)
+    pf.residual(dev["T"])
+    with pytest.raises(DlpnoError) as ei:
+        pf.vjp(dev["T"], G)
+    assert ei.value.status == -8 and "symmetric" in str(ei.value)
+    pf.close()
+    # one overlap block that is no longer the transpose of its reverse
+    e = int(prob.cpl_rowptr[7])
+    S2 = dev["S"].clone()
+    S2[int(prob.cpl_off_S[e]) + 3] += 1e-6
+    ps = Plan(prob, dev["B"], S2, dev["K"], eps_a, eps_b)
+    ps.residual(dev["T"])
+    with pytest.raises(DlpnoError) as ei:
+        ps.vjp(dev["T"], G)
+    assert ei.value.status == -8 and "transpose" in str(ei.value)
+    with pytest.raises(DlpnoError):                       # the verdict is kept
+        ps.vjp(dev["T"], G)
+    ps.close()

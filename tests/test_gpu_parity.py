@@ -36,10 +36,16 @@ def test_generator_bitwise_on_device():
         assert np.array_equal(got.view(np.uint64), host.view(np.uint64)), f
 
 
-@pytest.mark.parametrize("cfg", ["tiny", "mini"])
-def test_residual_update_energy_parity(cfg):
-    prob = build_problem("tiny") if cfg == "tiny" else build_problem("chain", n_occ=24, band=6, somos=(7, 16))
-    print("case", cfg, prob.n_pairs, "pairs", flush=True)
+@pytest.mark.parametrize("cfg,fock_spin", [("tiny", 0.0), ("mini", 0.0), ("tiny", 0.3), ("mini", 0.3)])
+def test_residual_update_energy_parity(cfg, fock_spin):
+    """fock_spin > 0: the beta off-diagonal occupied Fock differs from the
+    alpha one, so every projection term must take the Fock matrix of the
+    replaced electron's spin (a swap changes the residual by ~1e-5 relative)."""
+    if cfg == "tiny":
+        prob = build_problem("tiny", fock_spin=fock_spin)
+    else:
+        prob = build_problem("chain", n_occ=24, band=6, somos=(7, 16), fock_spin=fock_spin)
+    print("case", cfg, "fock_spin", fock_spin, prob.n_pairs, "pairs", flush=True)
     plan, dev = device_problem(prob)
     R = plan.residual(dev["T"])
     Tn, e_pair, e_tot = plan.update(dev["T"], R)
@@ -148,6 +154,39 @@ def test_iterations_match_oracle_with_diis():
     plan.close()
 
 
+def test_diis_drop_and_coefficients_match_oracle():
+    """DIIS in lockstep with the oracle on the 20-orbital chain: stored vector
+    counts, drops and extrapolation coefficients after every iteration up to
+    the first drop (iteration 7, where the normalised bordered matrix of the
+    eight errors has condition number ~2.5e15, 25x over the 1e14 threshold,
+    so rounding cannot flip the decision), energies and amplitudes after 12
+    iterations (later drop decisions lie within 1% of the threshold and are
+    not compared)."""
+    prob = build_problem("chain", n_occ=20, band=5, somos=(6, 13))
+    plan, dev = device_problem(prob, T_random=False)
+    inp = oracle_inputs(prob)
+    zero = unpack_T(prob, np.zeros(prob.n_T))
+    n_it, n_lock = 12, 8
+    trace = []
+    To, hist = oracle.solve(inp, zero, n_it, use_diis=True, trace=trace)
+    T = dev["T"]
+    for k in range(n_it):
+        plan.iterate(1, T)
+        cnt, drops, coef = plan.diis_state()
+        ocnt, odrops, oc = trace[k]
+        print("iteration", k, "gpu", cnt, drops, "oracle", ocnt, odrops, flush=True)
+        if k < n_lock:
+            assert (cnt, drops) == (ocnt, odrops), (k, cnt, drops, ocnt, odrops)
+            if oc is not None:
+                np.testing.assert_allclose(coef, oc, rtol=0, atol=1e-9)
+    assert trace[n_lock - 1][1] == 1                 # the drop happened ...
+    E_gpu, _ = plan.history()
+    for k in range(n_it):                            # ... and the solve still matches
+        assert abs(E_gpu[k] - hist[k][0]) <= 1e-10, (k, E_gpu[k], hist[k][0])
+    compare_blocks(prob, T.cpu().numpy(), To, rel=1e-9)
+    plan.close()
+
+
 def test_plain_jacobi_iterations_match_oracle():
     prob = build_problem("chain", n_occ=16, band=4, somos=(5, 11))
     plan, dev = device_problem(prob, diis_max=0, T_random=False)
@@ -173,14 +212,16 @@ def test_nonfinite_detected():
     plan.close()
 
 
-@pytest.mark.parametrize("cfg,nsample", [("chain", 12), ("c160", 6)])
-def test_full_size_sampled_residual(cfg, nsample):
+@pytest.mark.parametrize("cfg,nsample,fock_spin", [("chain", 12, 0.0), ("c160", 6, 0.0), ("chain", 12, 0.3)])
+def test_full_size_sampled_residual(cfg, nsample, fock_spin):
     """Full workload in the benchmark's launch configuration; a seeded sample of
-    target pairs recomputed by the oracle one by one (inputs regenerated)."""
-    prob = build_problem(cfg)
-    print("case", cfg, "pairs", prob.n_pairs, flush=True)
+    target pairs recomputed by the oracle one by one (inputs regenerated).
+    fock_spin > 0: spin-dependent off-diagonal occupied Fock."""
+    prob = build_problem(cfg, fock_spin=fock_spin)
+    print("case", cfg, "fock_spin", fock_spin, "pairs", prob.n_pairs, flush=True)
     plan, dev = device_problem(prob)
     R = plan.residual(dev["T"])
+    Tn, e_pair, _ = plan.update(dev["T"], R)
     torch.cuda.synchronize()
     rng = np.random.default_rng(1234)
     n = prob.npno
@@ -203,13 +244,23 @@ def test_full_size_sampled_residual(cfg, nsample):
             T[(p, name)] = segment_values(prob.seed, seg).reshape(n[p], n[p])
             o += int(n[p]) ** 2
     Ro = oracle.residual_os(inp, T, pairs=sorted(pick))
+    # Jacobi update and pair-block energies of the sampled pairs
+    Tno = oracle.jacobi(inp, {k: T[k] for k in Ro}, Ro)
+    eo = oracle.pair_energies(inp, Tno)
     Rg = R.cpu().numpy()
+    Tg = Tn.cpu().numpy()
+    ep = e_pair.cpu().numpy().reshape(-1, 4)
+    code = {"AA": 0, "BB": 1, "AB": 2, "BA": 3}
     for (p, name), ref in Ro.items():
         i = oracle.stored_blocks(int(prob.pi[p]), int(prob.pj[p]), prob.is_somo.astype(bool)).index(name)
         o = int(prob.off_T[p]) + i * int(n[p]) ** 2
         got = Rg[o:o + int(n[p]) ** 2].reshape(n[p], n[p])
         d = np.linalg.norm(got - ref)
         assert d <= 1e-12 * np.linalg.norm(ref), (p, name, d, np.linalg.norm(ref))
+        assert float(np.max(np.abs(got - ref))) <= 1e-12 * float(np.max(np.abs(ref))), (p, name)
+        tg = Tg[o:o + int(n[p]) ** 2].reshape(n[p], n[p])
+        assert np.linalg.norm(tg - Tno[(p, name)]) <= 1e-12 * np.linalg.norm(Tno[(p, name)]), (p, name)
+        assert abs(ep[p, code[name]] - eo[(p, name)]) <= 1e-10, (p, name, ep[p, code[name]], eo[(p, name)])
     plan.close()
 
 

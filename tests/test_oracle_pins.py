@@ -296,3 +296,104 @@ def test_vjp_matches_central_differences_and_adjoint_identity():
     fd = (L(T, Bp) - L(T, Bm)) / (2 * h)
     an = sum(float(np.sum(dB[p] * Bd[p])) for p in dB)
     assert abs(fd - an) <= 1e-8 * max(1.0, abs(an))
+
+
+# ------------------------------------------------------------- DIIS pins
+def test_diis_two_vector_closed_form():
+    # Pulay extrapolation minimises |sum c_k e_k| subject to sum c_k = 1; for two
+    # error vectors that is c1 = <e2, e2 - e1> / |e1 - e2|^2, c2 = 1 - c1
+    rng = np.random.default_rng(41)
+    d = oracle.DIIS(max_vec=8, start=2)
+    e1, e2 = rng.standard_normal(50), rng.standard_normal(50)
+    v1, v2 = rng.standard_normal(50), rng.standard_normal(50)
+    d.push(v1, e1)
+    d.push(v2, e2)
+    c = d.coefficients()
+    c1 = float(np.dot(e2, e2 - e1) / np.dot(e1 - e2, e1 - e2))
+    np.testing.assert_allclose(c, [c1, 1.0 - c1], rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(d.extrapolate(), c1 * v1 + (1 - c1) * v2, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("k", [3, 5, 8])
+def test_diis_extrapolated_error_orthogonal_to_affine_hull(k):
+    # optimality of the constrained minimum: the extrapolated error e* is
+    # orthogonal to every difference e_a - e_b, and the coefficients sum to 1
+    rng = np.random.default_rng(100 + k)
+    d = oracle.DIIS(max_vec=8, start=3)
+    E = rng.standard_normal((k, 40))
+    for a in range(k):
+        d.push(rng.standard_normal(40), E[a])
+    c = d.coefficients()
+    assert abs(float(np.sum(c)) - 1.0) < 1e-13
+    es = c @ E
+    for a in range(k):
+        for b in range(a + 1, k):
+            assert abs(float(np.dot(es, E[a] - E[b]))) < 1e-12 * float(np.dot(E[a] - E[b], E[a] - E[b]))
+    # and it is the minimum: moving inside the hull never lowers |e*|
+    for _ in range(20):
+        z = rng.standard_normal(k)
+        z -= z.mean()
+        assert np.linalg.norm((c + 1e-3 * z) @ E) >= np.linalg.norm(es)
+
+
+def test_diis_drops_the_oldest_of_a_near_dependent_history():
+    # e3 = e1 + 1e-9 w: the bordered matrix's condition number is ~1e18 > 1e14,
+    # so the oldest vector (e1) is dropped and the remaining two give the
+    # two-vector closed form
+    rng = np.random.default_rng(43)
+    e1, e2, w = rng.standard_normal(30), rng.standard_normal(30), rng.standard_normal(30)
+    e3 = e1 + 1e-9 * w
+    vs = [rng.standard_normal(30) for _ in range(3)]
+    d = oracle.DIIS(max_vec=8, start=3)
+    for v, e in zip(vs, (e1, e2, e3)):
+        d.push(v, e)
+    c = d.coefficients()
+    assert d.drops == 1 and len(d.errs) == 2
+    assert np.array_equal(d.errs[0], e2) and np.array_equal(d.errs[1], e3)
+    c1 = float(np.dot(e3, e3 - e2) / np.dot(e2 - e3, e2 - e3))
+    np.testing.assert_allclose(c, [c1, 1.0 - c1], rtol=1e-12)
+    # a well-conditioned history of three is kept whole
+    d2 = oracle.DIIS(max_vec=8, start=3)
+    for v, e in zip(vs, (e1, e2, w)):
+        d2.push(v, e)
+    d2.coefficients()
+    assert d2.drops == 0 and len(d2.errs) == 3
+
+
+def test_diis_ring_keeps_newest_eight_and_starts_at_three():
+    rng = np.random.default_rng(44)
+    d = oracle.DIIS(max_vec=8, start=3)
+    vs = [rng.standard_normal(12) for _ in range(10)]
+    d.push(vs[0], rng.standard_normal(12))
+    d.push(vs[1], rng.standard_normal(12))
+    # fewer than `start` stored: no extrapolation, the newest vector is taken
+    assert np.array_equal(d.extrapolate(), vs[1])
+    for v in vs[2:]:
+        d.push(v, rng.standard_normal(12))
+    assert len(d.vecs) == 8
+    assert all(np.array_equal(a, b) for a, b in zip(d.vecs, vs[2:]))
+
+
+def test_diis_drop_rule_is_scale_invariant():
+    # the drop test measures near linear dependence, not the size of the
+    # errors: the same history scaled by 1e-10 (a converging iteration) keeps
+    # every vector and gives the same coefficients; the near-dependent one
+    # still drops its oldest vector
+    rng = np.random.default_rng(45)
+    E = rng.standard_normal((6, 40))
+    for scale in (1.0, 1e-10):
+        d = oracle.DIIS(max_vec=8, start=3)
+        for e in E:
+            d.push(rng.standard_normal(40), scale * e)
+        c = d.coefficients()
+        assert d.drops == 0 and len(d.errs) == 6
+        if scale == 1.0:
+            c_ref = c
+        else:
+            np.testing.assert_allclose(c, c_ref, rtol=1e-10, atol=1e-12)
+    e1, e2, w = E[0], E[1], E[2]
+    d = oracle.DIIS(max_vec=8, start=3)
+    for e in (e1, e2, e1 + 1e-9 * w):
+        d.push(rng.standard_normal(40), 1e-10 * e)
+    d.coefficients()
+    assert d.drops == 1 and len(d.errs) == 2

@@ -55,3 +55,47 @@ def test_random_overlaps_of_reverse_couplings_are_transposes():
         assert np.array_equal(W, W2.T)
         checked += 1
     assert checked == len(where)
+
+
+def test_spin_dependent_offdiagonal_fock_option():
+    """fock_spin draws the beta off-diagonal occupied Fock from a field of its
+    own on the alpha support: symmetric, different from alpha, same coupling
+    list, and the default recipe unchanged."""
+    base = build_problem("chain", n_occ=24, band=6, somos=(7, 16))
+    prob = build_problem("chain", n_occ=24, band=6, somos=(7, 16), fock_spin=0.3)
+    assert np.array_equal(base.f_a, prob.f_a) and np.array_equal(base.f_b, build_problem(
+        "chain", n_occ=24, band=6, somos=(7, 16)).f_b)
+    d = prob.f_b - prob.f_a - np.diag(np.diag(prob.f_b - prob.f_a))
+    assert np.array_equal(prob.f_b, prob.f_b.T)
+    assert np.count_nonzero(d) == np.count_nonzero(prob.f_a - np.diag(np.diag(prob.f_a)))
+    assert np.array_equal(prob.cpl_src, base.cpl_src) and np.array_equal(prob.cpl_k, base.cpl_k)
+
+
+def test_spin_dependent_fock_makes_a_spin_swap_visible():
+    """With fock_spin, taking the alpha Fock matrix for a beta electron (or the
+    reverse) in the projection weights changes the residual far beyond the
+    1e-12 parity tolerance, in every spin-block class that has a beta
+    electron; without it only the diagonal differs, which the projection never
+    reads."""
+    import oracle
+    from oracle.model import unpack_T
+    for spin, expect_visible in ((0.3, True), (0.0, False)):
+        prob = build_problem("chain", n_occ=12, band=3, somos=(4, 8), npno=("fixed", 6), naux=("fixed", 10),
+                             fock_spin=spin)
+        inp = oracle.Inputs.from_problem(prob, B=prob.materialize("B"), K=prob.materialize("K"),
+                                         S=prob.materialize("S"))
+        T = unpack_T(prob, prob.materialize("T"))
+        R = oracle.residual_os(inp, T, terms=("projection",))
+        fb_swapped = prob.f_a.copy()
+        np.fill_diagonal(fb_swapped, np.diag(prob.f_b))     # keep the diagonal (it never enters)
+        bad = oracle.Inputs(inp.n_occ, inp.is_somo, inp.pairs, inp._B, inp.K, inp.eps_a, inp.eps_b,
+                            inp.f_a, fb_swapped, inp._S)
+        Rb = oracle.residual_os(bad, T, terms=("projection",))
+        scale = max(float(np.max(np.abs(v))) for v in R.values())
+        for name in ("BB", "AB", "BA"):
+            diff = max(float(np.max(np.abs(R[k] - Rb[k]))) for k in R if k[1] == name)
+            if expect_visible:
+                assert diff > 1e-6 * scale, (name, diff, scale)
+            else:
+                assert diff == 0.0, (name, diff)
+        assert max(float(np.max(np.abs(R[k] - Rb[k]))) for k in R if k[1] == "AA") == 0.0

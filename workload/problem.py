@@ -35,7 +35,7 @@ BLOCK_BITS = {"AA": 1, "BB": 2, "AB": 4, "BA": 8}
 BLOCK_SPINS = {"AA": (0, 0), "BB": (1, 1), "AB": (0, 1), "BA": (1, 0)}
 
 # Philox field ids (fourth counter word)
-F_NPNO, F_NAUX, F_B, F_T, F_K, F_EPS, F_FDIAG, F_FOFF, F_S, F_QR, F_W, F_F12 = range(1, 13)
+F_NPNO, F_NAUX, F_B, F_T, F_K, F_EPS, F_FDIAG, F_FOFF, F_S, F_QR, F_W, F_F12, F_FOFFB = range(1, 14)
 
 # F12 inputs (synthetic): W = V + C per stored block, in the amplitude layout,
 # and six scalars per block (V, V', B1..B4, see Problem.f12_scalars)
@@ -216,7 +216,10 @@ def _dims(rule, seed, fld, P):
 def build_problem(name="tiny", **override):
     """Build the descriptors and small inputs of a named (or customised) workload.
 
-    Overrides: any CONFIGS key, e.g. n_occ=24, band=6, somos=(8, 16)."""
+    Overrides: any CONFIGS key, e.g. n_occ=24, band=6, somos=(8, 16), and
+    fock_spin=x: beta off-diagonal occupied Fock elements f_b[i,k] = f_a[i,k] +
+    x 0.02 exp(-|i-k|/3) z' with z' from a field of their own (default 0: the
+    off-diagonal elements are the same for both spins)."""
     cfg = dict(CONFIGS[name]) if name in CONFIGS else {}
     cfg.update(override)
     seed = int(cfg["seed"])
@@ -271,6 +274,17 @@ def build_problem(name="tiny", **override):
         f_a[i, i + d] = v
         f_a[i + d, i] = v
     f_b = f_a.copy()
+    # optional spin dependence of the off-diagonal occupied Fock elements: the
+    # beta elements get an independent draw of relative size fock_spin on the
+    # same support (so the coupling list is unchanged)
+    fock_spin = float(cfg.get("fock_spin", 0.0))
+    if fock_spin != 0.0:
+        for d in range(1, min(band, n_occ - 1) + 1):
+            i = np.arange(n_occ - d)
+            z = philox.normals(seed, F_FOFFB, d, i.astype(np.uint64))
+            v = fock_spin * 0.02 * np.exp(-d / 3.0) * z
+            f_b[i, i + d] += v
+            f_b[i + d, i] += v
     pol_occ = np.zeros(n_occ)
     for s in somos:
         pol_occ += 0.05 * np.exp(-np.abs(occ_idx - s) / 2.0)
