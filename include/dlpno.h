@@ -162,6 +162,19 @@ dlpno_status dlpno_plan_destroy(dlpno_plan* plan);
  * DLPNO_ERR_HIP. */
 dlpno_status dlpno_residual(dlpno_plan* plan, const double* T, double* R, void* stream);
 
+/* dlpno_residual for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and results (bitwise equal to dlpno_residual on the same
+ * plan), with the partial-sum workspace taken from a static device array of
+ * the library - 256 MiB (2^25 doubles) per GPU, held until the process ends -
+ * instead of the plan's.  The call itself allocates nothing (no hipMalloc,
+ * no events; phase timing is skipped).  The caller passes T and R (device,
+ * n_T doubles) as for dlpno_residual.  A plan whose partial sums exceed the
+ * array gets DLPNO_ERR_DIM_RANGE (fewer workers or items per wave make fewer
+ * partial slots).  All calls on one GPU share the array: calls that overlap
+ * in time there (other streams or threads) race.  Asynchronous. */
+dlpno_status dlpno_residual_noalloc(dlpno_plan* plan, const double* T, double* R, void* stream);
+
 /* T_out = T - R / D; e_pair[4 p + c] = energy of block c (0 AA, 1 BB, 2 AB,
  * 3 BA) of pair p computed with T_out (0 for absent blocks); *e_total = sum.
  * All device pointers; e_pair has 4 n_pairs doubles.  T_out may equal T. */

@@ -659,6 +659,10 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   int dev = 0;
   HIPCK(hipGetDevice(&dev));
   P->device = dev;
+  {
+    const dlpno_status sst = scratch_init(dev);
+    if (sst != DLPNO_OK) return destroy_fail(sst);
+  }
   hipDeviceProp_t prop;
   HIPCK(hipGetDeviceProperties(&prop, dev));
   P->num_cu = prop.multiProcessorCount;
@@ -828,8 +832,9 @@ WorkQueues queues(const dlpno_plan* P, const Schedule& S, int kind) {
 
 // grouped kernel over amplitudes T (FP64 buffer given by the caller) in the
 // plan's precision, or in `prec` when given (FP64 residuals of a split plan)
-hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, bool general) {
+hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, bool general, double* ws) {
   hipError_t e;
+  double* const wsp = ws ? ws : P->d_ws;
   if (P->sched.items_h.empty()) return hipSuccess;
   if (prec < 0) prec = P->opt.precision;
   if (prec == DLPNO_FP32) {
@@ -851,7 +856,7 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
       SplitArgs a{P->sched.d_items + P->sched.kind_begin[kind], queues(P, P->sched, kind), P->d_pairs, P->d_blocks,
                   P->d_cpl, P->d_terms, P->d_pair_boff, P->d_pair_bscale, P->d_blk_toff, P->d_blk_tscale,
                   P->d_cpl_soff, P->Bs_hi, P->Bs_lo, P->Ss_hi, P->Ss_lo, P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo,
-                  P->d_ws, general ? 0 : 1, P->d_nonfinite};
+                  wsp, general ? 0 : 1, P->d_nonfinite};
       phase_begin(P, kind == ITEM_LADDER ? 0 : 5, s);
       e = launch_split_grouped(a, kind, prec == DLPNO_FP16X2, P->workers, s);
       phase_end(P, s);
@@ -876,11 +881,11 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
     phase_begin(P, phase, s);
     if (prec == DLPNO_FP32) {
       GroupedArgs<float> a{items, wq, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
-                           P->B32, P->S32, P->T32, P->d_ws, general ? 0 : 1, P->d_nonfinite};
+                           P->B32, P->S32, P->T32, wsp, general ? 0 : 1, P->d_nonfinite};
       e = launch_grouped_f32(a, kind, P->workers, s);
     } else {
       GroupedArgs<double> a{items, wq, P->d_pairs, P->d_blocks, P->d_cpl, P->d_terms,
-                            P->in.B, P->in.S, T, P->d_ws, general ? 0 : 1, P->d_nonfinite};
+                            P->in.B, P->in.S, T, wsp, general ? 0 : 1, P->d_nonfinite};
       e = launch_grouped_f64(a, kind, P->workers, s);
     }
     phase_end(P, s);
@@ -889,7 +894,7 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
   return hipSuccess;
 }
 
-FinishArgs finish_args(dlpno_plan* P, const double* T) {
+FinishArgs finish_args(dlpno_plan* P, const double* T, const double* ws) {
   FinishArgs f{};
   f.blocks = P->d_blocks;
   f.n_blocks = P->n_blocks;
@@ -897,7 +902,7 @@ FinishArgs finish_args(dlpno_plan* P, const double* T) {
   f.K = P->in.K;
   f.eps_a = P->in.eps_a;
   f.eps_b = P->in.eps_b;
-  f.ws = P->d_ws;
+  f.ws = ws ? ws : P->d_ws;
   f.e_block = P->d_e_block;
   f.rmax_block = P->d_rmax_block;
   f.nonfinite = P->d_nonfinite;

@@ -128,8 +128,13 @@ dlpno_status build_schedule(dlpno_plan* P);
 dlpno_status upload_schedule(dlpno_plan* P, hipStream_t s);
 // general: the amplitudes may lack the antisymmetry of same-spin blocks
 // (cotangents of the vector-Jacobian product), so every tile is computed
-hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec = -1, bool general = false);
-FinishArgs finish_args(dlpno_plan* P, const double* T);
+// ws: partial-sum workspace to use in place of the plan's own (nullptr: the plan's)
+hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec = -1, bool general = false,
+                       double* ws = nullptr);
+FinishArgs finish_args(dlpno_plan* P, const double* T, const double* ws = nullptr);
+// noalloc.hip: device address of the static scratch array, once per device
+// (called by dlpno_plan_create with the plan's device current)
+dlpno_status scratch_init(int device);
 hipError_t enqueue_iteration(dlpno_plan* P, double* T, double* R, double* e_pair, double* e_total, double* rmax,
                              hipStream_t s, const double* drv = nullptr, int prec = -1, bool record = true);
 bool is_split(int prec);

@@ -70,6 +70,7 @@ def lib():
         "dlpno_plan_create": [C.POINTER(Problem), C.POINTER(Inputs), C.POINTER(Options), vp, C.POINTER(vp)],
         "dlpno_plan_destroy": [vp],
         "dlpno_residual": [vp, vp, vp, vp],
+        "dlpno_residual_noalloc": [vp, vp, vp, vp],
         "dlpno_update": [vp, vp, vp, vp, vp, vp, vp],
         "dlpno_f12_energy": [vp, vp, vp, vp, vp, vp, vp],
         "dlpno_iterate": [vp, i32, vp, vp, vp, vp, vp, vp],
@@ -178,6 +179,12 @@ class Plan:
     def residual(self, T, R=None):
         R = self._new(self.n_T) if R is None else R
         _check(lib().dlpno_residual(self._h, _ptr(T), _ptr(R), _stream()))
+        return R
+
+    def residual_noalloc(self, T, R):
+        """dlpno_residual_noalloc: R = residual(T) with the library's static
+        scratch as workspace; the caller provides R (nothing is allocated)."""
+        _check(lib().dlpno_residual_noalloc(self._h, _ptr(T), _ptr(R), _stream()))
         return R
 
     def update(self, T, R, T_out=None):
