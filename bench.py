@@ -115,8 +115,15 @@ def main():
     ap.add_argument("--mixed-outer", type=int, default=3, help="FP64 refinement steps")
     ap.add_argument("--mixed-inner", type=int, default=4, help="low-precision iterations per refinement step")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-path leg")
+    ap.add_argument("--no-hole", action="store_true", help="skip the hole-hole ladder leg")
+    ap.add_argument("--hole-scale", type=float, default=0.02,
+                    help="scale of the synthetic occupied integrals of the hole-hole ladder leg")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy first (reference for HBM byte counters)")
+    ap.add_argument("--profile-residuals", type=int, default=0,
+                    help="profiling run: only N residual evaluations per precision of --profile-precisions "
+                         "(default schedule), one JSON line of their kernel times, nothing else")
+    ap.add_argument("--profile-precisions", default="fp64,bf16x2,fp16x2")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: runs on one GPU only (sharding the pairs across GPUs is not implemented); "
@@ -146,6 +153,9 @@ def main():
     log("inputs generated on the device")
     eps_a = torch.from_numpy(prob.eps_a).cuda()
     eps_b = torch.from_numpy(prob.eps_b).cuda()
+    if args.profile_residuals > 0:
+        print(json.dumps(profile_residuals(prob, dev, eps_a, eps_b, args, log)), flush=True)
+        return
     plan = Plan(prob, dev["B"], dev["S"], dev["K"], eps_a, eps_b, precision=args.precision)
     T = dev["T"]                 # seeded amplitudes: the autotuner times the grouped kernel on them
     log("plan created")
@@ -251,6 +261,8 @@ def main():
             out["mixed"] = mixed_leg(prob, dev, eps_a, eps_b, args, flops, ref, log)
         if not args.no_fp32:
             out["fp32"] = fp32_leg(prob, dev, eps_a, eps_b, args, fl_ladder, fl_proj, ref, log)
+    if not args.no_hole and args.precision == "fp64":
+        out["hole_ladder"] = hole_leg(args, dev, eps_a, eps_b, fl_proj, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, n_pairs=args.cpu_pairs)
     plan.close()
@@ -285,6 +297,73 @@ def f12_leg(prob, plan, T, log):
     log("f12 leg: %s" % res)
     del W
     return res
+
+
+def profile_residuals(prob, dev, eps_a, eps_b, args, log):
+    """Profiling run (rocprofv3 kernel traces and counters): for each precision,
+    a plan with the default schedule and args.profile_residuals residual
+    evaluations of the seeded amplitudes; their per-launch kernel times."""
+    import torch
+
+    from paper_2008_03237_amd import Plan
+    out = {"workload": args.workload, "residuals": args.profile_residuals, "launch_ms": {}}
+    names = ["ladder one-wave", "finish", "reduce", "diis", "convert", "projection one-wave", "ladder two-wave",
+             "ladder cooperative", "projection two-wave"]
+    for prec in args.profile_precisions.split(","):
+        plan = Plan(prob, dev["B"], dev["S"], dev["K"], eps_a, eps_b, precision=prec)
+        R = torch.empty_like(dev["T"])
+        plan.set_profiling(True)
+        for k in range(args.profile_residuals):
+            plan.residual(dev["T"], R)
+            log("%s residual %d done" % (prec, k))
+        torch.cuda.synchronize()
+        ms, cnt = plan.phase_times()
+        plan.set_profiling(False)
+        out["launch_ms"][prec] = {names[k]: round(ms[k] / cnt[k], 3) for k in range(len(names)) if cnt[k] > 0}
+        fl, fp = plan.flop_count()
+        out.setdefault("flops_per_residual", {"ladder": fl, "projection": fp})
+        plan.close()
+        del R
+    return out
+
+
+def hole_leg(args, dev, eps_a, eps_b, fl_proj_base, log):
+    """The same workload with the hole-hole ladder added (the first of the
+    CCSD terms beyond the hot path's model): synthetic occupied integrals
+    (k i | l j) within two orbitals of (i, j), one extra coupling per ordered
+    (k, l), run by the projection launches.  FP64 iterations from T = 0,
+    timed like the main leg."""
+    import torch
+
+    from paper_2008_03237_amd import Plan
+    from workload import build_problem
+    from workload.gpu import device_fields
+    prob = build_problem(args.workload, hole_ladder=args.hole_scale)
+    S = device_fields(prob, fields=("S",))["S"]          # B, K and eps are those of the main leg
+    plan = Plan(prob, dev["B"], S, dev["K"], eps_a, eps_b)
+    T = torch.zeros(max(prob.n_T, 1), dtype=torch.float64, device="cuda")
+    plan.iterate(args.warmup, T)
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    t0 = time.perf_counter()
+    _, _, e_tot, rmax = plan.iterate(args.steps, T)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) / max(args.steps, 1) * 1e3
+    ms, cnt = plan.phase_times()
+    plan.set_profiling(False)
+    fl, fp = plan.flop_count()
+    proj_ms = ms[5] / max(cnt[5], 1) + ms[8] / max(cnt[8], 1)
+    row = {"hole_hole_couplings": int(prob.n_hh), "ms_per_step": round(ms_step, 3),
+           "value_gflops": round((fl + fp) / (ms_step / 1e3) / 1e9, 2),
+           "flops_hole_hole": fp - fl_proj_base, "flops_projection_and_hole_hole": fp,
+           "projection_ms": round(proj_ms, 3),
+           "projection_tflops": round(fp / (proj_ms / 1e3) / 1e12, 3) if proj_ms > 0 else None,
+           "energy_after": float(e_tot.cpu()[0]), "iterations": args.warmup + args.steps,
+           "max_abs_R": float(rmax.cpu()[0]), "S_GB": round(prob.n_S * 8 / 1e9, 2)}
+    log("hole-hole ladder leg: %s" % row)
+    plan.close()
+    del S, T
+    return row
 
 
 def fp64_reference(prob, plan64, log):

@@ -98,6 +98,26 @@ typedef struct {
   int64_t off_S;
 } dlpno_coupling;
 
+/* One hole-hole ladder coupling of a target pair p = (i, j) (CSR row of p;
+ * the first slice of the CCSD terms beyond the model above): the ordered
+ * occupied pair (k, l), whose source pair is {min(k, l), max(k, l)}.  Every
+ * target block s s' with k in occ_s and l in occ_s' gets
+ *     + w S_{p,kl} T^{ss'}_{(k,l)} S_{kl,p},   w = (k i | l j)  (chemists' notation),
+ * with T_{(k,l)} for k > l the transposed s' s block of (l, k) and k = l only
+ * for s != s'.  This is the spin-orbital term 1/2 sum_KL <KL||IJ> t_KL^AB of
+ * the CCSD doubles residual in the pair's PNOs (Sec. II.B.3 solves the CC
+ * residual equations in that basis).  off_S: the overlap block between the
+ * source PNOs (rows) and the target PNOs (columns) as in dlpno_coupling; a
+ * source equal to the target needs an identity block.  Every ordered (k, l)
+ * is one coupling. */
+typedef struct {
+  int32_t src_pair;
+  int32_t k, l;
+  int32_t reserved;
+  int64_t off_S;
+  double w;
+} dlpno_hh_coupling;
+
 /* Problem description (all host memory, copied by dlpno_plan_create). */
 typedef struct {
   int32_t n_occ;
@@ -110,6 +130,9 @@ typedef struct {
   const double* f_a;               /* [n_occ * n_occ] alpha occupied Fock */
   const double* f_b;               /* [n_occ * n_occ] beta occupied Fock */
   int64_t n_B, n_T, n_K, n_eps, n_S; /* element counts of the buffers (bounds checks) */
+  int64_t n_hh;                    /* hole-hole ladder couplings (0: no such term) */
+  const int64_t* hh_rowptr;        /* [n_pairs + 1], CSR by target pair (may be NULL when n_hh = 0) */
+  const dlpno_hh_coupling* hh;     /* [n_hh] */
 } dlpno_problem;
 
 /* Device inputs (caller-owned, read-only, fixed for the life of the plan). */
@@ -253,7 +276,8 @@ dlpno_status dlpno_solve_mixed(dlpno_plan* plan, int32_t n_outer, int32_t n_inne
                                void* stream);
 
 /* Algorithmic FLOPs of one residual evaluation (ladder: 4 m n^3 per block;
- * projection: 2 n_p n_q (n_p + n_q) per applied term). */
+ * projection: 2 n_p n_q (n_p + n_q) per applied term, occupied-Fock and
+ * hole-hole ladder terms alike). */
 dlpno_status dlpno_flop_count(const dlpno_plan* plan, double* ladder, double* projection);
 
 /* Time every variant of the grouped kernel's tile schedule on the plan's

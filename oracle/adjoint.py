@@ -5,6 +5,8 @@ TEST INFRASTRUCTURE ONLY.
 For Gbar = dL/dR the residual's transpose map gives
   dT_p   = D o Gbar_p + sum_Q (B^Q)^T Gbar_p B^Q
            + scatter of -w S_pq^T Gbar_p S_pq to every source block read by p
+             (projection, w = f) and of +w S_pq^T Gbar_p S_pq (hole-hole
+             ladder, w = (k i | l j))
   dB^Q_p = sum_blocks ( Gbar B^Q T^T + Gbar^T B^Q T )
 (the last is the gradient for a general, unsymmetrised B, since the ladder is
 R = sum_Q B^Q T B^Q^T).  The oracle scatters; no symmetry of the operator is
@@ -12,7 +14,7 @@ assumed.
 """
 import numpy as np
 
-from .model import denominators, projection_terms
+from .model import denominators, projection_terms, hole_terms
 
 
 def vjp(inp, T, G):
@@ -36,6 +38,9 @@ def vjp(inp, T, G):
             dBp += np.einsum("ba,qbd,dc->qac", g, Bp, Tb, optimize=True)       # g^T B T
             for w, q, Spq, src in projection_terms(inp, T, p, name):
                 contrib = -w * (Spq.T @ g @ Spq)
+                dT[(src[0], src[1])] += contrib.T if src[2] else contrib
+            for w, q, Spq, src in hole_terms(inp, T, p, name):
+                contrib = w * (Spq.T @ g @ Spq)
                 dT[(src[0], src[1])] += contrib.T if src[2] else contrib
         dB[p] = dBp
     return dT, dB

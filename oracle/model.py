@@ -39,6 +39,21 @@ def name_of(s1, s2):
     raise KeyError((s1, s2))
 
 
+class OccInts:
+    """Occupied four-index integrals (k i | l j) (chemists' notation) from a dense
+    array g[k, i, l, j]; neighbors(i) lists the k for which (k i | . .) may be
+    non-zero (here every orbital)."""
+
+    def __init__(self, g):
+        self.g = np.asarray(g, dtype=np.float64)
+
+    def value(self, k, i, l, j):
+        return float(self.g[k, i, l, j])
+
+    def neighbors(self, i):
+        return range(self.g.shape[0])
+
+
 class Inputs:
     """Everything the residual reads, held per pair in plain numpy arrays.
 
@@ -48,10 +63,13 @@ class Inputs:
     eps_a[p], eps_b[p]   (n_p,) virtual PNO energies per spin
     f_a, f_b   (n_occ, n_occ) occupied Fock matrices per spin
     S(p, q)    overlap S_{p,q} (n_p x n_q) between the PNOs of two pairs
+    occ_ints   optional occupied integrals (k i | l j) of the hole-hole ladder:
+               an object with value(k, i, l, j) and neighbors(i) (the k that
+               can give a non-zero (k i | . .)); None: no hole-hole term
     B and S may be callables (lazy regeneration for large workloads).
     """
 
-    def __init__(self, n_occ, is_somo, pairs, B, K, eps_a, eps_b, f_a, f_b, S):
+    def __init__(self, n_occ, is_somo, pairs, B, K, eps_a, eps_b, f_a, f_b, S, occ_ints=None):
         self.n_occ = int(n_occ)
         self.is_somo = np.asarray(is_somo).astype(bool)
         self.pairs = [(int(i), int(j)) for i, j in pairs]
@@ -59,6 +77,7 @@ class Inputs:
         self._B, self.K, self.eps_a, self.eps_b = B, K, eps_a, eps_b
         self.f_a, self.f_b = np.asarray(f_a, dtype=np.float64), np.asarray(f_b, dtype=np.float64)
         self._S = S
+        self.occ_ints = occ_ints
 
     def B(self, p):
         return self._B(p) if callable(self._B) else self._B[p]
@@ -110,17 +129,20 @@ class Inputs:
             def Bf(p):
                 o = prob.off_B[p]
                 return B[o:o + m[p] * n[p] ** 2].reshape(m[p], n[p], n[p])
-        # coupling lookup (target, source) -> first CSR entry
+        # overlap lookup (target, source) -> offset of its block (Fock and
+        # hole-hole couplings share the blocks)
         where = {}
         for p in range(P):
             for e in range(prob.cpl_rowptr[p], prob.cpl_rowptr[p + 1]):
-                where.setdefault((p, int(prob.cpl_src[e])), e)
+                where.setdefault((p, int(prob.cpl_src[e])), int(prob.cpl_off_S[e]))
+            if prob.n_hh > 0:
+                for e in range(prob.hh_rowptr[p], prob.hh_rowptr[p + 1]):
+                    where.setdefault((p, int(prob.hh_src[e])), int(prob.hh_off_S[e]))
         S_full = S if S is not None else (prob.S_host if prob.S_host is not None else None)
         s_cache = {}
 
         def Sf(p, q):
-            e = where[(p, q)]
-            o = int(prob.cpl_off_S[e])
+            o = where[(p, q)]
             if S_full is not None:
                 W = S_full[o:o + n[q] * n[p]].reshape(n[q], n[p])
             else:
@@ -130,7 +152,24 @@ class Inputs:
                     s_cache[o] = prob.segment("S", u)[0]
                 W = s_cache[o]
             return W.T          # stored [c][a] = <c_q|a_p>  ->  S_{p,q}[a][c]
-        return cls(prob.n_occ, prob.is_somo, pairs, Bf, Kd, ea, eb, prob.f_a, prob.f_b, Sf)
+        occ = None
+        if prob.hole_scale != 0.0:
+            occ = _WorkloadOccInts(prob)
+        return cls(prob.n_occ, prob.is_somo, pairs, Bf, Kd, ea, eb, prob.f_a, prob.f_b, Sf, occ)
+
+
+class _WorkloadOccInts:
+    """The workload's synthetic occupied integrals, zero beyond |k - i| > range."""
+
+    def __init__(self, prob):
+        self.prob = prob
+
+    def value(self, k, i, l, j):
+        return self.prob.eri_occ(k, i, l, j)
+
+    def neighbors(self, i):
+        d = self.prob.hole_range
+        return range(max(0, i - d), min(self.prob.n_occ, i + d + 1))
 
 
 def unpack_T(prob, flat):
@@ -236,8 +275,42 @@ def projection_terms(inp, T, p, name):
     return out
 
 
-def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladder")):
-    """Open-shell residual blocks {(p, name): R} for the given target pairs."""
+def hole_terms(inp, T, p, name):
+    """The hole-hole ladder terms of block `name` of pair p = (i, j): list of
+    (weight, q, S_pq, source tuple from t_lookup).
+
+    In spin orbitals the term is 1/2 sum_KL <KL||IJ> t_KL^AB.  With I, J of
+    spins s, s' it keeps K = k_s, L = l_s' from <KL|IJ> = (k i | l j) and
+    K = k_s', L = l_s from <KL|JI>; relabelling the second and using
+    t_KL = -t_LK turns it into the first, so the term is
+      sum_{k in occ_s, l in occ_s'} (k i | l j) S_{p,kl} T^{ss'}_{(k,l)} S_{kl,p}
+    over ordered (k, l), with the amplitude lookup of t_lookup (zero for pairs
+    that are not retained).  Its spin-orbital form is checked by brute force."""
+    if inp.occ_ints is None:
+        return []
+    i, j = inp.pairs[p]
+    s1, s2 = SPIN[name]
+    occ1, occ2 = set(inp.occ(s1)), set(inp.occ(s2))
+    out = []
+    for k in inp.occ_ints.neighbors(i):
+        if k not in occ1:
+            continue
+        for l in inp.occ_ints.neighbors(j):
+            if l not in occ2:
+                continue
+            w = inp.occ_ints.value(k, i, l, j)
+            if w == 0.0:
+                continue
+            src = t_lookup(inp, T, k, l, s1, s2)
+            if src is None:
+                continue
+            out.append((w, src[0], inp.S(p, src[0]), src))
+    return out
+
+
+def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladder", "hole")):
+    """Open-shell residual blocks {(p, name): R} for the given target pairs.
+    The hole-hole term is present only when inp.occ_ints is given."""
     R = {}
     for p in (range(len(inp.pairs)) if pairs is None else pairs):
         Bp = inp.B(p) if "ladder" in terms else None
@@ -253,6 +326,9 @@ def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladd
                     r -= w * (Spq @ src[3] @ Spq.T)
             if "ladder" in terms:
                 r += ladder(Bp, Tb)
+            if "hole" in terms:
+                for w, q, Spq, src in hole_terms(inp, T, p, name):
+                    r += w * (Spq @ src[3] @ Spq.T)
             R[(p, name)] = r
     return R
 
@@ -276,11 +352,12 @@ def pair_energies(inp, T):
 # closed-shell reference (separate code path: spatial amplitudes only)
 # ---------------------------------------------------------------------------
 
-def residual_cs(pairs, B, K, eps, f, S, Tcs):
+def residual_cs(pairs, B, K, eps, f, S, Tcs, occ_ints=None):
     """Closed-shell residual of the same model on spatial amplitudes T_p (i <= j).
 
     R_p = K_p + (eps + eps - f_ii - f_jj) o T_p - sum_{k != i} f_ki S T_kj S^T
-          - sum_{k != j} f_kj S T_ik S^T + sum_Q B^Q T_p B^Q^T,
+          - sum_{k != j} f_kj S T_ik S^T + sum_Q B^Q T_p B^Q^T
+          + sum_{k,l} (k i | l j) S T_kl S^T       (with occ_ints),
     with T_(k,l) = T_(l,k)^T for k > l."""
     index = {pq: p for p, pq in enumerate(pairs)}
 
@@ -310,6 +387,14 @@ def residual_cs(pairs, B, K, eps, f, S, Tcs):
         Bp = B(p)
         for Q in range(Bp.shape[0]):
             r = r + Bp[Q] @ Tp @ Bp[Q].T
+        if occ_ints is not None:
+            for k in occ_ints.neighbors(i):
+                for l in occ_ints.neighbors(j):
+                    w = occ_ints.value(k, i, l, j)
+                    a = amp(k, l) if w != 0.0 else None
+                    if a is not None:
+                        Spq = S(p, a[0])
+                        r = r + w * (Spq @ a[1] @ Spq.T)
         R.append(r)
     return R
 

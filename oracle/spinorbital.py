@@ -9,9 +9,12 @@ terms of the model are formed from explicit antisymmetrised integrals:
 
   R_IJ^AB = <AB||IJ> + (e_A + e_B) t_IJ^AB - sum_K f_KI t_KJ^AB
             - sum_K f_KJ t_IK^AB + 1/2 sum_CD <AB||CD> t_IJ^CD
+            + 1/2 sum_KL <KL||IJ> t_KL^AB
   E       = 1/4 sum_IJAB <IJ||AB> t_IJ^AB
 
-with (ac|bd) = sum_Q B^Q_ac B^Q_bd and (ia|jb) given per ordered pair.
+with (ac|bd) = sum_Q B^Q_ac B^Q_bd, (ia|jb) given per ordered pair and the
+occupied integrals (ki|lj) given as a dense array (the last term is absent
+when they are not given).
 """
 import numpy as np
 
@@ -22,13 +25,14 @@ def _spin_orbitals(n_occ, is_somo, V):
     return occ, vir
 
 
-def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblocks, pairs):
+def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblocks, pairs, g_occ=None):
     """Pair blocks of the residual and the total energy of the given amplitudes.
 
     Bg       (m, V, V) three-index integrals shared by all pairs
     Kpair    {(i, j): V x V} (i a | j b) for i <= j
     Tblocks  {((i, j), name): V x V} stored amplitude blocks (same-spin antisymmetric)
     pairs    list of (i, j) covering every occupied pair (i <= j)
+    g_occ    optional (n_occ, n_occ, n_occ, n_occ) array g[k, i, l, j] = (k i | l j)
     Returns ({((i, j), name): V x V residual block}, energy of the amplitudes).
     """
     V = Bg.shape[1]
@@ -90,6 +94,20 @@ def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblo
          - np.einsum("ki,kjab->ijab", fo, t)
          - np.einsum("kj,ikab->ijab", fo, t)
          + 0.5 * np.einsum("abcd,ijcd->ijab", g_vvvv, t))
+    if g_occ is not None:
+        # <KL||IJ> = (KI|LJ) - (KJ|LI), spin orbitals of equal spin in each charge distribution
+        g_oooo = np.zeros((no, no, no, no))
+        for K, (k, sk) in enumerate(occ):
+            for L, (l, sl) in enumerate(occ):
+                for I, (i, si) in enumerate(occ):
+                    for J, (j, sj) in enumerate(occ):
+                        v = 0.0
+                        if sk == si and sl == sj:
+                            v += g_occ[k, i, l, j]
+                        if sk == sj and sl == si:
+                            v -= g_occ[k, j, l, i]
+                        g_oooo[K, L, I, J] = v
+        R = R + 0.5 * np.einsum("klij,klab->ijab", g_oooo, t)
     E = 0.25 * float(np.sum(g_vvoo.transpose(2, 3, 0, 1) * t))
     out = {}
     for (i, j) in pairs:

@@ -189,13 +189,25 @@ static dlpno_status check_vjp_preconditions(dlpno_plan* P, hipStream_t s) {
       for (int b = 0; b < 4; ++b) active = active || P->terms_h[(size_t)e * 4 + b].src_off >= 0;
       if (!active) continue;
       const int q = P->cpl_h[e].src, k = P->cpl_k_h[e];
-      const int rep = P->cpl_side_h[e] == 0 ? tp.i : tp.j;
       const PairDev& sq = P->pairs_h[q];
-      // reverse: target q reads p with rep replacing k (on the side where q holds k)
       int64_t rev = -1;
-      for (int64_t f = P->rowptr_h[q]; f < P->rowptr_h[q + 1] && rev < 0; ++f) {
-        if (P->cpl_h[f].src != p || P->cpl_k_h[f] != rep) continue;
-        if ((P->cpl_side_h[f] == 0 ? sq.i : sq.j) == k) rev = f;
+      if (P->cpl_side_h[e] == 2) {
+        // hole-hole (p <- ordered (k, l)): target q reads p as the ordered pair
+        // that puts i against k and j against l
+        const int l = P->cpl_l_h[e];
+        for (int64_t f = P->rowptr_h[q]; f < P->rowptr_h[q + 1] && rev < 0; ++f) {
+          if (P->cpl_side_h[f] != 2 || P->cpl_h[f].src != p) continue;
+          const int x = P->cpl_k_h[f], y = P->cpl_l_h[f];
+          if ((sq.i == k && sq.j == l && x == tp.i && y == tp.j) || (sq.i == l && sq.j == k && x == tp.j && y == tp.i))
+            rev = f;
+        }
+      } else {
+        // reverse: target q reads p with rep replacing k (on the side where q holds k)
+        const int rep = P->cpl_side_h[e] == 0 ? tp.i : tp.j;
+        for (int64_t f = P->rowptr_h[q]; f < P->rowptr_h[q + 1] && rev < 0; ++f) {
+          if (P->cpl_side_h[f] == 2 || P->cpl_h[f].src != p || P->cpl_k_h[f] != rep) continue;
+          if ((P->cpl_side_h[f] == 0 ? sq.i : sq.j) == k) rev = f;
+        }
       }
       if (rev < 0) {
         P->vjp_reason = "vector-Jacobian product: coupling " + std::to_string(e) + " (pair " + std::to_string(p) +

@@ -403,10 +403,10 @@ std::string dlpno::describe(const dlpno_plan* P) {
   char buf[1024];
   std::string s;
   snprintf(buf, sizeof buf,
-           "pairs=%d blocks=%d couplings=%lld terms=%lld precision=%d workers=%d items=%zu (ladder %d, ladder at two "
+           "pairs=%d blocks=%d couplings=%lld (hole-hole %lld) terms=%lld precision=%d workers=%d items=%zu (ladder %d, ladder at two "
            "waves per SIMD %d, cooperative ladder %d, projection %d, projection at two waves per SIMD %d) "
            "max_item/total=%.2e workspace=%.3f GB\n",
-           P->n_pairs, P->n_blocks, (long long)P->n_cpl, (long long)P->n_terms, (int)P->opt.precision, P->workers,
+           P->n_pairs, P->n_blocks, (long long)P->n_cpl, (long long)P->n_hh, (long long)P->n_terms, (int)P->opt.precision, P->workers,
            P->sched.items_h.size(), P->sched.kind_count[ITEM_LADDER], P->sched.kind_count[ITEM_LADDER2],
            P->sched.kind_count[ITEM_LADDER4], P->sched.kind_count[ITEM_PROJ], P->sched.kind_count[ITEM_PROJ2],
            P->total_mfma > 0 ? P->max_item_mfma / P->total_mfma : 0.0, P->ws_elems * 8.0 / 1e9);
@@ -439,7 +439,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if (n_occ < 1 || npairs < 0 || prob->n_couplings < 0)
     return fail(DLPNO_ERR_DIM_RANGE, "n_occ must be >= 1, n_pairs and n_couplings >= 0");
   if (!prob->is_somo || !prob->f_a || !prob->f_b || !prob->cpl_rowptr || (npairs > 0 && !prob->pairs) ||
-      (prob->n_couplings > 0 && !prob->cpl))
+      (prob->n_couplings > 0 && !prob->cpl) || (prob->n_hh > 0 && (!prob->hh_rowptr || !prob->hh)))
     return fail(DLPNO_ERR_INVALID_ARG, "a required host array is NULL");
   dlpno_options opt{};
   opt.precision = DLPNO_FP64;
@@ -455,7 +455,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   for (int k = 0; k < n_occ; ++k)
     if (prob->is_somo[k] > 1) return fail(DLPNO_ERR_INVALID_ARG, "is_somo entries must be 0 or 1");
   const bool need_inputs = npairs > 0;
-  if (need_inputs && (!in->B || !in->K || !in->eps_a || !in->eps_b || (prob->n_couplings > 0 && !in->S)))
+  if (need_inputs && (!in->B || !in->K || !in->eps_a || !in->eps_b || (prob->n_couplings + prob->n_hh > 0 && !in->S)))
     return fail(DLPNO_ERR_INVALID_ARG, "a device input pointer is NULL");
 
   hipStream_t s = (hipStream_t)stream;
@@ -463,7 +463,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   P->opt = opt;
   P->n_occ = n_occ;
   P->n_pairs = npairs;
-  P->n_cpl = prob->n_couplings;
+
   P->in = *in;
   P->n_B = prob->n_B;
   P->n_T = prob->n_T;
@@ -556,25 +556,74 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
       }
   }
   // ---- couplings and terms ----
-  P->rowptr_h.assign(prob->cpl_rowptr, prob->cpl_rowptr + npairs + 1);
-  if (P->rowptr_h[0] != 0 || P->rowptr_h[npairs] != prob->n_couplings)
+  // One merged list per target pair: its occupied-Fock couplings, then its
+  // hole-hole ladder couplings.  Both apply -w S_{p,q} X S_{p,q}^T to every
+  // target block for which the ordered source (x, y) has a block; the
+  // kernels do not distinguish them.
+  const int64_t n_fock = prob->n_couplings, n_hh = prob->n_hh;
+  if (n_hh < 0) return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, "n_hh must be >= 0"));
+  if (n_hh > 0 && (!prob->hh_rowptr || !prob->hh))
+    return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "hh_rowptr or hh is NULL with n_hh > 0"));
+  std::vector<int64_t> frow(prob->cpl_rowptr, prob->cpl_rowptr + npairs + 1);
+  std::vector<int64_t> hrow(npairs + 1, 0);
+  if (n_hh > 0) hrow.assign(prob->hh_rowptr, prob->hh_rowptr + npairs + 1);
+  if (frow[0] != 0 || frow[npairs] != n_fock)
     return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "cpl_rowptr must start at 0 and end at n_couplings"));
-  for (int p = 0; p < npairs; ++p)
-    if (P->rowptr_h[p + 1] < P->rowptr_h[p])
-      return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "cpl_rowptr must be non-decreasing"));
-  if (prob->n_couplings > INT32_MAX) return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, "too many couplings"));
-  P->cpl_h.resize(prob->n_couplings);
-  P->cpl_k_h.resize(prob->n_couplings);
-  P->cpl_side_h.resize(prob->n_couplings);
-  P->terms_h.assign((size_t)prob->n_couplings * 4, TermDev{-1, 0.0, 0, -1});
+  if (hrow[0] != 0 || hrow[npairs] != n_hh)
+    return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "hh_rowptr must start at 0 and end at n_hh"));
+  for (int p = 0; p < npairs; ++p) {
+    if (frow[p + 1] < frow[p]) return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "cpl_rowptr must be non-decreasing"));
+    if (hrow[p + 1] < hrow[p]) return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "hh_rowptr must be non-decreasing"));
+  }
+  if (n_fock + n_hh > INT32_MAX) return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, "too many couplings"));
+  const int64_t n_all = n_fock + n_hh;
+  P->n_cpl = n_all;
+  P->n_hh = n_hh;
+  P->rowptr_h.assign(npairs + 1, 0);
+  for (int p = 0; p <= npairs; ++p) P->rowptr_h[p] = frow[p] + hrow[p];
+  P->cpl_h.resize(n_all);
+  P->cpl_k_h.resize(n_all);
+  P->cpl_side_h.resize(n_all);
+  P->cpl_l_h.resize(n_all);
+  P->terms_h.assign((size_t)n_all * 4, TermDev{-1, 0.0, 0, -1});
   P->flops_proj = 0.0;
   P->n_terms = 0;
   for (int p = 0; p < npairs; ++p) {
     const dlpno_pair& d = prob->pairs[p];
     const PairDev& pd = P->pairs_h[p];
-    for (int64_t e = P->rowptr_h[p]; e < P->rowptr_h[p + 1]; ++e) {
-      const dlpno_coupling& c = prob->cpl[e];
-      const std::string where = "coupling " + std::to_string(e) + " of pair " + std::to_string(p);
+    int64_t out = P->rowptr_h[p];
+    // the term of merged coupling `e` (source pair q, ordered source (x, y)
+    // with electron spins (s1, s2)) on target block slot `slot`, weight w
+    auto add_term = [&](int64_t e, int slot, const dlpno_pair& q, int src_pair, int x, int y, int s1, int s2,
+                        double w) {
+      int scode, trans;
+      if (x == y) {
+        if (s1 == s2) return;                               // Pauli
+        scode = 2;
+        trans = s1 == 1;
+      } else if (x < y) {
+        scode = block_code(s1, s2);
+        trans = 0;
+      } else {
+        scode = block_code(s2, s1);
+        trans = 1;
+      }
+      if (!(q.blocks & kCodeBit[scode]) || w == 0.0) return;
+      int sslot = 0;
+      for (int cc = 0; cc < scode; ++cc)
+        if (q.blocks & kCodeBit[cc]) ++sslot;
+      const int64_t nq = q.npno;
+      TermDev& tm = P->terms_h[(size_t)e * 4 + slot];
+      tm.src_off = q.off_T + (int64_t)sslot * nq * nq;
+      tm.w = w;
+      tm.trans = trans;
+      tm.src_blk = P->pairs_h[src_pair].blk0 + sslot;
+      P->flops_proj += 2.0 * pd.n * (double)nq * (pd.n + nq);
+      ++P->n_terms;
+    };
+    for (int64_t fe = frow[p]; fe < frow[p + 1]; ++fe, ++out) {
+      const dlpno_coupling& c = prob->cpl[fe];
+      const std::string where = "coupling " + std::to_string(fe) + " of pair " + std::to_string(p);
       if (c.src_pair < 0 || c.src_pair >= npairs || c.k < 0 || c.k >= n_occ || (c.side != 0 && c.side != 1))
         return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, where + ": src_pair, k or side out of range"));
       const int rep = c.side == 0 ? d.i : d.j, keep = c.side == 0 ? d.j : d.i;
@@ -582,51 +631,56 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
       const dlpno_pair& q = prob->pairs[c.src_pair];
       if (q.i != std::min(c.k, keep) || q.j != std::max(c.k, keep))
         return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, where + ": source pair does not match (k, side)"));
-      const int64_t nq = q.npno;
-      if (c.off_S < 0 || c.off_S + nq * d.npno > prob->n_S)
+      if (c.off_S < 0 || c.off_S + (int64_t)q.npno * d.npno > prob->n_S)
         return destroy_fail(fail(DLPNO_ERR_ALIGNMENT, where + ": off_S exceeds the S buffer"));
-      CplDev& cd = P->cpl_h[e];
+      CplDev& cd = P->cpl_h[out];
       cd.src = c.src_pair;
       cd.nsrc = q.npno;
       cd.off_S = c.off_S;
-      P->cpl_k_h[e] = c.k;
-      P->cpl_side_h[e] = c.side;
-      // terms per target block
+      P->cpl_k_h[out] = c.k;
+      P->cpl_side_h[out] = c.side;
+      P->cpl_l_h[out] = -1;
+      // k replaces electron i (side 0) or j (side 1); weight f^s[k][replaced]
+      // of the replaced electron's spin s, which needs k occupied in s
       int slot = 0;
       for (int code = 0; code < 4; ++code) {
         if (!(d.blocks & kCodeBit[code])) continue;
         const int s1 = kCodeS1[code], s2 = kCodeS2[code];
-        const int sk = c.side == 0 ? s1 : s2;              // spin of the replaced electron
-        TermDev& tm = P->terms_h[(size_t)e * 4 + slot];
-        ++slot;
-        if (sk == 1 && prob->is_somo[c.k]) continue;       // k must be occupied in that spin
-        // ordered source pair (x, y) with spins (s1, s2)
-        const int x = c.side == 0 ? c.k : d.i, y = c.side == 0 ? d.j : c.k;
-        int scode, trans;
-        if (x == y) {
-          if (s1 == s2) continue;                           // Pauli
-          scode = 2;
-          trans = s1 == 1;
-        } else if (x < y) {
-          scode = block_code(s1, s2);
-          trans = 0;
-        } else {
-          scode = block_code(s2, s1);
-          trans = 1;
-        }
-        if (!(q.blocks & kCodeBit[scode])) continue;
-        int sslot = 0;
-        for (int cc = 0; cc < scode; ++cc)
-          if (q.blocks & kCodeBit[cc]) ++sslot;
+        const int sk = c.side == 0 ? s1 : s2;
+        const int this_slot = slot++;
+        if (sk == 1 && prob->is_somo[c.k]) continue;
         const double* f = sk == 0 ? prob->f_a : prob->f_b;
-        const double w = f[(size_t)c.k * n_occ + rep];
-        if (w == 0.0) continue;
-        tm.src_off = q.off_T + (int64_t)sslot * nq * nq;
-        tm.w = w;
-        tm.trans = trans;
-        tm.src_blk = P->pairs_h[c.src_pair].blk0 + sslot;
-        P->flops_proj += 2.0 * pd.n * (double)nq * (pd.n + nq);
-        ++P->n_terms;
+        const int x = c.side == 0 ? c.k : d.i, y = c.side == 0 ? d.j : c.k;
+        add_term(out, this_slot, q, c.src_pair, x, y, s1, s2, f[(size_t)c.k * n_occ + rep]);
+      }
+    }
+    for (int64_t he = hrow[p]; he < hrow[p + 1]; ++he, ++out) {
+      const dlpno_hh_coupling& c = prob->hh[he];
+      const std::string where = "hole-hole coupling " + std::to_string(he) + " of pair " + std::to_string(p);
+      if (c.src_pair < 0 || c.src_pair >= npairs || c.k < 0 || c.k >= n_occ || c.l < 0 || c.l >= n_occ)
+        return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, where + ": src_pair, k or l out of range"));
+      const dlpno_pair& q = prob->pairs[c.src_pair];
+      if (q.i != std::min(c.k, c.l) || q.j != std::max(c.k, c.l))
+        return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, where + ": source pair does not match (k, l)"));
+      if (!std::isfinite(c.w)) return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, where + ": weight is not finite"));
+      if (c.off_S < 0 || c.off_S + (int64_t)q.npno * d.npno > prob->n_S)
+        return destroy_fail(fail(DLPNO_ERR_ALIGNMENT, where + ": off_S exceeds the S buffer"));
+      CplDev& cd = P->cpl_h[out];
+      cd.src = c.src_pair;
+      cd.nsrc = q.npno;
+      cd.off_S = c.off_S;
+      P->cpl_k_h[out] = c.k;
+      P->cpl_side_h[out] = 2;
+      P->cpl_l_h[out] = c.l;
+      // ordered source (k, l) for spins (s1, s2): k in occ_s1, l in occ_s2;
+      // the residual gets +w S T S^T (the kernels apply -weight)
+      int slot = 0;
+      for (int code = 0; code < 4; ++code) {
+        if (!(d.blocks & kCodeBit[code])) continue;
+        const int s1 = kCodeS1[code], s2 = kCodeS2[code];
+        const int this_slot = slot++;
+        if ((s1 == 1 && prob->is_somo[c.k]) || (s2 == 1 && prob->is_somo[c.l])) continue;
+        add_term(out, this_slot, q, c.src_pair, c.k, c.l, s1, s2, -c.w);
       }
     }
   }
@@ -641,17 +695,19 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
     });
     std::vector<CplDev> c2;
     std::vector<TermDev> t2;
-    std::vector<int32_t> k2, s2;
+    std::vector<int32_t> k2, s2, l2;
     for (int64_t e : ord) {
       c2.push_back(P->cpl_h[e]);
       k2.push_back(P->cpl_k_h[e]);
       s2.push_back(P->cpl_side_h[e]);
+      l2.push_back(P->cpl_l_h[e]);
       for (int b = 0; b < 4; ++b) t2.push_back(P->terms_h[(size_t)e * 4 + b]);
     }
     for (int64_t k = 0; k < (int64_t)ord.size(); ++k) {
       P->cpl_h[e0 + k] = c2[k];
       P->cpl_k_h[e0 + k] = k2[k];
       P->cpl_side_h[e0 + k] = s2[k];
+      P->cpl_l_h[e0 + k] = l2[k];
       for (int b = 0; b < 4; ++b) P->terms_h[(size_t)(e0 + k) * 4 + b] = t2[(size_t)k * 4 + b];
     }
   }
@@ -714,7 +770,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   }
   if (is_split(opt.precision)) {
     const bool f16 = opt.precision == DLPNO_FP16X2;
-    std::vector<int64_t> boff(npairs), toff(nblk_total), soff(prob->n_couplings), ctgt(prob->n_couplings);
+    std::vector<int64_t> boff(npairs), toff(nblk_total), soff(P->n_cpl), ctgt(P->n_cpl);
     int64_t nb = 0, nt = 0, ns = 0;
     for (int p = 0; p < npairs; ++p) {
       const PairDev& pd = P->pairs_h[p];
@@ -752,7 +808,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
       if ((st = dev_alloc(&P->d_blk_tscale, std::max(nblk_total, 1), "T scales")) != DLPNO_OK) return destroy_fail(st);
     }
     HIPCK(launch_split_B(P->d_pairs, npairs, in->B, P->d_pair_boff, P->d_pair_bscale, P->Bs_hi, P->Bs_lo, f16, s));
-    HIPCK(launch_split_S(P->d_pairs, P->d_cpl_target, P->d_cpl, in->S, P->d_cpl_soff, prob->n_couplings, P->Ss_hi,
+    HIPCK(launch_split_S(P->d_pairs, P->d_cpl_target, P->d_cpl, in->S, P->d_cpl_soff, P->n_cpl, P->Ss_hi,
                          P->Ss_lo, f16, s));
   }
   HIPCK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));

@@ -46,7 +46,7 @@ struct dlpno_plan {
   dlpno_options opt{};
   int device = 0, num_cu = 0, workers = 0;
   int32_t n_occ = 0, n_pairs = 0, n_blocks = 0;
-  int64_t n_cpl = 0, n_terms = 0;
+  int64_t n_cpl = 0, n_terms = 0, n_hh = 0;   // couplings (Fock + hole-hole), of them hole-hole
   int64_t n_B = 0, n_T = 0, n_K = 0, n_eps = 0, n_S = 0;
   dlpno_inputs in{};
   std::vector<uint8_t> somo;
@@ -55,7 +55,9 @@ struct dlpno_plan {
   std::vector<dlpno::CplDev> cpl_h;
   std::vector<dlpno::TermDev> terms_h;
   std::vector<int64_t> rowptr_h;
-  std::vector<int32_t> cpl_k_h, cpl_side_h;   // k and side of each coupling (order of cpl_h)
+  // k and side of each coupling (order of cpl_h); side 2 marks a hole-hole
+  // coupling, whose ordered source is (k, l)
+  std::vector<int32_t> cpl_k_h, cpl_side_h, cpl_l_h;
   // preconditions of the vector-Jacobian product (the transposed residual is
   // evaluated by the forward kernels): symmetric occupied Fock matrices
   // (checked at creation), a reverse for every coupling with a term and

@@ -32,7 +32,8 @@ class Problem(C.Structure):
     _fields_ = [("n_occ", C.c_int32), ("n_pairs", C.c_int32), ("n_couplings", C.c_int64),
                 ("is_somo", C.c_void_p), ("pairs", C.c_void_p), ("cpl_rowptr", C.c_void_p), ("cpl", C.c_void_p),
                 ("f_a", C.c_void_p), ("f_b", C.c_void_p), ("n_B", C.c_int64), ("n_T", C.c_int64),
-                ("n_K", C.c_int64), ("n_eps", C.c_int64), ("n_S", C.c_int64)]
+                ("n_K", C.c_int64), ("n_eps", C.c_int64), ("n_S", C.c_int64),
+                ("n_hh", C.c_int64), ("hh_rowptr", C.c_void_p), ("hh", C.c_void_p)]
 
 
 class Inputs(C.Structure):
@@ -49,6 +50,8 @@ PAIR_DTYPE = np.dtype([("i", "<i4"), ("j", "<i4"), ("npno", "<i4"), ("naux", "<i
                        ("reserved", "<i4"), ("off_B", "<i8"), ("off_T", "<i8"), ("off_K", "<i8"),
                        ("off_eps", "<i8")])
 CPL_DTYPE = np.dtype([("src_pair", "<i4"), ("k", "<i4"), ("side", "<i4"), ("reserved", "<i4"), ("off_S", "<i8")])
+HH_DTYPE = np.dtype([("src_pair", "<i4"), ("k", "<i4"), ("l", "<i4"), ("reserved", "<i4"), ("off_S", "<i8"),
+                     ("w", "<f8")])
 
 _LIB = None
 
@@ -138,14 +141,24 @@ class Plan:
         cpl = np.zeros(max(ncpl, 1), dtype=CPL_DTYPE)
         cpl["src_pair"][:ncpl], cpl["k"][:ncpl], cpl["side"][:ncpl] = desc.cpl_src, desc.cpl_k, desc.cpl_side
         cpl["off_S"][:ncpl] = desc.cpl_off_S
+        # hole-hole ladder couplings (optional descriptor fields)
+        nhh = int(getattr(desc, "n_hh", 0) or 0)
+        hh = np.zeros(max(nhh, 1), dtype=HH_DTYPE)
+        hh_rowptr = np.zeros(P + 1, dtype=np.int64)
+        if nhh > 0:
+            hh["src_pair"][:nhh], hh["k"][:nhh], hh["l"][:nhh] = desc.hh_src, desc.hh_k, desc.hh_l
+            hh["off_S"][:nhh], hh["w"][:nhh] = desc.hh_off_S, desc.hh_w
+            hh_rowptr = np.ascontiguousarray(desc.hh_rowptr, dtype=np.int64)
         self._host = dict(
             somo=np.ascontiguousarray(desc.is_somo, dtype=np.uint8), pairs=pairs, cpl=cpl,
             rowptr=np.ascontiguousarray(desc.cpl_rowptr, dtype=np.int64),
-            f_a=np.ascontiguousarray(desc.f_a, dtype=np.float64), f_b=np.ascontiguousarray(desc.f_b, dtype=np.float64))
+            f_a=np.ascontiguousarray(desc.f_a, dtype=np.float64), f_b=np.ascontiguousarray(desc.f_b, dtype=np.float64),
+            hh=hh, hh_rowptr=hh_rowptr)
         h = self._host
         prob = Problem(int(desc.n_occ), P, ncpl, h["somo"].ctypes.data, h["pairs"].ctypes.data, h["rowptr"].ctypes.data,
                        h["cpl"].ctypes.data, h["f_a"].ctypes.data, h["f_b"].ctypes.data, int(desc.n_B), int(desc.n_T),
-                       int(desc.n_K), int(len(desc.eps_a)), int(desc.n_S))
+                       int(desc.n_K), int(len(desc.eps_a)), int(desc.n_S), nhh, h["hh_rowptr"].ctypes.data,
+                       h["hh"].ctypes.data)
         self._dev = [B, S, K, eps_a, eps_b]
         for t in self._dev:
             if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()):

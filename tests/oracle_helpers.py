@@ -24,10 +24,22 @@ def random_T(rng, inp, scale=1e-2, sym_diag=False):
     return T
 
 
+def occ_integrals(rng, n, scale):
+    """Random real occupied integrals g[k, i, l, j] = (k i | l j) with the
+    eightfold permutational symmetry of real two-electron integrals."""
+    g = rng.standard_normal((n, n, n, n))
+    g = g + g.transpose(1, 0, 2, 3)
+    g = g + g.transpose(0, 1, 3, 2)
+    g = g + g.transpose(2, 3, 0, 1)
+    return scale * g / 8.0
+
+
 def make_inputs(rng, n_occ, somos, npno, naux, band=None, dim=None, shared_space=False,
-                b_scale=0.1, k_scale=0.05, f_off=0.05, canonical=False):
+                b_scale=0.1, k_scale=0.05, f_off=0.05, canonical=False, hole=0.0):
     """Random model instance.  shared_space: all pairs use one untruncated
-    virtual space (identity overlaps, one B, one eps): the canonical limit."""
+    virtual space (identity overlaps, one B, one eps): the canonical limit.
+    hole: scale of random occupied integrals (k i | l j) of the hole-hole
+    ladder (0: no such term); they are kept in inp.g_occ as a dense array."""
     is_somo = np.zeros(n_occ, dtype=bool)
     is_somo[list(somos)] = True
     band = n_occ if band is None else band
@@ -74,7 +86,10 @@ def make_inputs(rng, n_occ, somos, npno, naux, band=None, dim=None, shared_space
     for p, (i, j) in enumerate(pairs):
         k = k_scale * rng.standard_normal((ns[p], ns[p]))
         K[p] = (k + k.T) / 2.0 if i == j else k
-    inp = oracle.Inputs(n_occ, is_somo, pairs, B, K, eps_a, eps_b, f, fb, S)
+    g = occ_integrals(rng, n_occ, hole) if hole else None
+    inp = oracle.Inputs(n_occ, is_somo, pairs, B, K, eps_a, eps_b, f, fb, S,
+                        oracle.OccInts(g) if g is not None else None)
+    inp.g_occ = g
     return inp
 
 

@@ -43,7 +43,7 @@ def _problem(**kw):
     keep = [pairs, cpl, somo, rowptr, prob.f_a, prob.f_b]
     P = Problem(prob.n_occ, prob.n_pairs, prob.n_couplings, somo.ctypes.data, pairs.ctypes.data, rowptr.ctypes.data,
                 cpl.ctypes.data, prob.f_a.ctypes.data, prob.f_b.ctypes.data, prob.n_B, prob.n_T, prob.n_K,
-                len(prob.eps_a), prob.n_S)
+                len(prob.eps_a), prob.n_S, 0, None, None)
     # fake (never dereferenced) device pointers: validation fails before any device access
     I = Inputs(16, 16, 16, 16, 16)
     return P, I, keep

@@ -56,7 +56,7 @@ def test_closed_shell_reduction_exact():
     # Abstract and Sec. II.B.2: with no SOMOs the open-shell formalism must reproduce
     # the closed-shell one (one PNO set for all spins).
     rng = np.random.default_rng(11)
-    inp = make_inputs(rng, n_occ=6, somos=(), npno=5, naux=7)
+    inp = make_inputs(rng, n_occ=6, somos=(), npno=5, naux=7, hole=0.05)
     Tcs = []
     for p, (i, j) in enumerate(inp.pairs):
         g = 1e-2 * rng.standard_normal((5, 5))
@@ -66,7 +66,7 @@ def test_closed_shell_reduction_exact():
         for name in inp.blocks(p):
             T[(p, name)] = Tcs[p] - Tcs[p].T if name in ("AA", "BB") else Tcs[p].copy()
     R = oracle.residual_os(inp, T)
-    Rcs = residual_cs(inp.pairs, inp.B, inp.K, inp.eps_a, inp.f_a, inp.S, Tcs)
+    Rcs = residual_cs(inp.pairs, inp.B, inp.K, inp.eps_a, inp.f_a, inp.S, Tcs, occ_ints=inp.occ_ints)
     for p, (i, j) in enumerate(inp.pairs):
         for name in inp.blocks(p):
             want = Rcs[p] - Rcs[p].T if name in ("AA", "BB") else Rcs[p]
@@ -91,17 +91,19 @@ def test_closed_shell_energy_identity_worked():
 
 
 # ------------------------------------ P2 canonical limit vs brute force
-@pytest.mark.parametrize("somos", [(1,), (1, 3)])
-def test_canonical_limit_matches_spin_orbital_bruteforce(somos):
-    # Sec. IV.A: with no truncation the method equals its canonical counterpart
-    rng = np.random.default_rng(5 + len(somos))
-    inp = make_inputs(rng, n_occ=5, somos=somos, npno=5, naux=6, shared_space=True)
+@pytest.mark.parametrize("somos,hole", [((1,), 0.0), ((1, 3), 0.0), ((1,), 0.05), ((1, 3), 0.05), ((), 0.05)])
+def test_canonical_limit_matches_spin_orbital_bruteforce(somos, hole):
+    # Sec. IV.A: with no truncation the method equals its canonical counterpart;
+    # hole > 0 adds the hole-hole ladder 1/2 sum_KL <KL||IJ> t_KL from explicit
+    # antisymmetrised occupied integrals
+    rng = np.random.default_rng(5 + len(somos) + int(100 * hole))
+    inp = make_inputs(rng, n_occ=5, somos=somos, npno=5, naux=6, shared_space=True, hole=hole)
     T = random_T(rng, inp, scale=0.05)
     R = oracle.residual_os(inp, T)
     Tb = {(inp.pairs[p], name): v for (p, name), v in T.items()}
     Kp = {inp.pairs[p]: inp.K[p] for p in range(len(inp.pairs))}
     Rbf, Ebf = oracle.residual_spinorbital(inp.n_occ, inp.is_somo, inp.B(0), Kp, inp.eps_a[0],
-                                           inp.eps_b[0], inp.f_a, inp.f_b, Tb, inp.pairs)
+                                           inp.eps_b[0], inp.f_a, inp.f_b, Tb, inp.pairs, g_occ=inp.g_occ)
     n_checked = 0
     for (p, name), r in R.items():
         np.testing.assert_allclose(r, Rbf[(inp.pairs[p], name)], rtol=0, atol=1e-13)
@@ -133,14 +135,17 @@ def _reversed_inputs(inp):
     fb = inp.f_b[np.ix_(perm, perm)]
     inv = {v: k for k, v in newp.items()}
     S = lambda p, q: inp.S(inv[p], inv[q])
-    new = oracle.Inputs(n, inp.is_somo[::-1].copy(), pairs, B, K, ea, eb, fa, fb, S)
+    occ = None
+    if inp.occ_ints is not None:
+        occ = oracle.OccInts(inp.g_occ[::-1, ::-1, ::-1, ::-1].copy())
+    new = oracle.Inputs(n, inp.is_somo[::-1].copy(), pairs, B, K, ea, eb, fa, fb, S, occ)
     return new, newp
 
 
 def test_orbital_relabelling_transposes_blocks():
     # R_(j,i)^{s's} = (R_(i,j)^{ss'})^T: reversing the chain swaps the electrons of every pair
     rng = np.random.default_rng(21)
-    inp = make_inputs(rng, n_occ=7, somos=(2, 5), npno=4, naux=5, band=3)
+    inp = make_inputs(rng, n_occ=7, somos=(2, 5), npno=4, naux=5, band=3, hole=0.05)
     T = random_T(rng, inp)
     new, newp = _reversed_inputs(inp)
     swap = {"AA": "AA", "BB": "BB", "AB": "BA", "BA": "AB"}
@@ -164,7 +169,7 @@ def test_pno_permutation_covariance():
     # Sec. II.B.2: pair energies and pair functions are invariant to unitary rotations
     # within the virtual space; a relabelling of one pair's PNOs permutes its residual
     rng = np.random.default_rng(8)
-    inp = make_inputs(rng, n_occ=5, somos=(3,), npno=5, naux=6)
+    inp = make_inputs(rng, n_occ=5, somos=(3,), npno=5, naux=6, hole=0.05)
     T = random_T(rng, inp)
     R = oracle.residual_os(inp, T)
     p0 = 4
@@ -181,7 +186,7 @@ def test_pno_permutation_covariance():
         if q == p0:
             s = s[:, pi]
         return s
-    new = oracle.Inputs(inp.n_occ, inp.is_somo, inp.pairs, B, K, ea, eb, inp.f_a, inp.f_b, S)
+    new = oracle.Inputs(inp.n_occ, inp.is_somo, inp.pairs, B, K, ea, eb, inp.f_a, inp.f_b, S, inp.occ_ints)
     Tp = {k: (v[np.ix_(pi, pi)] if k[0] == p0 else v) for k, v in T.items()}
     Rp = oracle.residual_os(new, Tp)
     for k, v in R.items():
@@ -221,7 +226,7 @@ def test_ladder_special_cases():
 # ----------------------------------------------------- P7 dense linear solve
 def test_jacobi_diis_converges_to_dense_solution():
     rng = np.random.default_rng(7)
-    inp = make_inputs(rng, n_occ=4, somos=(3,), npno=4, naux=6, b_scale=0.15)
+    inp = make_inputs(rng, n_occ=4, somos=(3,), npno=4, naux=6, b_scale=0.15, hole=0.05)
     Tstar, A = oracle.dense_solution(inp)
     zero = {k: np.zeros_like(v) for k, v in Tstar.items()}
     T, hist = oracle.solve(inp, zero, 60, use_diis=True, tol_r=1e-13, tol_e=1e-15)
@@ -240,7 +245,7 @@ def test_jacobi_diis_converges_to_dense_solution():
 # -------------------------------------------- P8 self-adjointness, Lambda = w T
 def test_operator_self_adjoint():
     rng = np.random.default_rng(9)
-    inp = make_inputs(rng, n_occ=6, somos=(2, 4), npno=5, naux=6, band=3)
+    inp = make_inputs(rng, n_occ=6, somos=(2, 4), npno=5, naux=6, band=3, hole=0.05)
     keys = keys_of(inp)
     G = {k: rng.standard_normal((5, 5)) for k in keys}
     T = {k: rng.standard_normal((5, 5)) for k in keys}
@@ -253,7 +258,7 @@ def test_lambda_equals_weighted_amplitudes():
     # the paper approximates Lambda by T^dagger (Sec. II.A); for this model the Lambda
     # equations (D + A)^T Lambda = -dE/dT give Lambda = w T exactly
     rng = np.random.default_rng(10)
-    inp = make_inputs(rng, n_occ=4, somos=(1,), npno=3, naux=4)
+    inp = make_inputs(rng, n_occ=4, somos=(1,), npno=3, naux=4, hole=0.05)
     Tstar, A = oracle.dense_solution(inp)
     keys = keys_of(inp)
     dE = {}
@@ -270,7 +275,7 @@ def test_lambda_equals_weighted_amplitudes():
 # ---------------------------------------------------- P10 VJP by finite differences
 def test_vjp_matches_central_differences_and_adjoint_identity():
     rng = np.random.default_rng(12)
-    inp = make_inputs(rng, n_occ=5, somos=(2,), npno=4, naux=5, band=2)
+    inp = make_inputs(rng, n_occ=5, somos=(2,), npno=4, naux=5, band=2, hole=0.05)
     keys = keys_of(inp)
     T = random_T(rng, inp, scale=0.1)
     Lam = {k: rng.standard_normal(v.shape) for k, v in T.items()}
@@ -278,7 +283,7 @@ def test_vjp_matches_central_differences_and_adjoint_identity():
 
     def L(Tx, Bx=None):
         src = inp if Bx is None else oracle.Inputs(inp.n_occ, inp.is_somo, inp.pairs, Bx, inp.K,
-                                                   inp.eps_a, inp.eps_b, inp.f_a, inp.f_b, inp.S)
+                                                   inp.eps_a, inp.eps_b, inp.f_a, inp.f_b, inp.S, inp.occ_ints)
         R = oracle.residual_os(src, Tx)
         return inner(Lam, R)
 

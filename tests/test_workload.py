@@ -99,3 +99,41 @@ def test_spin_dependent_fock_makes_a_spin_swap_visible():
             else:
                 assert diff == 0.0, (name, diff)
         assert max(float(np.max(np.abs(R[k] - Rb[k]))) for k in R if k[1] == "AA") == 0.0
+
+
+def test_hole_hole_couplings_follow_the_integral_rule():
+    """Hole-hole couplings of target (i, j): every ordered (k, l) with a
+    non-zero synthetic integral (k i | l j) whose pair {k, l} is retained,
+    weight = that integral; the integrals have the eightfold symmetry of real
+    two-electron integrals; self-couplings point at identity overlap blocks;
+    without the option the workload is unchanged."""
+    base = build_problem("chain", n_occ=16, band=4, somos=(5, 11))
+    prob = build_problem("chain", n_occ=16, band=4, somos=(5, 11), hole_ladder=0.02, hole_range=2)
+    assert base.n_hh == 0 and prob.n_hh > 0
+    assert np.array_equal(base.cpl_src, prob.cpl_src)
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        k, i, l, j = (int(x) for x in rng.integers(0, 16, 4))
+        v = prob.eri_occ(k, i, l, j)
+        for perm in ((i, k, l, j), (k, i, j, l), (l, j, k, i), (j, l, i, k)):
+            assert prob.eri_occ(*perm) == v
+        if abs(k - i) > 2 or abs(l - j) > 2:
+            assert v == 0.0
+    S = prob.materialize("S")
+    for p in range(prob.n_pairs):
+        i, j = int(prob.pi[p]), int(prob.pj[p])
+        want = {}
+        for k in range(16):
+            for l in range(16):
+                w = prob.eri_occ(k, i, l, j)
+                q = prob.pair_index.get((min(k, l), max(k, l)))
+                if w != 0.0 and q is not None:
+                    want[(k, l)] = (q, w)
+        got = {(int(prob.hh_k[e]), int(prob.hh_l[e])): (int(prob.hh_src[e]), float(prob.hh_w[e]))
+               for e in range(prob.hh_rowptr[p], prob.hh_rowptr[p + 1])}
+        assert got == want, p
+        for e in range(prob.hh_rowptr[p], prob.hh_rowptr[p + 1]):
+            if prob.hh_src[e] == p:
+                n = int(prob.npno[p])
+                o = int(prob.hh_off_S[e])
+                assert np.array_equal(S[o:o + n * n].reshape(n, n), np.eye(n))

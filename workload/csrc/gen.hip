@@ -64,6 +64,7 @@ __global__ __launch_bounds__(256) void gen_kernel(const Seg* segs, int64_t nseg,
       switch (sg.mode) {
         case 0: v = normal(lay + (uint64_t)x * 64u + y, sg.stream, sg.field, seed) * sg.scale; break;
         case 3: v = normal(lay + (uint64_t)y * 64u + x, sg.stream, sg.field, seed) * sg.scale; break;
+        case 4: v = x == y ? 1.0 : 0.0; break;   // identity block
         case 1: {
           const int lo = x < y ? x : y, hi = x < y ? y : x;
           v = normal(lay + (uint64_t)lo * 64u + hi, sg.stream, sg.field, seed) * sg.scale;

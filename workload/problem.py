@@ -35,14 +35,14 @@ BLOCK_BITS = {"AA": 1, "BB": 2, "AB": 4, "BA": 8}
 BLOCK_SPINS = {"AA": (0, 0), "BB": (1, 1), "AB": (0, 1), "BA": (1, 0)}
 
 # Philox field ids (fourth counter word)
-F_NPNO, F_NAUX, F_B, F_T, F_K, F_EPS, F_FDIAG, F_FOFF, F_S, F_QR, F_W, F_F12, F_FOFFB = range(1, 14)
+F_NPNO, F_NAUX, F_B, F_T, F_K, F_EPS, F_FDIAG, F_FOFF, F_S, F_QR, F_W, F_F12, F_FOFFB, F_HH = range(1, 15)
 
 # F12 inputs (synthetic): W = V + C per stored block, in the amplitude layout,
 # and six scalars per block (V, V', B1..B4, see Problem.f12_scalars)
 SIGMA_W = 0.05
 
 # segment generation modes (see segment_values)
-MODE_PLAIN, MODE_SYM, MODE_ANTI, MODE_TRANS = 0, 1, 2, 3
+MODE_PLAIN, MODE_SYM, MODE_ANTI, MODE_TRANS, MODE_EYE = 0, 1, 2, 3, 4
 
 SEG_DTYPE = np.dtype([("off", np.int64), ("stream", np.int64), ("field", np.int32),
                       ("mode", np.int32), ("layers", np.int32), ("rows", np.int32),
@@ -121,6 +121,27 @@ class Problem:
     segs: dict = field(default_factory=dict)   # name -> SEG_DTYPE array
     S_host: np.ndarray = None                  # set when S is built on the host (QR recipe)
     pair_index: dict = field(default_factory=dict)
+    # hole-hole ladder couplings (CSR by target pair; empty when the term is off):
+    # ordered occupied source (k, l), source pair {k, l}, weight (k i | l j), overlap block
+    hh_rowptr: np.ndarray = None
+    hh_src: np.ndarray = None
+    hh_k: np.ndarray = None
+    hh_l: np.ndarray = None
+    hh_w: np.ndarray = None
+    hh_off_S: np.ndarray = None
+    hole_scale: float = 0.0
+    hole_range: int = 2
+
+    @property
+    def n_hh(self):
+        return 0 if self.hh_src is None else len(self.hh_src)
+
+    def eri_occ(self, k, i, l, j):
+        """The synthetic occupied integral (k i | l j) of this workload (0 when
+        the hole-hole term is off)."""
+        if self.hole_scale == 0.0:
+            return 0.0
+        return float(occ_eri(self.seed, self.n_occ, self.hole_scale, self.hole_range, [k], [i], [l], [j])[0])
 
     @property
     def n_pairs(self):
@@ -185,6 +206,9 @@ def segment_values(seed, seg):
         idx = lay + y * np.uint64(64) + x
     elif mode == MODE_SYM:
         idx = lay + np.minimum(x, y) * np.uint64(64) + np.maximum(x, y)
+    elif mode == MODE_EYE:
+        # identity blocks (the overlap of a pair's PNOs with themselves)
+        return np.broadcast_to((x == y).astype(np.float64), (L, R, C)).copy()
     elif mode == MODE_ANTI:
         z1 = philox.normals(seed, fld, stream, lay + x * np.uint64(64) + y)
         z2 = philox.normals(seed, fld, stream, lay + y * np.uint64(64) + x)
@@ -213,13 +237,38 @@ def _dims(rule, seed, fld, P):
     raise ValueError(kind)
 
 
+def occ_eri(seed, n_occ, scale, rng, k, i, l, j):
+    """Synthetic occupied four-index integrals (k i | l j) (chemists' notation)
+    for arrays of indices: scale exp(-(|k - i| + |l - j|)) z with one normal z
+    per orbit of the eightfold permutational symmetry of real integrals
+    ((ki|lj) = (ik|lj) = (ki|jl) = (lj|ki) ...), zero unless |k - i| <= rng
+    and |l - j| <= rng.  A random draw of the inputs, not a computed integral."""
+    k, i, l, j = (np.asarray(x, dtype=np.int64) for x in (k, i, l, j))
+    a, b = np.minimum(k, i), np.maximum(k, i)
+    c, d = np.minimum(l, j), np.maximum(l, j)
+    swap = (a > c) | ((a == c) & (b > d))
+    a2, b2 = np.where(swap, c, a), np.where(swap, d, b)
+    c2, d2 = np.where(swap, a, c), np.where(swap, b, d)
+    n = np.int64(n_occ)
+    idx = (((a2 * n + b2) * n + c2) * n + d2).astype(np.uint64)
+    z = philox.normals(seed, F_HH, 0, idx)
+    dk, dl = np.abs(k - i), np.abs(l - j)
+    v = scale * np.exp(-(dk + dl).astype(np.float64)) * z
+    return np.where((dk <= rng) & (dl <= rng), v, 0.0)
+
+
 def build_problem(name="tiny", **override):
     """Build the descriptors and small inputs of a named (or customised) workload.
 
     Overrides: any CONFIGS key, e.g. n_occ=24, band=6, somos=(8, 16), and
     fock_spin=x: beta off-diagonal occupied Fock elements f_b[i,k] = f_a[i,k] +
     x 0.02 exp(-|i-k|/3) z' with z' from a field of their own (default 0: the
-    off-diagonal elements are the same for both spins)."""
+    off-diagonal elements are the same for both spins);
+    hole_ladder=c, hole_range=d: the hole-hole ladder's occupied integrals
+    (k i | l j) drawn by occ_eri with scale c and range d (default 0: no
+    hole-hole term), with one coupling per target pair (i, j) and ordered
+    occupied pair (k, l) whose integral is non-zero and whose pair {k, l} is
+    retained (the pair itself included: its overlap block is the identity)."""
     cfg = dict(CONFIGS[name]) if name in CONFIGS else {}
     cfg.update(override)
     seed = int(cfg["seed"])
@@ -324,13 +373,42 @@ def build_problem(name="tiny", **override):
     C = len(cpl_src)
     tgt = np.repeat(np.arange(P, dtype=np.int64), np.diff(rowptr))
 
-    # one S block per (target, source) pair of pairs; the two sides of a diagonal
-    # target that reach the same source share it
-    key = tgt * P + cpl_src
+    # ---- hole-hole ladder couplings (CSR by target): ordered (k, l) near (i, j) ----
+    hh_scale = float(cfg.get("hole_ladder", 0.0))
+    hh_range = int(cfg.get("hole_range", 2))
+    hh_rowptr = np.zeros(P + 1, dtype=np.int64)
+    hh_src = np.zeros(0, dtype=np.int32)
+    hh_k = np.zeros(0, dtype=np.int32)
+    hh_l = np.zeros(0, dtype=np.int32)
+    hh_w = np.zeros(0)
+    if hh_scale != 0.0:
+        offs = np.arange(-hh_range, hh_range + 1)
+        dk = np.repeat(offs, len(offs))
+        dl = np.tile(offs, len(offs))
+        pp = np.repeat(np.arange(P, dtype=np.int64), len(dk))
+        ci, cj = pi[pp].astype(np.int64), pj[pp].astype(np.int64)
+        ck, cl = ci + np.tile(dk, P), cj + np.tile(dl, P)
+        ok = (ck >= 0) & (ck < n_occ) & (cl >= 0) & (cl < n_occ)
+        pp, ci, cj, ck, cl = pp[ok], ci[ok], cj[ok], ck[ok], cl[ok]
+        w = occ_eri(seed, n_occ, hh_scale, hh_range, ck, ci, cl, cj)
+        pidx = np.full((n_occ, n_occ), -1, dtype=np.int64)
+        pidx[pi, pj] = np.arange(P)
+        q = pidx[np.minimum(ck, cl), np.maximum(ck, cl)]
+        ok = (w != 0.0) & (q >= 0)
+        pp, ck, cl, q, w = pp[ok], ck[ok], cl[ok], q[ok], w[ok]
+        hh_rowptr[1:] = np.cumsum(np.bincount(pp, minlength=P))
+        hh_src, hh_k, hh_l, hh_w = q.astype(np.int32), ck.astype(np.int32), cl.astype(np.int32), w
+    hh_tgt = np.repeat(np.arange(P, dtype=np.int64), np.diff(hh_rowptr))
+
+    # one S block per (target, source) pair of pairs, shared by every coupling
+    # (Fock or hole-hole) between them; the two sides of a diagonal target that
+    # reach the same source share it
+    key = np.concatenate([tgt * P + cpl_src, hh_tgt * P + hh_src.astype(np.int64)])
     ukey, first, inv = np.unique(key, return_index=True, return_inverse=True)
     sz_dir = np.array([_align(int(npno[int(k // P)]) * int(npno[int(k % P)])) for k in ukey], dtype=np.int64)
     off_dir = np.concatenate([[0], np.cumsum(sz_dir)[:-1]]).astype(np.int64)
-    cpl_off_S = off_dir[inv]
+    cpl_off_S = off_dir[inv[:C]]
+    hh_off_S = off_dir[inv[C:]]
     n_S = int(sz_dir.sum())
 
     # ---- generated segments ----
@@ -379,7 +457,7 @@ def build_problem(name="tiny", **override):
         S_host = np.zeros(n_S)
         for u, k in enumerate(ukey):
             p, q = int(k // P), int(k % P)
-            W = Qs[q].T @ Qs[p]                     # [c][a] = <c_q | a_p>
+            W = np.eye(int(npno[p])) if p == q else Qs[q].T @ Qs[p]     # [c][a] = <c_q | a_p>
             S_host[off_dir[u]:off_dir[u] + W.size] = W.ravel()
     else:
         # random overlaps: S_{lo,hi} = sigma * Z (n_lo x n_hi), S_{hi,lo} = its transpose
@@ -393,7 +471,7 @@ def build_problem(name="tiny", **override):
         segS["field"] = F_S
         # stored W[c][a] (c on source q, a on target p) = S_{q,p}[c][a]:
         #   q == lo: Z[c][a] (plain); q == hi: Z[a][c] (transposed)
-        segS["mode"] = np.where(q_s < p_t, MODE_PLAIN, MODE_TRANS)
+        segS["mode"] = np.where(q_s == p_t, MODE_EYE, np.where(q_s < p_t, MODE_PLAIN, MODE_TRANS))
         segS["layers"] = 1
         segS["rows"] = npno[q_s]
         segS["cols"] = npno[p_t]
@@ -409,4 +487,5 @@ def build_problem(name="tiny", **override):
                    off_eps=off_eps, cpl_rowptr=rowptr, cpl_src=cpl_src, cpl_k=cpl_k,
                    cpl_side=cpl_side, cpl_off_S=cpl_off_S, f_a=f_a, f_b=f_b, eps_a=eps_a,
                    eps_b=eps_b, n_B=n_B, n_T=n_T, n_K=n_K, n_S=n_S, segs=segs, S_host=S_host,
-                   pair_index=pair_index)
+                   pair_index=pair_index, hh_rowptr=hh_rowptr, hh_src=hh_src, hh_k=hh_k, hh_l=hh_l,
+                   hh_w=hh_w, hh_off_S=hh_off_S.astype(np.int64), hole_scale=hh_scale, hole_range=hh_range)
