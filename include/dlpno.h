@@ -47,7 +47,7 @@ typedef enum {
   DLPNO_ERR_ALIGNMENT = -3,     /* buffer offsets outside the declared buffer sizes */
   DLPNO_ERR_HIP = -4,           /* a HIP runtime call failed */
   DLPNO_ERR_NONFINITE = -5,     /* a residual element was NaN or Inf */
-  DLPNO_ERR_NOT_CONVERGED = -6, /* reserved */
+  DLPNO_ERR_NOT_CONVERGED = -6, /* dlpno_solve: no convergence in max_iter, or divergence */
   DLPNO_ERR_OOM = -7,           /* device allocation failed */
   DLPNO_ERR_UNSUPPORTED = -8    /* precision / option not available for this call */
 } dlpno_status;
@@ -242,6 +242,26 @@ dlpno_status dlpno_iterate(dlpno_plan* plan, int32_t n_iter, double* T, double* 
  * Waits for the work queued on `stream`. */
 dlpno_status dlpno_diis_state(const dlpno_plan* plan, int32_t* count, int32_t* drops, double* coef, void* stream);
 
+/* Iterates (as dlpno_iterate, checking every second iteration) until
+ * max|R| < tol_r and the total energy changed by less than tol_e since the
+ * previous iteration (DLPNO_OK), or at most max_iter iterations.  Returns
+ * DLPNO_ERR_NOT_CONVERGED when max_iter is reached first, and as soon as max|R|
+ * exceeds 1e3 times its smallest value of the call (the iteration diverges;
+ * the buffers hold that iteration's values).  *n_done (host, may be NULL) =
+ * iterations run.  Synchronous. */
+dlpno_status dlpno_solve(dlpno_plan* plan, int32_t max_iter, double tol_r, double tol_e, double* T, double* R,
+                         double* e_pair, double* e_total, double* max_abs_R, int32_t* n_done, void* stream);
+
+/* Checkpoint of the iteration state, to resume an interrupted solve: the
+ * amplitudes T (device, n_T doubles), the DIIS history (vectors, errors,
+ * Gram matrix, coefficients) and the energy/max|R| history, copied to or from
+ * caller-owned host memory of dlpno_checkpoint_size bytes.  A checkpoint
+ * loads only into a plan with the same sizes and DIIS options; resuming gives
+ * bitwise the iterations the saved plan would have run.  Synchronous. */
+dlpno_status dlpno_checkpoint_size(const dlpno_plan* plan, size_t* bytes);
+dlpno_status dlpno_checkpoint_save(const dlpno_plan* plan, const double* T, void* dst, void* stream);
+dlpno_status dlpno_checkpoint_load(dlpno_plan* plan, double* T, const void* src, void* stream);
+
 /* Clears the DIIS history and the iteration counter. */
 dlpno_status dlpno_reset(dlpno_plan* plan, void* stream);
 
@@ -285,6 +305,16 @@ dlpno_status dlpno_flop_count(const dlpno_plan* plan, double* ladder, double* pr
  * R: scratch of n_T doubles).  Synchronous.  The choice is reported through
  * dlpno_plan_info. */
 dlpno_status dlpno_autotune(dlpno_plan* plan, const double* T, double* R, void* stream);
+
+/* dlpno_autotune with a persistent cache: when the JSON file `path` holds
+ * choices for this device's architecture and the plan's precision, they are
+ * applied without timing (*hit = 1); otherwise dlpno_autotune runs and its
+ * choices are written to the file under that key, keeping its other entries
+ * (*hit = 0).  The choices: the ladder and projection tile variants per tile
+ * class of 16 PNOs, items per wave, the two-wave launches and the persistent
+ * workgroup count.  Synchronous. */
+dlpno_status dlpno_autotune_cached(dlpno_plan* plan, const double* T, double* R, const char* path, int32_t* hit,
+                                   void* stream);
 
 /* Kernel timing: when enabled, residual/iterate record HIP events around the
  * phases on the call's stream (graphs are bypassed) and dlpno_phase_times

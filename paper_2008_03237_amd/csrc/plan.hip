@@ -722,6 +722,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   hipDeviceProp_t prop;
   HIPCK(hipGetDeviceProperties(&prop, dev));
   P->num_cu = prop.multiProcessorCount;
+  P->arch = prop.gcnArchName;
   P->workers = opt.n_workers > 0 ? opt.n_workers : P->num_cu;
   if (opt.items_per_wave > 0) P->tune.items_per_wave = (double)opt.items_per_wave;
   // FP64 defaults: two-tile pairs take two blocks per item, so that they run

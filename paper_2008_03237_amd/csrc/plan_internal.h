@@ -45,6 +45,7 @@ struct PendingEvent {
 struct dlpno_plan {
   dlpno_options opt{};
   int device = 0, num_cu = 0, workers = 0;
+  std::string arch;                     // device architecture name (autotuner cache key)
   int32_t n_occ = 0, n_pairs = 0, n_blocks = 0;
   int64_t n_cpl = 0, n_terms = 0, n_hh = 0;   // couplings (Fock + hole-hole), of them hole-hole
   int64_t n_B = 0, n_T = 0, n_K = 0, n_eps = 0, n_S = 0;

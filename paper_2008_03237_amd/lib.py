@@ -82,12 +82,21 @@ def lib():
         "dlpno_solve_mixed": [vp, i32, i32, vp, vp, vp, vp, vp, vp],
         "dlpno_flop_count": [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)],
         "dlpno_diis_state": [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double), vp],
+        "dlpno_solve": [vp, i32, C.c_double, C.c_double, vp, vp, vp, vp, vp, C.POINTER(C.c_int32), vp],
+        "dlpno_checkpoint_size": [vp, C.POINTER(C.c_size_t)],
+        "dlpno_checkpoint_save": [vp, vp, vp, vp],
+        "dlpno_checkpoint_load": [vp, vp, vp, vp],
         "dlpno_autotune": [vp, vp, vp, vp],
+        "dlpno_autotune_cached": [vp, vp, vp, C.c_char_p, C.POINTER(C.c_int32), vp],
         "dlpno_set_profiling": [vp, i32],
         "dlpno_phase_times": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32],
     }
     for name, args in sig.items():
-        f = getattr(L, name)
+        # a library built from older sources lacks newer entry points: only
+        # calls of those fail (AttributeError), the others keep working
+        f = getattr(L, name, None)
+        if f is None:
+            continue
         f.argtypes = args
         f.restype = C.c_int
     L.dlpno_history.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), i32]
@@ -231,6 +240,32 @@ class Plan:
                                    _stream()))
         return R, e_pair, e_total, rmax
 
+    def solve(self, max_iter, T, tol_r=1e-9, tol_e=1e-10, R=None, e_pair=None, e_total=None, rmax=None):
+        """dlpno_solve: iterate to convergence.  Returns (R, e_pair, e_total,
+        max|R|, iterations run); raises DlpnoError (status -6) when it does not
+        converge in max_iter iterations or diverges."""
+        R = self._new(self.n_T) if R is None else R
+        e_pair = self._new(4 * self.n_pairs) if e_pair is None else e_pair
+        e_total = self._new(1) if e_total is None else e_total
+        rmax = self._new(1) if rmax is None else rmax
+        n = C.c_int32()
+        _check(lib().dlpno_solve(self._h, int(max_iter), float(tol_r), float(tol_e), _ptr(T), _ptr(R), _ptr(e_pair),
+                                 _ptr(e_total), _ptr(rmax), C.byref(n), _stream()))
+        return R, e_pair, e_total, rmax, n.value
+
+    def checkpoint(self, T):
+        """The iteration state (T, DIIS and energy histories) as a host byte array."""
+        size = C.c_size_t()
+        _check(lib().dlpno_checkpoint_size(self._h, C.byref(size)))
+        buf = np.empty(size.value, dtype=np.uint8)
+        _check(lib().dlpno_checkpoint_save(self._h, _ptr(T), buf.ctypes.data_as(C.c_void_p), _stream()))
+        return buf
+
+    def restore(self, T, buf):
+        """Loads a checkpoint into this plan and the device amplitudes T."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(lib().dlpno_checkpoint_load(self._h, _ptr(T), buf.ctypes.data_as(C.c_void_p), _stream()))
+
     def reset(self):
         _check(lib().dlpno_reset(self._h, _stream()))
 
@@ -273,6 +308,14 @@ class Plan:
     def autotune(self, T, R=None):
         R = self._new(self.n_T) if R is None else R
         _check(lib().dlpno_autotune(self._h, _ptr(T), _ptr(R), _stream()))
+
+    def autotune_cached(self, T, path, R=None):
+        """dlpno_autotune_cached: the tuned schedule from the JSON cache `path`
+        (True) or tuned now and stored there (False)."""
+        R = self._new(self.n_T) if R is None else R
+        hit = C.c_int32()
+        _check(lib().dlpno_autotune_cached(self._h, _ptr(T), _ptr(R), os.fsencode(path), C.byref(hit), _stream()))
+        return bool(hit.value)
 
     def set_profiling(self, on=True):
         _check(lib().dlpno_set_profiling(self._h, 1 if on else 0))

@@ -101,9 +101,20 @@ def test_autograd_lagrangian_central_differences_50_pairs(precision):
     T = dev["T"].clone().requires_grad_(True)
     B = dev["B"]
     B.requires_grad_(True)
-    # L = E(T) + <Lambda, R(T, B)>, E linear in T: sum_blocks w <K^{ss'}, T> (via update's energy of T)
+    # L = E(T) + <Lambda, R(T, B)> with the pair energy functional of the
+    # amplitudes E(T) = sum_blocks w <K^{ss'}, T> (w = 1/2 same spin, 1
+    # opposite spin), evaluated here with torch from the driver integrals
+    Kflat = prob.materialize("K")
+    Kw = np.zeros(prob.n_T)
+    for p in range(prob.n_pairs):
+        n, o = int(prob.npno[p]), int(prob.off_T[p])
+        Kp = Kflat[int(prob.off_K[p]):int(prob.off_K[p]) + n * n].reshape(n, n)
+        for name in prob.block_list(p):
+            Kw[o:o + n * n] = (0.5 * (Kp - Kp.T) if name in ("AA", "BB") else Kp).ravel()
+            o += n * n
+    Kw = torch.from_numpy(Kw).cuda()
     R = residual(T, B, plan)
-    L = torch.dot(Lam, R)
+    L = torch.dot(Kw, T) + torch.dot(Lam, R)
     L.backward()
     gT, gB = T.grad.detach(), B.grad.detach()
     B.requires_grad_(False)
@@ -126,7 +137,7 @@ def test_autograd_lagrangian_central_differences_50_pairs(precision):
     fp = Plan(prob, dev["B"], dev["S"], dev["K"], plan._dev[3], plan._dev[4])   # FP64 residuals for the differences
 
     def Lof(Tx):
-        return float(torch.dot(Lam, fp.residual(Tx)))
+        return float(torch.dot(Kw, Tx)) + float(torch.dot(Lam, fp.residual(Tx)))
     with torch.no_grad():
         fd_T = (Lof(dev["T"] + h * dTdir) - Lof(dev["T"] - h * dTdir)) / (2 * h)
         an_T = float(torch.dot(gT, dTdir))

@@ -1,0 +1,85 @@
+"""Iteration to convergence (dlpno_solve), divergence and iteration-limit
+detection, and checkpoint/resume of the iteration state, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.model import unpack_T
+from tests.gpu_helpers import device_problem, oracle_inputs
+from workload import build_problem
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def setup_module(module):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_solve_converges_to_the_oracle_fixed_point():
+    prob = build_problem("chain", n_occ=20, band=5, somos=(6, 13))
+    plan, dev = device_problem(prob, T_random=False)
+    R, e_pair, e_tot, rmax, n = plan.solve(60, dev["T"], tol_r=1e-11, tol_e=1e-12)
+    print("converged in", n, "iterations, max|R| %.3e" % float(rmax.cpu()[0]), flush=True)
+    assert float(rmax.cpu()[0]) < 1e-11 and 2 <= n < 60
+    inp = oracle_inputs(prob)
+    zero = unpack_T(prob, np.zeros(prob.n_T))
+    To, hist = oracle.solve(inp, zero, 60, use_diis=True, tol_r=1e-11, tol_e=1e-12)
+    assert abs(float(e_tot.cpu()[0]) - hist[-1][0]) <= 1e-10
+    plan.close()
+
+
+def test_solve_reports_an_iteration_limit():
+    from paper_2008_03237_amd import DlpnoError
+    prob = build_problem("chain", n_occ=12, band=3, somos=(4, 8))
+    plan, dev = device_problem(prob, T_random=False)
+    with pytest.raises(DlpnoError) as ei:
+        plan.solve(5, dev["T"], tol_r=0.0, tol_e=0.0)
+    assert ei.value.status == -6 and "5 iterations" in str(ei.value)
+    assert len(plan.history()[0]) == 5
+    plan.close()
+
+
+def test_solve_detects_divergence():
+    """Density-fitting integrals about 7x the contractive scale make the Jacobi
+    iteration (no DIIS) diverge: max|R| grows each step until it is 1e3 times
+    its smallest value, long before it overflows."""
+    from paper_2008_03237_amd import DlpnoError
+    prob = build_problem("chain", n_occ=12, band=3, somos=(4, 8), sigma_B=0.05)
+    plan, dev = device_problem(prob, diis_max=0, T_random=False)
+    with pytest.raises(DlpnoError) as ei:
+        plan.solve(200, dev["T"])
+    assert ei.value.status == -6 and "diverges" in str(ei.value)
+    E, Rm = plan.history()
+    print("diverged after", len(Rm), "iterations; max|R|", Rm[-3:], flush=True)
+    assert len(Rm) < 200 and np.all(np.isfinite(Rm)) and Rm[-1] > 1e3 * Rm.min()
+    plan.close()
+
+
+def test_checkpoint_resume_is_bitwise():
+    prob = build_problem("chain", n_occ=20, band=5, somos=(6, 13))
+    plan, dev = device_problem(prob, T_random=False)
+    T = dev["T"]
+    plan.iterate(4, T)
+    ck = plan.checkpoint(T)
+    plan.iterate(4, T)
+    T_a = T.clone()
+    E_a, R_a = plan.history()
+    # scramble the state, then resume from the checkpoint
+    plan.iterate(3, T)
+    plan.restore(T, ck)
+    assert len(plan.history()[0]) == 4
+    plan.iterate(4, T)
+    E_b, R_b = plan.history()
+    assert torch.equal(T.view(torch.int64), T_a.view(torch.int64))
+    assert np.array_equal(E_a, E_b) and np.array_equal(R_a, R_b)
+    # a checkpoint of another plan is refused
+    from paper_2008_03237_amd import DlpnoError
+    other = build_problem("chain", n_occ=12, band=3, somos=(4, 8))
+    p2, d2 = device_problem(other, T_random=False)
+    with pytest.raises(DlpnoError) as ei:
+        p2.restore(d2["T"], ck)
+    assert ei.value.status == -1
+    p2.close()
+    plan.close()
