@@ -194,15 +194,16 @@ constexpr int kCoopSlabWords = 64 * 64;
 // is antisymmetric; tiles above the diagonal (tb < ta) were not computed and
 // are written as the negated transpose of the tile below it, by whichever item
 // owns that tile's a-tile.
-template <typename F, int NT, int NU, typename V>
-__device__ __forceinline__ void store_tiles(double* dst, int n, int ta0, const V (&acc)[NT][NU], bool mirror,
-                                            double scale = 1.0, int dta = 1) {
+// (store_tiles_first: the first NS of the NU accumulator columns)
+template <typename F, int NT, int NS, int NU, typename V>
+__device__ __forceinline__ void store_tiles_first(double* dst, int n, int ta0, const V (&acc)[NT][NU], bool mirror,
+                                                  double scale = 1.0, int dta = 1) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int tb = 0; tb < NT; ++tb)
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
+    for (int u = 0; u < NS; ++u) {
       const int ta = ta0 + u * dta;
       if (mirror && tb < ta) continue;
       const int a = 16 * ta + r;
@@ -216,6 +217,11 @@ __device__ __forceinline__ void store_tiles(double* dst, int n, int ta0, const V
         }
       }
     }
+}
+template <typename F, int NT, int NU, typename V>
+__device__ __forceinline__ void store_tiles(double* dst, int n, int ta0, const V (&acc)[NT][NU], bool mirror,
+                                            double scale = 1.0, int dta = 1) {
+  store_tiles_first<F, NT, NU, NU>(dst, n, ta0, acc, mirror, scale, dta);
 }
 
 // ---------------------------------------------------------------------------
@@ -255,6 +261,12 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
   // of that d-tile are then also kept in the LDS slab, where the strips read
   // them at permuted lanes
   constexpr bool STRIPS = Strips<F>::value && R < 4;
+  // Column strips (FP64): when the item's last a-tile is the pair's last tile
+  // and holds at most 4 kColStrips PNO columns, that a-tile runs as R strips of
+  // four columns (four-block 4x4x4 MFMAs with the B operand broadcast across
+  // the blocks) in both stages instead of one 16-wide tile (see the loops).
+  constexpr int UL = NTA - 1;                      // accumulator column of the last a-tile
+  constexpr bool CS = STRIPS && R <= kColStrips && TA0 + UL * DTA == NT - 1;
   F Ar[REG ? NB : 1][REG ? NT : 1][REG ? S4 : 1];
 
   // X-form operands of the NB amplitude blocks, once per item
@@ -286,6 +298,16 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
     for (int t = 0; t < NT; ++t)
 #pragma unroll
       for (int u = 0; u < NTA; ++u) acc[b][t][u] = V{0, 0, 0, 0};
+  // column strips of the last a-tile: accC[b][tb][j], lane 16 g + 4 k + v
+  // holds Out^T[16 tb + 4 k + g][16 (NT - 1) + 4 j + v]
+  constexpr int RC = CS ? R : 1;
+  F accC[NB][NT][RC];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int j = 0; j < RC; ++j) accC[b][t][j] = F(0);
   // bit b of MASK: block b is antisymmetric (same spin), stage 2 only for
   // tiles with tb >= ta
   auto mir = [](int b) { return ((MASK >> b) & 1) != 0; };
@@ -312,25 +334,57 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
 #pragma unroll
     for (int td = 0; td < NT; ++td) {
       V d1[NB][NTA];
+      // column strips of the last a-tile: d1c[b][j] (full d-tile: lane
+      // 16 g + 4 k + v = Y^T[16 td + 4 k + g][col 4 j + v]) and, in the last
+      // d-tile run as row strips, d1cc[b][i][j] (every block = Y^T[16 td + 4 i
+      // + g][col 4 j + v], already the replicated B operand of stage 2)
+      F d1c[NB][RC], d1cc[NB][CS ? R : 1][RC];
       // stage 1: Y^T[d][a] = sum_c T[c][d] B^Q[c][a]   (d-tile td, every block)
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
 #pragma unroll
         for (int u = 0; u < NTA; ++u) d1[b][u] = V{0, 0, 0, 0};
 #pragma unroll
+        for (int j = 0; j < RC; ++j) {
+          d1c[b][j] = F(0);
+#pragma unroll
+          for (int i = 0; i < (CS ? R : 1); ++i) d1cc[b][i][j] = F(0);
+        }
+#pragma unroll
         for (int s = 0; s < S4; ++s) {
+          // B operand of a column strip: columns 4 j .. 4 j + 3 of the last
+          // a-tile, broadcast to all four blocks
+          F mb[RC];
+          if constexpr (CS) {
+#pragma unroll
+            for (int j = 0; j < RC; ++j) mb[j] = bcast_strip(M[NT - 1][s], j);
+          }
           if (STRIPS && td == NT - 1) {
             // strip i = k-step 4 td + i of stage 2; only the R strips with PNO rows
 #pragma unroll
             for (int i = 0; i < R; ++i) {
               const F av = aop_strip(b, s, i);
 #pragma unroll
-              for (int u = 0; u < NTA; ++u) d1[b][u][i] = mfma_strip(av, M[ta(u)][s], d1[b][u][i]);
+              for (int u = 0; u < NTA; ++u) {
+                if (CS && u == UL) continue;
+                d1[b][u][i] = mfma_strip(av, M[ta(u)][s], d1[b][u][i]);
+              }
+              if constexpr (CS) {
+#pragma unroll
+                for (int j = 0; j < RC; ++j) d1cc[b][i][j] = mfma_strip(av, mb[j], d1cc[b][i][j]);
+              }
             }
           } else {
             const F av = aop(b, td, s);
 #pragma unroll
-            for (int u = 0; u < NTA; ++u) d1[b][u] = Mfma<F>::op(av, M[ta(u)][s], d1[b][u]);
+            for (int u = 0; u < NTA; ++u) {
+              if (CS && u == UL) continue;
+              d1[b][u] = Mfma<F>::op(av, M[ta(u)][s], d1[b][u]);
+            }
+            if constexpr (CS) {
+#pragma unroll
+              for (int j = 0; j < RC; ++j) d1c[b][j] = mfma_strip(av, mb[j], d1c[b][j]);
+            }
           }
         }
       }
@@ -348,13 +402,14 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
               for (int tb = 0; tb < (STRIPS ? NT - 1 : NT); ++tb)
 #pragma unroll
                 for (int u = 0; u < NTA; ++u)
-                  if (tb >= ta(u)) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[b][u][i], acc[b][tb][u]);
+                  if (tb >= ta(u) && !(CS && u == UL))
+                    acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[b][u][i], acc[b][tb][u]);
             } else {
 #pragma unroll
               for (int tb = 0; tb < (STRIPS ? NT - 1 : NT); ++tb)
 #pragma unroll
                 for (int u = 0; u < NTA; ++u)
-                  acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[b][u][i], acc[b][tb][u]);
+                  if (!(CS && u == UL)) acc[b][tb][u] = Mfma<F>::op(M[tb][4 * td + i], d1[b][u][i], acc[b][tb][u]);
             }
           }
           if constexpr (STRIPS) {
@@ -366,8 +421,22 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
               for (int b = 0; b < NB; ++b)
 #pragma unroll
                 for (int u = 0; u < NTA; ++u)
-                  acc[b][NT - 1][u][j] = mfma_strip(mv, d1[b][u][i], acc[b][NT - 1][u][j]);
+                  if (!(CS && u == UL)) acc[b][NT - 1][u][j] = mfma_strip(mv, d1[b][u][i], acc[b][NT - 1][u][j]);
             }
+          }
+          if constexpr (CS) {
+            // column strips of the last a-tile: every b-tile as 16 rows (the
+            // last one included; its padded rows are never stored), B operand
+            // = k-step i of the stage-1 strip, broadcast to all blocks
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+              for (int j = 0; j < RC; ++j) {
+                const F yb = (STRIPS && td == NT - 1) ? d1cc[b][i < R ? i : 0][j] : bcast_strip(d1c[b][j], i);
+#pragma unroll
+                for (int tb = 0; tb < NT; ++tb)
+                  if (!mir(b) || tb >= NT - 1) accC[b][tb][j] = mfma_strip(M[tb][4 * td + i], yb, accC[b][tb][j]);
+              }
           }
         }
       }
@@ -409,7 +478,23 @@ __device__ __forceinline__ void ladder_item(const GroupedArgs<F>& A, const Item&
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     double* dst = A.ws + uni(A.blocks[blk0 + bslot0 + b].off_ws) + (int64_t)it.slot * nn;
-    store_tiles<F>(dst, n, TA0, acc[b], mir(b), 1.0, DTA);
+    if constexpr (CS) {
+      // the a-tiles before the last as 16x16 tiles, the last one from its strips
+      if constexpr (NTA > 1) store_tiles_first<F, NT, NTA - 1, NTA>(dst, n, TA0, acc[b], mir(b), 1.0, DTA);
+      const int kb = (lane >> 2) & 3, v = lane & 3;
+#pragma unroll
+      for (int tb = 0; tb < NT; ++tb) {
+        if (mir(b) && tb < NT - 1) continue;       // written mirrored by the item of a-tile tb
+        const int bb = 16 * tb + 4 * kb + g;
+#pragma unroll
+        for (int j = 0; j < RC; ++j) {
+          const int a = 16 * (NT - 1) + 4 * j + v;
+          if (a < n && bb < n) dst[bb * n + a] = (double)accC[b][tb][j];
+        }
+      }
+    } else {
+      store_tiles<F>(dst, n, TA0, acc[b], mir(b), 1.0, DTA);
+    }
   }
 }
 

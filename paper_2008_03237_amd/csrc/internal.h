@@ -88,6 +88,13 @@ __device__ __forceinline__ int next_item(const WorkQueues& Q, int& q, int& left)
   return -1;
 }
 
+// FP64 ladder: largest number of k-steps of 4 in the last 16-wide tile (that
+// is, at most 4 kColStrips PNOs in it) for which the last a-tile runs as
+// column strips of the four-block 4x4x4 MFMA.  Each strip costs about 0.22 of
+// a 16x16x4 MFMA plus a DPP broadcast of its operand; with three strips the
+// broadcasts eat the gain.
+constexpr int kColStrips = 2;
+
 // Tile variants compiled into the grouped kernel.
 // Ladder: (NT tiles of 16 per PNO index, NB blocks per item, NTA a-tiles per item).
 struct LadderVariant { int nt, nb, nta; };

@@ -93,23 +93,24 @@ namespace dlpno {
 // Work of one ladder item per auxiliary function and block, in 16x16x4 MFMA
 // times: both stages issue nt x nta x s4 of them.  In FP64 a partial last
 // tile (r = s4 - 4 (nt - 1) < 4 k-steps in it) runs as r row strips of the
-// four-block 4x4x4 MFMA, each about 0.22 of a 16x16x4 instruction.
-double ladder_mfma_per_q(int nt, int nta, int s4, bool strips) {
-  const int r = s4 - 4 * (nt - 1);
-  const double last = strips && r < 4 ? 0.22 * r : 1.0;
-  return 2.0 * nta * s4 * (nt - 1 + last);
-}
-
-// The same for one block and the a-tiles ta0 + u dta (u < nta), with stage 2
-// limited to the tiles tb >= ta of an antisymmetric block (mirror).
+// four-block 4x4x4 MFMA, each about 0.22 of a 16x16x4 instruction, and with
+// r <= kColStrips the last a-tile as r column strips in both stages.
 double ladder_block_mfma_per_q(int nt, int ta0, int nta, int dta, int s4, bool strips, bool mirror) {
   const int r = s4 - 4 * (nt - 1);
   const double last = strips && r < 4 ? 0.22 * r : 1.0;
-  double st2 = 0.0;
-  for (int u = 0; u < nta; ++u)
+  const bool cs = strips && r <= kColStrips && ta0 + (nta - 1) * dta == nt - 1;
+  double st1 = 0.0, st2 = 0.0;
+  for (int u = 0; u < nta; ++u) {
+    const bool colu = cs && u == nta - 1;
+    st1 += (nt - 1 + last) * (colu ? 0.22 * r : 1.0);
     for (int tb = 0; tb < nt; ++tb)
-      if (!mirror || tb >= ta0 + u * dta) st2 += tb == nt - 1 ? last : 1.0;
-  return s4 * (nta * (nt - 1 + last) + st2);
+      if (!mirror || tb >= ta0 + u * dta) st2 += colu ? 0.22 * r : tb == nt - 1 ? last : 1.0;
+  }
+  return s4 * (st1 + st2);
+}
+double ladder_mfma_per_q(int nt, int nta, int s4, bool strips) {
+  // a-tiles 0 .. nta - 1 of a block that computes every tile
+  return ladder_block_mfma_per_q(nt, 0, nta, 1, s4, strips, false);
 }
 
 // largest compiled variant with this tile shape handling at most maxnb blocks

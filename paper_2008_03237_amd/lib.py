@@ -57,7 +57,9 @@ _LIB = None
 
 
 def library_path():
-    return os.path.join(_HERE, "libdlpno.so")
+    """The in-tree libdlpno.so, or the file named by DLPNO_LIBRARY (another
+    build of the same sources, e.g. for side-by-side timing)."""
+    return os.environ.get("DLPNO_LIBRARY") or os.path.join(_HERE, "libdlpno.so")
 
 
 def lib():

@@ -284,11 +284,12 @@ def test_graph_replay_matches_eager():
     plan.close()
 
 
-@pytest.mark.parametrize("n", [1, 4, 5, 16, 17, 26, 33, 39, 43, 48, 49, 55, 59, 64])
+@pytest.mark.parametrize("n", [1, 4, 5, 8, 16, 17, 22, 24, 26, 33, 39, 43, 48, 49, 55, 59, 64])
 def test_every_tile_remainder_against_oracle(n):
     """Fixed PNO count n per pair: one, two, three and four tiles of 16 with
-    every remainder R of k-steps in the last tile (row strips for R < 4, full
-    tiles for R = 4) in the two-wave and the cooperative ladder launches,
+    every remainder R of k-steps in the last tile (row strips for R < 4, and
+    column strips of the last a-tile for R <= 2; full tiles for R = 4) in the
+    two-wave and the cooperative ladder launches,
     same-spin mirroring, and SOMO-SOMO pairs with one block next to diagonal
     SOMO pairs with none (SOMOs 3 and 5 within the band: pairs with none, one,
     two or four stored blocks)."""
