@@ -329,6 +329,56 @@ dlpno_status dlpno_autotune_cached(dlpno_plan* plan, const double* T, double* R,
 dlpno_status dlpno_set_profiling(dlpno_plan* plan, int32_t enable);
 dlpno_status dlpno_phase_times(const dlpno_plan* plan, double* ms, int64_t* launches, int32_t n);
 
+/* ---- PNO construction (Sec. II.B.2) ----
+ *
+ * For every pair p, from the pair's first-order amplitude blocks X^{ss'}
+ * (N_p x N_p each, in an orthonormal basis of the pair's domain of N_p
+ * virtual functions) and the domain's virtual Fock matrix F_p:
+ *   D_p = 1 / (2 (1 + delta_ij)) sum_{ss'} w_{ss'} (X X^T + X^T X),
+ *         w = 1/2 for same spin, 1 for opposite spin (all four spin blocks;
+ *         a diagonal pair's beta-alpha block, when not stored, is the
+ *         transpose of its alpha-beta block).  With no SOMOs this is the
+ *         closed-shell MP1 pair density, to which the paper's single set of
+ *         PNOs per pair reduces;
+ *   occupations = eigenvalues of D_p in descending order; the PNOs are the
+ *         eigenvectors whose occupation is >= t_cut (T_CutPNO), n_p of them;
+ *   semicanonical PNOs: the kept natural orbitals V_k rotated by the
+ *         eigenvectors U of V_k^T F_p V_k, C_p = V_k U, orbital energies eps
+ *         ascending; each column of C_p is signed so that its
+ *         largest-magnitude element (the first on ties) is positive.
+ * Domains of 1..64 functions.  Eigenproblems are solved by parallel cyclic
+ * Jacobi in FP64. */
+typedef struct {
+  int32_t dim;       /* N_p, 1..64 */
+  int32_t blocks;    /* stored amplitude blocks: bit 0 AA, 1 BB, 2 AB, 3 BA */
+  int32_t diagonal;  /* 1 when the pair is (i, i), else 0 */
+  int32_t reserved;  /* 0 */
+  int64_t off_X;     /* first stored block; blocks back to back in the order AA, BB, AB, BA,
+                      * each N_p x N_p row-major [a][b] */
+  int64_t off_F;     /* N_p x N_p row-major, symmetric */
+  int64_t off_C;     /* output, N_p x N_p row-major [domain function][PNO]: columns 0..n_p-1
+                      * hold C_p, the others are zero */
+  int64_t off_v;     /* outputs, N_p each: occupations (all N_p) and eps (first n_p, rest zero) */
+} dlpno_pno_pair;
+
+typedef struct dlpno_pno_plan dlpno_pno_plan;   /* opaque, owned by the library */
+
+/* Validates the descriptors against the buffer sizes (in doubles) and
+ * uploads them.  pairs: host array, read during the call.  Synchronous. */
+dlpno_status dlpno_pno_plan_create(const dlpno_pno_pair* pairs, int64_t n_pairs, int64_t n_X, int64_t n_F,
+                                   int64_t n_C, int64_t n_v, dlpno_pno_plan** out);
+
+/* Builds the PNOs of every pair.  X, F: inputs; occ, eps (n_v doubles each),
+ * C (n_C doubles), n_kept (n_pairs int32): outputs; sweeps: optional
+ * (NULL or 2 n_pairs int32: Jacobi sweeps of the density and of the PNO Fock
+ * matrix).  All device pointers, caller-owned.  n_kept[p] is n_p >= 0, or
+ * -1 (density eigenproblem not converged in 40 sweeps), -2 (PNO Fock
+ * eigenproblem not converged) or -3 (non-finite density); occupations, eps
+ * and C of such a pair are zero.  Asynchronous on stream. */
+dlpno_status dlpno_pno_build(dlpno_pno_plan* plan, const double* X, const double* F, double t_cut, double* occ,
+                             double* eps, double* C, int32_t* n_kept, int32_t* sweeps, void* stream);
+dlpno_status dlpno_pno_plan_destroy(dlpno_pno_plan* plan);
+
 /* Human-readable summary of the plan (schedule, variants, workspace). */
 const char* dlpno_plan_info(const dlpno_plan* plan);
 

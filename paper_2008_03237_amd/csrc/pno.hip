@@ -1,0 +1,448 @@
+// PNO construction (Sec. II.B.2): for every pair, the pair density of its
+// first-order amplitude blocks in the pair's domain, the density's
+// eigen-decomposition, truncation at T_CutPNO and semicanonicalisation (the
+// domain's virtual Fock matrix diagonalised in the kept natural orbitals).
+//
+// One workgroup of 256 threads per pair; domains of at most 64 functions so
+// that the matrix and its eigenvectors live in LDS (2 x 64 x 65 doubles,
+// two workgroups per CU).  Both eigenproblems use the parallel cyclic Jacobi
+// method: a sweep is N-1 rounds of N/2 disjoint rotations in round-robin
+// order (Brent and Luk's ordering; a zero dummy index pads an odd N), each
+// round computes its rotations, then updates the 2x2 blocks of the matrix
+// and the column pairs of the eigenvectors in one pass.  A rotation is
+// skipped when |a_pq| <= 1e-16 sqrt(|a_pp a_qq|) (the criterion of Demmel and
+// Veselic, which keeps small eigenvalues of a positive semidefinite matrix
+// to high relative accuracy); a sweep that skips all of them ends the
+// iteration.  Rotation angles follow Rutishauser's formulas.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "plan_internal.h"
+
+namespace {
+
+constexpr int kMaxDim = 64;
+constexpr int kLd = 65;          // LDS row stride (doubles)
+constexpr int kThreads = 256;
+constexpr int kMaxSweeps = 40;
+constexpr double kRelTol = 1e-16;
+
+struct JacobiLds {
+  double c[kMaxDim / 2], s[kMaxDim / 2], t[kMaxDim / 2], apq[kMaxDim / 2];
+  int p[kMaxDim / 2], q[kMaxDim / 2];
+  int rotated;
+};
+
+// Diagonalises the symmetric m x m matrix A (m even, LDS, stride kLd) in
+// place, accumulating the rotations into V (LDS, initialised by the caller).
+// Returns the number of sweeps, or -1 without convergence in kMaxSweeps.
+// Every thread of the workgroup calls it.
+__device__ int jacobi(double* A, double* V, int m, JacobiLds& J) {
+  const int tid = threadIdx.x;
+  const int half = m / 2;
+  if (m < 2) return 0;
+  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+    if (tid == 0) J.rotated = 0;
+    __syncthreads();
+    for (int r = 0; r < m - 1; ++r) {
+      if (tid < half) {
+        int p, q;
+        if (tid == 0) {
+          p = r;
+          q = m - 1;
+        } else {
+          p = (r + tid) % (m - 1);
+          q = (r - tid + (m - 1)) % (m - 1);
+          if (p > q) {
+            const int x = p;
+            p = q;
+            q = x;
+          }
+        }
+        const double app = A[p * kLd + p], aqq = A[q * kLd + q], apq = A[p * kLd + q];
+        double c = 1.0, s = 0.0, t = 0.0;
+        if (apq != 0.0 && fabs(apq) > kRelTol * sqrt(fabs(app) * fabs(aqq))) {
+          const double theta = (aqq - app) / (2.0 * apq);
+          t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+          c = 1.0 / sqrt(t * t + 1.0);
+          s = t * c;
+          J.rotated = 1;
+        }
+        J.p[tid] = p;
+        J.q[tid] = q;
+        J.c[tid] = c;
+        J.s[tid] = s;
+        J.t[tid] = t;
+        J.apq[tid] = apq;
+      }
+      __syncthreads();
+      // A <- J^T A J on every 2x2 block (rows of rotation k, columns of rotation l)
+      for (int b = tid; b < half * half; b += kThreads) {
+        const int k = b / half, l = b - k * half;
+        const int pk = J.p[k], qk = J.q[k], pl = J.p[l], ql = J.q[l];
+        if (k == l) {
+          const double d = J.t[k] * J.apq[k];
+          A[pk * kLd + pk] -= d;
+          A[qk * kLd + qk] += d;
+          A[pk * kLd + qk] = 0.0;
+          A[qk * kLd + pk] = 0.0;
+        } else {
+          const double ck = J.c[k], sk = J.s[k], cl = J.c[l], sl = J.s[l];
+          const double a = A[pk * kLd + pl], bq = A[pk * kLd + ql];
+          const double cq = A[qk * kLd + pl], d = A[qk * kLd + ql];
+          const double a1 = cl * a - sl * bq, b1 = sl * a + cl * bq;
+          const double c1 = cl * cq - sl * d, d1 = sl * cq + cl * d;
+          A[pk * kLd + pl] = ck * a1 - sk * c1;
+          A[qk * kLd + pl] = sk * a1 + ck * c1;
+          A[pk * kLd + ql] = ck * b1 - sk * d1;
+          A[qk * kLd + ql] = sk * b1 + ck * d1;
+        }
+      }
+      // V <- V J (column pairs)
+      for (int e = tid; e < m * half; e += kThreads) {
+        const int row = e / half, l = e - row * half;
+        const int pl = J.p[l], ql = J.q[l];
+        const double cl = J.c[l], sl = J.s[l];
+        const double vp = V[row * kLd + pl], vq = V[row * kLd + ql];
+        V[row * kLd + pl] = cl * vp - sl * vq;
+        V[row * kLd + ql] = sl * vp + cl * vq;
+      }
+      __syncthreads();
+    }
+    const int done = J.rotated == 0;
+    __syncthreads();
+    if (done) return sweep + 1;
+  }
+  return -1;
+}
+
+// rank of value v[r] among v[0..n): descending (or ascending) order, ties by index
+__device__ int rank_of(const double* v, int n, int r, bool descending) {
+  const double x = v[r];
+  int rank = 0;
+  for (int j = 0; j < n; ++j) {
+    const double y = v[j];
+    const bool before = descending ? (y > x) : (y < x);
+    rank += before || (y == x && j < r);
+  }
+  return rank;
+}
+
+__global__ __launch_bounds__(kThreads) void pno_build_kernel(const dlpno_pno_pair* __restrict__ pairs,
+                                                             int64_t n_pairs, const double* __restrict__ X,
+                                                             const double* __restrict__ F, double t_cut,
+                                                             double* __restrict__ occ, double* __restrict__ eps,
+                                                             double* __restrict__ C, int32_t* __restrict__ n_kept,
+                                                             int32_t* __restrict__ sweeps) {
+  __shared__ double A[kMaxDim * kLd];
+  __shared__ double V[kMaxDim * kLd];
+  __shared__ JacobiLds J;
+  __shared__ double lam[kMaxDim], sred[kThreads];
+  __shared__ int order[kMaxDim], ired[kThreads], colsign[kMaxDim];
+  __shared__ int s_n, s_bad;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, lane = tid & 63;
+
+  for (int64_t pi = blockIdx.x; pi < n_pairs; pi += gridDim.x) {
+    const dlpno_pno_pair d = pairs[pi];
+    const int N = d.dim, m = N + (N & 1);
+    if (tid == 0) {
+      s_n = 0;
+      s_bad = 0;
+    }
+
+    // ---- pair density: D = sum_b w_b (X X^T + X^T X) / (2 (1 + delta_ij)) ----
+    double acc[4][4] = {};
+    const int ti = tid >> 4, tj = tid & 15;
+    int64_t xo = d.off_X;
+    for (int b = 0; b < 4; ++b) {
+      if (!(d.blocks & (1 << b))) continue;
+      // same spin 1/2, opposite spin 1; a diagonal pair's missing beta-alpha
+      // block is the transpose of its alpha-beta block and adds the same
+      double wb = b < 2 ? 0.5 : 1.0;
+      if (b == 2 && d.diagonal && !(d.blocks & 8)) wb = 2.0;
+      __syncthreads();
+      for (int e = tid; e < N * N; e += kThreads) {
+        const int r = e / N;
+        V[r * kLd + (e - r * N)] = X[xo + e];
+      }
+      __syncthreads();
+      xo += (int64_t)N * N;
+      if (4 * ti < N && 4 * tj < N) {
+        double blk[4][4] = {};
+        for (int c = 0; c < N; ++c) {
+          double xa[4], xb[4], ya[4], yb[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int a = min(4 * ti + i, N - 1), bb = min(4 * tj + i, N - 1);
+            xa[i] = V[a * kLd + c];
+            xb[i] = V[bb * kLd + c];
+            ya[i] = V[c * kLd + a];
+            yb[i] = V[c * kLd + bb];
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) blk[i][j] += xa[i] * xb[j] + ya[i] * yb[j];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] += wb * blk[i][j];
+      }
+    }
+    __syncthreads();
+    const double dscale = 1.0 / (2.0 * (d.diagonal ? 2.0 : 1.0));
+    for (int e = tid; e < kMaxDim * kMaxDim; e += kThreads) {
+      const int r = e >> 6, c = e & 63;
+      if (r < m && c < m) A[r * kLd + c] = 0.0;
+      if (r < m && c < m) V[r * kLd + c] = r == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    bool bad = false;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int a = 4 * ti + i, bb = 4 * tj + j;
+        if (a < N && bb < N) {
+          const double v = acc[i][j] * dscale;
+          bad |= !isfinite(v);
+          A[a * kLd + bb] = v;
+        }
+      }
+    if (bad) s_bad = 1;
+    __syncthreads();
+    int status = 0;
+    int sw1 = 0, sw2 = 0;
+    if (s_bad) status = -3;
+    if (status == 0) {
+      sw1 = jacobi(A, V, m, J);
+      if (sw1 < 0) status = -1;
+    }
+
+    // ---- occupations in descending order, truncation ----
+    if (tid < N) lam[tid] = A[tid * kLd + tid];
+    __syncthreads();
+    if (tid < N) {
+      const int rk = rank_of(lam, N, tid, true);
+      order[rk] = tid;
+      occ[d.off_v + rk] = status == 0 ? lam[tid] : 0.0;
+      if (lam[tid] >= t_cut) atomicAdd(&s_n, 1);
+    }
+    __syncthreads();
+    const int n = status == 0 ? s_n : 0;
+    const int64_t co = d.off_C;
+
+    if (n > 0) {
+      // W = F V_k (N x n) in registers, F staged in A
+      for (int e = tid; e < N * N; e += kThreads) {
+        const int r = e / N;
+        A[r * kLd + (e - r * N)] = F[d.off_F + e];
+      }
+      __syncthreads();
+      double acc16[16];
+      const int ok = lane < n ? order[lane] : 0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc16[i] = 0.0;
+      for (int b = 0; b < N; ++b) {
+        const double v = V[b * kLd + ok];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc16[i] += A[min(w + 4 * i, N - 1) * kLd + b] * v;
+      }
+      // the kept natural orbitals go to C until the second eigenproblem is done
+      for (int e = tid; e < N * n; e += kThreads) {
+        const int r = e / n, k = e - r * n;
+        C[co + (int64_t)r * N + k] = V[r * kLd + order[k]];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (w + 4 * i < N && lane < n) A[(w + 4 * i) * kLd + lane] = acc16[i];
+      __syncthreads();
+      // F_PNO = V_k^T W (n x n)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc16[i] = 0.0;
+      for (int a = 0; a < N; ++a) {
+        const double wv = A[a * kLd + lane];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc16[i] += V[a * kLd + order[min(w + 4 * i, n - 1)]] * wv;
+      }
+      __syncthreads();
+      const int m2 = n + (n & 1);
+      for (int e = tid; e < kMaxDim * kMaxDim; e += kThreads) {
+        const int r = e >> 6, c = e & 63;
+        if (r < m2 && c < m2) {
+          A[r * kLd + c] = 0.0;
+          V[r * kLd + c] = r == c ? 1.0 : 0.0;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (w + 4 * i < n && lane < n) A[(w + 4 * i) * kLd + lane] = acc16[i];
+      __syncthreads();
+      sw2 = jacobi(A, V, m2, J);
+      if (sw2 < 0) status = -2;
+
+      // orbital energies in ascending order
+      if (tid < n) lam[tid] = A[tid * kLd + tid];
+      __syncthreads();
+      if (tid < n) {
+        const int rk = rank_of(lam, n, tid, false);
+        order[rk] = tid;
+        eps[d.off_v + rk] = lam[tid];
+      }
+      __syncthreads();
+      // C = V_k U (columns in ascending energy), V_k back from C into A
+      for (int e = tid; e < N * n; e += kThreads) {
+        const int r = e / n, k = e - r * n;
+        A[r * kLd + k] = C[co + (int64_t)r * N + k];
+      }
+      __syncthreads();
+      const int uk = order[lane < n ? lane : 0];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc16[i] = 0.0;
+      for (int j = 0; j < n; ++j) {
+        const double u = V[j * kLd + uk];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc16[i] += A[min(w + 4 * i, N - 1) * kLd + j] * u;
+      }
+      // sign convention: the largest-magnitude element of each column is
+      // positive (the first such row on ties)
+      double best = -1.0;
+      int bi = 0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int r = w + 4 * i;
+        if (r < N && fabs(acc16[i]) > best) {
+          best = fabs(acc16[i]);
+          bi = r;
+        }
+      }
+      sred[tid] = best;
+      ired[tid] = bi;
+      __syncthreads();
+      if (w == 0) {
+        double bv = sred[lane];
+        int br = ired[lane];
+        for (int x = 1; x < 4; ++x) {
+          const double v = sred[x * 64 + lane];
+          const int rr = ired[x * 64 + lane];
+          if (v > bv || (v == bv && rr < br)) {
+            bv = v;
+            br = rr;
+          }
+        }
+        ired[lane] = br;
+      }
+      __syncthreads();
+      const int srow = ired[lane];
+      const int owner = srow & 3, slot = srow >> 2;
+      if (w == owner) {
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (i == slot) v = acc16[i];
+        colsign[lane] = v < 0.0 ? -1 : 1;
+      }
+      __syncthreads();
+      const double sg = colsign[lane] < 0 ? -1.0 : 1.0;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int r = w + 4 * i;
+        if (r < N && lane < n) C[co + (int64_t)r * N + lane] = sg * acc16[i];
+      }
+    }
+    // columns past n, energies past n
+    for (int e = tid; e < N * N; e += kThreads) {
+      const int r = e / N, k = e - r * N;
+      if (k >= n) C[co + (int64_t)r * N + k] = 0.0;
+    }
+    if (tid < N && tid >= n) eps[d.off_v + tid] = 0.0;
+    if (tid == 0) {
+      n_kept[pi] = status == 0 ? n : status;
+      if (sweeps) {
+        sweeps[2 * pi] = sw1;
+        sweeps[2 * pi + 1] = sw2;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+struct dlpno_pno_plan {
+  int64_t n_pairs = 0;
+  dlpno_pno_pair* d_pairs = nullptr;
+  int device = 0;
+};
+
+using dlpno::fail;
+
+extern "C" dlpno_status dlpno_pno_plan_create(const dlpno_pno_pair* pairs, int64_t n_pairs, int64_t n_X,
+                                              int64_t n_F, int64_t n_C, int64_t n_v, dlpno_pno_plan** out) {
+  if (!out) return fail(DLPNO_ERR_INVALID_ARG, "pno_plan_create: out is NULL");
+  *out = nullptr;
+  if (n_pairs < 0 || (n_pairs > 0 && !pairs)) return fail(DLPNO_ERR_INVALID_ARG, "pno_plan_create: pairs");
+  for (int64_t p = 0; p < n_pairs; ++p) {
+    const dlpno_pno_pair& d = pairs[p];
+    const std::string at = "pno pair " + std::to_string(p) + ": ";
+    if (d.dim < 1 || d.dim > kMaxDim) return fail(DLPNO_ERR_DIM_RANGE, at + "dim outside 1..64");
+    if (d.blocks & ~15) return fail(DLPNO_ERR_INVALID_ARG, at + "block mask");
+    if (d.diagonal != 0 && d.diagonal != 1) return fail(DLPNO_ERR_INVALID_ARG, at + "diagonal flag");
+    if (d.reserved != 0) return fail(DLPNO_ERR_INVALID_ARG, at + "reserved field");
+    const int64_t n2 = (int64_t)d.dim * d.dim;
+    const int64_t nb = __builtin_popcount((unsigned)d.blocks);
+    if (d.off_X < 0 || (nb > 0 && d.off_X + nb * n2 > n_X)) return fail(DLPNO_ERR_ALIGNMENT, at + "X range");
+    if (d.off_F < 0 || d.off_F + n2 > n_F) return fail(DLPNO_ERR_ALIGNMENT, at + "F range");
+    if (d.off_C < 0 || d.off_C + n2 > n_C) return fail(DLPNO_ERR_ALIGNMENT, at + "C range");
+    if (d.off_v < 0 || d.off_v + d.dim > n_v) return fail(DLPNO_ERR_ALIGNMENT, at + "occupation range");
+  }
+  auto* P = new (std::nothrow) dlpno_pno_plan;
+  if (!P) return fail(DLPNO_ERR_OOM, "pno_plan_create: host allocation");
+  P->n_pairs = n_pairs;
+  if (hipGetDevice(&P->device) != hipSuccess) {
+    delete P;
+    return fail(DLPNO_ERR_HIP, "pno_plan_create: hipGetDevice");
+  }
+  if (n_pairs > 0) {
+    if (hipMalloc(&P->d_pairs, n_pairs * sizeof(dlpno_pno_pair)) != hipSuccess) {
+      delete P;
+      return fail(DLPNO_ERR_OOM, "pno_plan_create: device descriptors");
+    }
+    if (hipMemcpy(P->d_pairs, pairs, n_pairs * sizeof(dlpno_pno_pair), hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(P->d_pairs);
+      delete P;
+      return fail(DLPNO_ERR_HIP, "pno_plan_create: descriptor upload");
+    }
+  }
+  *out = P;
+  return DLPNO_OK;
+}
+
+extern "C" dlpno_status dlpno_pno_build(dlpno_pno_plan* plan, const double* X, const double* F, double t_cut,
+                                        double* occ, double* eps, double* C, int32_t* n_kept, int32_t* sweeps,
+                                        void* stream) {
+  if (!plan) return fail(DLPNO_ERR_INVALID_ARG, "pno_build: plan is NULL");
+  if (plan->n_pairs == 0) return DLPNO_OK;
+  if (!F || !occ || !eps || !C || !n_kept) return fail(DLPNO_ERR_INVALID_ARG, "pno_build: NULL buffer");
+  if (!std::isfinite(t_cut)) return fail(DLPNO_ERR_INVALID_ARG, "pno_build: t_cut not finite");
+  const int64_t grid = plan->n_pairs < (1 << 20) ? plan->n_pairs : (1 << 20);
+  hipLaunchKernelGGL(pno_build_kernel, dim3((unsigned)grid), dim3(kThreads), 0, (hipStream_t)stream,
+                     plan->d_pairs, plan->n_pairs, X, F, t_cut, occ, eps, C, n_kept, sweeps);
+  if (hipGetLastError() != hipSuccess) return fail(DLPNO_ERR_HIP, "pno_build: launch");
+  return DLPNO_OK;
+}
+
+extern "C" dlpno_status dlpno_pno_plan_destroy(dlpno_pno_plan* plan) {
+  if (!plan) return DLPNO_OK;
+  if (plan->d_pairs) (void)hipFree(plan->d_pairs);
+  delete plan;
+  return DLPNO_OK;
+}

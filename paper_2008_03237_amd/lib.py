@@ -92,6 +92,9 @@ def lib():
         "dlpno_autotune_cached": [vp, vp, vp, C.c_char_p, C.POINTER(C.c_int32), vp],
         "dlpno_set_profiling": [vp, i32],
         "dlpno_phase_times": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), i32],
+        "dlpno_pno_plan_create": [vp, i64, i64, i64, i64, i64, C.POINTER(vp)],
+        "dlpno_pno_build": [vp, vp, vp, C.c_double, vp, vp, vp, vp, vp, vp],
+        "dlpno_pno_plan_destroy": [vp],
     }
     for name, args in sig.items():
         # a library built from older sources lacks newer entry points: only
@@ -330,3 +333,47 @@ class Plan:
 
     def info(self):
         return lib().dlpno_plan_info(self._h).decode()
+
+
+class PnoPlan:
+    """PNO construction over device-resident inputs (dlpno_pno_*).
+
+    pairs: numpy array of workload.pno.PNO_PAIR_DTYPE (the dlpno_pno_pair
+    layout); n_X, n_F, n_C, n_v: buffer sizes in doubles."""
+
+    def __init__(self, pairs, n_X, n_F, n_C, n_v):
+        pairs = np.ascontiguousarray(pairs)
+        if pairs.dtype.itemsize != 48:
+            raise ValueError("pairs must use the 48-byte dlpno_pno_pair layout")
+        self.n_pairs, self.n_C, self.n_v = len(pairs), int(n_C), int(n_v)
+        self._pairs = pairs
+        self._h = C.c_void_p()
+        _check(lib().dlpno_pno_plan_create(pairs.ctypes.data_as(C.c_void_p), self.n_pairs, int(n_X), int(n_F),
+                                           self.n_C, self.n_v, C.byref(self._h)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            lib().dlpno_pno_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build(self, X, F, t_cut, occ=None, eps=None, Cout=None, n_kept=None, sweeps=None, want_sweeps=False):
+        """Returns (occ, eps, C, n_kept, sweeps) as device tensors (sweeps is
+        None unless requested)."""
+        import torch
+        dev = F.device
+        f64 = dict(dtype=torch.float64, device=dev)
+        occ = torch.empty(max(self.n_v, 1), **f64) if occ is None else occ
+        eps = torch.empty(max(self.n_v, 1), **f64) if eps is None else eps
+        Cout = torch.empty(max(self.n_C, 1), **f64) if Cout is None else Cout
+        n_kept = torch.empty(max(self.n_pairs, 1), dtype=torch.int32, device=dev) if n_kept is None else n_kept
+        if sweeps is None and want_sweeps:
+            sweeps = torch.empty(max(2 * self.n_pairs, 1), dtype=torch.int32, device=dev)
+        _check(lib().dlpno_pno_build(self._h, _ptr(X), _ptr(F), float(t_cut), _ptr(occ), _ptr(eps), _ptr(Cout),
+                                     _ptr(n_kept), _ptr(sweeps), _stream()))
+        return occ, eps, Cout, n_kept, sweeps

@@ -105,3 +105,22 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
                        timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_pno_plan_validation_on_host():
+    """dlpno_pno_plan_create rejects bad descriptors before touching the GPU."""
+    import ctypes as C
+    from paper_2008_03237_amd.lib import lib
+    from workload.pno import build_pno_problem, PNO_PAIR_DTYPE
+    prob = build_pno_problem("tiny")
+    L = lib()
+    for field, value, code in (("dim", 0, -2), ("dim", 65, -2), ("blocks", 16, -1), ("reserved", 1, -1),
+                               ("off_C", prob.n_C, -3), ("diagonal", 2, -1)):
+        bad = prob.pairs.copy()
+        bad[3][field] = value
+        h = C.c_void_p()
+        st = L.dlpno_pno_plan_create(bad.ctypes.data_as(C.c_void_p), len(bad), prob.n_X, prob.n_F, prob.n_C,
+                                     prob.n_v, C.byref(h))
+        assert st == code, (field, st)
+        assert h.value is None
+    assert PNO_PAIR_DTYPE.itemsize == 48

@@ -50,6 +50,12 @@ __device__ __forceinline__ double normal(uint64_t idx, uint64_t stream, uint32_t
   return x * 0x1.bb67ae8584caap+0;   // sqrt(3) rounded to double
 }
 
+__device__ __forceinline__ double uniform(uint64_t idx, uint64_t stream, uint32_t field, uint64_t seed) {
+  uint32_t c0 = (uint32_t)idx, c1 = (uint32_t)(idx >> 32), c2 = (uint32_t)stream, c3 = field;
+  philox(c0, c1, c2, c3, (uint32_t)seed, kSalt ^ (uint32_t)(seed >> 32));
+  return (double)c0 * 0x1p-32;
+}
+
 __global__ __launch_bounds__(256) void gen_kernel(const Seg* segs, int64_t nseg, uint64_t seed, double* out) {
   for (int64_t si = blockIdx.x; si < nseg; si += gridDim.x) {
     const Seg sg = segs[si];
@@ -65,6 +71,18 @@ __global__ __launch_bounds__(256) void gen_kernel(const Seg* segs, int64_t nseg,
         case 0: v = normal(lay + (uint64_t)x * 64u + y, sg.stream, sg.field, seed) * sg.scale; break;
         case 3: v = normal(lay + (uint64_t)y * 64u + x, sg.stream, sg.field, seed) * sg.scale; break;
         case 4: v = x == y ? 1.0 : 0.0; break;   // identity block
+        case 5: {   // staircase decay 2^-floor((x + y) / pad)
+          const double z = normal(lay + (uint64_t)x * 64u + y, sg.stream, sg.field, seed);
+          v = z * ldexp(1.0, -((x + y) / sg.pad)) * sg.scale;
+          break;
+        }
+        case 6: {   // symmetric Fock-like block: 0.2 + 2.8 u on the diagonal
+          const int lo = x < y ? x : y, hi = x < y ? y : x;
+          const uint64_t idx = lay + (uint64_t)lo * 64u + hi;
+          v = x == y ? 0.2 + 2.8 * uniform(idx, sg.stream, sg.field, seed)
+                     : normal(idx, sg.stream, sg.field, seed) * sg.scale;
+          break;
+        }
         case 1: {
           const int lo = x < y ? x : y, hi = x < y ? y : x;
           v = normal(lay + (uint64_t)lo * 64u + hi, sg.stream, sg.field, seed) * sg.scale;

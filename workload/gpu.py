@@ -58,3 +58,14 @@ def device_fields(prob, device="cuda", fields=("B", "S", "K", "T"), dtype=None):
             fill(t, prob.segs[f], prob.seed)
         out[f] = t
     return out
+
+
+def device_pno_fields(prob, device="cuda"):
+    """X and F of a PNO workload (workload.pno) generated on the GPU."""
+    import torch
+    out = {}
+    for f, n in (("X", prob.n_X), ("F", prob.n_F)):
+        t = torch.zeros(max(n, 1), dtype=torch.float64, device=device)
+        fill(t, prob.segs[f], prob.seed)
+        out[f] = t
+    return out

@@ -36,13 +36,15 @@ BLOCK_SPINS = {"AA": (0, 0), "BB": (1, 1), "AB": (0, 1), "BA": (1, 0)}
 
 # Philox field ids (fourth counter word)
 F_NPNO, F_NAUX, F_B, F_T, F_K, F_EPS, F_FDIAG, F_FOFF, F_S, F_QR, F_W, F_F12, F_FOFFB, F_HH = range(1, 15)
+# PNO-construction inputs (workload.pno)
+F_DOM, F_TAU, F_PX, F_PF = range(15, 19)
 
 # F12 inputs (synthetic): W = V + C per stored block, in the amplitude layout,
 # and six scalars per block (V, V', B1..B4, see Problem.f12_scalars)
 SIGMA_W = 0.05
 
 # segment generation modes (see segment_values)
-MODE_PLAIN, MODE_SYM, MODE_ANTI, MODE_TRANS, MODE_EYE = 0, 1, 2, 3, 4
+MODE_PLAIN, MODE_SYM, MODE_ANTI, MODE_TRANS, MODE_EYE, MODE_DECAY, MODE_FOCK = 0, 1, 2, 3, 4, 5, 6
 
 SEG_DTYPE = np.dtype([("off", np.int64), ("stream", np.int64), ("field", np.int32),
                       ("mode", np.int32), ("layers", np.int32), ("rows", np.int32),
@@ -206,6 +208,20 @@ def segment_values(seed, seg):
         idx = lay + y * np.uint64(64) + x
     elif mode == MODE_SYM:
         idx = lay + np.minimum(x, y) * np.uint64(64) + np.maximum(x, y)
+    elif mode == MODE_DECAY:
+        # plain normals times 2^-floor((x + y) / pad): a staircase decay of
+        # exact powers of two (bit-identical on both generators)
+        z = philox.normals(seed, fld, stream, lay + x * np.uint64(64) + y)
+        tau = int(seg["pad"])
+        e = -((x.astype(np.int64) + y.astype(np.int64)) // tau)
+        return z * np.ldexp(1.0, e) * scale
+    elif mode == MODE_FOCK:
+        # symmetric normals times scale off the diagonal, 0.2 + 2.8 u on it
+        # (u: the first Philox word of the diagonal element's counter / 2^32)
+        idx = lay + np.minimum(x, y) * np.uint64(64) + np.maximum(x, y)
+        z = philox.normals(seed, fld, stream, idx) * scale
+        u = philox.uniforms(seed, fld, stream, idx)
+        return np.where(x == y, 0.2 + 2.8 * u, z) + np.zeros((L, 1, 1))
     elif mode == MODE_EYE:
         # identity blocks (the overlap of a pair's PNOs with themselves)
         return np.broadcast_to((x == y).astype(np.float64), (L, R, C)).copy()
