@@ -116,6 +116,7 @@ def main():
     ap.add_argument("--mixed-inner", type=int, default=4, help="low-precision iterations per refinement step")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-path leg")
     ap.add_argument("--no-hole", action="store_true", help="skip the hole-hole ladder leg")
+    ap.add_argument("--no-pno", action="store_true", help="skip the PNO-construction leg")
     ap.add_argument("--hole-scale", type=float, default=0.02,
                     help="scale of the synthetic occupied integrals of the hole-hole ladder leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -206,14 +207,18 @@ def main():
     proj_ms = proj1_ms + proj2_ms
     achieved = fl_ladder / (kern_ms / 1e3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
-    traffic = None
+    # counter record of the ladder launches (rocprofv3, profiles/): HBM bytes
+    # and issued MFMA flops per residual, used only while it describes this
+    # kernel source and schedule
+    traffic, issued = None, None
     schedule = schedule_line(plan)
-    tfile = os.path.join(ROOT, "profiles", "grouped_%s_%s_traffic.json" % (args.workload, args.precision))
-    if os.path.exists(tfile):
-        with open(tfile) as f:
+    cfile = os.path.join(ROOT, "profiles", "grouped_%s_%s_counters.json" % (args.workload, args.precision))
+    if os.path.exists(cfile):
+        with open(cfile) as f:
             tr = json.load(f)
         if tr.get("kernel_source_sha") == kernel_source_sha() and tr.get("schedule") == schedule:
             traffic = tr.get("bytes_per_residual")
+            issued = tr.get("issued_flops_per_residual")
 
     out = {
         "metric": "pair-residual GFLOP/s (ladder + projection, algorithmic) per CCSD iteration",
@@ -235,6 +240,8 @@ def main():
                    "S_GB": round(prob.n_S * 8 / 1e9, 2), "hipgraph": True, "autotuned": not args.no_autotune},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": traffic,
+                     "frac_issued": round(issued / (kern_ms / 1e3) / 1e12 / peak, 4) if issued else None,
+                     "issued_flops_per_residual": issued,
                      "kernel": "grouped_kernel<%s, ladder items>" % ("double" if args.precision == "fp64" else "float"),
                      "kernel_ms": round(kern_ms, 3), "residuals": int(max(cnt[0], cnt[6], cnt[7])),
                      "launch_ms": {"two_waves_per_simd": round(lad2_ms, 3), "cooperative": round(lad4_ms, 3),
@@ -263,6 +270,8 @@ def main():
             out["fp32"] = fp32_leg(prob, dev, eps_a, eps_b, args, fl_ladder, fl_proj, ref, log)
     if not args.no_hole and args.precision == "fp64":
         out["hole_ladder"] = hole_leg(args, dev, eps_a, eps_b, fl_proj, log)
+    if not args.no_pno:
+        out["pno"] = pno_leg(args, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, n_pairs=args.cpu_pairs)
     plan.close()
@@ -320,11 +329,65 @@ def profile_residuals(prob, dev, eps_a, eps_b, args, log):
         ms, cnt = plan.phase_times()
         plan.set_profiling(False)
         out["launch_ms"][prec] = {names[k]: round(ms[k] / cnt[k], 3) for k in range(len(names)) if cnt[k] > 0}
+        out.setdefault("schedule", {})[prec] = schedule_line(plan)
         fl, fp = plan.flop_count()
         out.setdefault("flops_per_residual", {"ladder": fl, "projection": fp})
         plan.close()
         del R
     return out
+
+
+# LDS bandwidth of the chip: 256 CUs x 128 bytes per clock x 2.4 GHz
+LDS_PEAK_TBPS = 256 * 128 * 2.4e9 / 1e12
+
+
+def pno_leg(args, log):
+    """PNO construction for every pair of the workload's pair list (domains
+    of 40..64 functions, T_CutPNO = 1e-7): HIP-event time of dlpno_pno_build
+    (one launch).  Its bound is the LDS traffic of the Jacobi rotations: per
+    round of a sweep over an m x m matrix (m = N rounded up to even), the
+    matrix and the eigenvector matrix are each read and written once,
+    4 m^2 doubles; rounds = sweeps x (m - 1), from the launch's own sweep
+    counts, for the density and the PNO Fock matrix (m = n_p rounded up)."""
+    import numpy as np
+    import torch
+
+    from paper_2008_03237_amd import PnoPlan
+    from workload.gpu import device_pno_fields
+    from workload.pno import build_pno_problem
+    prob = build_pno_problem(args.workload)
+    dev = device_pno_fields(prob)
+    plan = PnoPlan(prob.pairs, prob.n_X, prob.n_F, prob.n_C, prob.n_v)
+    out = plan.build(dev["X"], dev["F"], prob.t_cut, want_sweeps=True)
+    torch.cuda.synchronize()
+    reps = 5
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        plan.build(dev["X"], dev["F"], prob.t_cut, *out[:4], sweeps=out[4])
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    nk = out[3].cpu().numpy().astype(np.int64)
+    sw = out[4].cpu().numpy().reshape(-1, 2).astype(np.int64)
+    if np.any(nk < 0):
+        raise RuntimeError("PNO construction failed for %d pairs" % int((nk < 0).sum()))
+    m1 = prob.pairs["dim"].astype(np.int64)
+    m1 += m1 & 1
+    m2 = nk + (nk & 1)
+    lds_bytes = int((32 * m1 * m1 * sw[:, 0] * np.maximum(m1 - 1, 0)).sum()
+                    + (32 * m2 * m2 * sw[:, 1] * np.maximum(m2 - 1, 0)).sum())
+    ach = lds_bytes / (ms / 1e3) / 1e12
+    plan.close()
+    del dev
+    log("PNO construction: %d pairs in %.3f ms, %.1f PNOs kept per pair" % (prob.n_pairs, ms, nk.mean()))
+    return {"kernel": "pno_build_kernel", "workload": "%s pair list, domains %d..%d, T_CutPNO %.0e"
+            % (args.workload, int(prob.pairs["dim"].min()), int(prob.pairs["dim"].max()), prob.t_cut),
+            "pairs": prob.n_pairs, "ms": round(ms, 3), "pairs_per_s": round(prob.n_pairs / (ms / 1e3), 1),
+            "kept_mean": round(float(nk.mean()), 2),
+            "sweeps_mean": [round(float(sw[:, 0].mean()), 2), round(float(sw[nk > 0, 1].mean()), 2)],
+            "roofline": {"bound": "lds", "achieved": round(ach, 3), "peak": round(LDS_PEAK_TBPS, 2), "unit": "TB/s",
+                         "frac": round(ach / LDS_PEAK_TBPS, 4), "lds_bytes": lds_bytes}}
 
 
 def hole_leg(args, dev, eps_a, eps_b, fl_proj_base, log):
