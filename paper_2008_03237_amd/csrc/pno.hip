@@ -8,8 +8,9 @@
 // two workgroups per CU).  Both eigenproblems use the parallel cyclic Jacobi
 // method: a sweep is N-1 rounds of N/2 disjoint rotations in round-robin
 // order (Brent and Luk's ordering; a zero dummy index pads an odd N), each
-// round computes its rotations, then updates the 2x2 blocks of the matrix
-// and the column pairs of the eigenvectors in one pass.  A rotation is
+// round computes its rotations, then updates the 2x2 blocks of the matrix;
+// the eigenvector columns take the round's rotations while the next
+// round's rotations are computed.  A rotation is
 // skipped when |a_pq| <= 1e-16 sqrt(|a_pp a_qq|) (the criterion of Demmel and
 // Veselic, which keeps small eigenvalues of a positive semidefinite matrix
 // to high relative accuracy); a sweep that skips all of them ends the
@@ -34,90 +35,191 @@ constexpr double kRelTol = 1e-16;
 struct JacobiLds {
   double c[kMaxDim / 2], s[kMaxDim / 2], t[kMaxDim / 2], apq[kMaxDim / 2];
   int p[kMaxDim / 2], q[kMaxDim / 2];
-  int rotated;
+  int rotated;   // some rotation of the round is applied
 };
 
-// Diagonalises the symmetric m x m matrix A (m even, LDS, stride kLd) in
-// place, accumulating the rotations into V (LDS, initialised by the caller).
-// Returns the number of sweeps, or -1 without convergence in kMaxSweeps.
-// Every thread of the workgroup calls it.
-__device__ int jacobi(double* A, double* V, int m, JacobiLds& J) {
+// Work of a round, listed once per eigenproblem in registers (no division
+// in the rounds): the 2x2 blocks (k, l), k <= l, of A over all 256 threads
+// (at most 528 blocks: 3 per thread); the column pairs (row, l) of V over
+// the 192 threads of waves 1..3 (at most 2048: 11 per thread).  A is kept
+// in its upper triangle only: element {x, y} lives at [min][max].
+constexpr int kBlkPerThread = 3;
+constexpr int kColPerThread = 11;
+static_assert(kBlkPerThread * kThreads >= (kMaxDim / 2) * (kMaxDim / 2 + 1) / 2, "block list");
+static_assert(kColPerThread * (kThreads - 64) >= kMaxDim * (kMaxDim / 2), "column list");
+
+__device__ __forceinline__ int upper(int x, int y) { return x < y ? x * kLd + y : y * kLd + x; }
+
+// V <- V J for the rotations in Jr (waves 1..3; vt: this thread's column pairs)
+__device__ __forceinline__ void rotate_columns(double* V, const int* vt, const JacobiLds& Jr) {
+  double nw[kColPerThread][2];
+  int iv[kColPerThread][2];
+#pragma unroll
+  for (int i = 0; i < kColPerThread; ++i) {
+    if (vt[i] >= 0) {
+      const int row = vt[i] >> 8, l = vt[i] & 255;
+      const double sl = Jr.s[l], cl = Jr.c[l];
+      iv[i][0] = row * kLd + Jr.p[l];
+      iv[i][1] = row * kLd + Jr.q[l];
+      const double vp = V[iv[i][0]], vq = V[iv[i][1]];
+      nw[i][0] = cl * vp - sl * vq;
+      nw[i][1] = sl * vp + cl * vq;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kColPerThread; ++i)
+    if (vt[i] >= 0) {
+      V[iv[i][0]] = nw[i][0];
+      V[iv[i][1]] = nw[i][1];
+    }
+}
+
+// Diagonalises the symmetric m x m matrix A (m even, LDS, stride kLd, both
+// triangles on entry; on exit the diagonal holds the eigenvalues and only the
+// upper triangle is meaningful) in place, accumulating the rotations into V
+// (LDS, initialised by the caller).  Returns the number of sweeps, or -1
+// without convergence in kMaxSweeps.  Every thread of the workgroup calls it.
+//
+// A round: wave 0 computes the round's rotations while waves 1..3 apply the
+// previous round's rotations to V (the rotation parameters are double
+// buffered), barrier, all threads update A, barrier.  A round whose
+// rotations are all skipped leaves A and V alone.  Each thread loads all its
+// elements before it stores any, so that their LDS latencies overlap.
+__device__ int jacobi(double* A, double* V, int m, JacobiLds* J2) {
   const int tid = threadIdx.x;
   const int half = m / 2;
   if (m < 2) return 0;
-  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-    if (tid == 0) J.rotated = 0;
-    __syncthreads();
-    for (int r = 0; r < m - 1; ++r) {
-      if (tid < half) {
-        int p, q;
-        if (tid == 0) {
-          p = r;
-          q = m - 1;
-        } else {
-          p = (r + tid) % (m - 1);
-          q = (r - tid + (m - 1)) % (m - 1);
-          if (p > q) {
-            const int x = p;
-            p = q;
-            q = x;
+  // this thread's blocks (k << 8 | l) and column pairs (row << 8 | l), -1 = none
+  int bt[kBlkPerThread], vt[kColPerThread];
+  {
+    const int nblk = half * (half + 1) / 2;
+#pragma unroll
+    for (int i = 0; i < kBlkPerThread; ++i) {
+      int b = tid + i * kThreads;
+      bt[i] = -1;
+      if (b < nblk) {
+        int k = 0;
+        while (b >= half - k) {   // row k holds blocks l = k .. half-1
+          b -= half - k;
+          ++k;
+        }
+        bt[i] = k << 8 | (k + b);
+      }
+    }
+    const int u = tid - 64;
+#pragma unroll
+    for (int i = 0; i < kColPerThread; ++i) {
+      const int e = u + i * (kThreads - 64);
+      vt[i] = (u >= 0 && e < m * half) ? ((e / half) << 8 | (e % half)) : -1;
+    }
+  }
+  if (tid == 0) J2[0].rotated = J2[1].rotated = 0;
+  __syncthreads();
+  int gr = 0;              // rounds so far, across sweeps (selects the buffer)
+  bool pending = false;    // V still owes the rotations of the previous round
+  int result = -1;
+  for (int sweep = 0; sweep < kMaxSweeps && result < 0; ++sweep) {
+    bool sweep_rot = false;
+    for (int r = 0; r < m - 1; ++r, ++gr) {
+      JacobiLds& J = J2[gr & 1];
+      if (tid < 64) {
+        if (tid < half) {
+          int p, q;
+          if (tid == 0) {
+            p = r;
+            q = m - 1;
+          } else {
+            p = r + tid;
+            if (p >= m - 1) p -= m - 1;
+            q = r - tid;
+            if (q < 0) q += m - 1;
+            if (p > q) {
+              const int x = p;
+              p = q;
+              q = x;
+            }
           }
+          const double app = A[p * kLd + p], aqq = A[q * kLd + q], apq = A[p * kLd + q];
+          double c = 1.0, s = 0.0, t = 0.0;
+          if (apq != 0.0 && fabs(apq) > kRelTol * sqrt(fabs(app) * fabs(aqq))) {
+            const double theta = (aqq - app) / (2.0 * apq);
+            t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+            J.rotated = 1;
+          }
+          J.p[tid] = p;
+          J.q[tid] = q;
+          J.c[tid] = c;
+          J.s[tid] = s;
+          J.t[tid] = t;
+          J.apq[tid] = apq;
         }
-        const double app = A[p * kLd + p], aqq = A[q * kLd + q], apq = A[p * kLd + q];
-        double c = 1.0, s = 0.0, t = 0.0;
-        if (apq != 0.0 && fabs(apq) > kRelTol * sqrt(fabs(app) * fabs(aqq))) {
-          const double theta = (aqq - app) / (2.0 * apq);
-          t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
-          s = t * c;
-          J.rotated = 1;
-        }
-        J.p[tid] = p;
-        J.q[tid] = q;
-        J.c[tid] = c;
-        J.s[tid] = s;
-        J.t[tid] = t;
-        J.apq[tid] = apq;
+      } else if (pending) {
+        rotate_columns(V, vt, J2[(gr + 1) & 1]);
       }
       __syncthreads();
-      // A <- J^T A J on every 2x2 block (rows of rotation k, columns of rotation l)
-      for (int b = tid; b < half * half; b += kThreads) {
-        const int k = b / half, l = b - k * half;
-        const int pk = J.p[k], qk = J.q[k], pl = J.p[l], ql = J.q[l];
-        if (k == l) {
-          const double d = J.t[k] * J.apq[k];
-          A[pk * kLd + pk] -= d;
-          A[qk * kLd + qk] += d;
-          A[pk * kLd + qk] = 0.0;
-          A[qk * kLd + pk] = 0.0;
-        } else {
-          const double ck = J.c[k], sk = J.s[k], cl = J.c[l], sl = J.s[l];
-          const double a = A[pk * kLd + pl], bq = A[pk * kLd + ql];
-          const double cq = A[qk * kLd + pl], d = A[qk * kLd + ql];
-          const double a1 = cl * a - sl * bq, b1 = sl * a + cl * bq;
-          const double c1 = cl * cq - sl * d, d1 = sl * cq + cl * d;
-          A[pk * kLd + pl] = ck * a1 - sk * c1;
-          A[qk * kLd + pl] = sk * a1 + ck * c1;
-          A[pk * kLd + ql] = ck * b1 - sk * d1;
-          A[qk * kLd + ql] = sk * b1 + ck * d1;
+      const bool any = J.rotated != 0;
+      // the other buffer's flag was read in the previous round; it is set
+      // again only after the barrier that ends this round
+      if (tid == 0) J2[(gr + 1) & 1].rotated = 0;
+      pending = any;
+      if (any) {
+        sweep_rot = true;
+        // A <- J^T A J on the 2x2 blocks (rows of rotation k, columns of rotation l)
+        double nv[kBlkPerThread][4];
+        int ia[kBlkPerThread][4];
+#pragma unroll
+        for (int i = 0; i < kBlkPerThread; ++i) {
+          if (bt[i] >= 0) {
+            const int k = bt[i] >> 8, l = bt[i] & 255;
+            const int pk = J.p[k], qk = J.q[k];
+            if (k == l) {
+              ia[i][0] = pk * kLd + pk;
+              ia[i][1] = pk * kLd + qk;
+              ia[i][3] = qk * kLd + qk;
+              const double dd = J.t[k] * J.apq[k];
+              nv[i][0] = A[ia[i][0]] - dd;
+              nv[i][1] = 0.0;
+              nv[i][3] = A[ia[i][3]] + dd;
+              ia[i][2] = ia[i][1];
+              nv[i][2] = 0.0;
+            } else {
+              const int pl = J.p[l], ql = J.q[l];
+              const double sk = J.s[k], ck = J.c[k], sl = J.s[l], cl = J.c[l];
+              ia[i][0] = upper(pk, pl);
+              ia[i][1] = upper(pk, ql);
+              ia[i][2] = upper(qk, pl);
+              ia[i][3] = upper(qk, ql);
+              const double a = A[ia[i][0]], bq = A[ia[i][1]], cq = A[ia[i][2]], d = A[ia[i][3]];
+              const double a1 = cl * a - sl * bq, b1 = sl * a + cl * bq;
+              const double c1 = cl * cq - sl * d, d1 = sl * cq + cl * d;
+              nv[i][0] = ck * a1 - sk * c1;
+              nv[i][2] = sk * a1 + ck * c1;
+              nv[i][1] = ck * b1 - sk * d1;
+              nv[i][3] = sk * b1 + ck * d1;
+            }
+          }
         }
-      }
-      // V <- V J (column pairs)
-      for (int e = tid; e < m * half; e += kThreads) {
-        const int row = e / half, l = e - row * half;
-        const int pl = J.p[l], ql = J.q[l];
-        const double cl = J.c[l], sl = J.s[l];
-        const double vp = V[row * kLd + pl], vq = V[row * kLd + ql];
-        V[row * kLd + pl] = cl * vp - sl * vq;
-        V[row * kLd + ql] = sl * vp + cl * vq;
+#pragma unroll
+        for (int i = 0; i < kBlkPerThread; ++i)
+          if (bt[i] >= 0) {
+            A[ia[i][0]] = nv[i][0];
+            A[ia[i][1]] = nv[i][1];
+            A[ia[i][2]] = nv[i][2];
+            A[ia[i][3]] = nv[i][3];
+          }
       }
       __syncthreads();
     }
-    const int done = J.rotated == 0;
-    __syncthreads();
-    if (done) return sweep + 1;
+    if (!sweep_rot) result = sweep + 1;
   }
-  return -1;
+  // rotations of the last round still owed to V (only when the sweeps ran out)
+  if (pending) {
+    if (tid >= 64) rotate_columns(V, vt, J2[(gr + 1) & 1]);
+    __syncthreads();
+  }
+  return result;
 }
 
 // rank of value v[r] among v[0..n): descending (or ascending) order, ties by index
@@ -132,7 +234,7 @@ __device__ int rank_of(const double* v, int n, int r, bool descending) {
   return rank;
 }
 
-__global__ __launch_bounds__(kThreads) void pno_build_kernel(const dlpno_pno_pair* __restrict__ pairs,
+__global__ __launch_bounds__(kThreads, 2) void pno_build_kernel(const dlpno_pno_pair* __restrict__ pairs,
                                                              int64_t n_pairs, const double* __restrict__ X,
                                                              const double* __restrict__ F, double t_cut,
                                                              double* __restrict__ occ, double* __restrict__ eps,
@@ -140,7 +242,7 @@ __global__ __launch_bounds__(kThreads) void pno_build_kernel(const dlpno_pno_pai
                                                              int32_t* __restrict__ sweeps) {
   __shared__ double A[kMaxDim * kLd];
   __shared__ double V[kMaxDim * kLd];
-  __shared__ JacobiLds J;
+  __shared__ JacobiLds J[2];
   __shared__ double lam[kMaxDim], sred[kThreads];
   __shared__ int order[kMaxDim], ired[kThreads], colsign[kMaxDim];
   __shared__ int s_n, s_bad;
