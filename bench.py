@@ -378,16 +378,37 @@ def pno_leg(args, log):
     lds_bytes = int((32 * m1 * m1 * sw[:, 0] * np.maximum(m1 - 1, 0)).sum()
                     + (32 * m2 * m2 * sw[:, 1] * np.maximum(m2 - 1, 0)).sum())
     ach = lds_bytes / (ms / 1e3) / 1e12
-    plan.close()
-    del dev
     log("PNO construction: %d pairs in %.3f ms, %.1f PNOs kept per pair" % (prob.n_pairs, ms, nk.mean()))
-    return {"kernel": "pno_build_kernel", "workload": "%s pair list, domains %d..%d, T_CutPNO %.0e"
-            % (args.workload, int(prob.pairs["dim"].min()), int(prob.pairs["dim"].max()), prob.t_cut),
-            "pairs": prob.n_pairs, "ms": round(ms, 3), "pairs_per_s": round(prob.n_pairs / (ms / 1e3), 1),
-            "kept_mean": round(float(nk.mean()), 2),
-            "sweeps_mean": [round(float(sw[:, 0].mean()), 2), round(float(sw[nk > 0, 1].mean()), 2)],
-            "roofline": {"bound": "lds", "achieved": round(ach, 3), "peak": round(LDS_PEAK_TBPS, 2), "unit": "TB/s",
-                         "frac": round(ach / LDS_PEAK_TBPS, 4), "lds_bytes": lds_bytes}}
+    res = {"kernel": "pno_build_kernel", "workload": "%s pair list, domains %d..%d, T_CutPNO %.0e"
+           % (args.workload, int(prob.pairs["dim"].min()), int(prob.pairs["dim"].max()), prob.t_cut),
+           "pairs": prob.n_pairs, "ms": round(ms, 3), "pairs_per_s": round(prob.n_pairs / (ms / 1e3), 1),
+           "kept_mean": round(float(nk.mean()), 2),
+           "sweeps_mean": [round(float(sw[:, 0].mean()), 2), round(float(sw[nk > 0, 1].mean()), 2)],
+           "roofline": {"bound": "lds", "achieved": round(ach, 3), "peak": round(LDS_PEAK_TBPS, 2), "unit": "TB/s",
+                        "frac": round(ach / LDS_PEAK_TBPS, 4), "lds_bytes": lds_bytes}}
+    # the S blocks of the residual's coupling list with these PNO counts; its
+    # algorithmic HBM bytes: every S block written once, every C read once
+    from workload import build_problem
+    rp = build_problem(args.workload, npno=("given", np.maximum(nk, 1)))
+    plan.overlap_prepare(nk, rp.cpl_rowptr, rp.cpl_src, rp.cpl_off_S, rp.n_S)
+    S = plan.overlap(out[2])
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        plan.overlap(out[2], S)
+    b.record()
+    torch.cuda.synchronize()
+    ms_o = a.elapsed_time(b) / reps
+    nbytes = 8 * (rp.n_S + prob.n_C)
+    log("PNO overlaps: %d couplings in %.3f ms" % (int(rp.cpl_rowptr[-1]), ms_o))
+    res["overlap"] = {"kernel": "pno_overlap_kernel", "couplings": int(rp.cpl_rowptr[-1]), "ms": round(ms_o, 3),
+                      "S_GB": round(rp.n_S * 8 / 1e9, 2),
+                      "roofline": {"bound": "hbm", "achieved": round(nbytes / (ms_o / 1e3) / 1e9, 1), "peak": 8000.0,
+                                   "unit": "GB/s", "frac": round(nbytes / (ms_o / 1e3) / 8e12, 4),
+                                   "algorithmic_bytes": nbytes}}
+    plan.close()
+    del dev, S, out
+    return res
 
 
 def hole_leg(args, dev, eps_a, eps_b, fl_proj_base, log):

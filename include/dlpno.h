@@ -352,7 +352,8 @@ typedef struct {
   int32_t dim;       /* N_p, 1..64 */
   int32_t blocks;    /* stored amplitude blocks: bit 0 AA, 1 BB, 2 AB, 3 BA */
   int32_t diagonal;  /* 1 when the pair is (i, i), else 0 */
-  int32_t reserved;  /* 0 */
+  int32_t first;     /* the domain is the window first .. first + dim - 1 of an orthonormal global
+                      * virtual space (used by dlpno_pno_overlap), >= 0 */
   int64_t off_X;     /* first stored block; blocks back to back in the order AA, BB, AB, BA,
                       * each N_p x N_p row-major [a][b] */
   int64_t off_F;     /* N_p x N_p row-major, symmetric */
@@ -378,6 +379,22 @@ dlpno_status dlpno_pno_plan_create(const dlpno_pno_pair* pairs, int64_t n_pairs,
 dlpno_status dlpno_pno_build(dlpno_pno_plan* plan, const double* X, const double* F, double t_cut, double* occ,
                              double* eps, double* C, int32_t* n_kept, int32_t* sweeps, void* stream);
 dlpno_status dlpno_pno_plan_destroy(dlpno_pno_plan* plan);
+
+/* PNO overlaps for a coupling list (the S input of the residual): for every
+ * coupling e of target pair p with source pair q = src[e] (CSR by target,
+ * rowptr[p] .. rowptr[p+1]-1), the n_q x n_p block at off_S[e], element
+ * [c][a] = sum over the global functions x shared by the two domain windows
+ * of C_q[x - first_q][c] C_p[x - first_p][a] (zero when the windows do not
+ * meet).  n_kept: the host copy of the n_kept that dlpno_pno_build returned
+ * (every entry >= 0; a pair's PNO count is max(n_kept, 1), the extra column
+ * of a pair that kept none being zero); rowptr, src, off_S: host arrays,
+ * validated (CSR monotonic, sources in range, blocks inside n_S doubles)
+ * and uploaded by _prepare, which is synchronous and replaces an earlier
+ * list.  dlpno_pno_overlap: C as written by dlpno_pno_build, S (n_S
+ * doubles): device pointers; asynchronous. */
+dlpno_status dlpno_pno_overlap_prepare(dlpno_pno_plan* plan, const int32_t* n_kept, const int64_t* rowptr,
+                                       const int32_t* src, const int64_t* off_S, int64_t n_S);
+dlpno_status dlpno_pno_overlap(dlpno_pno_plan* plan, const double* C, double* S, void* stream);
 
 /* Human-readable summary of the plan (schedule, variants, workspace). */
 const char* dlpno_plan_info(const dlpno_plan* plan);

@@ -18,10 +18,18 @@ T~ = 2T - T^T (these weights are the only ones that do).  The PNOs are the
 eigenvectors with occupation >= T_cut, rotated to diagonalise the domain's
 virtual Fock matrix (semicanonical).
 
+PNO overlaps between pairs: each domain is a contiguous window of an
+orthonormal global virtual space (first function `first`, N functions), so
+the overlap of source PNO c of pair q with target PNO a of pair p is the
+sum, over the global functions the two windows share, of the products of
+their coefficients (the metric between the two domains is the identity on
+the shared functions and zero elsewhere).
+
 Parity status: pinned by the closed-shell reduction of the density, the
 untruncated limit (an orthogonal C with C^T F C = eig(F)), a spectrum fixed
 by construction (truncation count and captured occupation), and the
-eigen-equations themselves.
+eigen-equations themselves; the overlaps by the identity for a pair with
+itself, the transpose rule, disjoint windows and the global embedding.
 """
 import numpy as np
 
@@ -68,3 +76,13 @@ def build_pnos(D, F, t_cut):
     eps, U = np.linalg.eigh(Fp)
     C = sign_convention(Vk @ U)
     return occ, n, C, eps
+
+
+def pno_overlap(C_p, first_p, C_q, first_q):
+    """Overlap block of a coupling (target p, source q): n_q x n_p, element
+    [c][a] = <PNO c of q | PNO a of p>.  C_p: N_p x n_p, C_q: N_q x n_q."""
+    lo = max(first_p, first_q)
+    hi = min(first_p + C_p.shape[0], first_q + C_q.shape[0])
+    if hi <= lo:
+        return np.zeros((C_q.shape[1], C_p.shape[1]))
+    return C_q[lo - first_q:hi - first_q].T @ C_p[lo - first_p:hi - first_p]

@@ -477,13 +477,80 @@ __global__ __launch_bounds__(kThreads, 2) void pno_build_kernel(const dlpno_pno_
   }
 }
 
+// PNO overlaps of a coupling list: one workgroup per target pair p, C_p in
+// LDS; per coupling, the shared rows of C_q in LDS and S[c][a] with lane a
+// and rows c = wave + 4 i (16 per thread).
+__global__ __launch_bounds__(kThreads, 2) void pno_overlap_kernel(
+    const dlpno_pno_pair* __restrict__ pairs, const int32_t* __restrict__ nk, const int64_t* __restrict__ rowptr,
+    const int32_t* __restrict__ src, const int64_t* __restrict__ off_S, int64_t n_pairs,
+    const double* __restrict__ C, double* __restrict__ S) {
+  __shared__ double Cp[kMaxDim * kLd];
+  __shared__ double Cq[kMaxDim * kLd];
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, lane = tid & 63;
+  for (int64_t p = blockIdx.x; p < n_pairs; p += gridDim.x) {
+    const dlpno_pno_pair dp = pairs[p];
+    const int Np = dp.dim, np_ = nk[p], fp = dp.first;
+    __syncthreads();
+    for (int e = tid; e < Np * np_; e += kThreads) {
+      const int x = e / np_, a = e - x * np_;
+      Cp[x * kLd + a] = C[dp.off_C + (int64_t)x * Np + a];
+    }
+    for (int64_t cpl = rowptr[p]; cpl < rowptr[p + 1]; ++cpl) {
+      const int32_t q = src[cpl];
+      const dlpno_pno_pair dq = pairs[q];
+      const int Nq = dq.dim, nq = nk[q], fq = dq.first;
+      const int lo = max(fp, fq), hi = min(fp + Np, fq + Nq);
+      const int L = max(hi - lo, 0);
+      __syncthreads();   // Cp loaded; the previous coupling's Cq no longer read
+      for (int e = tid; e < L * nq; e += kThreads) {
+        const int x = e / nq, c = e - x * nq;
+        Cq[x * kLd + c] = C[dq.off_C + (int64_t)(lo - fq + x) * Nq + c];
+      }
+      __syncthreads();
+      double acc[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+      const int shift = lo - fp;
+      for (int x = 0; x < L; ++x) {
+        const double cp = Cp[(x + shift) * kLd + lane];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] += Cq[x * kLd + w + 4 * i] * cp;
+      }
+      double* out = S + off_S[cpl];
+      if (lane < np_) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+          if (w + 4 * i < nq) out[(int64_t)(w + 4 * i) * np_ + lane] = acc[i];
+      }
+    }
+  }
+}
+
 }  // namespace
 
 struct dlpno_pno_plan {
   int64_t n_pairs = 0;
   dlpno_pno_pair* d_pairs = nullptr;
+  std::vector<dlpno_pno_pair> pairs_h;
   int device = 0;
+  // coupling list of dlpno_pno_overlap (device copies)
+  int32_t* d_nk = nullptr;
+  int64_t* d_rowptr = nullptr;
+  int32_t* d_src = nullptr;
+  int64_t* d_off_S = nullptr;
+  bool overlap_ready = false;
 };
+
+static void free_overlap(dlpno_pno_plan* P) {
+  for (void* ptr : {(void*)P->d_nk, (void*)P->d_rowptr, (void*)P->d_src, (void*)P->d_off_S})
+    if (ptr) (void)hipFree(ptr);
+  P->d_nk = nullptr;
+  P->d_rowptr = nullptr;
+  P->d_src = nullptr;
+  P->d_off_S = nullptr;
+  P->overlap_ready = false;
+}
 
 using dlpno::fail;
 
@@ -498,7 +565,7 @@ extern "C" dlpno_status dlpno_pno_plan_create(const dlpno_pno_pair* pairs, int64
     if (d.dim < 1 || d.dim > kMaxDim) return fail(DLPNO_ERR_DIM_RANGE, at + "dim outside 1..64");
     if (d.blocks & ~15) return fail(DLPNO_ERR_INVALID_ARG, at + "block mask");
     if (d.diagonal != 0 && d.diagonal != 1) return fail(DLPNO_ERR_INVALID_ARG, at + "diagonal flag");
-    if (d.reserved != 0) return fail(DLPNO_ERR_INVALID_ARG, at + "reserved field");
+    if (d.first < 0) return fail(DLPNO_ERR_DIM_RANGE, at + "negative domain start");
     const int64_t n2 = (int64_t)d.dim * d.dim;
     const int64_t nb = __builtin_popcount((unsigned)d.blocks);
     if (d.off_X < 0 || (nb > 0 && d.off_X + nb * n2 > n_X)) return fail(DLPNO_ERR_ALIGNMENT, at + "X range");
@@ -509,6 +576,7 @@ extern "C" dlpno_status dlpno_pno_plan_create(const dlpno_pno_pair* pairs, int64
   auto* P = new (std::nothrow) dlpno_pno_plan;
   if (!P) return fail(DLPNO_ERR_OOM, "pno_plan_create: host allocation");
   P->n_pairs = n_pairs;
+  P->pairs_h.assign(pairs, pairs + n_pairs);
   if (hipGetDevice(&P->device) != hipSuccess) {
     delete P;
     return fail(DLPNO_ERR_HIP, "pno_plan_create: hipGetDevice");
@@ -545,6 +613,56 @@ extern "C" dlpno_status dlpno_pno_build(dlpno_pno_plan* plan, const double* X, c
 extern "C" dlpno_status dlpno_pno_plan_destroy(dlpno_pno_plan* plan) {
   if (!plan) return DLPNO_OK;
   if (plan->d_pairs) (void)hipFree(plan->d_pairs);
+  free_overlap(plan);
   delete plan;
+  return DLPNO_OK;
+}
+
+extern "C" dlpno_status dlpno_pno_overlap_prepare(dlpno_pno_plan* plan, const int32_t* n_kept, const int64_t* rowptr,
+                                                  const int32_t* src, const int64_t* off_S, int64_t n_S) {
+  if (!plan || !n_kept || !rowptr) return fail(DLPNO_ERR_INVALID_ARG, "pno_overlap_prepare: NULL argument");
+  const int64_t P = plan->n_pairs;
+  if (rowptr[0] != 0) return fail(DLPNO_ERR_INVALID_ARG, "pno_overlap_prepare: rowptr[0] != 0");
+  std::vector<int32_t> nk(P);
+  for (int64_t p = 0; p < P; ++p) {
+    if (n_kept[p] < 0 || n_kept[p] > plan->pairs_h[p].dim)
+      return fail(DLPNO_ERR_DIM_RANGE, "pno_overlap_prepare: n_kept of pair " + std::to_string(p));
+    nk[p] = n_kept[p] > 0 ? n_kept[p] : 1;
+    if (rowptr[p + 1] < rowptr[p]) return fail(DLPNO_ERR_INVALID_ARG, "pno_overlap_prepare: rowptr not monotonic");
+  }
+  const int64_t n_cpl = rowptr[P];
+  if (n_cpl > 0 && (!src || !off_S)) return fail(DLPNO_ERR_INVALID_ARG, "pno_overlap_prepare: NULL src/off_S");
+  for (int64_t p = 0; p < P; ++p)
+    for (int64_t e = rowptr[p]; e < rowptr[p + 1]; ++e) {
+      if (src[e] < 0 || src[e] >= P) return fail(DLPNO_ERR_DIM_RANGE, "pno_overlap_prepare: source pair out of range");
+      if (off_S[e] < 0 || off_S[e] + (int64_t)nk[src[e]] * nk[p] > n_S)
+        return fail(DLPNO_ERR_ALIGNMENT, "pno_overlap_prepare: block " + std::to_string(e) + " outside S");
+    }
+  free_overlap(plan);
+  auto up = [&](void** dst, const void* h, size_t bytes) -> bool {
+    if (bytes == 0) return true;
+    if (hipMalloc(dst, bytes) != hipSuccess) return false;
+    return hipMemcpy(*dst, h, bytes, hipMemcpyHostToDevice) == hipSuccess;
+  };
+  if (!up((void**)&plan->d_nk, nk.data(), P * sizeof(int32_t)) ||
+      !up((void**)&plan->d_rowptr, rowptr, (P + 1) * sizeof(int64_t)) ||
+      !up((void**)&plan->d_src, src, n_cpl * sizeof(int32_t)) ||
+      !up((void**)&plan->d_off_S, off_S, n_cpl * sizeof(int64_t))) {
+    free_overlap(plan);
+    return fail(DLPNO_ERR_OOM, "pno_overlap_prepare: device upload");
+  }
+  plan->overlap_ready = true;
+  return DLPNO_OK;
+}
+
+extern "C" dlpno_status dlpno_pno_overlap(dlpno_pno_plan* plan, const double* C, double* S, void* stream) {
+  if (!plan) return fail(DLPNO_ERR_INVALID_ARG, "pno_overlap: plan is NULL");
+  if (!plan->overlap_ready) return fail(DLPNO_ERR_INVALID_ARG, "pno_overlap: no coupling list (call _prepare)");
+  if (plan->n_pairs == 0) return DLPNO_OK;
+  if (!C || !S) return fail(DLPNO_ERR_INVALID_ARG, "pno_overlap: NULL buffer");
+  const int64_t grid = plan->n_pairs < (1 << 20) ? plan->n_pairs : (1 << 20);
+  hipLaunchKernelGGL(pno_overlap_kernel, dim3((unsigned)grid), dim3(kThreads), 0, (hipStream_t)stream, plan->d_pairs,
+                     plan->d_nk, plan->d_rowptr, plan->d_src, plan->d_off_S, plan->n_pairs, C, S);
+  if (hipGetLastError() != hipSuccess) return fail(DLPNO_ERR_HIP, "pno_overlap: launch");
   return DLPNO_OK;
 }

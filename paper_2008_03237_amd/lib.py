@@ -95,6 +95,8 @@ def lib():
         "dlpno_pno_plan_create": [vp, i64, i64, i64, i64, i64, C.POINTER(vp)],
         "dlpno_pno_build": [vp, vp, vp, C.c_double, vp, vp, vp, vp, vp, vp],
         "dlpno_pno_plan_destroy": [vp],
+        "dlpno_pno_overlap_prepare": [vp, vp, vp, vp, vp, i64],
+        "dlpno_pno_overlap": [vp, vp, vp, vp],
     }
     for name, args in sig.items():
         # a library built from older sources lacks newer entry points: only
@@ -377,3 +379,18 @@ class PnoPlan:
         _check(lib().dlpno_pno_build(self._h, _ptr(X), _ptr(F), float(t_cut), _ptr(occ), _ptr(eps), _ptr(Cout),
                                      _ptr(n_kept), _ptr(sweeps), _stream()))
         return occ, eps, Cout, n_kept, sweeps
+
+    def overlap_prepare(self, n_kept, rowptr, src, off_S, n_S):
+        """Coupling list of overlap(): host arrays (n_kept as returned by
+        build, copied to the host)."""
+        self._cpl = [np.ascontiguousarray(n_kept, dtype=np.int32), np.ascontiguousarray(rowptr, dtype=np.int64),
+                     np.ascontiguousarray(src, dtype=np.int32), np.ascontiguousarray(off_S, dtype=np.int64)]
+        self.n_S = int(n_S)
+        _check(lib().dlpno_pno_overlap_prepare(self._h, *[a.ctypes.data_as(C.c_void_p) for a in self._cpl],
+                                               self.n_S))
+
+    def overlap(self, Cmat, S=None):
+        import torch
+        S = torch.empty(max(self.n_S, 1), dtype=torch.float64, device=Cmat.device) if S is None else S
+        _check(lib().dlpno_pno_overlap(self._h, _ptr(Cmat), _ptr(S), _stream()))
+        return S

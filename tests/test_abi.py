@@ -114,7 +114,7 @@ def test_pno_plan_validation_on_host():
     from workload.pno import build_pno_problem, PNO_PAIR_DTYPE
     prob = build_pno_problem("tiny")
     L = lib()
-    for field, value, code in (("dim", 0, -2), ("dim", 65, -2), ("blocks", 16, -1), ("reserved", 1, -1),
+    for field, value, code in (("dim", 0, -2), ("dim", 65, -2), ("blocks", 16, -1), ("first", -1, -2),
                                ("off_C", prob.n_C, -3), ("diagonal", 2, -1)):
         bad = prob.pairs.copy()
         bad[3][field] = value

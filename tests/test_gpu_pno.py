@@ -152,3 +152,84 @@ def test_pno_nonfinite_input_reported():
     nk = nk.cpu().numpy()
     assert nk[p] == -3 and np.all(np.delete(nk, p) >= 0)
     plan.close()
+
+
+def oracle_overlaps(prob_pno, res):
+    """S of every coupling of the residual workload `res` from the oracle's
+    own PNOs; also returns the per-pair coefficient tolerances."""
+    from oracle.pno import pno_overlap
+    Cs, tol = [], []
+    for p in range(prob_pno.n_pairs):
+        D, F, occ, n, C, eps = oracle_pair(prob_pno, p, prob_pno.t_cut)
+        N = C.shape[0]
+        if n == 0:
+            C = np.zeros((N, 1))
+            tol.append(0.0)
+        else:
+            g = occ[n - 1] - (occ[n] if n < N else 0.0)
+            h = np.min(np.diff(eps)) if n > 1 else 1.0
+            tol.append(64 * U * (max(occ[0], 1e-300) / g + np.linalg.norm(F, 2) / h) + 1e-14)
+        Cs.append(C)
+    S = np.zeros(res.n_S)
+    first = prob_pno.pairs["first"]
+    for p in range(res.n_pairs):
+        for e in range(res.cpl_rowptr[p], res.cpl_rowptr[p + 1]):
+            q = int(res.cpl_src[e])
+            blk = pno_overlap(Cs[p], int(first[p]), Cs[q], int(first[q]))
+            S[res.cpl_off_S[e]:res.cpl_off_S[e] + blk.size] = blk.ravel()
+    return S, np.array(tol)
+
+
+def gpu_pipeline(name):
+    """PNOs on the GPU, then the residual workload with n_p = the PNO counts
+    and the S blocks of its coupling list from dlpno_pno_overlap."""
+    from paper_2008_03237_amd import PnoPlan
+    from workload import build_problem
+    from workload.gpu import device_pno_fields
+    pp = build_pno_problem(name)
+    dev = device_pno_fields(pp)
+    plan = PnoPlan(pp.pairs, pp.n_X, pp.n_F, pp.n_C, pp.n_v)
+    occ, eps, C, nk, _ = plan.build(dev["X"], dev["F"], pp.t_cut)
+    nk_h = nk.cpu().numpy()
+    res = build_problem(name, npno=("given", np.maximum(nk_h, 1)))
+    plan.overlap_prepare(nk_h, res.cpl_rowptr, res.cpl_src, res.cpl_off_S, res.n_S)
+    S = plan.overlap(C)
+    torch.cuda.synchronize()
+    plan.close()
+    return pp, res, nk_h, S
+
+
+@pytest.mark.parametrize("name", ["tiny", "chain"])
+def test_pno_overlap_parity(name):
+    pp, res, nk, S = gpu_pipeline(name)
+    print("case pno overlap", name, int(res.cpl_rowptr[-1]), "couplings", flush=True)
+    S_o, tol = oracle_overlaps(pp, res)
+    S_g = S.cpu().numpy()[:res.n_S]
+    for p in range(res.n_pairs):
+        for e in range(res.cpl_rowptr[p], res.cpl_rowptr[p + 1]):
+            q = int(res.cpl_src[e])
+            o, size = int(res.cpl_off_S[e]), int(res.npno[p] * res.npno[q])
+            d = np.abs(S_g[o:o + size] - S_o[o:o + size]).max()
+            assert d <= 8.0 * (tol[p] + tol[q]) + 1e-13, (p, q, d)
+
+
+def test_residual_on_pno_built_inputs():
+    """The hot path on inputs produced by the PNO stage: n_p and S from the GPU
+    PNO build, against the oracle residual with n_p and S from the oracle's PNO
+    build.  S inherits the PNOs' subspace error (1e-10 at worst here), hence the
+    looser 1e-8 bound on R."""
+    import oracle
+    from oracle.model import unpack_T
+    from paper_2008_03237_amd import Plan
+    from tests.gpu_helpers import compare_blocks
+    from workload.gpu import device_fields
+    pp, res, nk, S = gpu_pipeline("tiny")
+    res.S_host, _ = oracle_overlaps(pp, res)
+    dev = device_fields(res, fields=("B", "K", "T"))
+    plan = Plan(res, dev["B"], S, dev["K"], torch.from_numpy(res.eps_a).cuda(), torch.from_numpy(res.eps_b).cuda())
+    R = plan.residual(dev["T"])
+    torch.cuda.synchronize()
+    inp = oracle.Inputs.from_problem(res, B=res.materialize("B"), K=res.materialize("K"), S=res.materialize("S"))
+    Ro = oracle.residual_os(inp, unpack_T(res, res.materialize("T")))
+    compare_blocks(res, R.cpu().numpy(), Ro, rel=1e-8)
+    plan.close()

@@ -3,7 +3,7 @@ semicanonical PNOs) against what the paper and the mathematics fix."""
 import numpy as np
 import pytest
 
-from oracle.pno import build_pnos, pair_density, sign_convention
+from oracle.pno import build_pnos, pair_density, pno_overlap, sign_convention
 
 
 def _sym(rng, n, scale=1.0):
@@ -89,3 +89,34 @@ def test_density_is_positive_semidefinite_and_sign_convention():
     C = sign_convention(rng.standard_normal((N, 4)))
     for k in range(4):
         assert C[np.argmax(np.abs(C[:, k])), k] > 0
+
+
+def _pnos(rng, N, n):
+    A = rng.standard_normal((N, N))
+    occ, k, C, eps = build_pnos(A @ A.T, _sym(rng, N, 0.2) + np.diag(np.linspace(0.2, 3.0, N)), 0.0)
+    return C[:, :n]
+
+
+def test_overlap_of_a_pair_with_itself_is_the_identity():
+    rng = np.random.default_rng(19)
+    C = _pnos(rng, 11, 6)
+    np.testing.assert_allclose(pno_overlap(C, 5, C, 5), np.eye(6), atol=1e-13)
+
+
+def test_overlap_against_the_global_embedding():
+    # each PNO as a vector of the global space (zero outside its window): the
+    # overlap is the plain inner product of those vectors
+    rng = np.random.default_rng(23)
+    G = 40
+    for (Np, fp, n1), (Nq, fq, n2) in [((10, 3, 4), (12, 8, 5)), ((9, 20, 9), (7, 22, 3)),
+                                        ((6, 0, 2), (6, 30, 4)), ((13, 10, 7), (13, 10, 7))]:
+        Cp, Cq = _pnos(rng, Np, n1), _pnos(rng, Nq, n2)
+        Ep, Eq = np.zeros((G, n1)), np.zeros((G, n2))
+        Ep[fp:fp + Np], Eq[fq:fq + Nq] = Cp, Cq
+        want = np.array([[Eq[:, c] @ Ep[:, a] for a in range(n1)] for c in range(n2)])
+        got = pno_overlap(Cp, fp, Cq, fq)
+        assert got.shape == (n2, n1)
+        np.testing.assert_allclose(got, want, atol=1e-14)
+        np.testing.assert_allclose(pno_overlap(Cq, fq, Cp, fp), got.T, atol=1e-14)
+    # disjoint windows do not overlap
+    assert not np.any(pno_overlap(_pnos(rng, 5, 3), 0, _pnos(rng, 5, 2), 5))

@@ -4,7 +4,10 @@ blocks of the pair in that basis and the domain's virtual Fock matrix.
 
 Pairs and stored spin blocks follow the residual workloads (same chain, band
 and SOMOs).  Per pair p = (i, j):
-  * N_p (1..64) from a uniform or fixed rule;
+  * N_p (1..64) from a uniform or fixed rule; the domain is the window of N_p
+    functions of an orthonormal global virtual space (4 functions per
+    occupied orbital along the chain) centred on the pair: first_p =
+    max(0, 2 (i + j) - N_p / 2);
   * each stored block X (N_p x N_p, row-major [a][b]) has elements
     sigma_p z 2^-floor((a + b) / tau_p), z unit normal, sigma_p =
     sigma_X exp(-|i - j| / 20), tau_p uniform on a small integer range: a
@@ -27,7 +30,7 @@ from .problem import (CONFIGS, BLOCK_BITS, BLOCK_NAMES, SEG_DTYPE, MODE_DECAY, M
 
 # matches dlpno_pno_pair in include/dlpno.h (48 bytes)
 PNO_PAIR_DTYPE = np.dtype([("dim", np.int32), ("blocks", np.int32), ("diagonal", np.int32),
-                           ("reserved", np.int32), ("off_X", np.int64), ("off_F", np.int64),
+                           ("first", np.int32), ("off_X", np.int64), ("off_F", np.int64),
                            ("off_C", np.int64), ("off_v", np.int64)])
 
 PNO_CONFIGS = {
@@ -136,6 +139,7 @@ def build_pno_problem(name="tiny", **override):
     pairs["dim"] = dim
     pairs["blocks"] = [sum(BLOCK_BITS[n] for n in nm) for nm in names]
     pairs["diagonal"] = (pi == pj).astype(np.int32)
+    pairs["first"] = np.maximum(0, 2 * (pi.astype(np.int64) + pj) - dim // 2)
     pairs["off_X"] = np.concatenate([[0], np.cumsum(szX)[:-1]])
     pairs["off_F"] = np.concatenate([[0], np.cumsum(szF)[:-1]])
     pairs["off_C"] = pairs["off_F"]

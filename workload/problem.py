@@ -238,6 +238,11 @@ def _dims(rule, seed, fld, P):
     kind = rule[0]
     if kind == "fixed":
         return np.full(P, rule[1], dtype=np.int32)
+    if kind == "given":          # one value per pair, e.g. PNO counts from a PNO build
+        v = np.asarray(rule[1], dtype=np.int32)
+        if v.shape != (P,):
+            raise ValueError("given dimensions: %d values for %d pairs" % (v.size, P))
+        return v.copy()
     streams = np.arange(P, dtype=np.uint64)
     if kind == "uniform":
         lo, hi = rule[1], rule[2]
