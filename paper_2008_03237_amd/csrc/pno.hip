@@ -478,51 +478,114 @@ __global__ __launch_bounds__(kThreads, 2) void pno_build_kernel(const dlpno_pno_
 }
 
 // PNO overlaps of a coupling list: one workgroup per target pair p, C_p in
-// LDS; per coupling, the shared rows of C_q in LDS and S[c][a] with lane a
-// and rows c = wave + 4 i (16 per thread).
-__global__ __launch_bounds__(kThreads, 2) void pno_overlap_kernel(
-    const dlpno_pno_pair* __restrict__ pairs, const int32_t* __restrict__ nk, const int64_t* __restrict__ rowptr,
-    const int32_t* __restrict__ src, const int64_t* __restrict__ off_S, int64_t n_pairs,
-    const double* __restrict__ C, double* __restrict__ S) {
-  __shared__ double Cp[kMaxDim * kLd];
-  __shared__ double Cq[kMaxDim * kLd];
-  const int tid = threadIdx.x;
-  const int w = tid >> 6, lane = tid & 63;
-  for (int64_t p = blockIdx.x; p < n_pairs; p += gridDim.x) {
-    const dlpno_pno_pair dp = pairs[p];
-    const int Np = dp.dim, np_ = nk[p], fp = dp.first;
-    __syncthreads();
-    for (int e = tid; e < Np * np_; e += kThreads) {
-      const int x = e / np_, a = e - x * np_;
-      Cp[x * kLd + a] = C[dp.off_C + (int64_t)x * Np + a];
+// LDS.  Per coupling, the shared rows of C_q go through registers into LDS;
+// the next coupling's rows are loaded while this one is computed.  Each
+// thread computes a tile of S (overlap_tile).  LDS rows are 68 doubles so
+// that tiles load as 16-byte pairs.
+constexpr int kLdO = 68;
+constexpr int kPrefetch = kMaxDim * kMaxDim / kThreads;   // 16 elements per thread
+
+// one coupling of the list, resolved on the host at prepare time so that the
+// kernel needs one load per coupling (and issues it a coupling ahead)
+struct OverlapItem {
+  int64_t base;    // first element of the shared rows of C_q
+  int64_t off_S;   // output block
+  int32_t Nq, nq;  // source domain size and PNO count
+  int32_t L;       // shared rows (0: the windows do not meet)
+  int32_t shift;   // first shared row within the target's domain
+};
+
+// T x T tile of S per thread on a 16 x 16 grid of tiles (T = 2: blocks of
+// at most 32 x 32, every thread busy; T = 4: up to 64 x 64)
+template <int T>
+__device__ __forceinline__ void overlap_tile(const double* Cq, const double* Cp, int shift, int L, int nq, int np_,
+                                             double* out) {
+  const int ti = threadIdx.x >> 4, tj = threadIdx.x & 15;
+  if (T * ti >= nq || T * tj >= np_) return;
+  double acc[T][T] = {};
+  for (int x = 0; x < L; ++x) {
+    double qv[T], pv[T];
+#pragma unroll
+    for (int h = 0; h < T; h += 2) {
+      const double2 q = *reinterpret_cast<const double2*>(&Cq[x * kLdO + T * ti + h]);
+      const double2 v = *reinterpret_cast<const double2*>(&Cp[(x + shift) * kLdO + T * tj + h]);
+      qv[h] = q.x;
+      qv[h + 1] = q.y;
+      pv[h] = v.x;
+      pv[h + 1] = v.y;
     }
-    for (int64_t cpl = rowptr[p]; cpl < rowptr[p + 1]; ++cpl) {
-      const int32_t q = src[cpl];
-      const dlpno_pno_pair dq = pairs[q];
-      const int Nq = dq.dim, nq = nk[q], fq = dq.first;
-      const int lo = max(fp, fq), hi = min(fp + Np, fq + Nq);
-      const int L = max(hi - lo, 0);
-      __syncthreads();   // Cp loaded; the previous coupling's Cq no longer read
-      for (int e = tid; e < L * nq; e += kThreads) {
-        const int x = e / nq, c = e - x * nq;
-        Cq[x * kLd + c] = C[dq.off_C + (int64_t)(lo - fq + x) * Nq + c];
+#pragma unroll
+    for (int i = 0; i < T; ++i)
+#pragma unroll
+      for (int j = 0; j < T; ++j) acc[i][j] += qv[i] * pv[j];
+  }
+#pragma unroll
+  for (int i = 0; i < T; ++i) {
+    const int c = T * ti + i;
+    if (c < nq)
+#pragma unroll
+      for (int j = 0; j < T; ++j)
+        if (T * tj + j < np_) out[(int64_t)c * np_ + T * tj + j] = acc[i][j];
+  }
+}
+
+__global__ __launch_bounds__(kThreads, 2) void pno_overlap_kernel(const dlpno_pno_pair* __restrict__ pairs,
+                                                                   const int32_t* __restrict__ nk,
+                                                                   const int64_t* __restrict__ rowptr,
+                                                                   const OverlapItem* __restrict__ items,
+                                                                   int64_t n_pairs, const double* __restrict__ C,
+                                                                   double* __restrict__ S) {
+  __shared__ __attribute__((aligned(16))) double Cp[kMaxDim * kLdO];
+  __shared__ __attribute__((aligned(16))) double Cq[kMaxDim * kLdO];
+  const int tid = threadIdx.x;
+  // element (row, column) = (w + 4 j, lane) of every C block a thread moves
+  const int w = tid >> 6, lane = tid & 63;
+  // workgroup it runs on XCD it % 8: each XCD takes a contiguous range of
+  // target pairs, so that the source rows that neighbouring targets share
+  // are found in its L2
+  const int64_t chunk = (n_pairs + 7) / 8;
+  for (int64_t it = blockIdx.x; it < 8 * chunk; it += gridDim.x) {
+    const int64_t p = (it & 7) * chunk + (it >> 3);
+    if (p >= n_pairs) continue;
+    const dlpno_pno_pair dp = pairs[p];
+    const int Np = dp.dim, np_ = nk[p];
+    const int64_t e0 = rowptr[p], e1 = rowptr[p + 1];
+    __syncthreads();
+    if (lane < np_)
+      for (int x = w; x < Np; x += 4) Cp[x * kLdO + lane] = C[dp.off_C + (int64_t)x * Np + lane];
+    double pre[kPrefetch];
+    OverlapItem cur{}, nxt{};
+    if (e0 < e1) {
+      cur = items[e0];
+      if (e0 + 1 < e1) nxt = items[e0 + 1];
+#pragma unroll
+      for (int j = 0; j < kPrefetch; ++j) {
+        const int x = w + 4 * j;
+        pre[j] = (x < cur.L && lane < cur.nq) ? C[cur.base + (int64_t)x * cur.Nq + lane] : 0.0;
+      }
+    }
+    for (int64_t cpl = e0; cpl < e1; ++cpl) {
+      const OverlapItem r = cur;
+      __syncthreads();   // C_p stored; the previous coupling's rows no longer read
+#pragma unroll
+      for (int j = 0; j < kPrefetch; ++j) {
+        const int x = w + 4 * j;
+        if (x < r.L && lane < r.nq) Cq[x * kLdO + lane] = pre[j];
       }
       __syncthreads();
-      double acc[16];
+      if (cpl + 1 < e1) {   // rows of the next coupling, in flight during this one
+        cur = nxt;
+        if (cpl + 2 < e1) nxt = items[cpl + 2];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) acc[i] = 0.0;
-      const int shift = lo - fp;
-      for (int x = 0; x < L; ++x) {
-        const double cp = Cp[(x + shift) * kLd + lane];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) acc[i] += Cq[x * kLd + w + 4 * i] * cp;
+        for (int j = 0; j < kPrefetch; ++j) {
+          const int x = w + 4 * j;
+          pre[j] = (x < cur.L && lane < cur.nq) ? C[cur.base + (int64_t)x * cur.Nq + lane] : 0.0;
+        }
       }
-      double* out = S + off_S[cpl];
-      if (lane < np_) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-          if (w + 4 * i < nq) out[(int64_t)(w + 4 * i) * np_ + lane] = acc[i];
-      }
+      if (r.nq <= 32 && np_ <= 32)
+        overlap_tile<2>(Cq, Cp, r.shift, r.L, r.nq, np_, S + r.off_S);
+      else
+        overlap_tile<4>(Cq, Cp, r.shift, r.L, r.nq, np_, S + r.off_S);
     }
   }
 }
@@ -537,18 +600,16 @@ struct dlpno_pno_plan {
   // coupling list of dlpno_pno_overlap (device copies)
   int32_t* d_nk = nullptr;
   int64_t* d_rowptr = nullptr;
-  int32_t* d_src = nullptr;
-  int64_t* d_off_S = nullptr;
+  OverlapItem* d_items = nullptr;
   bool overlap_ready = false;
 };
 
 static void free_overlap(dlpno_pno_plan* P) {
-  for (void* ptr : {(void*)P->d_nk, (void*)P->d_rowptr, (void*)P->d_src, (void*)P->d_off_S})
+  for (void* ptr : {(void*)P->d_nk, (void*)P->d_rowptr, (void*)P->d_items})
     if (ptr) (void)hipFree(ptr);
   P->d_nk = nullptr;
   P->d_rowptr = nullptr;
-  P->d_src = nullptr;
-  P->d_off_S = nullptr;
+  P->d_items = nullptr;
   P->overlap_ready = false;
 }
 
@@ -638,6 +699,21 @@ extern "C" dlpno_status dlpno_pno_overlap_prepare(dlpno_pno_plan* plan, const in
       if (off_S[e] < 0 || off_S[e] + (int64_t)nk[src[e]] * nk[p] > n_S)
         return fail(DLPNO_ERR_ALIGNMENT, "pno_overlap_prepare: block " + std::to_string(e) + " outside S");
     }
+  std::vector<OverlapItem> items(n_cpl);
+  for (int64_t p = 0; p < P; ++p) {
+    const dlpno_pno_pair& dp = plan->pairs_h[p];
+    for (int64_t e = rowptr[p]; e < rowptr[p + 1]; ++e) {
+      const dlpno_pno_pair& dq = plan->pairs_h[src[e]];
+      const int lo = std::max(dp.first, dq.first), hi = std::min(dp.first + dp.dim, dq.first + dq.dim);
+      OverlapItem& it = items[e];
+      it.L = std::max(hi - lo, 0);
+      it.base = dq.off_C + (int64_t)(it.L > 0 ? lo - dq.first : 0) * dq.dim;
+      it.off_S = off_S[e];
+      it.Nq = dq.dim;
+      it.nq = nk[src[e]];
+      it.shift = it.L > 0 ? lo - dp.first : 0;
+    }
+  }
   free_overlap(plan);
   auto up = [&](void** dst, const void* h, size_t bytes) -> bool {
     if (bytes == 0) return true;
@@ -646,8 +722,7 @@ extern "C" dlpno_status dlpno_pno_overlap_prepare(dlpno_pno_plan* plan, const in
   };
   if (!up((void**)&plan->d_nk, nk.data(), P * sizeof(int32_t)) ||
       !up((void**)&plan->d_rowptr, rowptr, (P + 1) * sizeof(int64_t)) ||
-      !up((void**)&plan->d_src, src, n_cpl * sizeof(int32_t)) ||
-      !up((void**)&plan->d_off_S, off_S, n_cpl * sizeof(int64_t))) {
+      !up((void**)&plan->d_items, items.data(), n_cpl * sizeof(OverlapItem))) {
     free_overlap(plan);
     return fail(DLPNO_ERR_OOM, "pno_overlap_prepare: device upload");
   }
@@ -660,9 +735,10 @@ extern "C" dlpno_status dlpno_pno_overlap(dlpno_pno_plan* plan, const double* C,
   if (!plan->overlap_ready) return fail(DLPNO_ERR_INVALID_ARG, "pno_overlap: no coupling list (call _prepare)");
   if (plan->n_pairs == 0) return DLPNO_OK;
   if (!C || !S) return fail(DLPNO_ERR_INVALID_ARG, "pno_overlap: NULL buffer");
-  const int64_t grid = plan->n_pairs < (1 << 20) ? plan->n_pairs : (1 << 20);
+  const int64_t slots = 8 * ((plan->n_pairs + 7) / 8);
+  const int64_t grid = slots < (1 << 20) ? slots : (1 << 20);
   hipLaunchKernelGGL(pno_overlap_kernel, dim3((unsigned)grid), dim3(kThreads), 0, (hipStream_t)stream, plan->d_pairs,
-                     plan->d_nk, plan->d_rowptr, plan->d_src, plan->d_off_S, plan->n_pairs, C, S);
+                     plan->d_nk, plan->d_rowptr, plan->d_items, plan->n_pairs, C, S);
   if (hipGetLastError() != hipSuccess) return fail(DLPNO_ERR_HIP, "pno_overlap: launch");
   return DLPNO_OK;
 }
