@@ -66,10 +66,17 @@ class Inputs:
     occ_ints   optional occupied integrals (k i | l j) of the hole-hole ladder:
                an object with value(k, i, l, j) and neighbors(i) (the k that
                can give a non-zero (k i | . .)); None: no hole-hole term
+    n_sv[p]    optional: the last n_sv[p] of the pair's n_p virtual functions
+               are SOMOs (Sec. II.B.4: every PNO set is augmented by the
+               SOMOs, which are virtual for beta electrons only); they belong
+               to the beta virtual space, not to the alpha one.  B, K, S and
+               eps cover all n_p functions (the SOMO part of S between two
+               pairs is the identity); residual blocks vanish outside the
+               virtual spaces of their spins.  None: no SOMO functions.
     B and S may be callables (lazy regeneration for large workloads).
     """
 
-    def __init__(self, n_occ, is_somo, pairs, B, K, eps_a, eps_b, f_a, f_b, S, occ_ints=None):
+    def __init__(self, n_occ, is_somo, pairs, B, K, eps_a, eps_b, f_a, f_b, S, occ_ints=None, n_sv=None):
         self.n_occ = int(n_occ)
         self.is_somo = np.asarray(is_somo).astype(bool)
         self.pairs = [(int(i), int(j)) for i, j in pairs]
@@ -78,6 +85,7 @@ class Inputs:
         self.f_a, self.f_b = np.asarray(f_a, dtype=np.float64), np.asarray(f_b, dtype=np.float64)
         self._S = S
         self.occ_ints = occ_ints
+        self.n_sv = None if n_sv is None else [int(x) for x in n_sv]
 
     def B(self, p):
         return self._B(p) if callable(self._B) else self._B[p]
@@ -96,6 +104,14 @@ class Inputs:
 
     def eps(self, s, p):
         return self.eps_a[p] if s == 0 else self.eps_b[p]
+
+    def vmask(self, s, p):
+        """Which of pair p's virtual functions belong to spin s's virtual space."""
+        n = self.npno(p)
+        m = np.ones(n, dtype=bool)
+        if s == 0 and self.n_sv is not None and self.n_sv[p] > 0:
+            m[n - self.n_sv[p]:] = False
+        return m
 
     def blocks(self, p):
         i, j = self.pairs[p]
@@ -155,7 +171,8 @@ class Inputs:
         occ = None
         if prob.hole_scale != 0.0:
             occ = _WorkloadOccInts(prob)
-        return cls(prob.n_occ, prob.is_somo, pairs, Bf, Kd, ea, eb, prob.f_a, prob.f_b, Sf, occ)
+        n_sv = getattr(prob, "n_sv", None)
+        return cls(prob.n_occ, prob.is_somo, pairs, Bf, Kd, ea, eb, prob.f_a, prob.f_b, Sf, occ, n_sv)
 
 
 class _WorkloadOccInts:
@@ -310,7 +327,11 @@ def hole_terms(inp, T, p, name):
 
 def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladder", "hole")):
     """Open-shell residual blocks {(p, name): R} for the given target pairs.
-    The hole-hole term is present only when inp.occ_ints is given."""
+    The hole-hole term is present only when inp.occ_ints is given.  With SOMO
+    virtual functions (inp.n_sv) each block is the model residual restricted
+    to its spins' virtual spaces (the rows of an alpha virtual index and the
+    columns of an alpha virtual index vanish at SOMO functions); amplitudes
+    must vanish there too."""
     R = {}
     for p in (range(len(inp.pairs)) if pairs is None else pairs):
         Bp = inp.B(p) if "ladder" in terms else None
@@ -329,6 +350,9 @@ def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladd
             if "hole" in terms:
                 for w, q, Spq, src in hole_terms(inp, T, p, name):
                     r += w * (Spq @ src[3] @ Spq.T)
+            if inp.n_sv is not None:
+                s1, s2 = SPIN[name]
+                r = r * (inp.vmask(s1, p)[:, None] & inp.vmask(s2, p)[None, :])
             R[(p, name)] = r
     return R
 

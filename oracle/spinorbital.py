@@ -14,18 +14,20 @@ terms of the model are formed from explicit antisymmetrised integrals:
 
 with (ac|bd) = sum_Q B^Q_ac B^Q_bd, (ia|jb) given per ordered pair and the
 occupied integrals (ki|lj) given as a dense array (the last term is absent
-when they are not given).
+when they are not given).  With n_sv > 0 the last n_sv spatial virtual
+functions are SOMOs: beta virtual spin orbitals only (their alpha spin
+orbitals are occupied), Sec. II.B.4.
 """
 import numpy as np
 
 
-def _spin_orbitals(n_occ, is_somo, V):
+def _spin_orbitals(n_occ, is_somo, V, n_sv=0):
     occ = [(i, 0) for i in range(n_occ)] + [(i, 1) for i in range(n_occ) if not is_somo[i]]
-    vir = [(a, 0) for a in range(V)] + [(a, 1) for a in range(V)]
+    vir = [(a, 0) for a in range(V - n_sv)] + [(a, 1) for a in range(V)]
     return occ, vir
 
 
-def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblocks, pairs, g_occ=None):
+def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblocks, pairs, g_occ=None, n_sv=0):
     """Pair blocks of the residual and the total energy of the given amplitudes.
 
     Bg       (m, V, V) three-index integrals shared by all pairs
@@ -33,13 +35,18 @@ def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblo
     Tblocks  {((i, j), name): V x V} stored amplitude blocks (same-spin antisymmetric)
     pairs    list of (i, j) covering every occupied pair (i <= j)
     g_occ    optional (n_occ, n_occ, n_occ, n_occ) array g[k, i, l, j] = (k i | l j)
-    Returns ({((i, j), name): V x V residual block}, energy of the amplitudes).
+    n_sv     SOMO functions among the V (the last n_sv; beta virtual only)
+    Returns ({((i, j), name): V x V residual block, zero outside the blocks'
+    virtual spaces}, energy of the amplitudes).
     """
     V = Bg.shape[1]
-    occ, vir = _spin_orbitals(n_occ, is_somo, V)
+    occ, vir = _spin_orbitals(n_occ, is_somo, V, n_sv)
     no, nv = len(occ), len(vir)
     oidx = {o: x for x, o in enumerate(occ)}
+    vidx = {v: x for x, v in enumerate(vir)}
     spins = {"AA": (0, 0), "BB": (1, 1), "AB": (0, 1), "BA": (1, 0)}
+    sp_a = np.array([a for a, _ in vir])      # spatial index of each virtual spin orbital
+    sp_s = np.array([sa for _, sa in vir])    # its spin
 
     def Kord(i, j):
         return Kpair[(i, j)] if i <= j else Kpair[(j, i)].T
@@ -56,20 +63,13 @@ def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblo
                     if sa == sj and sb == si:
                         v -= Kord(j, i)[a, b]
                     g_vvoo[A, B, I, J] = v
-    # <AB||CD>
+    # <AB||CD> = (AC|BD) - (AD|BC), spin orbitals of equal spin in each charge distribution
     acbd = np.einsum("qac,qbd->abcd", Bg, Bg)          # (ac|bd)
-    g_vvvv = np.zeros((nv, nv, nv, nv))
-    for sa in (0, 1):
-        for sb in (0, 1):
-            for sc in (0, 1):
-                for sd in (0, 1):
-                    blk = np.zeros((V, V, V, V))
-                    if sa == sc and sb == sd:
-                        blk += acbd
-                    if sa == sd and sb == sc:
-                        blk -= acbd.transpose(0, 1, 3, 2)      # (ad|bc)
-                    g_vvvv[sa * V:(sa + 1) * V, sb * V:(sb + 1) * V,
-                           sc * V:(sc + 1) * V, sd * V:(sd + 1) * V] = blk
+    a4 = np.ix_(sp_a, sp_a, sp_a, sp_a)
+    s_ = sp_s
+    same_ac_bd = (s_[:, None, None, None] == s_[None, None, :, None]) & (s_[None, :, None, None] == s_[None, None, None, :])
+    same_ad_bc = (s_[:, None, None, None] == s_[None, None, None, :]) & (s_[None, :, None, None] == s_[None, None, :, None])
+    g_vvvv = np.where(same_ac_bd, acbd[a4], 0.0) - np.where(same_ad_bc, acbd.transpose(0, 1, 3, 2)[a4], 0.0)
     # amplitudes as a fully antisymmetric tensor
     t = np.zeros((no, no, nv, nv))
     for ((i, j), name), Tb in Tblocks.items():
@@ -77,7 +77,10 @@ def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblo
         I, J = oidx[(i, s1)], oidx[(j, s2)]
         for a in range(V):
             for b in range(V):
-                A, B = s1 * V + a, s2 * V + b
+                if (a, s1) not in vidx or (b, s2) not in vidx:
+                    assert Tb[a, b] == 0.0, "amplitude outside the virtual spaces"
+                    continue
+                A, B = vidx[(a, s1)], vidx[(b, s2)]
                 t[I, J, A, B] = Tb[a, b]
                 t[J, I, B, A] = Tb[a, b]
                 t[I, J, B, A] = -Tb[a, b]
@@ -88,7 +91,7 @@ def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblo
         for I, (i, si) in enumerate(occ):
             if sk == si:
                 fo[K, I] = (f_a if sk == 0 else f_b)[k, i]
-    ev = np.concatenate([eps_a, eps_b])
+    ev = np.array([(eps_a if sa == 0 else eps_b)[a] for a, sa in vir])
     R = (g_vvoo.transpose(2, 3, 0, 1)
          + (ev[None, None, :, None] + ev[None, None, None, :]) * t
          - np.einsum("ki,kjab->ijab", fo, t)
@@ -114,5 +117,9 @@ def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblo
         for name, (s1, s2) in spins.items():
             if (i, s1) in oidx and (j, s2) in oidx:
                 I, J = oidx[(i, s1)], oidx[(j, s2)]
-                out[((i, j), name)] = R[I, J][s1 * V:(s1 + 1) * V, s2 * V:(s2 + 1) * V].copy()
+                blk = np.zeros((V, V))
+                ra = [A for A, (a, sa) in enumerate(vir) if sa == s1]
+                rb = [B for B, (b, sb) in enumerate(vir) if sb == s2]
+                blk[np.ix_(sp_a[ra], sp_a[rb])] = R[I, J][np.ix_(ra, rb)]
+                out[((i, j), name)] = blk
     return out, E

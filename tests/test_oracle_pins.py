@@ -402,3 +402,84 @@ def test_diis_drop_rule_is_scale_invariant():
         d.push(rng.standard_normal(40), 1e-10 * e)
     d.coefficients()
     assert d.drops == 1 and len(d.errs) == 2
+
+
+# ------------------------- SOMO-augmented virtual spaces (Sec. II.B.4)
+def _mask_T(inp, T):
+    for (p, name), Tb in T.items():
+        s1, s2 = oracle.model.SPIN[name]
+        Tb *= inp.vmask(s1, p)[:, None] & inp.vmask(s2, p)[None, :]
+    return T
+
+
+@pytest.mark.parametrize("somos,hole", [((1,), 0.0), ((1, 3), 0.0), ((1, 3), 0.05)])
+def test_somo_augmented_canonical_limit_matches_bruteforce(somos, hole):
+    # every PNO set augmented by the SOMOs, which are beta virtuals only: the
+    # pair residual on the augmented space, restricted to each block's virtual
+    # spaces, equals the spin-orbital residual whose beta virtual space holds
+    # the SOMOs and whose alpha virtual space does not
+    rng = np.random.default_rng(41 + len(somos) + int(100 * hole))
+    ns = len(somos)
+    inp = make_inputs(rng, n_occ=5, somos=somos, npno=4 + ns, naux=6, shared_space=True, hole=hole)
+    inp.n_sv = [ns] * len(inp.pairs)
+    T = _mask_T(inp, random_T(rng, inp, scale=0.05))
+    R = oracle.residual_os(inp, T)
+    Tb = {(inp.pairs[p], name): v for (p, name), v in T.items()}
+    Kp = {inp.pairs[p]: inp.K[p] for p in range(len(inp.pairs))}
+    Rbf, Ebf = oracle.residual_spinorbital(inp.n_occ, inp.is_somo, inp.B(0), Kp, inp.eps_a[0], inp.eps_b[0],
+                                           inp.f_a, inp.f_b, Tb, inp.pairs, g_occ=inp.g_occ, n_sv=ns)
+    for (p, name), r in R.items():
+        np.testing.assert_allclose(r, Rbf[(inp.pairs[p], name)], rtol=0, atol=1e-13)
+    # the masks matter: the alpha rows of an AB block vanish at the SOMOs, its
+    # beta columns do not
+    p = next(p for p, (i, j) in enumerate(inp.pairs) if (p, "AB") in R and i != j)
+    assert np.all(R[(p, "AB")][-ns:, :] == 0.0) and np.any(R[(p, "AB")][:, -ns:] != 0.0)
+    assert abs(sum(oracle.pair_energies(inp, T).values()) - Ebf) < 1e-14
+
+
+def test_somo_augmentation_leaves_alpha_alpha_blocks_alone():
+    # alpha-alpha amplitudes and residuals live in the PNOs only: augmenting
+    # every space by SOMO functions (identity overlap block, arbitrary
+    # integrals with them) changes no alpha-alpha residual element; with
+    # amplitudes that vanish on the SOMOs the PNO part of every block is
+    # unchanged, while beta blocks extend into the SOMO rows and columns
+    rng = np.random.default_rng(47)
+    inp = make_inputs(rng, n_occ=6, somos=(2, 4), npno=[5] * 21, naux=7, band=5)
+    T = random_T(rng, inp, scale=0.05)
+    R0 = oracle.residual_os(inp, T)
+    ns, P = 2, len(inp.pairs)
+    n = 5 + ns
+
+    def grow(M):
+        out = rng.standard_normal(M.shape[:-2] + (n, n)) * 0.05
+        out[..., :5, :5] = M
+        return out
+    B = {}
+    for p in range(P):
+        b = grow(inp.B(p))
+        B[p] = (b + b.transpose(0, 2, 1)) / 2.0
+        B[p][:, :5, :5] = inp.B(p)
+    K = {p: grow(inp.K[p]) for p in range(P)}
+    ea = {p: np.concatenate([inp.eps_a[p], [9.0, 9.0]]) for p in range(P)}
+    eb = {p: np.concatenate([inp.eps_b[p], rng.uniform(0.1, 0.3, ns)]) for p in range(P)}
+
+    def S(p, q):
+        M = np.zeros((n, n))
+        M[:5, :5] = inp.S(p, q)
+        M[5:, 5:] = np.eye(ns)
+        return M
+    aug = oracle.Inputs(inp.n_occ, inp.is_somo, inp.pairs, B, K, ea, eb, inp.f_a, inp.f_b, S, n_sv=[ns] * P)
+    Ta = {}
+    for key, Tb in T.items():
+        X = np.zeros((n, n))
+        X[:5, :5] = Tb
+        Ta[key] = X
+    Ta = _mask_T(aug, Ta)
+    Ra = oracle.residual_os(aug, Ta)
+    for (p, name), r in R0.items():
+        if name == "AA":
+            np.testing.assert_allclose(Ra[(p, name)][:5, :5], r, rtol=0, atol=1e-15)
+            assert np.all(Ra[(p, name)][5:, :] == 0.0) and np.all(Ra[(p, name)][:, 5:] == 0.0)
+        elif name == "BB":   # beta virtuals include the SOMOs: the block grows into them
+            np.testing.assert_allclose(Ra[(p, name)][:5, :5], r, rtol=0, atol=1e-15)
+            assert np.any(Ra[(p, name)][5:, :] != 0.0)
