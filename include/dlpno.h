@@ -79,7 +79,13 @@ typedef struct {
   int32_t npno;      /* 1..64 */
   int32_t naux;      /* 1..65536 */
   uint32_t blocks;   /* DLPNO_AA | DLPNO_BB | DLPNO_AB | DLPNO_BA */
-  int32_t reserved;
+  int32_t n_somo_virt; /* 0, or the number of SOMOs appended to the pair's PNOs (Sec. II.B.4):
+                        * the last n_somo_virt of the npno virtual functions are SOMOs, which
+                        * are virtual for beta electrons only.  B, K, S and eps cover all npno
+                        * functions (the SOMO part of an overlap block is the identity); every
+                        * residual element whose alpha virtual index falls on a SOMO function
+                        * is zero, and amplitudes must be zero there.  0 <= n_somo_virt <
+                        * npno, at most the number of SOMOs. */
   int64_t off_B, off_T, off_K, off_eps;
 } dlpno_pair;
 

@@ -22,6 +22,8 @@ struct BlockDev {
   double w;                      // energy weight (1/2 same spin, 1 opposite spin)
   int64_t off_ws;                // first partial slot of this block (n*n doubles per slot)
   int32_t nslot, slot_proj;      // partial slots; first projection slot (== nslot: none)
+  int32_t rows, cols;            // rows / columns inside the virtual spaces of s1 / s2 (the
+                                 // others are SOMO functions of an alpha index: residual zero)
 };
 
 // Coupling table (CSR order by target pair).

@@ -478,6 +478,8 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   };
 
   // ---- pairs ----
+  int n_somo_total = 0;
+  for (int k = 0; k < n_occ; ++k) n_somo_total += prob->is_somo[k];
   std::map<std::pair<int, int>, int> index;
   P->pairs_h.resize(npairs);
   int nblk_total = 0;
@@ -489,6 +491,9 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
       return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, "pair " + std::to_string(p) + ": npno must be in 1..64"));
     if (d.naux < 1 || d.naux > 65536)
       return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, "pair " + std::to_string(p) + ": naux must be in 1..65536"));
+    if (d.n_somo_virt < 0 || d.n_somo_virt >= d.npno || d.n_somo_virt > n_somo_total)
+      return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, "pair " + std::to_string(p) +
+                                                        ": n_somo_virt must be below npno and at most the SOMO count"));
     if (!index.emplace(std::make_pair(d.i, d.j), p).second)
       return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "pair " + std::to_string(p) + " duplicates an earlier pair"));
     const uint32_t want = rule_mask(d.i, d.j, prob->is_somo);
@@ -536,6 +541,9 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
       const double* f2 = b.s2 == 0 ? prob->f_a : prob->f_b;
       b.fsum = f1[(size_t)d.i * n_occ + d.i] + f2[(size_t)d.j * n_occ + d.j];
       b.w = b.anti ? 0.5 : 1.0;
+      b.rows = b.s1 == 0 ? pd.n - d.n_somo_virt : pd.n;
+      b.cols = b.s2 == 0 ? pd.n - d.n_somo_virt : pd.n;
+      if (d.n_somo_virt > 0) P->somo_virt = true;
       P->flops_ladder += 4.0 * pd.m * (double)pd.n * pd.n * pd.n;
       ++slot;
     }

@@ -53,6 +53,7 @@ struct dlpno_plan {
   std::vector<uint8_t> somo;
   std::vector<dlpno::PairDev> pairs_h;
   std::vector<dlpno::BlockDev> blocks_h;
+  bool somo_virt = false;                // some pair has SOMO virtual functions
   std::vector<dlpno::CplDev> cpl_h;
   std::vector<dlpno::TermDev> terms_h;
   std::vector<int64_t> rowptr_h;

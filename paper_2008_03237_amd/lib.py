@@ -19,7 +19,7 @@ class DlpnoError(RuntimeError):
 
 class Pair(C.Structure):
     _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("npno", C.c_int32), ("naux", C.c_int32),
-                ("blocks", C.c_uint32), ("reserved", C.c_int32), ("off_B", C.c_int64), ("off_T", C.c_int64),
+                ("blocks", C.c_uint32), ("n_somo_virt", C.c_int32), ("off_B", C.c_int64), ("off_T", C.c_int64),
                 ("off_K", C.c_int64), ("off_eps", C.c_int64)]
 
 
@@ -47,7 +47,7 @@ class Options(C.Structure):
 
 
 PAIR_DTYPE = np.dtype([("i", "<i4"), ("j", "<i4"), ("npno", "<i4"), ("naux", "<i4"), ("blocks", "<u4"),
-                       ("reserved", "<i4"), ("off_B", "<i8"), ("off_T", "<i8"), ("off_K", "<i8"),
+                       ("n_somo_virt", "<i4"), ("off_B", "<i8"), ("off_T", "<i8"), ("off_K", "<i8"),
                        ("off_eps", "<i8")])
 CPL_DTYPE = np.dtype([("src_pair", "<i4"), ("k", "<i4"), ("side", "<i4"), ("reserved", "<i4"), ("off_S", "<i8")])
 HH_DTYPE = np.dtype([("src_pair", "<i4"), ("k", "<i4"), ("l", "<i4"), ("reserved", "<i4"), ("off_S", "<i8"),
@@ -152,6 +152,8 @@ class Plan:
         pairs = np.zeros(P, dtype=PAIR_DTYPE)
         pairs["i"], pairs["j"], pairs["npno"], pairs["naux"] = desc.pi, desc.pj, desc.npno, desc.naux
         pairs["blocks"] = desc.blocks
+        if getattr(desc, "n_sv", None) is not None:
+            pairs["n_somo_virt"] = desc.n_sv
         pairs["off_B"], pairs["off_T"], pairs["off_K"], pairs["off_eps"] = desc.off_B, desc.off_T, desc.off_K, desc.off_eps
         ncpl = len(desc.cpl_src)
         cpl = np.zeros(max(ncpl, 1), dtype=CPL_DTYPE)

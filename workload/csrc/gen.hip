@@ -76,6 +76,17 @@ __global__ __launch_bounds__(256) void gen_kernel(const Seg* segs, int64_t nseg,
           v = z * ldexp(1.0, -((x + y) / sg.pad)) * sg.scale;
           break;
         }
+        case 7:
+        case 8: {   // overlap of SOMO-augmented PNO sets: identity on the last pad rows/columns
+          const int xs = x - (sg.rows - sg.pad), ys = y - (sg.cols - sg.pad);
+          if (xs < 0 && ys < 0) {
+            const uint64_t idx = sg.mode == 7 ? lay + (uint64_t)x * 64u + y : lay + (uint64_t)y * 64u + x;
+            v = normal(idx, sg.stream, sg.field, seed) * sg.scale;
+          } else {
+            v = (xs >= 0 && xs == ys) ? 1.0 : 0.0;
+          }
+          break;
+        }
         case 6: {   // symmetric Fock-like block: 0.2 + 2.8 u on the diagonal
           const int lo = x < y ? x : y, hi = x < y ? y : x;
           const uint64_t idx = lay + (uint64_t)lo * 64u + hi;

@@ -45,6 +45,7 @@ SIGMA_W = 0.05
 
 # segment generation modes (see segment_values)
 MODE_PLAIN, MODE_SYM, MODE_ANTI, MODE_TRANS, MODE_EYE, MODE_DECAY, MODE_FOCK = 0, 1, 2, 3, 4, 5, 6
+MODE_AUG_PLAIN, MODE_AUG_TRANS = 7, 8
 
 SEG_DTYPE = np.dtype([("off", np.int64), ("stream", np.int64), ("field", np.int32),
                       ("mode", np.int32), ("layers", np.int32), ("rows", np.int32),
@@ -133,6 +134,30 @@ class Problem:
     hh_off_S: np.ndarray = None
     hole_scale: float = 0.0
     hole_range: int = 2
+    # SOMO virtual functions appended to every pair's PNOs (None: none)
+    n_sv: np.ndarray = None
+
+    def t_mask(self):
+        """Flat boolean array over the amplitude layout: True inside the
+        virtual spaces of each block's spins (everything, without SOMO
+        virtual functions)."""
+        mask = np.ones(self.n_T, dtype=bool)
+        if self.n_sv is None:
+            return mask
+        for p in range(self.n_pairs):
+            n, ns, o = int(self.npno[p]), int(self.n_sv[p]), int(self.off_T[p])
+            for name in BLOCK_NAMES:
+                if not self.blocks[p] & BLOCK_BITS[name]:
+                    continue
+                s1, s2 = BLOCK_SPINS[name]
+                m = np.ones((n, n), dtype=bool)
+                if s1 == 0 and ns:
+                    m[n - ns:, :] = False
+                if s2 == 0 and ns:
+                    m[:, n - ns:] = False
+                mask[o:o + n * n] = m.ravel()
+                o += n * n
+        return mask
 
     @property
     def n_hh(self):
@@ -222,6 +247,14 @@ def segment_values(seed, seg):
         z = philox.normals(seed, fld, stream, idx) * scale
         u = philox.uniforms(seed, fld, stream, idx)
         return np.where(x == y, 0.2 + 2.8 * u, z) + np.zeros((L, 1, 1))
+    elif mode in (MODE_AUG_PLAIN, MODE_AUG_TRANS):
+        # overlap block of two SOMO-augmented PNO sets: the PNO part as
+        # MODE_PLAIN / MODE_TRANS, the last pad rows and columns the identity
+        ns = int(seg["pad"])
+        idx = lay + (x * np.uint64(64) + y if mode == MODE_AUG_PLAIN else y * np.uint64(64) + x)
+        z = philox.normals(seed, fld, stream, idx) * scale
+        xs, ys = x.astype(np.int64) - (R - ns), y.astype(np.int64) - (C - ns)
+        return np.where((xs < 0) & (ys < 0), z, np.where((xs >= 0) & (xs == ys), 1.0, 0.0)) + np.zeros((L, 1, 1))
     elif mode == MODE_EYE:
         # identity blocks (the overlap of a pair's PNOs with themselves)
         return np.broadcast_to((x == y).astype(np.float64), (L, R, C)).copy()
@@ -289,7 +322,13 @@ def build_problem(name="tiny", **override):
     (k i | l j) drawn by occ_eri with scale c and range d (default 0: no
     hole-hole term), with one coupling per target pair (i, j) and ordered
     occupied pair (k, l) whose integral is non-zero and whose pair {k, l} is
-    retained (the pair itself included: its overlap block is the identity)."""
+    retained (the pair itself included: its overlap block is the identity);
+    somo_virt=True: every pair's PNOs are followed by the SOMOs as virtual
+    functions for beta electrons (Sec. II.B.4): n_p = min(n_p, 64 - N_SOMO) +
+    N_SOMO, B and K cover all of them, the SOMO part of every overlap block
+    is the identity, the SOMOs' beta virtual energies are 0.1 + 0.2 u (the
+    alpha entries there are the same numbers and never used), and
+    Problem.t_mask() gives the amplitude elements that exist."""
     cfg = dict(CONFIGS[name]) if name in CONFIGS else {}
     cfg.update(override)
     seed = int(cfg["seed"])
@@ -313,6 +352,11 @@ def build_problem(name="tiny", **override):
 
     npno = _dims(cfg["npno"], seed, F_NPNO, P)
     naux = _dims(cfg["naux"], seed, F_NAUX, P)
+    n_sv = None
+    if cfg.get("somo_virt", False):
+        ns = len(cfg["somos"])
+        npno = (np.minimum(npno, 64 - ns) + ns).astype(np.int32)
+        n_sv = np.full(P, ns, dtype=np.int32)
 
     blocks = np.zeros(P, dtype=np.uint32)
     nblk = np.zeros(P, dtype=np.int64)
@@ -369,8 +413,13 @@ def build_problem(name="tiny", **override):
         ea = 0.2 + 2.8 * u
         d = np.minimum(np.abs(pi[p] - np.array(somos)), np.abs(pj[p] - np.array(somos))) if somos else np.zeros(0)
         shift = float(np.sum(0.05 * np.exp(-d / 2.0)))
+        eb = ea + shift
+        if n_sv is not None and n_sv[p]:
+            ns = int(n_sv[p])
+            ea[n - ns:] = 0.1 + 0.2 * u[n - ns:]
+            eb[n - ns:] = ea[n - ns:]
         eps_a[off_eps[p]:off_eps[p] + n] = ea
-        eps_b[off_eps[p]:off_eps[p] + n] = ea + shift
+        eps_b[off_eps[p]:off_eps[p] + n] = eb
 
     # ---- couplings (CSR by target) ----
     src, kk, side = [], [], []
@@ -470,8 +519,9 @@ def build_problem(name="tiny", **override):
     if cfg["S"] == "qr60":
         # orthonormal PNO bases over a shared 60-dimensional virtual space
         Qs = []
+        nsv = np.zeros(P, dtype=np.int64) if n_sv is None else n_sv
         for p in range(P):
-            n = int(npno[p])
+            n = int(npno[p] - nsv[p])
             G = philox.normals(seed, F_QR, p, (np.arange(60)[:, None] * 64 + np.arange(n)[None, :]).astype(np.uint64))
             Qm, Rm = np.linalg.qr(G)
             Qs.append(Qm * np.sign(np.diag(Rm))[None, :])
@@ -479,6 +529,11 @@ def build_problem(name="tiny", **override):
         for u, k in enumerate(ukey):
             p, q = int(k // P), int(k % P)
             W = np.eye(int(npno[p])) if p == q else Qs[q].T @ Qs[p]     # [c][a] = <c_q | a_p>
+            if p != q and nsv[p]:        # SOMO functions: identity block
+                Wa = np.zeros((int(npno[q]), int(npno[p])))
+                Wa[:W.shape[0], :W.shape[1]] = W
+                Wa[W.shape[0]:, W.shape[1]:] = np.eye(int(nsv[p]))
+                W = Wa
             S_host[off_dir[u]:off_dir[u] + W.size] = W.ravel()
     else:
         # random overlaps: S_{lo,hi} = sigma * Z (n_lo x n_hi), S_{hi,lo} = its transpose
@@ -493,6 +548,9 @@ def build_problem(name="tiny", **override):
         # stored W[c][a] (c on source q, a on target p) = S_{q,p}[c][a]:
         #   q == lo: Z[c][a] (plain); q == hi: Z[a][c] (transposed)
         segS["mode"] = np.where(q_s == p_t, MODE_EYE, np.where(q_s < p_t, MODE_PLAIN, MODE_TRANS))
+        if n_sv is not None:
+            segS["mode"] = np.where(q_s == p_t, MODE_EYE, np.where(q_s < p_t, MODE_AUG_PLAIN, MODE_AUG_TRANS))
+            segS["pad"] = n_sv[p_t]
         segS["layers"] = 1
         segS["rows"] = npno[q_s]
         segS["cols"] = npno[p_t]
@@ -509,4 +567,5 @@ def build_problem(name="tiny", **override):
                    cpl_side=cpl_side, cpl_off_S=cpl_off_S, f_a=f_a, f_b=f_b, eps_a=eps_a,
                    eps_b=eps_b, n_B=n_B, n_T=n_T, n_K=n_K, n_S=n_S, segs=segs, S_host=S_host,
                    pair_index=pair_index, hh_rowptr=hh_rowptr, hh_src=hh_src, hh_k=hh_k, hh_l=hh_l,
-                   hh_w=hh_w, hh_off_S=hh_off_S.astype(np.int64), hole_scale=hh_scale, hole_range=hh_range)
+                   hh_w=hh_w, hh_off_S=hh_off_S.astype(np.int64), hole_scale=hh_scale, hole_range=hh_range,
+                   n_sv=n_sv)
