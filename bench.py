@@ -112,11 +112,14 @@ def main():
     ap.add_argument("--no-f12", action="store_true", help="skip the F12-correction leg")
     ap.add_argument("--mixed-precisions", default="bf16x2,fp16x2",
                     help="comma-separated split precisions of the mixed leg (bf16x2, fp16x2, fp32)")
-    ap.add_argument("--mixed-outer", type=int, default=3, help="FP64 refinement steps")
+    ap.add_argument("--mixed-outer", type=int, default=2, help="FP64 refinement steps")
     ap.add_argument("--mixed-inner", type=int, default=4, help="low-precision iterations per refinement step")
+    ap.add_argument("--mixed-also", default="3x3",
+                    help="further refinement schedules OUTERxINNER timed for every split precision ('' = none)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-path leg")
     ap.add_argument("--no-hole", action="store_true", help="skip the hole-hole ladder leg")
     ap.add_argument("--no-pno", action="store_true", help="skip the PNO-construction leg")
+    ap.add_argument("--no-somo-virt", action="store_true", help="skip the SOMO-augmented virtual space leg")
     ap.add_argument("--hole-scale", type=float, default=0.02,
                     help="scale of the synthetic occupied integrals of the hole-hole ladder leg")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -272,9 +275,14 @@ def main():
         out["hole_ladder"] = hole_leg(args, dev, eps_a, eps_b, fl_proj, log)
     if not args.no_pno:
         out["pno"] = pno_leg(args, log)
+    plan.close()
+    if not args.no_somo_virt and args.precision == "fp64":
+        # the main leg's inputs make room for the larger augmented ones
+        del plan, dev, T, eps_a, eps_b
+        torch.cuda.empty_cache()
+        out["somo_virt"] = somo_virt_leg(args, flops, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(prob, n_pairs=args.cpu_pairs)
-    plan.close()
     print(json.dumps(out), flush=True)
 
 
@@ -411,6 +419,40 @@ def pno_leg(args, log):
     return res
 
 
+def somo_virt_leg(args, flops_base, log):
+    """The same workload with every PNO set augmented by the SOMOs as beta-only
+    virtual functions (n_p + 2 functions per pair, masks on the alpha
+    indices): FP64 iterations from T = 0, timed like the main leg."""
+    import torch
+
+    from paper_2008_03237_amd import Plan
+    from workload import build_problem
+    from workload.gpu import device_fields
+    prob = build_problem(args.workload, somo_virt=True)
+    dev = device_fields(prob, fields=("B", "S", "K"))
+    eps_a = torch.from_numpy(prob.eps_a).cuda()
+    eps_b = torch.from_numpy(prob.eps_b).cuda()
+    plan = Plan(prob, dev["B"], dev["S"], dev["K"], eps_a, eps_b)
+    T = torch.zeros(max(prob.n_T, 1), dtype=torch.float64, device="cuda")
+    plan.iterate(args.warmup, T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, e_tot, rmax = plan.iterate(args.steps, T)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) / max(args.steps, 1) * 1e3
+    fl, fp = plan.flop_count()
+    row = {"pno_plus_somo_mean": round(float(prob.npno.mean()), 2), "ms_per_step": round(ms_step, 3),
+           "value_gflops": round((fl + fp) / (ms_step / 1e3) / 1e9, 2), "flops": fl + fp,
+           "flops_vs_main": round((fl + fp) / flops_base, 4), "energy_after": float(e_tot.cpu()[0]),
+           "iterations": args.warmup + args.steps, "max_abs_R": float(rmax.cpu()[0]),
+           "B_GB": round(prob.n_B * 8 / 1e9, 2)}
+    log("SOMO-augmented leg: %s" % row)
+    plan.close()
+    del dev, T
+    torch.cuda.empty_cache()
+    return row
+
+
 def hole_leg(args, dev, eps_a, eps_b, fl_proj_base, log):
     """The same workload with the hole-hole ladder added (the first of the
     CCSD terms beyond the hot path's model): synthetic occupied integrals
@@ -491,6 +533,25 @@ def split_precision_row(prob, dev, eps_a, eps_b, precision, args, flops, ref, lo
     _, em, etm, rm = mp.solve_mixed(args.mixed_outer, args.mixed_inner, Tm)
     torch.cuda.synchronize()
     tm = time.perf_counter() - t0
+    emn = em.cpu().numpy().reshape(-1, 4).sum(1)
+    # other schedules (e.g. three refinements), each from T = 0
+    others = {}
+    for sched in [x for x in args.mixed_also.split(",") if x]:
+        no, ni = (int(v) for v in sched.split("x"))
+        To = torch.zeros_like(Tm)
+        mp.reset()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, eo, eto, ro = mp.solve_mixed(no, ni, To)
+        torch.cuda.synchronize()
+        eon = eo.cpu().numpy().reshape(-1, 4).sum(1)
+        te = abs(float(eto.cpu()[0]) - ref["energy"])
+        pe = float(np.max(np.abs(eon - ref["e_pair"])))
+        others[sched] = {"mixed_solve_s": round(time.perf_counter() - t1, 3),
+                         "vs_fp64_solve": round((time.perf_counter() - t1) / ref["seconds"], 3),
+                         "total_energy_error": te, "max_pair_energy_error": pe,
+                         "gate_1e-7_pair_1e-6_total": bool(pe <= 1e-7 and te <= 1e-6)}
+        del To
     # split grouped kernel alone (HIP events inside the library)
     mp.set_profiling(True)
     for _ in range(3):
@@ -501,7 +562,6 @@ def split_precision_row(prob, dev, eps_a, eps_b, precision, args, flops, ref, lo
     k_proj = ms[5] / max(cnt[5], 1)
     k_ms = k_lad + k_proj
     conv_ms = ms[4] / max(cnt[4], 1)
-    emn = em.cpu().numpy().reshape(-1, 4).sum(1)
     # inner only: the low-precision residuals iterated (FP64 update, energies
     # and DIIS) with no FP64 refinement, until max|R| stops falling
     Ti = torch.zeros_like(Tm)
@@ -534,6 +594,7 @@ def split_precision_row(prob, dev, eps_a, eps_b, precision, args, flops, ref, lo
            "inner_only": {"iterations": n_in, "max_abs_R": r_now,
                           "total_energy_error": abs(float(eti.cpu()[0]) - ref["energy"]),
                           "max_pair_energy_error": float(np.max(np.abs(ein - ref["e_pair"])))},
+           "other_schedules": others,
            "split_bytes_per_launch": split_B + split_S,
            "hbm_frac": round((split_B + split_S) / (k_ms / 1e3) / 8e12, 4)}
     log("mixed leg %s: %s" % (precision, row))
