@@ -128,6 +128,8 @@ def main():
                     help="profiling run: only N residual evaluations per precision of --profile-precisions "
                          "(default schedule), one JSON line of their kernel times, nothing else")
     ap.add_argument("--profile-precisions", default="fp64,bf16x2,fp16x2")
+    ap.add_argument("--profile-pno", type=int, default=0,
+                    help="profiling run: only N PNO builds and N overlap launches of the workload, one JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: runs on one GPU only (sharding the pairs across GPUs is not implemented); "
@@ -151,6 +153,9 @@ def main():
         y.copy_(x)
         torch.cuda.synchronize()
         del x, y
+    if args.profile_pno > 0:
+        print(json.dumps(profile_pno(args, log)), flush=True)
+        return
     prob = build_problem(args.workload)
     log("workload %s: %d pairs, %d couplings" % (args.workload, prob.n_pairs, prob.n_couplings))
     dev = device_fields(prob)
@@ -409,13 +414,57 @@ def pno_leg(args, log):
     ms_o = a.elapsed_time(b) / reps
     nbytes = 8 * (rp.n_S + prob.n_C)
     log("PNO overlaps: %d couplings in %.3f ms" % (int(rp.cpl_rowptr[-1]), ms_o))
+    # counter record (rocprofv3 FETCH_SIZE + WRITE_SIZE of one launch), used
+    # only while it describes this source and workload
+    traffic = None
+    cfile = os.path.join(ROOT, "profiles", "pno_%s_counters.json" % args.workload)
+    if os.path.exists(cfile):
+        with open(cfile) as f:
+            rec = json.load(f)
+        if rec.get("pno_source_sha") == pno_source_sha():
+            traffic = rec.get("overlap_bytes_per_launch")
     res["overlap"] = {"kernel": "pno_overlap_kernel", "couplings": int(rp.cpl_rowptr[-1]), "ms": round(ms_o, 3),
                       "S_GB": round(rp.n_S * 8 / 1e9, 2),
                       "roofline": {"bound": "hbm", "achieved": round(nbytes / (ms_o / 1e3) / 1e9, 1), "peak": 8000.0,
                                    "unit": "GB/s", "frac": round(nbytes / (ms_o / 1e3) / 8e12, 4),
-                                   "algorithmic_bytes": nbytes}}
+                                   "algorithmic_bytes": nbytes, "traffic": traffic}}
     plan.close()
     del dev, S, out
+    return res
+
+
+def profile_pno(args, log):
+    """args.profile_pno PNO builds and overlap launches of the workload (for
+    rocprofv3), with their HIP-event times."""
+    import numpy as np
+    import torch
+
+    from paper_2008_03237_amd import PnoPlan
+    from workload import build_problem
+    from workload.gpu import device_pno_fields
+    from workload.pno import build_pno_problem
+    prob = build_pno_problem(args.workload)
+    dev = device_pno_fields(prob)
+    plan = PnoPlan(prob.pairs, prob.n_X, prob.n_F, prob.n_C, prob.n_v)
+    out = plan.build(dev["X"], dev["F"], prob.t_cut, want_sweeps=True)
+    torch.cuda.synchronize()
+    nk = out[3].cpu().numpy().astype(np.int64)
+    rp = build_problem(args.workload, npno=("given", np.maximum(nk, 1)))
+    plan.overlap_prepare(nk, rp.cpl_rowptr, rp.cpl_src, rp.cpl_off_S, rp.n_S)
+    S = plan.overlap(out[2])
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {"workload": args.workload, "pairs": prob.n_pairs, "couplings": int(rp.cpl_rowptr[-1])}
+    for name, fn in (("pno_build_kernel", lambda: plan.build(dev["X"], dev["F"], prob.t_cut, *out[:4], sweeps=out[4])),
+                     ("pno_overlap_kernel", lambda: plan.overlap(out[2], S))):
+        a.record()
+        for _ in range(args.profile_pno):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        res[name + "_ms"] = round(a.elapsed_time(b) / args.profile_pno, 3)
+        log("%s: %.3f ms" % (name, res[name + "_ms"]))
+    plan.close()
     return res
 
 
@@ -684,6 +733,14 @@ def kernel_source_sha():
         with open(os.path.join(ROOT, "paper_2008_03237_amd", "csrc", f)) as fh:
             h.update(_code_only(fh.read()).encode())
     return h.hexdigest()[:16]
+
+
+def pno_source_sha():
+    """Hash of the PNO kernels' source, comments left out (the counter record
+    of the PNO leg is used only while it describes this code)."""
+    import hashlib
+    with open(os.path.join(ROOT, "paper_2008_03237_amd", "csrc", "pno.hip")) as fh:
+        return hashlib.sha256(_code_only(fh.read()).encode()).hexdigest()[:16]
 
 
 if __name__ == "__main__":
