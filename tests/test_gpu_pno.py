@@ -122,8 +122,10 @@ def test_pno_keep_all_and_keep_none():
     assert np.array_equal(got[3], prob.pairs["dim"])
     for p in range(0, prob.n_pairs, 3):
         check_pair(prob, p, got, -1.0, guard=False)
-    got = run_gpu(prob, t_cut=1.0)            # none kept
-    assert np.all(got[3] == 0) and np.all(got[2][:prob.n_C] == 0.0)
+    got = run_gpu(prob, t_cut=1.0)            # none kept: every pair's C block is zero
+    assert np.all(got[3] == 0)
+    for d in prob.pairs:                      # (the alignment gaps between blocks are never written)
+        assert np.all(got[2][d["off_C"]:d["off_C"] + d["dim"] ** 2] == 0.0)
     for p in range(0, prob.n_pairs, 5):
         check_pair(prob, p, got, 1.0)
 
