@@ -86,6 +86,7 @@ class Inputs:
         self._S = S
         self.occ_ints = occ_ints
         self.n_sv = None if n_sv is None else [int(x) for x in n_sv]
+        self.quadratic = False   # add the quadratic term over the hole-hole couplings
 
     def B(self, p):
         return self._B(p) if callable(self._B) else self._B[p]
@@ -172,7 +173,9 @@ class Inputs:
         if prob.hole_scale != 0.0:
             occ = _WorkloadOccInts(prob)
         n_sv = getattr(prob, "n_sv", None)
-        return cls(prob.n_occ, prob.is_somo, pairs, Bf, Kd, ea, eb, prob.f_a, prob.f_b, Sf, occ, n_sv)
+        inp = cls(prob.n_occ, prob.is_somo, pairs, Bf, Kd, ea, eb, prob.f_a, prob.f_b, Sf, occ, n_sv)
+        inp.quadratic = bool(getattr(prob, "quadratic", False))
+        return inp
 
 
 class _WorkloadOccInts:
@@ -292,7 +295,26 @@ def projection_terms(inp, T, p, name):
     return out
 
 
-def hole_terms(inp, T, p, name):
+def quadratic_weight(inp, T, p, name, k, l, q, Spq):
+    """Weight that the quadratic CCSD term adds to the hole-hole coupling
+    (k, l) of block `name` of pair p (source pair q = {k, l}, S_pq = S(p, q)).
+
+    In spin orbitals the term is 1/4 sum_KLCD <KL||CD> t_IJ^CD t_KL^AB, i.e.
+    the hole-hole ladder 1/2 sum_KL W_KLIJ t_KL^AB with <KL||IJ> replaced by
+    W_KLIJ = 1/2 sum_CD <KL||CD> t_IJ^CD.  Reduced to spin blocks like the
+    hole-hole term, W adds c_ss' <(k c | l d), T^{ss'}_p> to (k i | l j), with
+    c = 1/2 for same spin and 1 for opposite spin, c and d in pair p's PNOs.
+    Reading: (k c | l d) in pair p's PNOs is the projection S_pq K_(k,l) S_pq^T
+    of pair q's exchange integrals K_q = (min a | max b) (K_q^T when k > l):
+    exact when the two pairs share their PNOs (the canonical limit, where a
+    brute-force pin checks it)."""
+    s1, s2 = SPIN[name]
+    Kq = inp.K[q] if k <= l else inp.K[q].T
+    c = 0.5 if s1 == s2 else 1.0
+    return c * float(np.sum((Spq @ Kq @ Spq.T) * T[(p, name)]))
+
+
+def hole_terms(inp, T, p, name, quadratic=False):
     """The hole-hole ladder terms of block `name` of pair p = (i, j): list of
     (weight, q, S_pq, source tuple from t_lookup).
 
@@ -316,18 +338,23 @@ def hole_terms(inp, T, p, name):
             if l not in occ2:
                 continue
             w = inp.occ_ints.value(k, i, l, j)
-            if w == 0.0:
+            if w == 0.0 and not quadratic:
                 continue
             src = t_lookup(inp, T, k, l, s1, s2)
             if src is None:
                 continue
-            out.append((w, src[0], inp.S(p, src[0]), src))
+            Spq = inp.S(p, src[0])
+            if quadratic:
+                w += quadratic_weight(inp, T, p, name, k, l, src[0], Spq)
+            out.append((w, src[0], Spq, src))
     return out
 
 
-def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladder", "hole")):
+def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladder", "hole", "quadratic")):
     """Open-shell residual blocks {(p, name): R} for the given target pairs.
-    The hole-hole term is present only when inp.occ_ints is given.  With SOMO
+    The hole-hole term is present only when inp.occ_ints is given; with
+    inp.quadratic set, its couplings carry the quadratic CCSD term too
+    (quadratic_weight).  With SOMO
     virtual functions (inp.n_sv) each block is the model residual restricted
     to its spins' virtual spaces (the rows of an alpha virtual index and the
     columns of an alpha virtual index vanish at SOMO functions); amplitudes
@@ -348,7 +375,8 @@ def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladd
             if "ladder" in terms:
                 r += ladder(Bp, Tb)
             if "hole" in terms:
-                for w, q, Spq, src in hole_terms(inp, T, p, name):
+                quad = "quadratic" in terms and getattr(inp, "quadratic", False)
+                for w, q, Spq, src in hole_terms(inp, T, p, name, quadratic=quad):
                     r += w * (Spq @ src[3] @ Spq.T)
             if inp.n_sv is not None:
                 s1, s2 = SPIN[name]

@@ -10,6 +10,7 @@ terms of the model are formed from explicit antisymmetrised integrals:
   R_IJ^AB = <AB||IJ> + (e_A + e_B) t_IJ^AB - sum_K f_KI t_KJ^AB
             - sum_K f_KJ t_IK^AB + 1/2 sum_CD <AB||CD> t_IJ^CD
             + 1/2 sum_KL <KL||IJ> t_KL^AB
+           [+ 1/4 sum_KLCD <KL||CD> t_IJ^CD t_KL^AB]
   E       = 1/4 sum_IJAB <IJ||AB> t_IJ^AB
 
 with (ac|bd) = sum_Q B^Q_ac B^Q_bd, (ia|jb) given per ordered pair and the
@@ -27,7 +28,8 @@ def _spin_orbitals(n_occ, is_somo, V, n_sv=0):
     return occ, vir
 
 
-def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblocks, pairs, g_occ=None, n_sv=0):
+def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblocks, pairs, g_occ=None, n_sv=0,
+                         quadratic=False):
     """Pair blocks of the residual and the total energy of the given amplitudes.
 
     Bg       (m, V, V) three-index integrals shared by all pairs
@@ -36,6 +38,7 @@ def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblo
     pairs    list of (i, j) covering every occupied pair (i <= j)
     g_occ    optional (n_occ, n_occ, n_occ, n_occ) array g[k, i, l, j] = (k i | l j)
     n_sv     SOMO functions among the V (the last n_sv; beta virtual only)
+    quadratic  add 1/4 sum_KLCD <KL||CD> t_IJ^CD t_KL^AB
     Returns ({((i, j), name): V x V residual block, zero outside the blocks'
     virtual spaces}, energy of the amplitudes).
     """
@@ -111,6 +114,9 @@ def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblo
                             v -= g_occ[k, j, l, i]
                         g_oooo[K, L, I, J] = v
         R = R + 0.5 * np.einsum("klij,klab->ijab", g_oooo, t)
+    if quadratic:
+        # <KL||CD> = <CD||KL> (real orbitals) = g_vvoo[C, D, K, L]
+        R = R + 0.25 * np.einsum("cdkl,ijcd,klab->ijab", g_vvoo, t, t)
     E = 0.25 * float(np.sum(g_vvoo.transpose(2, 3, 0, 1) * t))
     out = {}
     for (i, j) in pairs:

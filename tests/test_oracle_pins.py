@@ -483,3 +483,47 @@ def test_somo_augmentation_leaves_alpha_alpha_blocks_alone():
         elif name == "BB":   # beta virtuals include the SOMOs: the block grows into them
             np.testing.assert_allclose(Ra[(p, name)][:5, :5], r, rtol=0, atol=1e-15)
             assert np.any(Ra[(p, name)][5:, :] != 0.0)
+
+
+# ------------------- quadratic CCSD term over the hole-hole couplings
+@pytest.mark.parametrize("somos", [(), (1,), (1, 3)])
+def test_quadratic_term_canonical_limit_matches_bruteforce(somos):
+    # 1/4 sum_KLCD <KL||CD> t_IJ^CD t_KL^AB from explicit antisymmetrised
+    # integrals, against the pair form: the hole-hole couplings with the
+    # weights (k i | l j) + c <K_(k,l), T_ij> (c = 1/2 same spin, 1 opposite)
+    rng = np.random.default_rng(61 + len(somos))
+    inp = make_inputs(rng, n_occ=5, somos=somos, npno=5, naux=6, shared_space=True, hole=0.05)
+    inp.quadratic = True
+    T = random_T(rng, inp, scale=0.2)
+    R = oracle.residual_os(inp, T)
+    Tb = {(inp.pairs[p], name): v for (p, name), v in T.items()}
+    Kp = {inp.pairs[p]: inp.K[p] for p in range(len(inp.pairs))}
+    Rbf, _ = oracle.residual_spinorbital(inp.n_occ, inp.is_somo, inp.B(0), Kp, inp.eps_a[0], inp.eps_b[0],
+                                         inp.f_a, inp.f_b, Tb, inp.pairs, g_occ=inp.g_occ, quadratic=True)
+    Rlin, _ = oracle.residual_spinorbital(inp.n_occ, inp.is_somo, inp.B(0), Kp, inp.eps_a[0], inp.eps_b[0],
+                                          inp.f_a, inp.f_b, Tb, inp.pairs, g_occ=inp.g_occ)
+    big = 0.0
+    for (p, name), r in R.items():
+        np.testing.assert_allclose(r, Rbf[(inp.pairs[p], name)], rtol=0, atol=1e-13)
+        big = max(big, np.abs(Rbf[(inp.pairs[p], name)] - Rlin[(inp.pairs[p], name)]).max())
+    assert big > 1e-4            # the quadratic term is not negligible at these amplitudes
+
+
+def test_quadratic_term_is_quadratic():
+    # R(T) - R_linear(T) scales as the square of T and vanishes with T
+    rng = np.random.default_rng(67)
+    inp = make_inputs(rng, n_occ=6, somos=(2,), npno=[6] * 21, naux=5, hole=0.05)
+    T = random_T(rng, inp, scale=0.1)
+    lin = ("driver", "fock", "projection", "ladder", "hole")
+
+    def quad(x):
+        Tx = {k: x * v for k, v in T.items()}
+        inp.quadratic = True
+        Rq = oracle.residual_os(inp, Tx)
+        inp.quadratic = False
+        Rl = oracle.residual_os(inp, Tx, terms=lin)
+        return {k: Rq[k] - Rl[k] for k in Rq}
+    d1, d2 = quad(1.0), quad(2.0)
+    for k in d1:
+        np.testing.assert_allclose(d2[k], 4.0 * d1[k], rtol=1e-9, atol=1e-13)
+    assert max(np.abs(v).max() for v in d1.values()) > 1e-6
