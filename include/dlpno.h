@@ -171,6 +171,18 @@ typedef struct {
  * compute every tile. */
 #define DLPNO_FLAG_GENERAL_T 1
 
+/* Adds the quadratic CCSD term 1/4 sum_KLCD <KL||CD> t_IJ^CD t_KL^AB over the
+ * hole-hole couplings (so n_hh > 0 is required; FP64 plans only).  Reduced to
+ * spin blocks it is the hole-hole ladder with the weights (k i | l j) +
+ * c <K_(k,l), S_pq^T T_p S_pq>, c = 1/2 same spin and 1 opposite spin,
+ * K_(k,l)[c][d] = (k c | l d) over the source pair's PNOs (its K block, or the
+ * transpose for k > l): the integrals in the target's PNOs are taken as the
+ * projection S_pq K_(k,l) S_pq^T.  Every residual evaluation first computes
+ * the weights from its T (a separate kernel, phase 9 of dlpno_phase_times);
+ * the residual is then quadratic in T.  Vector-Jacobian products and
+ * low-precision plans refuse such plans. */
+#define DLPNO_FLAG_QUADRATIC 2
+
 typedef struct dlpno_plan dlpno_plan;   /* opaque, owned by the library */
 
 /* Validates the descriptors (ranges, offsets against the buffer sizes, the
@@ -331,7 +343,8 @@ dlpno_status dlpno_autotune_cached(dlpno_plan* plan, const double* T, double* R,
  *   waves per SIMD (FP64 plans: pairs of at most 48 PNOs), 7 cooperative
  *   ladder launch (FP64 plans: pairs of 49 to 64 PNOs, one workgroup per
  *   item), 8 projection items run at two waves per SIMD (FP64 plans: target
- *   and source pairs of at most 48 PNOs). */
+ *   and source pairs of at most 48 PNOs), 9 weights of the quadratic term
+ *   (DLPNO_FLAG_QUADRATIC). */
 dlpno_status dlpno_set_profiling(dlpno_plan* plan, int32_t enable);
 dlpno_status dlpno_phase_times(const dlpno_plan* plan, double* ms, int64_t* launches, int32_t n);
 

@@ -177,6 +177,10 @@ __global__ __launch_bounds__(256) void s_transpose_check_kernel(const SPair* pr,
 static dlpno_status check_vjp_preconditions(dlpno_plan* P, hipStream_t s) {
   if (P->vjp_checked != 0) return P->vjp_checked > 0 ? DLPNO_OK : fail(DLPNO_ERR_UNSUPPORTED, P->vjp_reason);
   P->vjp_checked = -1;
+  if (!P->quad_h.empty()) {
+    P->vjp_reason = "vector-Jacobian product: not available with the quadratic term";
+    return fail(DLPNO_ERR_UNSUPPORTED, P->vjp_reason);
+  }
   if (P->somo_virt) {
     P->vjp_reason = "vector-Jacobian product: not available with SOMO virtual functions";
     return fail(DLPNO_ERR_UNSUPPORTED, P->vjp_reason);

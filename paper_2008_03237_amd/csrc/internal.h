@@ -40,6 +40,20 @@ struct TermDev {
   int32_t src_blk;               // global index of the source block
 };
 
+// One hole-hole coupling whose weights carry the quadratic term (quadratic.hip):
+// per active target block, the term to rewrite, the target block in T, the
+// static weight -(k i | l j) and the factor -c (c = 1/2 same spin, 1 opposite).
+struct QuadCpl {
+  int64_t off_S;        // overlap block [c][a], n_q x n_p
+  int64_t off_K;        // K of the source pair, n_q x n_q
+  int32_t np, nq;
+  int32_t transK;       // k > l: K_(k,l) is K_q transposed
+  int32_t nblk;         // active target blocks (1..4)
+  int64_t term[4];      // index into the term table
+  int64_t off_T[4];     // target block in T
+  double w0[4], c[4];
+};
+
 // ITEM_LADDER2: ladder items of an FP64 plan run by the launch at two waves
 // per SIMD (at most three tiles of 16 PNOs and the variants below).
 // ITEM_LADDER4: four-tile ladder items of an FP64 plan, each run by a whole
@@ -152,6 +166,8 @@ constexpr int32_t kErrNoBody = 2;      // a work item had no compiled kernel bod
 hipError_t launch_grouped_f64(const GroupedArgs<double>& a, int kind, int workers, hipStream_t s);
 hipError_t launch_grouped_f32(const GroupedArgs<float>& a, int kind, int workers, hipStream_t s);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);
+hipError_t launch_quad_weights(const QuadCpl* list, int64_t n, const double* S, const double* K, const double* T,
+                               TermDev* terms, hipStream_t s);
 
 // elementwise.hip
 // DIIS on device.  State lives in a small device struct; vectors in rings.

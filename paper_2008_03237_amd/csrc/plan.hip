@@ -422,7 +422,8 @@ std::string dlpno::describe(const dlpno_plan* P) {
     snprintf(buf, sizeof buf, "FP64 items for refinement residuals: %zu\n", P->sched64.items_h.size());
     s += buf;
   }
-  snprintf(buf, sizeof buf, "flops/residual: ladder %.4e projection %.4e\n", P->flops_ladder, P->flops_proj);
+  snprintf(buf, sizeof buf, "flops/residual: ladder %.4e projection %.4e quadratic-term weights %.4e\n",
+           P->flops_ladder, P->flops_proj, P->flops_quad);
   s += buf;
   return s;
 }
@@ -450,7 +451,12 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if (opt.precision < DLPNO_FP64 || opt.precision > DLPNO_FP16X2)
     return fail(DLPNO_ERR_INVALID_ARG, "unknown precision");
   if (opt.diis_max < 0 || opt.diis_max > 8) return fail(DLPNO_ERR_INVALID_ARG, "diis_max must be in 0..8");
-  if ((opt.flags & ~DLPNO_FLAG_GENERAL_T) != 0) return fail(DLPNO_ERR_INVALID_ARG, "unknown option flag");
+  if ((opt.flags & ~(DLPNO_FLAG_GENERAL_T | DLPNO_FLAG_QUADRATIC)) != 0)
+    return fail(DLPNO_ERR_INVALID_ARG, "unknown option flag");
+  const bool quad = (opt.flags & DLPNO_FLAG_QUADRATIC) != 0;
+  if (quad && opt.precision != DLPNO_FP64)
+    return fail(DLPNO_ERR_UNSUPPORTED, "the quadratic term needs an FP64 plan");
+  if (quad && prob->n_hh <= 0) return fail(DLPNO_ERR_INVALID_ARG, "the quadratic term needs hole-hole couplings");
   if (opt.diis_max > 0 && (opt.diis_start < 1 || opt.diis_start > opt.diis_max))
     return fail(DLPNO_ERR_INVALID_ARG, "diis_start must be in 1..diis_max");
   for (int k = 0; k < n_occ; ++k)
@@ -604,7 +610,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
     // the term of merged coupling `e` (source pair q, ordered source (x, y)
     // with electron spins (s1, s2)) on target block slot `slot`, weight w
     auto add_term = [&](int64_t e, int slot, const dlpno_pair& q, int src_pair, int x, int y, int s1, int s2,
-                        double w) {
+                        double w, bool is_hh) {
       int scode, trans;
       if (x == y) {
         if (s1 == s2) return;                               // Pauli
@@ -617,7 +623,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
         scode = block_code(s2, s1);
         trans = 1;
       }
-      if (!(q.blocks & kCodeBit[scode]) || w == 0.0) return;
+      if (!(q.blocks & kCodeBit[scode]) || (w == 0.0 && !(quad && is_hh))) return;
       int sslot = 0;
       for (int cc = 0; cc < scode; ++cc)
         if (q.blocks & kCodeBit[cc]) ++sslot;
@@ -660,7 +666,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
         if (sk == 1 && prob->is_somo[c.k]) continue;
         const double* f = sk == 0 ? prob->f_a : prob->f_b;
         const int x = c.side == 0 ? c.k : d.i, y = c.side == 0 ? d.j : c.k;
-        add_term(out, this_slot, q, c.src_pair, x, y, s1, s2, f[(size_t)c.k * n_occ + rep]);
+        add_term(out, this_slot, q, c.src_pair, x, y, s1, s2, f[(size_t)c.k * n_occ + rep], false);
       }
     }
     for (int64_t he = hrow[p]; he < hrow[p + 1]; ++he, ++out) {
@@ -689,7 +695,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
         const int s1 = kCodeS1[code], s2 = kCodeS2[code];
         const int this_slot = slot++;
         if ((s1 == 1 && prob->is_somo[c.k]) || (s2 == 1 && prob->is_somo[c.l])) continue;
-        add_term(out, this_slot, q, c.src_pair, c.k, c.l, s1, s2, -c.w);
+        add_term(out, this_slot, q, c.src_pair, c.k, c.l, s1, s2, -c.w, true);
       }
     }
   }
@@ -720,6 +726,36 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
       for (int b = 0; b < 4; ++b) P->terms_h[(size_t)(e0 + k) * 4 + b] = t2[(size_t)k * 4 + b];
     }
   }
+  // ---- quadratic term: the hole-hole couplings' T-dependent weights ----
+  if (quad) {
+    for (int p = 0; p < npairs; ++p) {
+      const PairDev& pd = P->pairs_h[p];
+      const dlpno_pair& d = prob->pairs[p];
+      for (int64_t e = P->rowptr_h[p]; e < P->rowptr_h[p + 1]; ++e) {
+        if (P->cpl_side_h[e] != 2) continue;
+        QuadCpl qc{};
+        qc.off_S = P->cpl_h[e].off_S;
+        qc.off_K = prob->pairs[P->cpl_h[e].src].off_K;
+        qc.np = pd.n;
+        qc.nq = P->cpl_h[e].nsrc;
+        qc.transK = P->cpl_k_h[e] > P->cpl_l_h[e];
+        int slot = 0;
+        for (int code = 0; code < 4; ++code) {
+          if (!(d.blocks & kCodeBit[code])) continue;
+          const int this_slot = slot++;
+          const TermDev& tm = P->terms_h[(size_t)e * 4 + this_slot];
+          if (tm.src_off < 0) continue;
+          const int b = qc.nblk++;
+          qc.term[b] = e * 4 + this_slot;
+          qc.off_T[b] = pd.off_T + (int64_t)this_slot * pd.n * pd.n;
+          qc.w0[b] = tm.w;
+          qc.c[b] = kCodeS1[code] == kCodeS2[code] ? -0.5 : -1.0;
+          P->flops_quad += 2.0 * pd.n * (double)qc.nq * (pd.n + qc.nq);
+        }
+        if (qc.nblk > 0) P->quad_h.push_back(qc);
+      }
+    }
+  }
   // ---- device ----
   int dev = 0;
   HIPCK(hipGetDevice(&dev));
@@ -746,6 +782,8 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if ((st = upload(&P->d_pairs, P->pairs_h, "pair table", s)) != DLPNO_OK) return destroy_fail(st);
   if ((st = upload(&P->d_cpl, P->cpl_h, "coupling table", s)) != DLPNO_OK) return destroy_fail(st);
   if ((st = upload(&P->d_terms, P->terms_h, "term table", s)) != DLPNO_OK) return destroy_fail(st);
+  if (!P->quad_h.empty() && (st = upload(&P->d_quad, P->quad_h, "quadratic-term table", s)) != DLPNO_OK)
+    return destroy_fail(st);
   if ((st = upload_schedule(P, s)) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_counter, kKinds * kQueues, "queue heads")) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_e_block, std::max(1, nblk_total), "block energies")) != DLPNO_OK) return destroy_fail(st);
@@ -839,7 +877,7 @@ extern "C" dlpno_status dlpno_plan_destroy(dlpno_plan* P) {
                   P->d_diis_partial, P->d_ring_vecs, P->d_ring_errs, P->B32, P->S32, P->T32,
                   P->d_vjp_items, P->d_mixed, P->G32, P->d_pair_boff, P->d_blk_toff, P->d_cpl_soff,
                   P->d_cpl_target, P->d_pair_bscale, P->d_blk_tscale, P->Bs_hi, P->Bs_lo, P->Ss_hi, P->Ss_lo,
-                  P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo, P->d_mix_r, P->d_mix_delta, P->d_hist_iter};
+                  P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo, P->d_mix_r, P->d_mix_delta, P->d_hist_iter, P->d_quad};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete P;
@@ -903,6 +941,12 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
   double* const wsp = ws ? ws : P->d_ws;
   if (P->sched.items_h.empty()) return hipSuccess;
   if (prec < 0) prec = P->opt.precision;
+  if (!P->quad_h.empty() && prec == DLPNO_FP64) {
+    phase_begin(P, 9, s);
+    e = launch_quad_weights(P->d_quad, (int64_t)P->quad_h.size(), P->in.S, P->in.K, T, P->d_terms, s);
+    phase_end(P, s);
+    if (e != hipSuccess) return e;
+  }
   if (prec == DLPNO_FP32) {
     phase_begin(P, 4, s);
     if ((e = launch_convert_f32(T, P->T32, P->n_T, s)) != hipSuccess) return e;

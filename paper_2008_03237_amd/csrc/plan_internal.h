@@ -14,7 +14,7 @@ namespace dlpno {
 
 constexpr int kHistCap = 4096;   // iterations kept in the device history
 constexpr int kDiisParts = 1024; // workgroups of the DIIS dot-product kernel
-constexpr int kPhases = 9;
+constexpr int kPhases = 10;
 
 // schedule choices (set by defaults or the autotuner)
 struct Tuning {
@@ -54,6 +54,9 @@ struct dlpno_plan {
   std::vector<dlpno::PairDev> pairs_h;
   std::vector<dlpno::BlockDev> blocks_h;
   bool somo_virt = false;                // some pair has SOMO virtual functions
+  std::vector<dlpno::QuadCpl> quad_h;    // hole-hole couplings with quadratic weights
+  dlpno::QuadCpl* d_quad = nullptr;
+  double flops_quad = 0.0;               // the weights' contractions per residual
   std::vector<dlpno::CplDev> cpl_h;
   std::vector<dlpno::TermDev> terms_h;
   std::vector<int64_t> rowptr_h;

@@ -9,6 +9,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 FP64, FP32, BF16X2, FP16X2 = 0, 1, 2, 3
 _PREC = {"fp64": FP64, "fp32": FP32, "bf16x2": BF16X2, "fp16x2": FP16X2}
 FLAG_GENERAL_T = 1     # same-spin amplitude blocks need not be antisymmetric
+FLAG_QUADRATIC = 2     # quadratic CCSD term over the hole-hole couplings
 
 
 class DlpnoError(RuntimeError):
@@ -145,7 +146,7 @@ class Plan:
     """
 
     def __init__(self, desc, B, S, K, eps_a, eps_b, precision="fp64", diis_max=8, diis_start=3, n_workers=0,
-                 items_per_wave=0, general_T=False):
+                 items_per_wave=0, general_T=False, quadratic=False):
         import torch
         L = lib()
         P = len(desc.pi)
@@ -184,7 +185,8 @@ class Plan:
         inp = Inputs(B.data_ptr(), S.data_ptr() if S is not None else None, K.data_ptr(), eps_a.data_ptr(),
                      eps_b.data_ptr())
         prec = _PREC[precision] if isinstance(precision, str) else int(precision)
-        opt = Options(prec, diis_max, diis_start, n_workers, int(items_per_wave), FLAG_GENERAL_T if general_T else 0)
+        flags = (FLAG_GENERAL_T if general_T else 0) | (FLAG_QUADRATIC if quadratic else 0)
+        opt = Options(prec, diis_max, diis_start, n_workers, int(items_per_wave), flags)
         self.precision = prec
         self.n_T, self.n_B, self.n_pairs = int(desc.n_T), int(desc.n_B), P
         self.n_blocks = int(sum(bin(int(b)).count("1") for b in desc.blocks))
@@ -330,9 +332,9 @@ class Plan:
         _check(lib().dlpno_set_profiling(self._h, 1 if on else 0))
 
     def phase_times(self):
-        ms = (C.c_double * 9)()
-        n = (C.c_int64 * 9)()
-        _check(lib().dlpno_phase_times(self._h, ms, n, 9))
+        ms = (C.c_double * 10)()
+        n = (C.c_int64 * 10)()
+        _check(lib().dlpno_phase_times(self._h, ms, n, 10))
         return list(ms), list(n)
 
     def info(self):

@@ -1,0 +1,126 @@
+"""Quadratic CCSD term 1/4 sum_KLCD <KL||CD> t_IJ^CD t_KL^AB over the hole-hole
+couplings (DLPNO_FLAG_QUADRATIC) on the GPU against the FP64 oracle, through
+the C ABI: per residual a kernel computes the couplings' weights
+(k i | l j) + c <S^T T_ij S, K_(k,l)> from the current amplitudes, then the
+projection launches apply them."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle.model import unpack_T
+from tests.gpu_helpers import compare_blocks, device_problem, oracle_inputs
+from workload import build_problem
+from workload.problem import segment_values
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+CODE = {"AA": 0, "BB": 1, "AB": 2, "BA": 3}
+
+
+def setup_module(module):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _prob(cfg, **kw):
+    # amplitudes of 0.1 so that the quadratic part stands well above the tolerance
+    if cfg == "tiny":
+        return build_problem("tiny", hole_ladder=0.02, quadratic=True, sigma_T=0.1, **kw)
+    return build_problem("chain", n_occ=24, band=6, somos=(7, 16), hole_ladder=0.02, quadratic=True,
+                         sigma_T=0.1, **kw)
+
+
+@pytest.mark.parametrize("cfg,fock_spin", [("tiny", 0.0), ("mini", 0.0), ("mini", 0.3)])
+def test_residual_update_energy_parity(cfg, fock_spin):
+    prob = _prob(cfg, fock_spin=fock_spin)
+    print("case quadratic", cfg, prob.n_pairs, "pairs", prob.n_hh, "hole-hole couplings", flush=True)
+    plan, dev = device_problem(prob, quadratic=True)
+    R = plan.residual(dev["T"])
+    Tn, e_pair, e_tot = plan.update(dev["T"], R)
+    torch.cuda.synchronize()
+    inp = oracle_inputs(prob)
+    assert inp.quadratic
+    T = unpack_T(prob, prob.materialize("T"))
+    Ro = oracle.residual_os(inp, T)
+    # the quadratic part is far above the tolerance
+    Rl = oracle.residual_os(inp, T, terms=("driver", "fock", "projection", "ladder", "hole"))
+    d = max(float(np.max(np.abs(Ro[k] - Rl[k]))) for k in Ro)
+    assert d > 1e-6 * max(float(np.max(np.abs(v))) for v in Ro.values())
+    Tno = oracle.jacobi(inp, T, Ro)
+    eo = oracle.pair_energies(inp, Tno)
+    compare_blocks(prob, R.cpu().numpy(), Ro, rel=1e-12)
+    compare_blocks(prob, Tn.cpu().numpy(), Tno, rel=1e-12)
+    ep = e_pair.cpu().numpy().reshape(-1, 4)
+    for (p, name), v in eo.items():
+        assert abs(ep[p, CODE[name]] - v) <= 1e-10, (p, name)
+    # the same plan without the flag gives the linear residual
+    plan_l, _ = device_problem(prob)
+    compare_blocks(prob, plan_l.residual(dev["T"]).cpu().numpy(), Rl, rel=1e-12)
+    plan.close()
+    plan_l.close()
+
+
+def test_iterations_with_diis_match_oracle():
+    prob = build_problem("chain", n_occ=20, band=5, somos=(6, 13), hole_ladder=0.02, quadratic=True)
+    plan, dev = device_problem(prob, quadratic=True, T_random=False)
+    n_it = 8
+    plan.iterate(n_it, dev["T"])            # one hipGraph per iteration
+    E_gpu, rmax_gpu = plan.history()
+    inp = oracle_inputs(prob)
+    zero = {k: np.zeros_like(v) for k, v in unpack_T(prob, np.zeros(prob.n_T)).items()}
+    To, hist = oracle.solve(inp, zero, n_it, use_diis=True)
+    for k in range(n_it):
+        assert abs(E_gpu[k] - hist[k][0]) <= 1e-10, (k, E_gpu[k], hist[k][0])
+        assert abs(rmax_gpu[k] - hist[k][1]) <= 1e-12 * max(1.0, hist[k][1]) + 1e-14
+    compare_blocks(prob, dev["T"].cpu().numpy(), To, rel=1e-10)
+    plan.close()
+
+
+def test_full_chain_sampled():
+    """The 3,150-pair chain with the hole-hole ladder and the quadratic term in
+    the benchmark's launch configuration; sampled target pairs recomputed by
+    the oracle (their amplitudes and those of every source they read)."""
+    prob = build_problem("chain", hole_ladder=0.02, quadratic=True)
+    print("case quadratic chain", prob.n_pairs, "pairs", prob.n_hh, "hole-hole couplings", flush=True)
+    plan, dev = device_problem(prob, quadratic=True)
+    R = plan.residual(dev["T"])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(91)
+    pick = sorted(set(rng.choice(prob.n_pairs, 8, replace=False).tolist()) | {0})
+    inp = oracle_inputs(prob, full=False)
+    need = set(pick)
+    for p in pick:
+        need.update(prob.cpl_src[prob.cpl_rowptr[p]:prob.cpl_rowptr[p + 1]].tolist())
+        need.update(prob.hh_src[prob.hh_rowptr[p]:prob.hh_rowptr[p + 1]].tolist())
+    n = prob.npno
+    T = {}
+    for p in need:
+        o = int(prob.off_T[p])
+        for name in oracle.stored_blocks(int(prob.pi[p]), int(prob.pj[p]), prob.is_somo.astype(bool)):
+            seg = prob.segs["T"][np.searchsorted(prob.segs["T"]["off"], o)]
+            T[(p, name)] = segment_values(prob.seed, seg).reshape(n[p], n[p])
+            o += int(n[p]) ** 2
+    Ro = oracle.residual_os(inp, T, pairs=pick)
+    Rg = R.cpu().numpy()
+    for (p, name), ref in Ro.items():
+        i = oracle.stored_blocks(int(prob.pi[p]), int(prob.pj[p]), prob.is_somo.astype(bool)).index(name)
+        o = int(prob.off_T[p]) + i * int(n[p]) ** 2
+        got = Rg[o:o + int(n[p]) ** 2].reshape(n[p], n[p])
+        assert np.linalg.norm(got - ref) <= 1e-12 * np.linalg.norm(ref), (p, name)
+    plan.close()
+
+
+def test_refusals():
+    from paper_2008_03237_amd import DlpnoError
+    prob = _prob("tiny")
+    plan, dev = device_problem(prob, quadratic=True)
+    with pytest.raises(DlpnoError) as ex:
+        plan.vjp(dev["T"], dev["T"])
+    assert ex.value.status == -8
+    plan.close()
+    with pytest.raises(DlpnoError) as ex:
+        device_problem(prob, precision="bf16x2", quadratic=True)
+    assert ex.value.status == -8
+    with pytest.raises(DlpnoError) as ex:
+        device_problem(build_problem("tiny"), quadratic=True)     # no hole-hole couplings
+    assert ex.value.status == -1

@@ -136,6 +136,8 @@ class Problem:
     hole_range: int = 2
     # SOMO virtual functions appended to every pair's PNOs (None: none)
     n_sv: np.ndarray = None
+    # the quadratic CCSD term over the hole-hole couplings (needs hole_ladder)
+    quadratic: bool = False
 
     def t_mask(self):
         """Flat boolean array over the amplitude layout: True inside the
@@ -323,6 +325,8 @@ def build_problem(name="tiny", **override):
     hole-hole term), with one coupling per target pair (i, j) and ordered
     occupied pair (k, l) whose integral is non-zero and whose pair {k, l} is
     retained (the pair itself included: its overlap block is the identity);
+    quadratic=True (with hole_ladder): the quadratic CCSD term over the
+    hole-hole couplings is part of the residual (Problem.quadratic);
     somo_virt=True: every pair's PNOs are followed by the SOMOs as virtual
     functions for beta electrons (Sec. II.B.4): n_p = min(n_p, 64 - N_SOMO) +
     N_SOMO, B and K cover all of them, the SOMO part of every overlap block
@@ -568,4 +572,4 @@ def build_problem(name="tiny", **override):
                    eps_b=eps_b, n_B=n_B, n_T=n_T, n_K=n_K, n_S=n_S, segs=segs, S_host=S_host,
                    pair_index=pair_index, hh_rowptr=hh_rowptr, hh_src=hh_src, hh_k=hh_k, hh_l=hh_l,
                    hh_w=hh_w, hh_off_S=hh_off_S.astype(np.int64), hole_scale=hh_scale, hole_range=hh_range,
-                   n_sv=n_sv)
+                   n_sv=n_sv, quadratic=bool(cfg.get("quadratic", False)) and hh_scale != 0.0)
