@@ -507,7 +507,8 @@ def hole_leg(args, dev, eps_a, eps_b, fl_proj_base, log):
     CCSD terms beyond the hot path's model): synthetic occupied integrals
     (k i | l j) within two orbitals of (i, j), one extra coupling per ordered
     (k, l), run by the projection launches.  FP64 iterations from T = 0,
-    timed like the main leg."""
+    timed like the main leg; then the same with the quadratic term on those
+    couplings."""
     import torch
 
     from paper_2008_03237_amd import Plan
@@ -537,6 +538,28 @@ def hole_leg(args, dev, eps_a, eps_b, fl_proj_base, log):
            "max_abs_R": float(rmax.cpu()[0]), "S_GB": round(prob.n_S * 8 / 1e9, 2)}
     log("hole-hole ladder leg: %s" % row)
     plan.close()
+    # the same couplings carrying the quadratic term: per residual a kernel
+    # computes their weights from T (phase 9), then the same launches run
+    pq = Plan(prob, dev["B"], S, dev["K"], eps_a, eps_b, quadratic=True)
+    T.zero_()
+    pq.iterate(args.warmup, T)
+    torch.cuda.synchronize()
+    pq.set_profiling(True)
+    t0 = time.perf_counter()
+    _, _, e_q, r_q = pq.iterate(args.steps, T)
+    torch.cuda.synchronize()
+    ms_q = (time.perf_counter() - t0) / max(args.steps, 1) * 1e3
+    msq, cntq = pq.phase_times()
+    pq.set_profiling(False)
+    fq = [l for l in pq.info().splitlines() if "quadratic-term weights" in l]
+    fl_w = float(fq[0].split()[-1]) if fq else None
+    w_ms = msq[9] / max(cntq[9], 1)
+    row["quadratic"] = {"ms_per_step": round(ms_q, 3), "weights_kernel_ms": round(w_ms, 3),
+                        "weights_flops": fl_w,
+                        "weights_tflops": round(fl_w / (w_ms / 1e3) / 1e12, 3) if fl_w and w_ms > 0 else None,
+                        "energy_after": float(e_q.cpu()[0]), "max_abs_R": float(r_q.cpu()[0])}
+    log("quadratic term: %s" % row["quadratic"])
+    pq.close()
     del S, T
     return row
 

@@ -46,6 +46,7 @@ struct TermDev {
 struct QuadCpl {
   int64_t off_S;        // overlap block [c][a], n_q x n_p
   int64_t off_K;        // K of the source pair, n_q x n_q
+  int64_t off_G;        // G = S_pq K_(k,l) S_pq^T in the plan's table, n_p x n_p
   int32_t np, nq;
   int32_t transK;       // k > l: K_(k,l) is K_q transposed
   int32_t nblk;         // active target blocks (1..4)
@@ -166,8 +167,10 @@ constexpr int32_t kErrNoBody = 2;      // a work item had no compiled kernel bod
 hipError_t launch_grouped_f64(const GroupedArgs<double>& a, int kind, int workers, hipStream_t s);
 hipError_t launch_grouped_f32(const GroupedArgs<float>& a, int kind, int workers, hipStream_t s);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);
-hipError_t launch_quad_weights(const QuadCpl* list, int64_t n, const double* S, const double* K, const double* T,
-                               TermDev* terms, hipStream_t s);
+hipError_t launch_quad_prepare(const QuadCpl* list, int64_t n, const double* S, const double* K, double* G,
+                               hipStream_t s);
+hipError_t launch_quad_weights(const QuadCpl* list, int64_t n, const double* G, const double* T, TermDev* terms,
+                               hipStream_t s);
 
 // elementwise.hip
 // DIIS on device.  State lives in a small device struct; vectors in rings.

@@ -425,6 +425,13 @@ std::string dlpno::describe(const dlpno_plan* P) {
   snprintf(buf, sizeof buf, "flops/residual: ladder %.4e projection %.4e quadratic-term weights %.4e\n",
            P->flops_ladder, P->flops_proj, P->flops_quad);
   s += buf;
+  if (!P->quad_h.empty()) {
+    snprintf(buf, sizeof buf, "quadratic term: %zu couplings, factors S K S^T %.3f GB (%.4e flops, once)\n",
+             P->quad_h.size(), P->n_quadG * 8e-9, P->flops_quad_prep);
+  } else {
+    buf[0] = 0;
+  }
+  s += buf;
   return s;
 }
 
@@ -739,6 +746,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
         qc.np = pd.n;
         qc.nq = P->cpl_h[e].nsrc;
         qc.transK = P->cpl_k_h[e] > P->cpl_l_h[e];
+        qc.off_G = P->n_quadG;
         int slot = 0;
         for (int code = 0; code < 4; ++code) {
           if (!(d.blocks & kCodeBit[code])) continue;
@@ -750,9 +758,13 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
           qc.off_T[b] = pd.off_T + (int64_t)this_slot * pd.n * pd.n;
           qc.w0[b] = tm.w;
           qc.c[b] = kCodeS1[code] == kCodeS2[code] ? -0.5 : -1.0;
-          P->flops_quad += 2.0 * pd.n * (double)qc.nq * (pd.n + qc.nq);
+          P->flops_quad += 2.0 * pd.n * (double)pd.n;
         }
-        if (qc.nblk > 0) P->quad_h.push_back(qc);
+        if (qc.nblk > 0) {
+          P->quad_h.push_back(qc);
+          P->n_quadG += (int64_t)pd.n * pd.n;
+          P->flops_quad_prep += 2.0 * pd.n * (double)qc.nq * (pd.n + qc.nq);
+        }
       }
     }
   }
@@ -782,8 +794,13 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if ((st = upload(&P->d_pairs, P->pairs_h, "pair table", s)) != DLPNO_OK) return destroy_fail(st);
   if ((st = upload(&P->d_cpl, P->cpl_h, "coupling table", s)) != DLPNO_OK) return destroy_fail(st);
   if ((st = upload(&P->d_terms, P->terms_h, "term table", s)) != DLPNO_OK) return destroy_fail(st);
-  if (!P->quad_h.empty() && (st = upload(&P->d_quad, P->quad_h, "quadratic-term table", s)) != DLPNO_OK)
-    return destroy_fail(st);
+  if (!P->quad_h.empty()) {
+    if ((st = upload(&P->d_quad, P->quad_h, "quadratic-term table", s)) != DLPNO_OK) return destroy_fail(st);
+    if ((st = dev_alloc(&P->d_quadG, P->n_quadG, "quadratic-term factors")) != DLPNO_OK) return destroy_fail(st);
+    if (launch_quad_prepare(P->d_quad, (int64_t)P->quad_h.size(), P->in.S, P->in.K, P->d_quadG, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return destroy_fail(fail(DLPNO_ERR_HIP, "quadratic-term factors"));
+  }
   if ((st = upload_schedule(P, s)) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_counter, kKinds * kQueues, "queue heads")) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_e_block, std::max(1, nblk_total), "block energies")) != DLPNO_OK) return destroy_fail(st);
@@ -877,7 +894,8 @@ extern "C" dlpno_status dlpno_plan_destroy(dlpno_plan* P) {
                   P->d_diis_partial, P->d_ring_vecs, P->d_ring_errs, P->B32, P->S32, P->T32,
                   P->d_vjp_items, P->d_mixed, P->G32, P->d_pair_boff, P->d_blk_toff, P->d_cpl_soff,
                   P->d_cpl_target, P->d_pair_bscale, P->d_blk_tscale, P->Bs_hi, P->Bs_lo, P->Ss_hi, P->Ss_lo,
-                  P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo, P->d_mix_r, P->d_mix_delta, P->d_hist_iter, P->d_quad};
+                  P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo, P->d_mix_r, P->d_mix_delta, P->d_hist_iter, P->d_quad,
+                  P->d_quadG};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete P;
@@ -943,7 +961,7 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
   if (prec < 0) prec = P->opt.precision;
   if (!P->quad_h.empty() && prec == DLPNO_FP64) {
     phase_begin(P, 9, s);
-    e = launch_quad_weights(P->d_quad, (int64_t)P->quad_h.size(), P->in.S, P->in.K, T, P->d_terms, s);
+    e = launch_quad_weights(P->d_quad, (int64_t)P->quad_h.size(), P->d_quadG, T, P->d_terms, s);
     phase_end(P, s);
     if (e != hipSuccess) return e;
   }

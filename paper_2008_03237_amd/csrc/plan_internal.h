@@ -56,7 +56,10 @@ struct dlpno_plan {
   bool somo_virt = false;                // some pair has SOMO virtual functions
   std::vector<dlpno::QuadCpl> quad_h;    // hole-hole couplings with quadratic weights
   dlpno::QuadCpl* d_quad = nullptr;
-  double flops_quad = 0.0;               // the weights' contractions per residual
+  double* d_quadG = nullptr;             // S K S^T per quadratic coupling (built once)
+  int64_t n_quadG = 0;
+  double flops_quad = 0.0;               // the weights' dot products per residual
+  double flops_quad_prep = 0.0;          // building the factors S K S^T (once)
   std::vector<dlpno::CplDev> cpl_h;
   std::vector<dlpno::TermDev> terms_h;
   std::vector<int64_t> rowptr_h;

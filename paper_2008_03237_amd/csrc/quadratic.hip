@@ -11,10 +11,12 @@
 // and S_pq maps the target's PNOs onto the source's: the integrals in the
 // target's PNOs are taken as the projection S_pq K_(k,l) S_pq^T.
 //
-// One workgroup per coupling: the overlap block in LDS, then per target block
-// Z = T_p S_pq (n_p x n_q), U = S_pq^T Z and <K, U>, reduced in a fixed order;
-// the new weight is written into the coupling's term of that block, which the
-// projection launches of the same residual then read.
+// The factor G = S_pq K_(k,l) S_pq^T (n_p x n_p) depends only on the plan's
+// inputs: it is computed once per coupling when the plan is built (one
+// workgroup per coupling, S_pq and K in LDS), and every residual evaluation
+// only forms <G, T_p> for the coupling's target blocks (one wave per coupling,
+// reduced in a fixed order), writing the new weight into the term table that
+// the projection launches of the same residual then read.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -24,14 +26,11 @@ namespace {
 
 constexpr int kLdq = 65;
 
-__global__ __launch_bounds__(256, 2) void quad_weights_kernel(const QuadCpl* __restrict__ list, int64_t n,
+__global__ __launch_bounds__(256, 2) void quad_prepare_kernel(const QuadCpl* __restrict__ list, int64_t n,
                                                               const double* __restrict__ S,
-                                                              const double* __restrict__ K,
-                                                              const double* __restrict__ T,
-                                                              TermDev* __restrict__ terms) {
+                                                              const double* __restrict__ K, double* __restrict__ G) {
   __shared__ double W[64 * kLdq];   // W[c][a] = S_pq[a][c] (the stored overlap block)
-  __shared__ double Z[64 * kLdq];   // T_p staged, then Z = T_p S_pq
-  __shared__ double red[4];
+  __shared__ double V[64 * kLdq];   // K_q staged, then V = K_(k,l) W
   const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
   for (int64_t it = blockIdx.x; it < n; it += gridDim.x) {
     const QuadCpl q = list[it];
@@ -39,57 +38,84 @@ __global__ __launch_bounds__(256, 2) void quad_weights_kernel(const QuadCpl* __r
     __syncthreads();
     if (lane < np_)
       for (int c = w; c < nq; c += 4) W[c * kLdq + lane] = S[q.off_S + (int64_t)c * np_ + lane];
-    for (int b = 0; b < q.nblk; ++b) {
-      __syncthreads();   // W stored; the previous block's Z no longer read
-      if (lane < np_)
-        for (int a = w; a < np_; a += 4) Z[a * kLdq + lane] = T[q.off_T[b] + (int64_t)a * np_ + lane];
-      __syncthreads();
-      // Z[a][d] = sum_x T[a][x] S[x][d] = sum_x T[a][x] W[d][x]: rows a = w + 4 i, column d = lane
-      double acc[16];
+    if (lane < nq)
+      for (int c = w; c < nq; c += 4) V[c * kLdq + lane] = K[q.off_K + (int64_t)c * nq + lane];
+    __syncthreads();
+    // V[c][b] = sum_d K_(k,l)[c][d] W[d][b]: rows c = w + 4 i, column b = lane
+    double acc[16];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) acc[i] = 0.0;
-      if (lane < nq)
-        for (int x = 0; x < np_; ++x) {
-          const double sv = W[lane * kLdq + x];
-#pragma unroll
-          for (int i = 0; i < 16; ++i) acc[i] += Z[min(w + 4 * i, 63) * kLdq + x] * sv;
-        }
-      __syncthreads();
-      if (lane < nq)
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-          if (w + 4 * i < np_) Z[(w + 4 * i) * kLdq + lane] = acc[i];
-      __syncthreads();
-      // U[c][d] = sum_a W[c][a] Z[a][d]: rows c = w + 4 i, column d = lane; then <K_(k,l), U>
-      double part = 0.0;
-      if (lane < nq)
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+    if (lane < np_)
+      for (int d = 0; d < nq; ++d) {
+        const double wv = W[d * kLdq + lane];
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-          const int c = w + 4 * i;
-          if (c >= nq) break;
-          double u = 0.0;
-          for (int a = 0; a < np_; ++a) u += W[c * kLdq + a] * Z[a * kLdq + lane];
-          const double kv = q.transK ? K[q.off_K + (int64_t)lane * nq + c] : K[q.off_K + (int64_t)c * nq + lane];
-          part += kv * u;
+          const int c = min(w + 4 * i, 63);
+          acc[i] += (q.transK ? V[d * kLdq + c] : V[c * kLdq + d]) * wv;
         }
-      for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
-      if (lane == 0) red[w] = part;
-      __syncthreads();
-      if (tid == 0) {
-        const double dot = ((red[0] + red[1]) + red[2]) + red[3];
-        terms[q.term[b]].w = q.w0[b] + q.c[b] * dot;
       }
+    __syncthreads();
+    if (lane < np_)
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (w + 4 * i < nq) V[(w + 4 * i) * kLdq + lane] = acc[i];
+    __syncthreads();
+    // G[a][b] = sum_c W[c][a] V[c][b]: rows a = w + 4 i, column b = lane
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+    if (lane < np_)
+      for (int c = 0; c < nq; ++c) {
+        const double vv = V[c * kLdq + lane];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] += W[c * kLdq + min(w + 4 * i, 63)] * vv;
+      }
+    if (lane < np_)
+#pragma unroll
+      for (int i = 0; i < 16; ++i)
+        if (w + 4 * i < np_) G[q.off_G + (int64_t)(w + 4 * i) * np_ + lane] = acc[i];
+  }
+}
+
+__global__ __launch_bounds__(256) void quad_weights_kernel(const QuadCpl* __restrict__ list, int64_t n,
+                                                           const double* __restrict__ G,
+                                                           const double* __restrict__ T,
+                                                           TermDev* __restrict__ terms) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t e = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); e < n; e += waves) {
+    const QuadCpl q = list[e];
+    const int nn = q.np * q.np;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int x = lane; x < nn; x += 64) {
+      const double g = G[q.off_G + x];
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        if (b < q.nblk) acc[b] += g * T[q.off_T[b] + x];
     }
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      for (int o = 32; o > 0; o >>= 1) acc[b] += __shfl_xor(acc[b], o);
+    if (lane == 0)
+      for (int b = 0; b < q.nblk; ++b) terms[q.term[b]].w = q.w0[b] + q.c[b] * acc[b];
   }
 }
 
 }  // namespace
 
-hipError_t launch_quad_weights(const QuadCpl* list, int64_t n, const double* S, const double* K, const double* T,
-                               TermDev* terms, hipStream_t s) {
+hipError_t launch_quad_prepare(const QuadCpl* list, int64_t n, const double* S, const double* K, double* G,
+                               hipStream_t s) {
   if (n <= 0) return hipSuccess;
   const int64_t grid = n < (1 << 20) ? n : (1 << 20);
-  hipLaunchKernelGGL(quad_weights_kernel, dim3((unsigned)grid), dim3(256), 0, s, list, n, S, K, T, terms);
+  hipLaunchKernelGGL(quad_prepare_kernel, dim3((unsigned)grid), dim3(256), 0, s, list, n, S, K, G);
+  return hipGetLastError();
+}
+
+hipError_t launch_quad_weights(const QuadCpl* list, int64_t n, const double* G, const double* T, TermDev* terms,
+                               hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 3) / 4;
+  const int64_t grid = blocks < (1 << 20) ? blocks : (1 << 20);
+  hipLaunchKernelGGL(quad_weights_kernel, dim3((unsigned)grid), dim3(256), 0, s, list, n, G, T, terms);
   return hipGetLastError();
 }
 
