@@ -177,10 +177,13 @@ typedef struct {
  * c <K_(k,l), S_pq^T T_p S_pq>, c = 1/2 same spin and 1 opposite spin,
  * K_(k,l)[c][d] = (k c | l d) over the source pair's PNOs (its K block, or the
  * transpose for k > l): the integrals in the target's PNOs are taken as the
- * projection S_pq K_(k,l) S_pq^T.  Every residual evaluation first computes
- * the weights from its T (a separate kernel, phase 9 of dlpno_phase_times);
- * the residual is then quadratic in T.  Vector-Jacobian products and
- * low-precision plans refuse such plans. */
+ * projection S_pq K_(k,l) S_pq^T.  The factors S_pq K_(k,l) S_pq^T are built
+ * once by dlpno_plan_create; every residual evaluation of T first computes
+ * the weights from T in FP64 (a separate kernel, phase 9 of
+ * dlpno_phase_times), so the residual is quadratic in T.  In dlpno_solve_mixed
+ * the FP64 refinement residuals compute them and the low-precision iterations
+ * on the correction equation keep them.  The vector-Jacobian product refuses
+ * such plans. */
 #define DLPNO_FLAG_QUADRATIC 2
 
 typedef struct dlpno_plan dlpno_plan;   /* opaque, owned by the library */

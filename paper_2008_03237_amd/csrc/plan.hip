@@ -461,8 +461,6 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if ((opt.flags & ~(DLPNO_FLAG_GENERAL_T | DLPNO_FLAG_QUADRATIC)) != 0)
     return fail(DLPNO_ERR_INVALID_ARG, "unknown option flag");
   const bool quad = (opt.flags & DLPNO_FLAG_QUADRATIC) != 0;
-  if (quad && opt.precision != DLPNO_FP64)
-    return fail(DLPNO_ERR_UNSUPPORTED, "the quadratic term needs an FP64 plan");
   if (quad && prob->n_hh <= 0) return fail(DLPNO_ERR_INVALID_ARG, "the quadratic term needs hole-hole couplings");
   if (opt.diis_max > 0 && (opt.diis_start < 1 || opt.diis_start > opt.diis_max))
     return fail(DLPNO_ERR_INVALID_ARG, "diis_start must be in 1..diis_max");
@@ -954,12 +952,16 @@ WorkQueues queues(const dlpno_plan* P, const Schedule& S, int kind) {
 
 // grouped kernel over amplitudes T (FP64 buffer given by the caller) in the
 // plan's precision, or in `prec` when given (FP64 residuals of a split plan)
-hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, bool general, double* ws) {
+hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, bool general, double* ws,
+                       bool weights) {
   hipError_t e;
   double* const wsp = ws ? ws : P->d_ws;
   if (P->sched.items_h.empty()) return hipSuccess;
   if (prec < 0) prec = P->opt.precision;
-  if (!P->quad_h.empty() && prec == DLPNO_FP64) {
+  // quadratic-term weights from T in FP64 for every residual of T; the
+  // correction equations of the mixed solve (weights = false) keep the
+  // weights of the last FP64 refinement residual
+  if (!P->quad_h.empty() && weights) {
     phase_begin(P, 9, s);
     e = launch_quad_weights(P->d_quad, (int64_t)P->quad_h.size(), P->d_quadG, T, P->d_terms, s);
     phase_end(P, s);
@@ -1044,7 +1046,7 @@ hipError_t enqueue_iteration(dlpno_plan* P, double* T, double* R, double* e_pair
   hipError_t e;
   const bool diis = P->opt.diis_max > 0;
   if (diis && (e = launch_diis_slot(P->d_diis, s)) != hipSuccess) return e;
-  if ((e = run_grouped(P, T, s, prec)) != hipSuccess) return e;
+  if ((e = run_grouped(P, T, s, prec, false, nullptr, drv == nullptr)) != hipSuccess) return e;
   FinishArgs f = finish_args(P, T);
   f.R = R;
   f.drv = drv;

@@ -140,7 +140,7 @@ dlpno_status upload_schedule(dlpno_plan* P, hipStream_t s);
 // (cotangents of the vector-Jacobian product), so every tile is computed
 // ws: partial-sum workspace to use in place of the plan's own (nullptr: the plan's)
 hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec = -1, bool general = false,
-                       double* ws = nullptr);
+                       double* ws = nullptr, bool weights = true);
 FinishArgs finish_args(dlpno_plan* P, const double* T, const double* ws = nullptr);
 // noalloc.hip: device address of the static scratch array, once per device
 // (called by dlpno_plan_create with the plan's device current)

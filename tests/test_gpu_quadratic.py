@@ -110,6 +110,40 @@ def test_full_chain_sampled():
     plan.close()
 
 
+@pytest.mark.parametrize("precision", ["bf16x2", "fp16x2"])
+def test_mixed_refinement_with_quadratic_term(precision):
+    """Split-precision refinement with the quadratic term: the FP64 refinement
+    residuals recompute the weights, the inner iterations keep them; the
+    result matches the converged FP64 solve within the gates."""
+    prob = build_problem("chain", n_occ=20, band=5, somos=(6, 13), hole_ladder=0.02, quadratic=True)
+    p64, d64 = device_problem(prob, quadratic=True, T_random=False)
+    _, _, _, _, n64 = p64.solve(60, d64["T"], tol_r=1e-11, tol_e=1e-12)
+    _, e64, et64, _ = p64.iterate(1, d64["T"])
+    torch.cuda.synchronize()
+    pm, dm = device_problem(prob, precision=precision, quadratic=True, T_random=False)
+    _, em, etm, rm = pm.solve_mixed(3, 6, dm["T"])
+    torch.cuda.synchronize()
+    ep64 = e64.cpu().numpy().reshape(-1, 4).sum(1)
+    epm = em.cpu().numpy().reshape(-1, 4).sum(1)
+    print(precision, "FP64 iterations", n64, "max pair error %.2e total %.2e max|R| %.2e" % (
+        np.max(np.abs(epm - ep64)), abs(float(etm.cpu()[0]) - float(et64.cpu()[0])), float(rm.cpu()[0])))
+    assert np.max(np.abs(epm - ep64)) <= 1e-7
+    assert abs(float(etm.cpu()[0]) - float(et64.cpu()[0])) <= 1e-6
+    p64.close()
+    pm.close()
+
+
+def test_fp32_plan_with_quadratic_term():
+    prob = _prob("mini")
+    plan, dev = device_problem(prob, precision="fp32", quadratic=True)
+    R = plan.residual(dev["T"])
+    torch.cuda.synchronize()
+    inp = oracle_inputs(prob)
+    Ro = oracle.residual_os(inp, unpack_T(prob, prob.materialize("T")))
+    compare_blocks(prob, R.cpu().numpy(), Ro, rel=2e-5)
+    plan.close()
+
+
 def test_refusals():
     from paper_2008_03237_amd import DlpnoError
     prob = _prob("tiny")
@@ -118,9 +152,6 @@ def test_refusals():
         plan.vjp(dev["T"], dev["T"])
     assert ex.value.status == -8
     plan.close()
-    with pytest.raises(DlpnoError) as ex:
-        device_problem(prob, precision="bf16x2", quadratic=True)
-    assert ex.value.status == -8
     with pytest.raises(DlpnoError) as ex:
         device_problem(build_problem("tiny"), quadratic=True)     # no hole-hole couplings
     assert ex.value.status == -1
