@@ -248,7 +248,10 @@ dlpno_status dlpno_f12_energy(dlpno_plan* plan, const double* T, const double* W
  * iteration, replayed.  T is in/out; R, e_pair, e_total, max_abs_R receive
  * the last iteration's values (device).  Blocks until done and returns
  * DLPNO_ERR_NONFINITE if any residual element was not finite.  DIIS history
- * persists across calls until dlpno_reset. */
+ * persists across calls until dlpno_reset.  When every element of T is zero
+ * on entry, the first residual is the driver K^{ss'} alone (its ladder and
+ * projection terms vanish exactly) and its grouped launches are skipped; the
+ * same holds for the first refinement step of dlpno_solve_mixed. */
 dlpno_status dlpno_iterate(dlpno_plan* plan, int32_t n_iter, double* T, double* R,
                            double* e_pair, double* e_total, double* max_abs_R, void* stream);
 

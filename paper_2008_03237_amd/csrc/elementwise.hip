@@ -61,9 +61,10 @@ __global__ __launch_bounds__(kEwThreads) void finish_kernel(FinishArgs a) {
   // The partial slots hold Out^T (row b, column a): they are summed with
   // coalesced reads into LDS and read back transposed (n <= 64).
   __shared__ double part[64 * 64];
+  const int nslot = a.no_partials ? 0 : bk.nslot;
   for (int idx = threadIdx.x; idx < nn; idx += kEwThreads) {
     double v = 0.0;
-    for (int sl = 0; sl < bk.nslot; ++sl) v += ws[(int64_t)sl * nn + idx];
+    for (int sl = 0; sl < nslot; ++sl) v += ws[(int64_t)sl * nn + idx];
     part[idx] = v;
   }
   __syncthreads();
@@ -453,6 +454,20 @@ static int grid_for(int64_t n) {
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
   return (int)g;
+}
+
+__global__ __launch_bounds__(256) void any_nonzero_kernel(const double* x, int64_t n, int32_t* flag) {
+  bool nz = false;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    nz = nz || !(x[i] == 0.0);
+  if (__any(nz) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+hipError_t launch_any_nonzero(const double* x, int64_t n, int32_t* flag, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(any_nonzero_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, x, n, flag);
+  return hipGetLastError();
 }
 
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s) {

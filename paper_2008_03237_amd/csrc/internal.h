@@ -199,7 +199,7 @@ struct FinishArgs {
   double* rmax_block;      // per block max |R|
   int32_t* nonfinite;      // status word: kErrNonfinite set when a residual element is not finite
   int32_t with_driver;     // 0: R = D o T + partials (linear part only, used by the VJP)
-  int32_t pad;
+  int32_t no_partials;     // 1: the partial slots are not read (T = 0: the grouped launches add nothing)
   const double* drv;       // when set, replaces the driver: R = drv + D o T + partials
   // DIIS ring: when ring != null, T_new -> ring_vecs[head], err = T_new - T -> ring_errs[head]
   const DiisState* ring;
@@ -208,6 +208,8 @@ struct FinishArgs {
   int64_t ring_stride;
 };
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
+// flag |= 1 when some element of x[0..n) is not zero (NaN included); the caller zeroes flag
+hipError_t launch_any_nonzero(const double* x, int64_t n, int32_t* flag, hipStream_t s);
 
 struct UpdateArgs {         // Jacobi from a given residual
   const BlockDev* blocks;

@@ -25,10 +25,11 @@ using namespace dlpno;
 // same-spin blocks are antisymmetric here (projected after every correction)
 // unless the plan takes general amplitudes.
 static hipError_t fp64_residual(dlpno_plan* P, const double* T, double* r, double* scratch, double* e_pair,
-                                double* e_total, double* rmax, bool in_place, hipStream_t s) {
+                                double* e_total, double* rmax, bool in_place, hipStream_t s, bool zero_T = false) {
   hipError_t e;
-  if ((e = run_grouped(P, T, s, DLPNO_FP64)) != hipSuccess) return e;
+  if (!zero_T && (e = run_grouped(P, T, s, DLPNO_FP64)) != hipSuccess) return e;
   FinishArgs f = finish_args(P, T);
+  f.no_partials = zero_T ? 1 : 0;   // T = 0: the residual is the driver alone
   f.R = r;
   f.T_new = in_place ? const_cast<double*>(T) : scratch;
   if ((e = launch_finish(f, s)) != hipSuccess) return e;
@@ -72,8 +73,10 @@ extern "C" dlpno_status dlpno_solve_mixed(dlpno_plan* P, int32_t n_outer, int32_
   // the FP64 residual mirrors those blocks) at the start and after each step.
   const bool project = (P->opt.flags & DLPNO_FLAG_GENERAL_T) == 0;
   if (project) MIXCK(launch_antisymmetrize(P->d_blocks, P->n_blocks, T, s));
+  bool zero = false;
+  if (n_outer > 0 && P->n_T > 0) MIXCK(amplitudes_zero(P, T, s, &zero));
   for (int o = 0; o < n_outer; ++o) {
-    MIXCK(fp64_residual(P, T, P->d_mix_r, P->d_mix_delta, nullptr, nullptr, nullptr, false, s));
+    MIXCK(fp64_residual(P, T, P->d_mix_r, P->d_mix_delta, nullptr, nullptr, nullptr, false, s, o == 0 && zero));
     MIXCK(launch_fill(P->d_mix_delta, 0.0, P->n_T, s));
     MIXCK(launch_diis_reset(P->d_diis, std::max(1, P->opt.diis_max), std::max(1, P->opt.diis_start), s));
     for (int k = 0; k < n_inner; ++k)

@@ -809,6 +809,7 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if ((st = dev_alloc(&P->d_rmax_block, std::max(1, nblk_total), "block residual maxima")) != DLPNO_OK)
     return destroy_fail(st);
   if ((st = dev_alloc(&P->d_nonfinite, 4, "non-finite flag")) != DLPNO_OK) return destroy_fail(st);
+  if ((st = dev_alloc(&P->d_flagz, 1, "zero-amplitude flag")) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_hist_iter, 4, "history counter")) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_hist, 2 * kHistCap, "history")) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_diis, 1, "DIIS state")) != DLPNO_OK) return destroy_fail(st);
@@ -893,7 +894,7 @@ extern "C" dlpno_status dlpno_plan_destroy(dlpno_plan* P) {
                   P->d_vjp_items, P->d_mixed, P->G32, P->d_pair_boff, P->d_blk_toff, P->d_cpl_soff,
                   P->d_cpl_target, P->d_pair_bscale, P->d_blk_tscale, P->Bs_hi, P->Bs_lo, P->Ss_hi, P->Ss_lo,
                   P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo, P->d_mix_r, P->d_mix_delta, P->d_hist_iter, P->d_quad,
-                  P->d_quadG};
+                  P->d_quadG, P->d_flagz};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete P;
@@ -1040,14 +1041,26 @@ FinishArgs finish_args(dlpno_plan* P, const double* T, const double* ws) {
   return f;
 }
 
+hipError_t amplitudes_zero(dlpno_plan* P, const double* T, hipStream_t s, bool* zero) {
+  hipError_t e;
+  int32_t h = 1;
+  if ((e = launch_zero_i32(P->d_flagz, 1, s)) != hipSuccess) return e;
+  if ((e = launch_any_nonzero(T, P->n_T, P->d_flagz, s)) != hipSuccess) return e;
+  if ((e = hipMemcpyAsync(&h, P->d_flagz, sizeof h, hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+  if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+  *zero = h == 0;
+  return hipSuccess;
+}
+
 // one full iteration on stream s (capturable: kernels only)
 hipError_t enqueue_iteration(dlpno_plan* P, double* T, double* R, double* e_pair, double* e_total, double* rmax,
-                             hipStream_t s, const double* drv, int prec, bool record) {
+                             hipStream_t s, const double* drv, int prec, bool record, bool zero_T) {
   hipError_t e;
   const bool diis = P->opt.diis_max > 0;
   if (diis && (e = launch_diis_slot(P->d_diis, s)) != hipSuccess) return e;
-  if ((e = run_grouped(P, T, s, prec, false, nullptr, drv == nullptr)) != hipSuccess) return e;
+  if (!zero_T && (e = run_grouped(P, T, s, prec, false, nullptr, drv == nullptr)) != hipSuccess) return e;
   FinishArgs f = finish_args(P, T);
+  f.no_partials = zero_T ? 1 : 0;
   f.R = R;
   f.drv = drv;
   if (diis) {
@@ -1163,10 +1176,21 @@ extern "C" dlpno_status dlpno_iterate(dlpno_plan* P, int32_t n_iter, double* T, 
                                       double* e_total, double* max_abs_R, void* stream) {
   if (!P || n_iter < 0 || ((!T || !R) && P->n_T > 0)) return fail(DLPNO_ERR_INVALID_ARG, "bad arguments");
   hipStream_t s = (hipStream_t)stream;
+  // from T = 0 the first residual is the driver alone: its grouped launches
+  // (which would add exact zeros) are skipped
+  int first = 0;
+  if (n_iter > 0 && P->n_T > 0) {
+    bool zero = false;
+    HIPCK(amplitudes_zero(P, T, s, &zero));
+    if (zero) {
+      HIPCK(enqueue_iteration(P, T, R, e_pair, e_total, max_abs_R, s, nullptr, -1, true, true));
+      first = 1;
+    }
+  }
   if (P->profiling) {
-    for (int k = 0; k < n_iter; ++k) HIPCK(enqueue_iteration(P, T, R, e_pair, e_total, max_abs_R, s));
+    for (int k = first; k < n_iter; ++k) HIPCK(enqueue_iteration(P, T, R, e_pair, e_total, max_abs_R, s));
     phase_collect(P);
-  } else {
+  } else if (first < n_iter) {
     const void* key[5] = {T, R, e_pair, e_total, max_abs_R};
     if (!P->graph_valid || memcmp(key, P->graph_key, sizeof key) != 0) {
       if (P->gexec) {
@@ -1184,7 +1208,7 @@ extern "C" dlpno_status dlpno_iterate(dlpno_plan* P, int32_t n_iter, double* T, 
       memcpy(P->graph_key, key, sizeof key);
       P->graph_valid = true;
     }
-    for (int k = 0; k < n_iter; ++k) HIPCK(hipGraphLaunch(P->gexec, s));
+    for (int k = first; k < n_iter; ++k) HIPCK(hipGraphLaunch(P->gexec, s));
   }
   P->host_iter += n_iter;
   return read_status(P, s);

@@ -57,6 +57,7 @@ struct dlpno_plan {
   std::vector<dlpno::QuadCpl> quad_h;    // hole-hole couplings with quadratic weights
   dlpno::QuadCpl* d_quad = nullptr;
   double* d_quadG = nullptr;             // S K S^T per quadratic coupling (built once)
+  int32_t* d_flagz = nullptr;            // flag of amplitudes_zero
   int64_t n_quadG = 0;
   double flops_quad = 0.0;               // the weights' dot products per residual
   double flops_quad_prep = 0.0;          // building the factors S K S^T (once)
@@ -146,7 +147,11 @@ FinishArgs finish_args(dlpno_plan* P, const double* T, const double* ws = nullpt
 // (called by dlpno_plan_create with the plan's device current)
 dlpno_status scratch_init(int device);
 hipError_t enqueue_iteration(dlpno_plan* P, double* T, double* R, double* e_pair, double* e_total, double* rmax,
-                             hipStream_t s, const double* drv = nullptr, int prec = -1, bool record = true);
+                             hipStream_t s, const double* drv = nullptr, int prec = -1, bool record = true,
+                             bool zero_T = false);
+// *zero = every element of T is zero (synchronises the stream); then R(T) is
+// the driver alone and the grouped launches can be skipped
+hipError_t amplitudes_zero(dlpno_plan* P, const double* T, hipStream_t s, bool* zero);
 bool is_split(int prec);
 dlpno_status read_status(dlpno_plan* P, hipStream_t s);
 std::string describe(const dlpno_plan* P);

@@ -83,3 +83,24 @@ def test_checkpoint_resume_is_bitwise():
     assert ei.value.status == -1
     p2.close()
     plan.close()
+
+
+def test_first_iteration_from_zero_runs_no_grouped_launch():
+    """From T = 0 the first residual is the driver alone: dlpno_iterate skips
+    its grouped launches (phase counts), and the iterations still match the
+    oracle's."""
+    prob = build_problem("chain", n_occ=20, band=5, somos=(6, 13))
+    plan, dev = device_problem(prob, T_random=False)
+    plan.set_profiling(True)
+    plan.iterate(3, dev["T"])
+    ms, cnt = plan.phase_times()
+    plan.set_profiling(False)
+    assert cnt[1] == 3                                        # three finish launches
+    assert max(cnt[k] for k in (0, 5, 6, 7, 8)) == 2           # grouped launches of two residuals
+    E, _ = plan.history()
+    inp = oracle_inputs(prob)
+    zero = {k: np.zeros_like(v) for k, v in unpack_T(prob, np.zeros(prob.n_T)).items()}
+    _, hist = oracle.solve(inp, zero, 3, use_diis=True)
+    for k in range(3):
+        assert abs(E[k] - hist[k][0]) <= 1e-10
+    plan.close()
