@@ -79,8 +79,9 @@ extern "C" dlpno_status dlpno_solve_mixed(dlpno_plan* P, int32_t n_outer, int32_
     MIXCK(fp64_residual(P, T, P->d_mix_r, P->d_mix_delta, nullptr, nullptr, nullptr, false, s, o == 0 && zero));
     MIXCK(launch_fill(P->d_mix_delta, 0.0, P->n_T, s));
     MIXCK(launch_diis_reset(P->d_diis, std::max(1, P->opt.diis_max), std::max(1, P->opt.diis_start), s));
+    // delta starts at zero: the first inner residual is -r alone (no grouped launches)
     for (int k = 0; k < n_inner; ++k)
-      MIXCK(enqueue_iteration(P, P->d_mix_delta, R, nullptr, nullptr, nullptr, s, P->d_mix_r, -1, false));
+      MIXCK(enqueue_iteration(P, P->d_mix_delta, R, nullptr, nullptr, nullptr, s, P->d_mix_r, -1, false, k == 0));
     MIXCK(launch_axpy(T, P->d_mix_delta, 1.0, P->n_T, s));
     if (project) MIXCK(launch_antisymmetrize(P->d_blocks, P->n_blocks, T, s));
   }
