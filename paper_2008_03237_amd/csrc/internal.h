@@ -116,19 +116,23 @@ constexpr int kColStrips = 2;
 // Ladder: (NT tiles of 16 per PNO index, NB blocks per item, NTA a-tiles per item).
 struct LadderVariant { int nt, nb, nta; };
 struct ProjVariant { int nt, nb; };
-constexpr int kNumLadderVariants = 11;
+constexpr int kNumLadderVariants = 13;
 constexpr LadderVariant kLadderVariants[kNumLadderVariants] = {
     {1, 4, 1}, {1, 2, 1}, {1, 1, 1}, {2, 4, 2}, {2, 2, 2}, {2, 1, 2}, {2, 4, 1}, {3, 1, 3}, {4, 1, 2},
-    {4, 2, 4}, {4, 1, 4}};
+    {4, 2, 4}, {4, 1, 4}, {3, 2, 3}, {4, 2, 2}};
+// variants compiled into the split-precision kernel only (two blocks per item
+// for three- and four-tile pairs: each B^Q slice serves both)
+constexpr bool kLadderSplitOnly[kNumLadderVariants] = {false, false, false, false, false, false, false,
+                                                       false, false, false, false, true, true};
 // the cooperative variants (FP64 only): a workgroup per item of two blocks
 // (kLadderCoopPair) or one
 constexpr int kLadderCoopPair = 9, kLadderCoopOne = 10;
 constexpr bool kLadderCoop[kNumLadderVariants] = {false, false, false, false, false, false, false, false, false,
-                                                  true, true};
+                                                  true, true, false, false};
 // ladder variants compiled into the two-wave launch: their X operands fit a
 // 40-operand LDS slab (or registers) and their registers fit 256 per lane
 constexpr bool kLadderTwoWave[kNumLadderVariants] = {true, true, true, false, true, true, false, true, false,
-                                                     false, false};
+                                                     false, false, false, false};
 constexpr int kNumProjVariants = 9;
 constexpr ProjVariant kProjVariants[kNumProjVariants] = {
     {1, 4}, {1, 2}, {1, 1}, {2, 4}, {2, 2}, {2, 1}, {3, 2}, {3, 1}, {4, 1}};

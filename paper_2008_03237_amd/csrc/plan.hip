@@ -114,16 +114,19 @@ double ladder_mfma_per_q(int nt, int nta, int s4, bool strips) {
 }
 
 // largest compiled variant with this tile shape handling at most maxnb blocks
-int pick_ladder(int nt, int nta, int maxnb) {
+// (split-only variants only for split-precision items)
+int pick_ladder(int nt, int nta, int maxnb, bool split) {
   int best = -1;
   for (int v = 0; v < kNumLadderVariants; ++v) {
     const LadderVariant& V = kLadderVariants[v];
+    if (kLadderSplitOnly[v] && !split) continue;
     if (V.nt == nt && V.nta == nta && V.nb <= maxnb && (best < 0 || V.nb > kLadderVariants[best].nb)) best = v;
   }
   if (best >= 0) return best;
   // no variant with this a-tile grouping fits: any of the same tile count
   for (int v = 0; v < kNumLadderVariants; ++v) {
     const LadderVariant& V = kLadderVariants[v];
+    if (kLadderSplitOnly[v] && !split) continue;
     if (V.nt == nt && V.nb <= maxnb && (best < 0 || V.nb > kLadderVariants[best].nb)) best = v;
   }
   return best;
@@ -144,7 +147,8 @@ bool item_compiled(const Item& it, int prec) {
   const bool fp64 = prec == DLPNO_FP64;
   const int v = it.variant;
   switch (it.kind) {
-    case ITEM_LADDER: return v >= 0 && v < kNumLadderVariants && !kLadderCoop[v];
+    case ITEM_LADDER:
+      return v >= 0 && v < kNumLadderVariants && !kLadderCoop[v] && (is_split(prec) || !kLadderSplitOnly[v]);
     case ITEM_LADDER2: return fp64 && v >= 0 && v < kNumLadderVariants && kLadderTwoWave[v];
     case ITEM_LADDER4: return fp64 && (v == kLadderCoopPair || v == kLadderCoopOne);
     case ITEM_PROJ2: {
@@ -257,10 +261,11 @@ dlpno_status build_schedule(dlpno_plan* P) {
     nL[p] = chunks;
     // the items of ladder slot c (Q in [lo, hi)) with variant lvx; tw: the
     // FP64 two-wave launches are in use, stx: FP64 row strips
-    auto emit_ladder = [&](std::vector<Cand>& out, int lvx, bool tw, bool stx, int c, int lo, int hi) -> bool {
+    auto emit_ladder = [&](std::vector<Cand>& out, int lvx, bool tw, bool stx, int c, int lo, int hi,
+                           bool splitx) -> bool {
       const LadderVariant VX = kLadderVariants[lvx];
       for (int b0 = 0; b0 < pr.nblk;) {
-        const int v = pick_ladder(nt, VX.nta, std::min(VX.nb, pr.nblk - b0));
+        const int v = pick_ladder(nt, VX.nta, std::min(VX.nb, pr.nblk - b0), splitx);
         if (v < 0) return false;
         const LadderVariant W = kLadderVariants[v];
         for (int ta0 = 0; ta0 < nt; ta0 += W.nta) {
@@ -290,8 +295,8 @@ dlpno_status build_schedule(dlpno_plan* P) {
     };
     for (int c = 0; c < chunks; ++c) {
       const int lo = (int)((int64_t)pr.m * c / chunks), hi = (int)((int64_t)pr.m * (c + 1) / chunks);
-      if (!emit_ladder(cand, lv, two_wave, strips, c, lo, hi) ||
-          (split && !emit_ladder(cand64, kFp64Ladder[nt - 1], true, true, c, lo, hi)))
+      if (!emit_ladder(cand, lv, two_wave, strips, c, lo, hi, split) ||
+          (split && !emit_ladder(cand64, kFp64Ladder[nt - 1], true, true, c, lo, hi, false)))
         return fail(DLPNO_ERR_INVALID_ARG, "no ladder tile variant for this block group");
     }
     // projection
@@ -786,6 +791,11 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if (opt.precision == DLPNO_FP64) {
     P->tune.ladder_variant[1] = 4;
     P->tune.ladder_variant[3] = kLadderCoopPair;
+  }
+  // split defaults: three- and four-tile pairs take two blocks per item
+  if (is_split(opt.precision)) {
+    P->tune.ladder_variant[2] = 11;
+    P->tune.ladder_variant[3] = 12;
   }
   dlpno_status st;
   if ((st = build_schedule(P)) != DLPNO_OK) return destroy_fail(st);

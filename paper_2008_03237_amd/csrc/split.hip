@@ -452,6 +452,11 @@ __device__ __forceinline__ void split_run_item(const SplitArgs& A, const Item& i
         if (it.ta0 == 0) split_ladder_masked<S, 4, 1, 2, 0>(A, it);
         else split_ladder_masked<S, 4, 1, 2, 2>(A, it);
         break;
+      case 11: split_ladder_masked<S, 3, 2, 3, 0>(A, it); break;
+      case 12:
+        if (it.ta0 == 0) split_ladder_masked<S, 4, 2, 2, 0>(A, it);
+        else split_ladder_masked<S, 4, 2, 2, 2>(A, it);
+        break;
       default: no_body(A.err); break;
     }
   } else {

@@ -71,6 +71,7 @@ extern "C" dlpno_status dlpno_autotune(dlpno_plan* P, const double* T, double* R
       if (kLadderVariants[v].nt != nt || v == P->tune.ladder_variant[nt - 1]) continue;
       // cooperative items: FP64 only; the one-block form serves remainders
       if (kLadderCoop[v] && (P->opt.precision != DLPNO_FP64 || v == kLadderCoopOne)) continue;
+      if (kLadderSplitOnly[v] && !is_split(P->opt.precision)) continue;
       const int keep = P->tune.ladder_variant[nt - 1];
       P->tune.ladder_variant[nt - 1] = v;
       if ((st = apply(P, s)) != DLPNO_OK) return st;
