@@ -18,8 +18,10 @@ from .model import denominators, projection_terms, hole_terms
 
 
 def vjp(inp, T, G):
-    if getattr(inp, "quadratic", False) or getattr(inp, "n_sv", None) is not None:
-        raise NotImplementedError("vjp covers the linear residual on unmasked spaces only")
+    if (getattr(inp, "quadratic", False) or getattr(inp, "n_sv", None) is not None
+            or getattr(inp, "ring", None) is not None):
+        raise NotImplementedError("vjp covers the residual without the quadratic and ring terms on unmasked "
+                                  "spaces only")
     dT = {k: np.zeros_like(v) for k, v in T.items()}
     dB = {}
     for p in range(len(inp.pairs)):

@@ -73,10 +73,13 @@ class Inputs:
                eps cover all n_p functions (the SOMO part of S between two
                pairs is the identity); residual blocks vanish outside the
                virtual spaces of their spins.  None: no SOMO functions.
+    ring       optional integrals of the ring/exchange term (RingInts or an
+               object with the same couplings(p)); None: no such term
     B and S may be callables (lazy regeneration for large workloads).
     """
 
-    def __init__(self, n_occ, is_somo, pairs, B, K, eps_a, eps_b, f_a, f_b, S, occ_ints=None, n_sv=None):
+    def __init__(self, n_occ, is_somo, pairs, B, K, eps_a, eps_b, f_a, f_b, S, occ_ints=None, n_sv=None,
+                 ring=None):
         self.n_occ = int(n_occ)
         self.is_somo = np.asarray(is_somo).astype(bool)
         self.pairs = [(int(i), int(j)) for i, j in pairs]
@@ -87,6 +90,7 @@ class Inputs:
         self.occ_ints = occ_ints
         self.n_sv = None if n_sv is None else [int(x) for x in n_sv]
         self.quadratic = False   # add the quadratic term over the hole-hole couplings
+        self.ring = ring
 
     def B(self, p):
         return self._B(p) if callable(self._B) else self._B[p]
@@ -155,6 +159,9 @@ class Inputs:
             if prob.n_hh > 0:
                 for e in range(prob.hh_rowptr[p], prob.hh_rowptr[p + 1]):
                     where.setdefault((p, int(prob.hh_src[e])), int(prob.hh_off_S[e]))
+            if getattr(prob, "n_ring", 0) > 0:
+                for e in range(prob.ring_rowptr[p], prob.ring_rowptr[p + 1]):
+                    where.setdefault((p, int(prob.ring_src[e])), int(prob.ring_off_S[e]))
         S_full = S if S is not None else (prob.S_host if prob.S_host is not None else None)
         s_cache = {}
 
@@ -173,9 +180,25 @@ class Inputs:
         if prob.hole_scale != 0.0:
             occ = _WorkloadOccInts(prob)
         n_sv = getattr(prob, "n_sv", None)
-        inp = cls(prob.n_occ, prob.is_somo, pairs, Bf, Kd, ea, eb, prob.f_a, prob.f_b, Sf, occ, n_sv)
+        ring = _WorkloadRing(prob) if getattr(prob, "n_ring", 0) > 0 else None
+        inp = cls(prob.n_occ, prob.is_somo, pairs, Bf, Kd, ea, eb, prob.f_a, prob.f_b, Sf, occ, n_sv, ring)
         inp.quadratic = bool(getattr(prob, "quadratic", False))
         return inp
+
+
+class _WorkloadRing:
+    """The workload's ring couplings, integrals regenerated per target pair."""
+
+    def __init__(self, prob):
+        self.prob = prob
+        self.cache = {}
+
+    def couplings(self, p):
+        if p not in self.cache:
+            pr = self.prob
+            self.cache[p] = [(int(pr.ring_role[e]), int(pr.ring_m[e]), int(pr.ring_src[e]), pr.ring_matrix(e, 0),
+                              pr.ring_matrix(e, 1)) for e in range(pr.ring_rowptr[p], pr.ring_rowptr[p + 1])]
+        return self.cache[p]
 
 
 class _WorkloadOccInts:
@@ -350,11 +373,91 @@ def hole_terms(inp, T, p, name, quadratic=False):
     return out
 
 
-def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladder", "hole", "quadratic")):
+class RingInts:
+    """Integrals of the ring/exchange term, listed per target pair.
+
+    couplings(p) gives (role, m, q, X, J) tuples for target pair p = (i, j):
+    role 0 keeps the target's first occupied index x = i (other index y = j),
+    role 1 its second, x = j (y = i); m is the replacing occupied orbital and
+    q the retained source pair {x, m};
+        X[e][b] = (m e | b y),   J[e][b] = (m y | b e)   (chemists' notation)
+    with e over the source's PNOs (rows) and b over the target's (columns).
+    A diagonal target (i == j) lists role 0 only: it serves both index orders.
+    """
+
+    def __init__(self, table):
+        self.table = table          # {p: [(role, m, q, X, J), ...]}
+
+    def couplings(self, p):
+        return self.table.get(p, [])
+
+
+def ring_amplitude(inp, T, x, sx, m, sm, ra, se):
+    """The doubles amplitude t_{(x sx)(m sm)}^{(r ra)(e se)} as a matrix [r][e]
+    over the PNOs of pair {x, m}, with the pair index: (q, matrix) or None.
+    It vanishes unless the virtual spins are those of the occupied ones in
+    some order; exchanging the two virtual labels alone changes its sign."""
+    if sx == ra and sm == se:
+        src = t_lookup(inp, T, x, m, sx, sm)
+        return None if src is None else (src[0], src[3])
+    if sx == se and sm == ra:
+        src = t_lookup(inp, T, x, m, sx, sm)
+        return None if src is None else (src[0], -src[3].T)
+    return None
+
+
+def ring_part(inp, T, p, role, ra, cb, s1, s2):
+    """F[r][c] = sum_{M, E} t_{X M}^{R E} <M C||E Y> for target pair p, where
+    (X, Y) are the target's occupied spin orbitals (i s1, j s2) for role 0 and
+    (j s2, i s1) for role 1, R and C virtuals of spins ra and cb in the
+    target's PNOs.  <M C||E Y> = (m e | c y) when e has the spin of m and
+    c that of y, minus (m y | c e) when m has the spin of y and e that of c;
+    the amplitude's virtual index r is carried into the target's PNOs by
+    S_{p,q}."""
+    i, j = inp.pairs[p]
+    (x, sx), (y, sy) = ((i, s1), (j, s2)) if role == 0 else ((j, s2), (i, s1))
+    n = inp.npno(p)
+    out = np.zeros((n, n))
+    for crole, m, q, X, J in inp.ring.couplings(p):
+        if i != j and crole != role:
+            continue
+        Spq = inp.S(p, q)
+        for sm in (0, 1):
+            if sm == 1 and inp.is_somo[m]:      # M must be occupied: SOMOs are alpha only
+                continue
+            if cb == sy:                        # (m e | c y), e of spin sm
+                a = ring_amplitude(inp, T, x, sx, m, sm, ra, sm)
+                if a is not None:
+                    assert a[0] == q
+                    out += Spq @ a[1] @ X
+            if sm == sy:                        # (m y | c e), e of spin cb
+                a = ring_amplitude(inp, T, x, sx, m, sm, ra, cb)
+                if a is not None:
+                    assert a[0] == q
+                    out -= Spq @ a[1] @ J
+    return out
+
+
+def ring_block(inp, T, p, name):
+    """Ring/exchange term of block `name` of pair p.  In spin orbitals it is
+    P(ij) P(ab) sum_ME t_IM^AE <MB||EJ>, the part of the CCSD doubles residual
+    that is linear in the doubles and couples pairs through one shared
+    occupied index: with F(XY, ab) = sum_ME t_XM^aE <Mb||EY>,
+        R_IJ^AB += F(IJ, AB) - F(JI, AB) - F(IJ, BA) + F(JI, BA),
+    which for block s s' (A of spin s, B of spin s') is ring_part with role
+    0 / 1 and virtual spins (s, s') / (s', s), the latter transposed.  Its
+    spin-orbital form is checked by brute force in the canonical limit."""
+    s1, s2 = SPIN[name]
+    return (ring_part(inp, T, p, 0, s1, s2, s1, s2) - ring_part(inp, T, p, 1, s1, s2, s1, s2)
+            - ring_part(inp, T, p, 0, s2, s1, s1, s2).T + ring_part(inp, T, p, 1, s2, s1, s1, s2).T)
+
+
+def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladder", "hole", "quadratic", "ring")):
     """Open-shell residual blocks {(p, name): R} for the given target pairs.
     The hole-hole term is present only when inp.occ_ints is given; with
     inp.quadratic set, its couplings carry the quadratic CCSD term too
-    (quadratic_weight).  With SOMO
+    (quadratic_weight); the ring/exchange term only when inp.ring is given
+    (ring_block).  With SOMO
     virtual functions (inp.n_sv) each block is the model residual restricted
     to its spins' virtual spaces (the rows of an alpha virtual index and the
     columns of an alpha virtual index vanish at SOMO functions); amplitudes
@@ -378,6 +481,8 @@ def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladd
                 quad = "quadratic" in terms and getattr(inp, "quadratic", False)
                 for w, q, Spq, src in hole_terms(inp, T, p, name, quadratic=quad):
                     r += w * (Spq @ src[3] @ Spq.T)
+            if "ring" in terms and getattr(inp, "ring", None) is not None:
+                r += ring_block(inp, T, p, name)
             if inp.n_sv is not None:
                 s1, s2 = SPIN[name]
                 r = r * (inp.vmask(s1, p)[:, None] & inp.vmask(s2, p)[None, :])

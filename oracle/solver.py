@@ -26,7 +26,7 @@ def unflatten(v, keys, inp):
 
 def apply_operator(inp, T):
     """The linear part (D + A)(T) of the residual: everything but the driver."""
-    return residual_os(inp, T, terms=("fock", "projection", "ladder", "hole"))
+    return residual_os(inp, T, terms=("fock", "projection", "ladder", "hole", "ring"))
 
 
 class DIIS:

@@ -11,11 +11,14 @@ terms of the model are formed from explicit antisymmetrised integrals:
             - sum_K f_KJ t_IK^AB + 1/2 sum_CD <AB||CD> t_IJ^CD
             + 1/2 sum_KL <KL||IJ> t_KL^AB
            [+ 1/4 sum_KLCD <KL||CD> t_IJ^CD t_KL^AB]
+           [+ P(IJ) P(AB) sum_KC <KB||CJ> t_IK^AC]
   E       = 1/4 sum_IJAB <IJ||AB> t_IJ^AB
 
 with (ac|bd) = sum_Q B^Q_ac B^Q_bd, (ia|jb) given per ordered pair and the
-occupied integrals (ki|lj) given as a dense array (the last term is absent
-when they are not given).  With n_sv > 0 the last n_sv spatial virtual
+occupied integrals (ki|lj) given as a dense array (the hole-hole term is
+absent when they are not given); P(IJ) X_IJ = X_IJ - X_JI.  The ring term
+takes <KB||CJ> = (kc|bj) - (kj|bc) from dense arrays g_ovvo[k, c, b, j] =
+(k c | b j) and g_oovv[k, j, b, c] = (k j | b c) when they are given.  With n_sv > 0 the last n_sv spatial virtual
 functions are SOMOs: beta virtual spin orbitals only (their alpha spin
 orbitals are occupied), Sec. II.B.4.
 """
@@ -29,7 +32,7 @@ def _spin_orbitals(n_occ, is_somo, V, n_sv=0):
 
 
 def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblocks, pairs, g_occ=None, n_sv=0,
-                         quadratic=False):
+                         quadratic=False, g_ovvo=None, g_oovv=None):
     """Pair blocks of the residual and the total energy of the given amplitudes.
 
     Bg       (m, V, V) three-index integrals shared by all pairs
@@ -39,6 +42,8 @@ def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblo
     g_occ    optional (n_occ, n_occ, n_occ, n_occ) array g[k, i, l, j] = (k i | l j)
     n_sv     SOMO functions among the V (the last n_sv; beta virtual only)
     quadratic  add 1/4 sum_KLCD <KL||CD> t_IJ^CD t_KL^AB
+    g_ovvo, g_oovv  optional (n_occ, V, V, n_occ) and (n_occ, n_occ, V, V) arrays
+             of the ring term (both or neither)
     Returns ({((i, j), name): V x V residual block, zero outside the blocks'
     virtual spaces}, energy of the amplitudes).
     """
@@ -117,6 +122,22 @@ def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblo
     if quadratic:
         # <KL||CD> = <CD||KL> (real orbitals) = g_vvoo[C, D, K, L]
         R = R + 0.25 * np.einsum("cdkl,ijcd,klab->ijab", g_vvoo, t, t)
+    if g_ovvo is not None:
+        # <KB||CJ> = <KB|CJ> - <KB|JC> = (KC|BJ) - (KJ|BC), each charge
+        # distribution of one spin
+        w = np.zeros((no, nv, nv, no))
+        for K, (k, sk) in enumerate(occ):
+            for B, (b, sb) in enumerate(vir):
+                for C, (c, sc) in enumerate(vir):
+                    for J, (j, sj) in enumerate(occ):
+                        v = 0.0
+                        if sk == sc and sb == sj:
+                            v += g_ovvo[k, c, b, j]
+                        if sk == sj and sb == sc:
+                            v -= g_oovv[k, j, b, c]
+                        w[K, B, C, J] = v
+        X = np.einsum("ikac,kbcj->ijab", t, w)
+        R = R + X - X.transpose(1, 0, 2, 3) - X.transpose(0, 1, 3, 2) + X.transpose(1, 0, 3, 2)
     E = 0.25 * float(np.sum(g_vvoo.transpose(2, 3, 0, 1) * t))
     out = {}
     for (i, j) in pairs:

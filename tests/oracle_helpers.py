@@ -34,12 +34,46 @@ def occ_integrals(rng, n, scale):
     return scale * g / 8.0
 
 
+def ring_dense(rng, n_occ, V, scale):
+    """Random real integrals of the ring term, (k c | b j) as g_ovvo[k, c, b, j]
+    and (k j | b c) as g_oovv[k, j, b, c], with the permutational symmetries
+    of real two-electron integrals."""
+    a = rng.standard_normal((n_occ, V, V, n_occ))
+    a = (a + a.transpose(3, 2, 1, 0)) / 2.0            # (kc|bj) = (jb|ck)
+    b = rng.standard_normal((n_occ, n_occ, V, V))
+    b = (b + b.transpose(1, 0, 2, 3)) / 2.0            # (kj|bc) = (jk|bc)
+    b = (b + b.transpose(0, 1, 3, 2)) / 2.0            # (kj|bc) = (kj|cb)
+    return scale * a, scale * b
+
+
+def ring_couplings(inp, make):
+    """RingInts over every retained source {x, m}: make(p, role, m, q, x, y)
+    returns the (X, J) matrices of one coupling."""
+    table = {}
+    for p, (i, j) in enumerate(inp.pairs):
+        rows = []
+        for role, (x, y) in enumerate(((i, j), (j, i))):
+            if role == 1 and i == j:
+                continue
+            for m in range(inp.n_occ):
+                q = inp.index.get((min(x, m), max(x, m)))
+                if q is None:
+                    continue
+                X, J = make(p, role, m, q, x, y)
+                rows.append((role, m, q, X, J))
+        table[p] = rows
+    return oracle.RingInts(table)
+
+
 def make_inputs(rng, n_occ, somos, npno, naux, band=None, dim=None, shared_space=False,
-                b_scale=0.1, k_scale=0.05, f_off=0.05, canonical=False, hole=0.0):
+                b_scale=0.1, k_scale=0.05, f_off=0.05, canonical=False, hole=0.0, ring=0.0):
     """Random model instance.  shared_space: all pairs use one untruncated
     virtual space (identity overlaps, one B, one eps): the canonical limit.
     hole: scale of random occupied integrals (k i | l j) of the hole-hole
-    ladder (0: no such term); they are kept in inp.g_occ as a dense array."""
+    ladder (0: no such term); they are kept in inp.g_occ as a dense array.
+    ring: scale of the ring term's integrals (0: no such term); in the shared
+    space they come from dense arrays inp.g_ovvo, inp.g_oovv, otherwise each
+    coupling gets its own random X and J."""
     is_somo = np.zeros(n_occ, dtype=bool)
     is_somo[list(somos)] = True
     band = n_occ if band is None else band
@@ -90,6 +124,14 @@ def make_inputs(rng, n_occ, somos, npno, naux, band=None, dim=None, shared_space
     inp = oracle.Inputs(n_occ, is_somo, pairs, B, K, eps_a, eps_b, f, fb, S,
                         oracle.OccInts(g) if g is not None else None)
     inp.g_occ = g
+    inp.g_ovvo = inp.g_oovv = None
+    if ring and shared_space:
+        inp.g_ovvo, inp.g_oovv = ring_dense(rng, n_occ, npno, ring)
+        inp.ring = ring_couplings(inp, lambda p, role, m, q, x, y: (inp.g_ovvo[m, :, :, y].copy(),
+                                                                     inp.g_oovv[m, y].T.copy()))
+    elif ring:
+        inp.ring = ring_couplings(inp, lambda p, role, m, q, x, y: (
+            ring * rng.standard_normal((ns[q], ns[p])), ring * rng.standard_normal((ns[q], ns[p]))))
     return inp
 
 

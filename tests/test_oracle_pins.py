@@ -527,3 +527,53 @@ def test_quadratic_term_is_quadratic():
     for k in d1:
         np.testing.assert_allclose(d2[k], 4.0 * d1[k], rtol=1e-9, atol=1e-13)
     assert max(np.abs(v).max() for v in d1.values()) > 1e-6
+
+
+# ---------------------------------- ring/exchange term (linear in T2)
+@pytest.mark.parametrize("somos,n_sv", [((), 0), ((1,), 0), ((1, 3), 0), ((1, 3), 2)])
+def test_ring_term_canonical_limit_matches_bruteforce(somos, n_sv):
+    # P(IJ) P(AB) sum_KC <KB||CJ> t_IK^AC from explicit antisymmetrised
+    # integrals, against the pair form: per target block four oriented
+    # contractions S_pq op(T_q) X / J over the couplings that share an index
+    rng = np.random.default_rng(71 + len(somos) + 10 * n_sv)
+    inp = make_inputs(rng, n_occ=5, somos=somos, npno=4 + n_sv, naux=6, shared_space=True, hole=0.05,
+                      ring=0.05)
+    if n_sv:
+        inp.n_sv = [n_sv] * len(inp.pairs)
+    T = random_T(rng, inp, scale=0.05)
+    if n_sv:
+        T = _mask_T(inp, T)
+    R = oracle.residual_os(inp, T)
+    Tb = {(inp.pairs[p], name): v for (p, name), v in T.items()}
+    Kp = {inp.pairs[p]: inp.K[p] for p in range(len(inp.pairs))}
+    args = (inp.n_occ, inp.is_somo, inp.B(0), Kp, inp.eps_a[0], inp.eps_b[0], inp.f_a, inp.f_b, Tb, inp.pairs)
+    Rbf, _ = oracle.residual_spinorbital(*args, g_occ=inp.g_occ, n_sv=n_sv, g_ovvo=inp.g_ovvo, g_oovv=inp.g_oovv)
+    Rno, _ = oracle.residual_spinorbital(*args, g_occ=inp.g_occ, n_sv=n_sv)
+    big = 0.0
+    for (p, name), r in R.items():
+        np.testing.assert_allclose(r, Rbf[(inp.pairs[p], name)], rtol=0, atol=1e-13)
+        big = max(big, np.abs(Rbf[(inp.pairs[p], name)] - Rno[(inp.pairs[p], name)]).max())
+    assert big > 1e-3            # the ring term is far above the tolerance
+    # every spin case of the ring term is exercised: opposite-spin blocks
+    # read same-spin sources and the reverse
+    names = {name for (_, name) in R}
+    assert {"AA", "AB"} <= names
+
+
+def test_ring_term_is_linear_and_separate():
+    # truncated PNO spaces: the ring term is linear in T, vanishes with its
+    # integrals, and adds to the rest of the residual
+    rng = np.random.default_rng(73)
+    inp = make_inputs(rng, n_occ=6, somos=(2,), npno=[5, 6, 4, 5, 6, 4, 5, 6, 4, 5, 6, 4, 5, 6, 4, 5, 6, 4, 5,
+                                                      6, 4], naux=5, ring=0.05)
+    T = random_T(rng, inp, scale=0.1)
+    base = ("driver", "fock", "projection", "ladder", "hole")
+    Rf = oracle.residual_os(inp, T)
+    Rb = oracle.residual_os(inp, T, terms=base)
+    T2 = {k: 2.0 * v for k, v in T.items()}
+    Rf2 = oracle.residual_os(inp, T2)
+    Rb2 = oracle.residual_os(inp, T2, terms=base)
+    for k in Rf:
+        d1, d2 = Rf[k] - Rb[k], Rf2[k] - Rb2[k]
+        np.testing.assert_allclose(d2, 2.0 * d1, rtol=1e-12, atol=1e-15)
+    assert max(np.abs(Rf[k] - Rb[k]).max() for k in Rf) > 1e-4

@@ -137,3 +137,41 @@ def test_hole_hole_couplings_follow_the_integral_rule():
                 n = int(prob.npno[p])
                 o = int(prob.hh_off_S[e])
                 assert np.array_equal(S[o:o + n * n].reshape(n, n), np.eye(n))
+
+
+def test_ring_couplings_follow_their_rule():
+    """Ring couplings of target (i, j): role 0 (x = i, y = j) and, for i < j,
+    role 1 (x = j, y = i), every m with |m - x| <= range whose pair {x, m} is
+    retained; self-couplings point at identity overlap blocks; the integral
+    blocks are regenerable and sized n_src x n_target; without the option
+    the workload is unchanged."""
+    base = build_problem("chain", n_occ=16, band=4, somos=(5, 11))
+    prob = build_problem("chain", n_occ=16, band=4, somos=(5, 11), ring=0.05, ring_range=2)
+    assert base.n_ring == 0 and prob.n_ring > 0
+    assert np.array_equal(base.cpl_src, prob.cpl_src) and np.array_equal(base.off_T, prob.off_T)
+    S = prob.materialize("S")
+    Rg = prob.materialize("Rg")
+    for p in range(prob.n_pairs):
+        i, j = int(prob.pi[p]), int(prob.pj[p])
+        want = []
+        for role, x in enumerate((i, j)):
+            if role == 1 and i == j:
+                continue
+            for m in range(max(0, x - 2), min(16, x + 3)):
+                q = prob.pair_index.get((min(x, m), max(x, m)))
+                if q is not None:
+                    want.append((role, m, q))
+        rows = range(prob.ring_rowptr[p], prob.ring_rowptr[p + 1])
+        assert [(int(prob.ring_role[e]), int(prob.ring_m[e]), int(prob.ring_src[e])) for e in rows] == want, p
+        n = int(prob.npno[p])
+        for e in rows:
+            q = int(prob.ring_src[e])
+            nq = int(prob.npno[q])
+            if q == p:
+                o = int(prob.ring_off_S[e])
+                assert np.array_equal(S[o:o + n * n].reshape(n, n), np.eye(n))
+            for which, off in ((0, prob.ring_off_X[e]), (1, prob.ring_off_J[e])):
+                M = prob.ring_matrix(e, which)
+                assert M.shape == (nq, n)
+                assert np.array_equal(Rg[int(off):int(off) + nq * n].reshape(nq, n), M)
+    assert not np.array_equal(prob.ring_matrix(0, 0), prob.ring_matrix(0, 1))

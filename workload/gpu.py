@@ -48,7 +48,7 @@ def device_fields(prob, device="cuda", fields=("B", "S", "K", "T"), dtype=None):
     """Allocate and generate the requested flat fields on the GPU."""
     import torch
     out = {}
-    sizes = {"B": prob.n_B, "S": prob.n_S, "K": prob.n_K, "T": prob.n_T, "W": prob.n_T}
+    sizes = {"B": prob.n_B, "S": prob.n_S, "K": prob.n_K, "T": prob.n_T, "W": prob.n_T, "Rg": prob.n_Rg}
     for f in fields:
         t = torch.empty(max(sizes[f], 1), dtype=torch.float64, device=device)
         if f == "S" and prob.S_host is not None:

@@ -38,6 +38,8 @@ BLOCK_SPINS = {"AA": (0, 0), "BB": (1, 1), "AB": (0, 1), "BA": (1, 0)}
 F_NPNO, F_NAUX, F_B, F_T, F_K, F_EPS, F_FDIAG, F_FOFF, F_S, F_QR, F_W, F_F12, F_FOFFB, F_HH = range(1, 15)
 # PNO-construction inputs (workload.pno)
 F_DOM, F_TAU, F_PX, F_PF = range(15, 19)
+# ring/exchange-term integrals (stream 2 e for X, 2 e + 1 for J of ring coupling e)
+F_RING = 19
 
 # F12 inputs (synthetic): W = V + C per stored block, in the amplitude layout,
 # and six scalars per block (V, V', B1..B4, see Problem.f12_scalars)
@@ -138,6 +140,20 @@ class Problem:
     n_sv: np.ndarray = None
     # the quadratic CCSD term over the hole-hole couplings (needs hole_ladder)
     quadratic: bool = False
+    # ring/exchange-term couplings (CSR by target pair; empty when the term is
+    # off): role (0: the target's i is shared, 1: its j), replacing occupied m,
+    # source pair {x, m}, overlap block, and the integral blocks X = (m e|b y),
+    # J = (m y|b e) (n_src x n_target, [e][b]) in the ring buffer of n_Rg
+    ring_rowptr: np.ndarray = None
+    ring_src: np.ndarray = None
+    ring_role: np.ndarray = None
+    ring_m: np.ndarray = None
+    ring_off_S: np.ndarray = None
+    ring_off_X: np.ndarray = None
+    ring_off_J: np.ndarray = None
+    n_Rg: int = 0
+    ring_scale: float = 0.0
+    ring_range: int = 2
 
     def t_mask(self):
         """Flat boolean array over the amplitude layout: True inside the
@@ -165,6 +181,15 @@ class Problem:
     def n_hh(self):
         return 0 if self.hh_src is None else len(self.hh_src)
 
+    @property
+    def n_ring(self):
+        return 0 if self.ring_src is None else len(self.ring_src)
+
+    def ring_matrix(self, e, which):
+        """X (which = 0) or J (which = 1) of ring coupling e, n_src x n_target."""
+        seg = self.segs["Rg"][2 * e + which]
+        return segment_values(self.seed, seg).reshape(seg["rows"], seg["cols"])
+
     def eri_occ(self, k, i, l, j):
         """The synthetic occupied integral (k i | l j) of this workload (0 when
         the hole-hole term is off)."""
@@ -188,8 +213,8 @@ class Problem:
 
     # ---------------- materialisation of the large fields ----------------
     def materialize(self, what):
-        """Full flat array of 'B', 'T', 'K', 'S' or 'W' (host memory; small problems)."""
-        size = {"B": self.n_B, "T": self.n_T, "K": self.n_K, "S": self.n_S, "W": self.n_T}[what]
+        """Full flat array of 'B', 'T', 'K', 'S', 'W' or 'Rg' (host memory; small problems)."""
+        size = {"B": self.n_B, "T": self.n_T, "K": self.n_K, "S": self.n_S, "W": self.n_T, "Rg": self.n_Rg}[what]
         if what == "S" and self.S_host is not None:
             return self.S_host.copy()
         out = np.zeros(size, dtype=np.float64)
@@ -327,6 +352,12 @@ def build_problem(name="tiny", **override):
     retained (the pair itself included: its overlap block is the identity);
     quadratic=True (with hole_ladder): the quadratic CCSD term over the
     hole-hole couplings is part of the residual (Problem.quadratic);
+    ring=c, ring_range=d: the ring/exchange term, with one coupling per target
+    pair (i, j), role (x = i, y = j or, for i < j, x = j, y = i) and occupied
+    m with |m - x| <= d whose pair {x, m} is retained (the pair itself
+    included when m = y: identity overlap); its integral blocks X and J are
+    normals times c exp(-(|m - x| + |m - y|) / 2) / sqrt(n_target) (default
+    c = 0: no ring term);
     somo_virt=True: every pair's PNOs are followed by the SOMOs as virtual
     functions for beta electrons (Sec. II.B.4): n_p = min(n_p, 64 - N_SOMO) +
     N_SOMO, B and K cover all of them, the SOMO part of every overlap block
@@ -474,15 +505,42 @@ def build_problem(name="tiny", **override):
         hh_src, hh_k, hh_l, hh_w = q.astype(np.int32), ck.astype(np.int32), cl.astype(np.int32), w
     hh_tgt = np.repeat(np.arange(P, dtype=np.int64), np.diff(hh_rowptr))
 
+    # ---- ring/exchange-term couplings (CSR by target): (role, m) near x ----
+    ring_scale = float(cfg.get("ring", 0.0))
+    ring_range = int(cfg.get("ring_range", 2))
+    ring_rowptr = np.zeros(P + 1, dtype=np.int64)
+    r_src, r_role, r_m = [], [], []
+    if ring_scale != 0.0:
+        for p in range(P):
+            i, j = int(pi[p]), int(pj[p])
+            for role, x in enumerate((i, j)):
+                if role == 1 and i == j:
+                    continue
+                for m in range(max(0, x - ring_range), min(n_occ, x + ring_range + 1)):
+                    q = pair_index.get((min(x, m), max(x, m)))
+                    if q is None:
+                        continue
+                    r_src.append(q)
+                    r_role.append(role)
+                    r_m.append(m)
+            ring_rowptr[p + 1] = len(r_src)
+    ring_src = np.array(r_src, dtype=np.int32)
+    ring_role = np.array(r_role, dtype=np.int32)
+    ring_m = np.array(r_m, dtype=np.int32)
+    ring_tgt = np.repeat(np.arange(P, dtype=np.int64), np.diff(ring_rowptr))
+
     # one S block per (target, source) pair of pairs, shared by every coupling
     # (Fock or hole-hole) between them; the two sides of a diagonal target that
     # reach the same source share it
-    key = np.concatenate([tgt * P + cpl_src, hh_tgt * P + hh_src.astype(np.int64)])
+    key = np.concatenate([tgt * P + cpl_src, hh_tgt * P + hh_src.astype(np.int64),
+                          ring_tgt * P + ring_src.astype(np.int64)])
     ukey, first, inv = np.unique(key, return_index=True, return_inverse=True)
     sz_dir = np.array([_align(int(npno[int(k // P)]) * int(npno[int(k % P)])) for k in ukey], dtype=np.int64)
     off_dir = np.concatenate([[0], np.cumsum(sz_dir)[:-1]]).astype(np.int64)
+    H = len(hh_src)
     cpl_off_S = off_dir[inv[:C]]
-    hh_off_S = off_dir[inv[C:]]
+    hh_off_S = off_dir[inv[C:C + H]]
+    ring_off_S = off_dir[inv[C + H:]].astype(np.int64)
     n_S = int(sz_dir.sum())
 
     # ---- generated segments ----
@@ -519,6 +577,28 @@ def build_problem(name="tiny", **override):
     segW["field"], segW["mode"], segW["scale"] = F_W, MODE_PLAIN, SIGMA_W
 
     segs = {"B": segB, "K": segK, "T": segT, "W": segW}
+
+    # ring integral blocks: X then J per coupling, n_src x n_target each
+    NR = len(ring_src)
+    r_rows = npno[ring_src].astype(np.int64) if NR else np.zeros(0, dtype=np.int64)
+    r_cols = npno[ring_tgt].astype(np.int64) if NR else np.zeros(0, dtype=np.int64)
+    r_sz = np.repeat(np.array([_align(int(a) * int(b)) for a, b in zip(r_rows, r_cols)], dtype=np.int64), 2)
+    r_off = np.concatenate([[0], np.cumsum(r_sz)[:-1]]).astype(np.int64) if NR else np.zeros(0, dtype=np.int64)
+    n_Rg = int(r_sz.sum())
+    segR = np.zeros(2 * NR, dtype=SEG_DTYPE)
+    if NR:
+        x_r = np.where(ring_role == 0, pi[ring_tgt], pj[ring_tgt]).astype(np.int64)
+        y_r = np.where(ring_role == 0, pj[ring_tgt], pi[ring_tgt]).astype(np.int64)
+        dec = ring_scale * np.exp(-(np.abs(ring_m - x_r) + np.abs(ring_m - y_r)) / 2.0) / np.sqrt(r_cols)
+        segR["off"] = r_off
+        segR["stream"] = np.arange(2 * NR)
+        segR["field"] = F_RING
+        segR["mode"] = MODE_PLAIN
+        segR["layers"] = 1
+        segR["rows"] = np.repeat(r_rows, 2)
+        segR["cols"] = np.repeat(r_cols, 2)
+        segR["scale"] = np.repeat(dec, 2)
+    segs["Rg"] = segR
     S_host = None
     if cfg["S"] == "qr60":
         # orthonormal PNO bases over a shared 60-dimensional virtual space
@@ -572,4 +652,7 @@ def build_problem(name="tiny", **override):
                    eps_b=eps_b, n_B=n_B, n_T=n_T, n_K=n_K, n_S=n_S, segs=segs, S_host=S_host,
                    pair_index=pair_index, hh_rowptr=hh_rowptr, hh_src=hh_src, hh_k=hh_k, hh_l=hh_l,
                    hh_w=hh_w, hh_off_S=hh_off_S.astype(np.int64), hole_scale=hh_scale, hole_range=hh_range,
-                   n_sv=n_sv, quadratic=bool(cfg.get("quadratic", False)) and hh_scale != 0.0)
+                   n_sv=n_sv, quadratic=bool(cfg.get("quadratic", False)) and hh_scale != 0.0,
+                   ring_rowptr=ring_rowptr, ring_src=ring_src, ring_role=ring_role, ring_m=ring_m,
+                   ring_off_S=ring_off_S, ring_off_X=r_off[0::2].copy(), ring_off_J=r_off[1::2].copy(),
+                   n_Rg=n_Rg, ring_scale=ring_scale, ring_range=ring_range)
