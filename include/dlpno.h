@@ -124,6 +124,31 @@ typedef struct {
   double w;
 } dlpno_hh_coupling;
 
+/* One ring/exchange coupling of a target pair p = (i, j) (CSR row of p; a
+ * further slice of the CCSD terms beyond the model above).  role 0 keeps the
+ * target's first occupied index, x = i, with y = j; role 1 keeps x = j, with
+ * y = i.  m is the replacing occupied orbital and src_pair the retained pair
+ * {min(x, m), max(x, m)} (the target itself when m = y).  In
+ * dlpno_inputs.ring_ints, two row-major n_src x n_target blocks [e][b]:
+ *     X at off_X:  (m e | b y),   J at off_J:  (m y | b e)   (chemists' notation),
+ * e over the source's PNOs, b over the target's.  off_S: the overlap block
+ * between the source PNOs (rows) and the target PNOs (columns) as in
+ * dlpno_coupling (an identity block when the source is the target).  The
+ * couplings add the spin-orbital term P(IJ) P(AB) sum_ME t_IM^AE <MB||EJ> of
+ * the CCSD doubles residual, <MB||EJ> = (m e | b j) - (m j | b e) within
+ * each spin, linear in the amplitudes, to every stored block: per block,
+ * spin of M and orientation, terms +-S_{p,q} op(T_q) X or J (and their
+ * transposes) over the source blocks that exist.  A diagonal target (i == j)
+ * lists role 0 only; each of its couplings serves both index orders.  FP64
+ * plans only; the vector-Jacobian product refuses such plans. */
+typedef struct {
+  int32_t src_pair;
+  int32_t m;
+  int32_t role;
+  int32_t reserved;
+  int64_t off_S, off_X, off_J;
+} dlpno_ring_coupling;
+
 /* Problem description (all host memory, copied by dlpno_plan_create). */
 typedef struct {
   int32_t n_occ;
@@ -139,6 +164,10 @@ typedef struct {
   int64_t n_hh;                    /* hole-hole ladder couplings (0: no such term) */
   const int64_t* hh_rowptr;        /* [n_pairs + 1], CSR by target pair (may be NULL when n_hh = 0) */
   const dlpno_hh_coupling* hh;     /* [n_hh] */
+  int64_t n_ring;                  /* ring/exchange couplings (0: no such term) */
+  const int64_t* ring_rowptr;      /* [n_pairs + 1], CSR by target pair (may be NULL when n_ring = 0) */
+  const dlpno_ring_coupling* ring; /* [n_ring] */
+  int64_t n_ring_ints;             /* element count of dlpno_inputs.ring_ints */
 } dlpno_problem;
 
 /* Device inputs (caller-owned, read-only, fixed for the life of the plan). */
@@ -148,6 +177,7 @@ typedef struct {
   const double* K;
   const double* eps_a;
   const double* eps_b;
+  const double* ring_ints;   /* integral blocks of the ring couplings (NULL when n_ring = 0) */
 } dlpno_inputs;
 
 typedef struct {
@@ -350,8 +380,12 @@ dlpno_status dlpno_autotune_cached(dlpno_plan* plan, const double* T, double* R,
  *   ladder launch (FP64 plans: pairs of 49 to 64 PNOs, one workgroup per
  *   item), 8 projection items run at two waves per SIMD (FP64 plans: target
  *   and source pairs of at most 48 PNOs), 9 weights of the quadratic term
- *   (DLPNO_FLAG_QUADRATIC). */
+ *   (DLPNO_FLAG_QUADRATIC), 10 ring/exchange term (n_ring > 0). */
 dlpno_status dlpno_set_profiling(dlpno_plan* plan, int32_t enable);
+/* Useful FP64 flops of the ring/exchange term per residual evaluation
+ * (2 n_p n_q (n_q + n_p) per contraction S_{p,q} op(T_q) X) and the number
+ * of such contractions; both 0 without ring couplings. */
+dlpno_status dlpno_ring_flop_count(const dlpno_plan* plan, double* flops, int64_t* contractions);
 dlpno_status dlpno_phase_times(const dlpno_plan* plan, double* ms, int64_t* launches, int32_t n);
 
 /* ---- PNO construction (Sec. II.B.2) ----

@@ -17,7 +17,7 @@ FLAGS = ["-O3", "--offload-arch=" + ARCH, "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 LIB_SOURCES = ["grouped_f64.hip", "grouped_f32.hip", "split.hip", "adjoint.hip", "elementwise.hip", "plan.hip",
-               "mixed.hip", "tune.hip", "noalloc.hip", "solve.hip", "pno.hip", "quadratic.hip"]
+               "mixed.hip", "tune.hip", "noalloc.hip", "solve.hip", "pno.hip", "quadratic.hip", "ring.hip"]
 GEN_SOURCES = [os.path.join(ROOT, "workload", "csrc", "gen.hip")]
 
 

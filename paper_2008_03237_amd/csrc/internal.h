@@ -55,6 +55,24 @@ struct QuadCpl {
   double w0[4], c[4];
 };
 
+// One contraction of the ring/exchange term (ring.hip):  Out += w L^T op(T_q) M
+// with L and M n_q x n_p row-major blocks ([c][a]) read from the overlap
+// buffer S or the ring integral buffer, op(T_q) = T_q or T_q^T.
+struct RxTerm {
+  int64_t src_off;      // source amplitude block in T, n_q x n_q
+  int64_t off_L, off_M;
+  int32_t nq;
+  int32_t flags;        // kRxL / kRxM: that factor is in the ring integral buffer; kRxTrans: op = ^T
+  double w;
+};
+constexpr int32_t kRxL = 1, kRxM = 2, kRxTrans = 4;
+// The ring contractions of one target block, summed into its last partial slot.
+struct RxUnit {
+  int32_t blk;          // global block index
+  int32_t pad;
+  int64_t t0, t1;       // terms [t0, t1)
+};
+
 // ITEM_LADDER2: ladder items of an FP64 plan run by the launch at two waves
 // per SIMD (at most three tiles of 16 PNOs and the variants below).
 // ITEM_LADDER4: four-tile ladder items of an FP64 plan, each run by a whole
@@ -175,6 +193,9 @@ hipError_t launch_quad_prepare(const QuadCpl* list, int64_t n, const double* S, 
                                hipStream_t s);
 hipError_t launch_quad_weights(const QuadCpl* list, int64_t n, const double* G, const double* T, TermDev* terms,
                                hipStream_t s);
+// ring.hip: every unit's ring contractions into its block's last partial slot
+hipError_t launch_ring(const RxUnit* units, int64_t n_units, const RxTerm* terms, const BlockDev* blocks,
+                       const double* T, const double* S, const double* ring_ints, double* ws, hipStream_t s);
 
 // elementwise.hip
 // DIIS on device.  State lives in a small device struct; vectors in rings.

@@ -355,7 +355,8 @@ dlpno_status build_schedule(dlpno_plan* P) {
     const PairDev& pr = P->pairs_h[p];
     for (int b = 0; b < pr.nblk; ++b) {
       BlockDev& bk = P->blocks_h[pr.blk0 + b];
-      bk.nslot = nL[p] + nP[p];
+      // the ring/exchange contractions of a block own its last slot
+      bk.nslot = nL[p] + nP[p] + (P->rx_block.empty() ? 0 : P->rx_block[pr.blk0 + b]);
       bk.slot_proj = nL[p];
       bk.off_ws = ws;
       ws += (int64_t)bk.nslot * pr.n * pr.n;
@@ -437,6 +438,11 @@ std::string dlpno::describe(const dlpno_plan* P) {
     buf[0] = 0;
   }
   s += buf;
+  if (P->n_ring > 0) {
+    snprintf(buf, sizeof buf, "ring/exchange term: %lld couplings, %zu contractions over %zu blocks, %.4e flops\n",
+             (long long)P->n_ring, P->rx_terms_h.size(), P->rx_units_h.size(), P->flops_rx);
+    s += buf;
+  }
   return s;
 }
 
@@ -453,8 +459,10 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if (n_occ < 1 || npairs < 0 || prob->n_couplings < 0)
     return fail(DLPNO_ERR_DIM_RANGE, "n_occ must be >= 1, n_pairs and n_couplings >= 0");
   if (!prob->is_somo || !prob->f_a || !prob->f_b || !prob->cpl_rowptr || (npairs > 0 && !prob->pairs) ||
-      (prob->n_couplings > 0 && !prob->cpl) || (prob->n_hh > 0 && (!prob->hh_rowptr || !prob->hh)))
+      (prob->n_couplings > 0 && !prob->cpl) || (prob->n_hh > 0 && (!prob->hh_rowptr || !prob->hh)) ||
+      (prob->n_ring > 0 && (!prob->ring_rowptr || !prob->ring)))
     return fail(DLPNO_ERR_INVALID_ARG, "a required host array is NULL");
+  if (prob->n_ring < 0 || prob->n_ring_ints < 0) return fail(DLPNO_ERR_DIM_RANGE, "n_ring and n_ring_ints must be >= 0");
   dlpno_options opt{};
   opt.precision = DLPNO_FP64;
   opt.diis_max = 8;
@@ -467,12 +475,16 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
     return fail(DLPNO_ERR_INVALID_ARG, "unknown option flag");
   const bool quad = (opt.flags & DLPNO_FLAG_QUADRATIC) != 0;
   if (quad && prob->n_hh <= 0) return fail(DLPNO_ERR_INVALID_ARG, "the quadratic term needs hole-hole couplings");
+  if (prob->n_ring > 0 && opt.precision != DLPNO_FP64)
+    return fail(DLPNO_ERR_UNSUPPORTED, "the ring/exchange term needs an FP64 plan");
   if (opt.diis_max > 0 && (opt.diis_start < 1 || opt.diis_start > opt.diis_max))
     return fail(DLPNO_ERR_INVALID_ARG, "diis_start must be in 1..diis_max");
   for (int k = 0; k < n_occ; ++k)
     if (prob->is_somo[k] > 1) return fail(DLPNO_ERR_INVALID_ARG, "is_somo entries must be 0 or 1");
   const bool need_inputs = npairs > 0;
-  if (need_inputs && (!in->B || !in->K || !in->eps_a || !in->eps_b || (prob->n_couplings + prob->n_hh > 0 && !in->S)))
+  if (need_inputs && (!in->B || !in->K || !in->eps_a || !in->eps_b ||
+                     (prob->n_couplings + prob->n_hh + prob->n_ring > 0 && !in->S) ||
+                     (prob->n_ring > 0 && !in->ring_ints)))
     return fail(DLPNO_ERR_INVALID_ARG, "a device input pointer is NULL");
 
   hipStream_t s = (hipStream_t)stream;
@@ -771,6 +783,130 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
       }
     }
   }
+  // ---- ring/exchange term ----
+  // P(IJ) P(AB) sum_ME t_IM^AE <MB||EJ>: per target block (spins s1, s2 of
+  // electrons i, j), role (X, Y) = (i s1, j s2) with sign +1 or (j s2, i s1)
+  // with sign -1, orientation (virtual spins (ra, cb) = (s1, s2), added as is,
+  // or (s2, s1), added transposed with sign -1) and spin sm of M:
+  //   (m e | c y) when cb is the spin of Y, e of spin sm;
+  //  -(m y | c e) when sm is the spin of Y, e of spin cb;
+  // each with the amplitude t_{X M}^{r e} of the source pair {x, m}: its
+  // stored block when (ra, e-spin) are the spins of (X, M), minus its
+  // transpose when they are swapped.
+  P->n_ring = prob->n_ring;
+  P->rx_block.assign(nblk_total, 0);
+  if (prob->n_ring > 0) {
+    std::vector<int64_t> rrow(prob->ring_rowptr, prob->ring_rowptr + npairs + 1);
+    if (rrow[0] != 0 || rrow[npairs] != prob->n_ring)
+      return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "ring_rowptr must start at 0 and end at n_ring"));
+    for (int p = 0; p < npairs; ++p)
+      if (rrow[p + 1] < rrow[p]) return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, "ring_rowptr must be non-decreasing"));
+    for (int p = 0; p < npairs; ++p) {
+      const dlpno_pair& d = prob->pairs[p];
+      const PairDev& pd = P->pairs_h[p];
+      std::vector<std::vector<RxTerm>> per_slot(pd.nblk);
+      for (int64_t re = rrow[p]; re < rrow[p + 1]; ++re) {
+        const dlpno_ring_coupling& c = prob->ring[re];
+        const std::string where = "ring coupling " + std::to_string(re) + " of pair " + std::to_string(p);
+        if (c.src_pair < 0 || c.src_pair >= npairs || c.m < 0 || c.m >= n_occ || (c.role != 0 && c.role != 1))
+          return destroy_fail(fail(DLPNO_ERR_DIM_RANGE, where + ": src_pair, m or role out of range"));
+        if (d.i == d.j && c.role != 0)
+          return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, where + ": a diagonal target lists role 0 only"));
+        const int xr = c.role == 0 ? d.i : d.j;
+        const dlpno_pair& q = prob->pairs[c.src_pair];
+        if (q.i != std::min(xr, c.m) || q.j != std::max(xr, c.m))
+          return destroy_fail(fail(DLPNO_ERR_INVALID_ARG, where + ": source pair does not match (role, m)"));
+        const int64_t blk = (int64_t)q.npno * d.npno;
+        if (c.off_S < 0 || c.off_S + blk > prob->n_S)
+          return destroy_fail(fail(DLPNO_ERR_ALIGNMENT, where + ": off_S exceeds the S buffer"));
+        if (c.off_X < 0 || c.off_X + blk > prob->n_ring_ints || c.off_J < 0 || c.off_J + blk > prob->n_ring_ints)
+          return destroy_fail(fail(DLPNO_ERR_ALIGNMENT, where + ": off_X or off_J exceeds the ring integral buffer"));
+        const int64_t nq = q.npno;
+        // stored block of the ordered source (x sx, m sm): slot and transpose, or -1
+        auto lookup = [&](int x, int sx, int sm, int& trans) -> int {
+          int scode;
+          if (x == c.m) {
+            if (sx == sm) return -1;
+            scode = 2;
+            trans = sx == 1;
+          } else if (x < c.m) {
+            scode = block_code(sx, sm);
+            trans = 0;
+          } else {
+            scode = block_code(sm, sx);
+            trans = 1;
+          }
+          if (!(q.blocks & kCodeBit[scode])) return -1;
+          int sslot = 0;
+          for (int cc = 0; cc < scode; ++cc)
+            if (q.blocks & kCodeBit[cc]) ++sslot;
+          return sslot;
+        };
+        int slot = 0;
+        for (int code = 0; code < 4; ++code) {
+          if (!(d.blocks & kCodeBit[code])) continue;
+          const int this_slot = slot++;
+          const int s1 = kCodeS1[code], s2 = kCodeS2[code];
+          for (int role = 0; role < 2; ++role) {
+            if (d.i != d.j && role != c.role) continue;      // a diagonal target applies each coupling twice
+            const int x = role == 0 ? d.i : d.j, sx = role == 0 ? s1 : s2, sy = role == 0 ? s2 : s1;
+            for (int orient = 0; orient < 2; ++orient) {
+              const int ra = orient == 0 ? s1 : s2, cb = orient == 0 ? s2 : s1;
+              const double sgn = (role == 0 ? 1.0 : -1.0) * (orient == 0 ? 1.0 : -1.0);
+              for (int sm = 0; sm < 2; ++sm) {
+                if (sm == 1 && prob->is_somo[c.m]) continue;   // M occupied: SOMOs are alpha only
+                for (int part = 0; part < 2; ++part) {       // 0: X = (m e|c y), 1: J = (m y|c e)
+                  const int se = part == 0 ? sm : cb;
+                  if (part == 0 ? cb != sy : sm != sy) continue;
+                  int trans = 0;
+                  double asign;
+                  int sslot;
+                  if (sx == ra && sm == se) {
+                    sslot = lookup(x, sx, sm, trans);
+                    asign = 1.0;
+                  } else if (sx == se && sm == ra) {
+                    sslot = lookup(x, sx, sm, trans);
+                    trans ^= 1;
+                    asign = -1.0;
+                  } else {
+                    continue;
+                  }
+                  if (sslot < 0) continue;
+                  RxTerm t{};
+                  t.src_off = q.off_T + (int64_t)sslot * nq * nq;
+                  t.nq = (int32_t)nq;
+                  t.w = sgn * asign * (part == 0 ? 1.0 : -1.0);
+                  const int64_t off_W = part == 0 ? c.off_X : c.off_J;
+                  // orientation 0: S^T op(T) W;  1: (S^T op(T) W)^T = W^T op(T)^T S
+                  if (orient == 0) {
+                    t.off_L = c.off_S;
+                    t.off_M = off_W;
+                    t.flags = kRxM | (trans ? kRxTrans : 0);
+                  } else {
+                    t.off_L = off_W;
+                    t.off_M = c.off_S;
+                    t.flags = kRxL | (trans ? 0 : kRxTrans);
+                  }
+                  per_slot[this_slot].push_back(t);
+                  P->flops_rx += 2.0 * pd.n * (double)nq * (nq + pd.n);
+                }
+              }
+            }
+          }
+        }
+      }
+      for (int b = 0; b < pd.nblk; ++b) {
+        if (per_slot[b].empty()) continue;
+        RxUnit u{};
+        u.blk = pd.blk0 + b;
+        u.t0 = (int64_t)P->rx_terms_h.size();
+        P->rx_terms_h.insert(P->rx_terms_h.end(), per_slot[b].begin(), per_slot[b].end());
+        u.t1 = (int64_t)P->rx_terms_h.size();
+        P->rx_units_h.push_back(u);
+        P->rx_block[pd.blk0 + b] = 1;
+      }
+    }
+  }
   // ---- device ----
   int dev = 0;
   HIPCK(hipGetDevice(&dev));
@@ -808,6 +944,10 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
     if (launch_quad_prepare(P->d_quad, (int64_t)P->quad_h.size(), P->in.S, P->in.K, P->d_quadG, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
       return destroy_fail(fail(DLPNO_ERR_HIP, "quadratic-term factors"));
+  }
+  if (!P->rx_units_h.empty()) {
+    if ((st = upload(&P->d_rx_terms, P->rx_terms_h, "ring term table", s)) != DLPNO_OK) return destroy_fail(st);
+    if ((st = upload(&P->d_rx_units, P->rx_units_h, "ring unit table", s)) != DLPNO_OK) return destroy_fail(st);
   }
   if ((st = upload_schedule(P, s)) != DLPNO_OK) return destroy_fail(st);
   if ((st = dev_alloc(&P->d_counter, kKinds * kQueues, "queue heads")) != DLPNO_OK) return destroy_fail(st);
@@ -904,7 +1044,7 @@ extern "C" dlpno_status dlpno_plan_destroy(dlpno_plan* P) {
                   P->d_vjp_items, P->d_mixed, P->G32, P->d_pair_boff, P->d_blk_toff, P->d_cpl_soff,
                   P->d_cpl_target, P->d_pair_bscale, P->d_blk_tscale, P->Bs_hi, P->Bs_lo, P->Ss_hi, P->Ss_lo,
                   P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo, P->d_mix_r, P->d_mix_delta, P->d_hist_iter, P->d_quad,
-                  P->d_quadG, P->d_flagz};
+                  P->d_quadG, P->d_flagz, P->d_rx_terms, P->d_rx_units};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete P;
@@ -967,6 +1107,14 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
                        bool weights) {
   hipError_t e;
   double* const wsp = ws ? ws : P->d_ws;
+  // ring/exchange contractions (FP64 plans only) into the blocks' last slots
+  if (!P->rx_units_h.empty()) {
+    phase_begin(P, 10, s);
+    e = launch_ring(P->d_rx_units, (int64_t)P->rx_units_h.size(), P->d_rx_terms, P->d_blocks, T, P->in.S,
+                    P->in.ring_ints, wsp, s);
+    phase_end(P, s);
+    if (e != hipSuccess) return e;
+  }
   if (P->sched.items_h.empty()) return hipSuccess;
   if (prec < 0) prec = P->opt.precision;
   // quadratic-term weights from T in FP64 for every residual of T; the
@@ -1258,6 +1406,13 @@ extern "C" dlpno_status dlpno_flop_count(const dlpno_plan* P, double* ladder, do
   if (!P) return fail(DLPNO_ERR_INVALID_ARG, "NULL plan");
   if (ladder) *ladder = P->flops_ladder;
   if (projection) *projection = P->flops_proj;
+  return DLPNO_OK;
+}
+
+extern "C" dlpno_status dlpno_ring_flop_count(const dlpno_plan* P, double* flops, int64_t* contractions) {
+  if (!P) return fail(DLPNO_ERR_INVALID_ARG, "NULL plan");
+  if (flops) *flops = P->flops_rx;
+  if (contractions) *contractions = (int64_t)P->rx_terms_h.size();
   return DLPNO_OK;
 }
 

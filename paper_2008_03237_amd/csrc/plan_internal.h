@@ -14,7 +14,7 @@ namespace dlpno {
 
 constexpr int kHistCap = 4096;   // iterations kept in the device history
 constexpr int kDiisParts = 1024; // workgroups of the DIIS dot-product kernel
-constexpr int kPhases = 10;
+constexpr int kPhases = 11;
 
 // schedule choices (set by defaults or the autotuner)
 struct Tuning {
@@ -61,6 +61,14 @@ struct dlpno_plan {
   int64_t n_quadG = 0;
   double flops_quad = 0.0;               // the weights' dot products per residual
   double flops_quad_prep = 0.0;          // building the factors S K S^T (once)
+  // ring/exchange term: contractions per target block (units), last partial slot
+  std::vector<dlpno::RxTerm> rx_terms_h;
+  std::vector<dlpno::RxUnit> rx_units_h;
+  std::vector<uint8_t> rx_block;         // per block: 1 = has ring contractions (owns the last slot)
+  dlpno::RxTerm* d_rx_terms = nullptr;
+  dlpno::RxUnit* d_rx_units = nullptr;
+  int64_t n_ring = 0;
+  double flops_rx = 0.0;
   std::vector<dlpno::CplDev> cpl_h;
   std::vector<dlpno::TermDev> terms_h;
   std::vector<int64_t> rowptr_h;

@@ -34,12 +34,14 @@ class Problem(C.Structure):
                 ("is_somo", C.c_void_p), ("pairs", C.c_void_p), ("cpl_rowptr", C.c_void_p), ("cpl", C.c_void_p),
                 ("f_a", C.c_void_p), ("f_b", C.c_void_p), ("n_B", C.c_int64), ("n_T", C.c_int64),
                 ("n_K", C.c_int64), ("n_eps", C.c_int64), ("n_S", C.c_int64),
-                ("n_hh", C.c_int64), ("hh_rowptr", C.c_void_p), ("hh", C.c_void_p)]
+                ("n_hh", C.c_int64), ("hh_rowptr", C.c_void_p), ("hh", C.c_void_p),
+                ("n_ring", C.c_int64), ("ring_rowptr", C.c_void_p), ("ring", C.c_void_p),
+                ("n_ring_ints", C.c_int64)]
 
 
 class Inputs(C.Structure):
     _fields_ = [("B", C.c_void_p), ("S", C.c_void_p), ("K", C.c_void_p), ("eps_a", C.c_void_p),
-                ("eps_b", C.c_void_p)]
+                ("eps_b", C.c_void_p), ("ring_ints", C.c_void_p)]
 
 
 class Options(C.Structure):
@@ -53,6 +55,8 @@ PAIR_DTYPE = np.dtype([("i", "<i4"), ("j", "<i4"), ("npno", "<i4"), ("naux", "<i
 CPL_DTYPE = np.dtype([("src_pair", "<i4"), ("k", "<i4"), ("side", "<i4"), ("reserved", "<i4"), ("off_S", "<i8")])
 HH_DTYPE = np.dtype([("src_pair", "<i4"), ("k", "<i4"), ("l", "<i4"), ("reserved", "<i4"), ("off_S", "<i8"),
                      ("w", "<f8")])
+RING_DTYPE = np.dtype([("src_pair", "<i4"), ("m", "<i4"), ("role", "<i4"), ("reserved", "<i4"), ("off_S", "<i8"),
+                       ("off_X", "<i8"), ("off_J", "<i8")])
 
 _LIB = None
 
@@ -84,6 +88,7 @@ def lib():
         "dlpno_residual_vjp": [vp, vp, vp, vp, vp, vp],
         "dlpno_solve_mixed": [vp, i32, i32, vp, vp, vp, vp, vp, vp],
         "dlpno_flop_count": [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+        "dlpno_ring_flop_count": [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
         "dlpno_diis_state": [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.POINTER(C.c_double), vp],
         "dlpno_solve": [vp, i32, C.c_double, C.c_double, vp, vp, vp, vp, vp, C.POINTER(C.c_int32), vp],
         "dlpno_checkpoint_size": [vp, C.POINTER(C.c_size_t)],
@@ -146,7 +151,7 @@ class Plan:
     """
 
     def __init__(self, desc, B, S, K, eps_a, eps_b, precision="fp64", diis_max=8, diis_start=3, n_workers=0,
-                 items_per_wave=0, general_T=False, quadratic=False):
+                 items_per_wave=0, general_T=False, quadratic=False, ring_ints=None):
         import torch
         L = lib()
         P = len(desc.pi)
@@ -168,22 +173,32 @@ class Plan:
             hh["src_pair"][:nhh], hh["k"][:nhh], hh["l"][:nhh] = desc.hh_src, desc.hh_k, desc.hh_l
             hh["off_S"][:nhh], hh["w"][:nhh] = desc.hh_off_S, desc.hh_w
             hh_rowptr = np.ascontiguousarray(desc.hh_rowptr, dtype=np.int64)
+        # ring/exchange couplings (optional descriptor fields; need ring_ints)
+        nring = int(getattr(desc, "n_ring", 0) or 0) if ring_ints is not None else 0
+        ring = np.zeros(max(nring, 1), dtype=RING_DTYPE)
+        ring_rowptr = np.zeros(P + 1, dtype=np.int64)
+        if nring > 0:
+            ring["src_pair"][:nring], ring["m"][:nring], ring["role"][:nring] = desc.ring_src, desc.ring_m, desc.ring_role
+            ring["off_S"][:nring], ring["off_X"][:nring], ring["off_J"][:nring] = (desc.ring_off_S, desc.ring_off_X,
+                                                                                   desc.ring_off_J)
+            ring_rowptr = np.ascontiguousarray(desc.ring_rowptr, dtype=np.int64)
         self._host = dict(
             somo=np.ascontiguousarray(desc.is_somo, dtype=np.uint8), pairs=pairs, cpl=cpl,
             rowptr=np.ascontiguousarray(desc.cpl_rowptr, dtype=np.int64),
             f_a=np.ascontiguousarray(desc.f_a, dtype=np.float64), f_b=np.ascontiguousarray(desc.f_b, dtype=np.float64),
-            hh=hh, hh_rowptr=hh_rowptr)
+            hh=hh, hh_rowptr=hh_rowptr, ring=ring, ring_rowptr=ring_rowptr)
         h = self._host
         prob = Problem(int(desc.n_occ), P, ncpl, h["somo"].ctypes.data, h["pairs"].ctypes.data, h["rowptr"].ctypes.data,
                        h["cpl"].ctypes.data, h["f_a"].ctypes.data, h["f_b"].ctypes.data, int(desc.n_B), int(desc.n_T),
                        int(desc.n_K), int(len(desc.eps_a)), int(desc.n_S), nhh, h["hh_rowptr"].ctypes.data,
-                       h["hh"].ctypes.data)
-        self._dev = [B, S, K, eps_a, eps_b]
+                       h["hh"].ctypes.data, nring, h["ring_rowptr"].ctypes.data, h["ring"].ctypes.data,
+                       int(getattr(desc, "n_Rg", 0) or 0) if nring > 0 else 0)
+        self._dev = [B, S, K, eps_a, eps_b, ring_ints]
         for t in self._dev:
             if t is not None and (t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous()):
                 raise ValueError("inputs must be contiguous float64 CUDA tensors")
         inp = Inputs(B.data_ptr(), S.data_ptr() if S is not None else None, K.data_ptr(), eps_a.data_ptr(),
-                     eps_b.data_ptr())
+                     eps_b.data_ptr(), ring_ints.data_ptr() if ring_ints is not None else None)
         prec = _PREC[precision] if isinstance(precision, str) else int(precision)
         flags = (FLAG_GENERAL_T if general_T else 0) | (FLAG_QUADRATIC if quadratic else 0)
         opt = Options(prec, diis_max, diis_start, n_workers, int(items_per_wave), flags)
@@ -332,10 +347,17 @@ class Plan:
         _check(lib().dlpno_set_profiling(self._h, 1 if on else 0))
 
     def phase_times(self):
-        ms = (C.c_double * 10)()
-        n = (C.c_int64 * 10)()
-        _check(lib().dlpno_phase_times(self._h, ms, n, 10))
+        ms = (C.c_double * 11)()
+        n = (C.c_int64 * 11)()
+        _check(lib().dlpno_phase_times(self._h, ms, n, 11))
         return list(ms), list(n)
+
+    def ring_flop_count(self):
+        """(flops, contractions) of the ring/exchange term per residual."""
+        f = C.c_double()
+        k = C.c_int64()
+        _check(lib().dlpno_ring_flop_count(self._h, C.byref(f), C.byref(k)))
+        return f.value, k.value
 
     def info(self):
         return lib().dlpno_plan_info(self._h).decode()

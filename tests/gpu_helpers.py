@@ -9,9 +9,12 @@ def device_problem(prob, precision="fp64", diis_max=8, diis_start=3, T_random=Tr
     import torch
     from paper_2008_03237_amd import Plan
     from workload.gpu import device_fields
-    dev = device_fields(prob)
+    ring = getattr(prob, "n_ring", 0) > 0
+    dev = device_fields(prob, fields=("B", "S", "K", "T", "Rg") if ring else ("B", "S", "K", "T"))
     eps_a = torch.from_numpy(prob.eps_a).cuda()
     eps_b = torch.from_numpy(prob.eps_b).cuda()
+    if ring:
+        plan_options.setdefault("ring_ints", dev["Rg"])
     plan = Plan(prob, dev["B"], dev["S"], dev["K"], eps_a, eps_b, precision=precision, diis_max=diis_max,
                 diis_start=diis_start, **plan_options)
     if not T_random:

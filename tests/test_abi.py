@@ -15,6 +15,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libdlpno.so not
 
 def declared():
     src = open(os.path.join(ROOT, "include", "dlpno.h")).read()
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)      # declarations only, not the comments
     return sorted(set(re.findall(r"\b(dlpno_[a-z_]+)\s*\(", src)))
 
 
@@ -124,3 +125,65 @@ def test_pno_plan_validation_on_host():
         assert st == code, (field, st)
         assert h.value is None
     assert PNO_PAIR_DTYPE.itemsize == 48
+
+
+def _ring_problem(precision=0, **mut):
+    """The tiny workload with ring couplings (descriptors only; fake device
+    pointers that validation never dereferences)."""
+    from paper_2008_03237_amd.lib import Problem, Inputs, Options, PAIR_DTYPE, CPL_DTYPE, RING_DTYPE
+    from workload import build_problem
+    prob = build_problem("tiny", ring=0.05)
+    pairs = np.zeros(prob.n_pairs, dtype=PAIR_DTYPE)
+    for f, v in (("i", prob.pi), ("j", prob.pj), ("npno", prob.npno), ("naux", prob.naux), ("blocks", prob.blocks),
+                 ("off_B", prob.off_B), ("off_T", prob.off_T), ("off_K", prob.off_K), ("off_eps", prob.off_eps)):
+        pairs[f] = v
+    cpl = np.zeros(prob.n_couplings, dtype=CPL_DTYPE)
+    cpl["src_pair"], cpl["k"], cpl["side"], cpl["off_S"] = prob.cpl_src, prob.cpl_k, prob.cpl_side, prob.cpl_off_S
+    ring = np.zeros(prob.n_ring, dtype=RING_DTYPE)
+    ring["src_pair"], ring["m"], ring["role"] = prob.ring_src, prob.ring_m, prob.ring_role
+    ring["off_S"], ring["off_X"], ring["off_J"] = prob.ring_off_S, prob.ring_off_X, prob.ring_off_J
+    rrow = prob.ring_rowptr.copy()
+    for fn in mut.values():
+        fn(prob, ring, rrow)
+    keep = [pairs, cpl, ring, rrow, prob]
+    P = Problem(prob.n_occ, prob.n_pairs, prob.n_couplings, prob.is_somo.ctypes.data, pairs.ctypes.data,
+                prob.cpl_rowptr.ctypes.data, cpl.ctypes.data, prob.f_a.ctypes.data, prob.f_b.ctypes.data, prob.n_B,
+                prob.n_T, prob.n_K, len(prob.eps_a), prob.n_S, 0, None, None, len(ring), rrow.ctypes.data,
+                ring.ctypes.data, prob.n_Rg)
+    I = Inputs(16, 16, 16, 16, 16, 16)
+    return P, I, Options(precision, 8, 3, 0, 0, 0), keep
+
+
+def _diag_ring(prob):
+    """Index of a ring coupling whose target is a diagonal pair."""
+    for p in range(prob.n_pairs):
+        if prob.pi[p] == prob.pj[p] and prob.ring_rowptr[p + 1] > prob.ring_rowptr[p]:
+            return int(prob.ring_rowptr[p])
+    raise AssertionError("no diagonal target")
+
+
+@pytest.mark.parametrize("mut,status", [
+    ({"role": lambda pr, r, rr: r.__setitem__("role", np.where(np.arange(len(r)) == 4, 2, r["role"]))}, -2),
+    ({"diag": lambda pr, r, rr: r["role"].__setitem__(_diag_ring(pr), 1)}, -1),
+    ({"m": lambda pr, r, rr: r.__setitem__("m", np.where(np.arange(len(r)) == 4, (r["m"] + 1) % pr.n_occ, r["m"]))}, -1),
+    ({"offX": lambda pr, r, rr: r["off_X"].__setitem__(9, pr.n_Rg)}, -3),
+    ({"offJ": lambda pr, r, rr: r["off_J"].__setitem__(9, -1)}, -3),
+    ({"offS": lambda pr, r, rr: r["off_S"].__setitem__(9, pr.n_S)}, -3),
+    ({"csr": lambda pr, r, rr: rr.__setitem__(3, rr[4] + 1)}, -1),
+])
+def test_ring_validation_errors(mut, status):
+    P, I, opts, keep = _ring_problem(**mut)
+    st, msg = _create(P, I, opts)
+    assert st == status, (st, msg)
+    assert msg
+
+
+def test_ring_needs_fp64_and_its_integrals():
+    from paper_2008_03237_amd.lib import Inputs
+    for prec in (1, 2, 3):
+        P, I, opts, keep = _ring_problem(precision=prec)
+        st, msg = _create(P, I, opts)
+        assert st == -8 and "ring" in msg, (prec, st, msg)
+    P, I, opts, keep = _ring_problem()
+    st, msg = _create(P, Inputs(16, 16, 16, 16, 16, None), opts)
+    assert st == -1, (st, msg)
