@@ -118,6 +118,9 @@ def main():
                     help="further refinement schedules OUTERxINNER timed for every split precision ('' = none)")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-path leg")
     ap.add_argument("--no-hole", action="store_true", help="skip the hole-hole ladder leg")
+    ap.add_argument("--no-ring", action="store_true", help="skip the ring/exchange-term leg")
+    ap.add_argument("--ring-scale", type=float, default=0.05,
+                    help="scale of the synthetic integral blocks of the ring/exchange-term leg")
     ap.add_argument("--no-pno", action="store_true", help="skip the PNO-construction leg")
     ap.add_argument("--no-somo-virt", action="store_true", help="skip the SOMO-augmented virtual space leg")
     ap.add_argument("--hole-scale", type=float, default=0.02,
@@ -278,6 +281,8 @@ def main():
             out["fp32"] = fp32_leg(prob, dev, eps_a, eps_b, args, fl_ladder, fl_proj, ref, log)
     if not args.no_hole and args.precision == "fp64":
         out["hole_ladder"] = hole_leg(args, dev, eps_a, eps_b, fl_proj, log)
+    if not args.no_ring and args.precision == "fp64":
+        out["ring"] = ring_leg(args, dev, eps_a, eps_b, log)
     if not args.no_pno:
         out["pno"] = pno_leg(args, log)
     plan.close()
@@ -561,6 +566,48 @@ def hole_leg(args, dev, eps_a, eps_b, fl_proj_base, log):
     log("quadratic term: %s" % row["quadratic"])
     pq.close()
     del S, T
+    return row
+
+
+def ring_leg(args, dev, eps_a, eps_b, log):
+    """The same workload with the ring/exchange term added (linear in the
+    doubles): synthetic integral blocks X = (m e|b y) and J = (m y|b e) for
+    every replacing occupied m within two orbitals of the shared index, summed
+    per target block by the ring kernel (FP64 MFMA).  FP64 iterations from
+    T = 0, timed like the main leg; the ring kernel's time per residual and its
+    rate against the FP64 MFMA peak."""
+    import torch
+
+    from paper_2008_03237_amd import Plan
+    from workload import build_problem
+    from workload.gpu import device_fields
+    prob = build_problem(args.workload, ring=args.ring_scale)
+    f = device_fields(prob, fields=("S", "Rg"))         # B, K and eps are those of the main leg
+    plan = Plan(prob, dev["B"], f["S"], dev["K"], eps_a, eps_b, ring_ints=f["Rg"])
+    T = torch.zeros(max(prob.n_T, 1), dtype=torch.float64, device="cuda")
+    plan.iterate(args.warmup, T)
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    t0 = time.perf_counter()
+    _, _, e_tot, rmax = plan.iterate(args.steps, T)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) / max(args.steps, 1) * 1e3
+    ms, cnt = plan.phase_times()
+    plan.set_profiling(False)
+    fl_ring, n_contr = plan.ring_flop_count()
+    ring_ms = ms[10] / max(cnt[10], 1)
+    tf = fl_ring / (ring_ms / 1e3) / 1e12 if ring_ms > 0 else None
+    row = {"ring_couplings": int(prob.n_ring), "contractions": int(n_contr), "ms_per_step": round(ms_step, 3),
+           "ring_kernel": "ring_kernel (FP64 MFMA 16x16x4)", "ring_kernel_ms": round(ring_ms, 3),
+           "ring_flops_per_residual": fl_ring, "ring_tflops": round(tf, 3) if tf else None,
+           "ring_frac_fp64_peak": round(tf / 78.6, 4) if tf else None,
+           "energy_after": float(e_tot.cpu()[0]), "iterations": args.warmup + args.steps,
+           "max_abs_R": float(rmax.cpu()[0]), "ring_ints_GB": round(prob.n_Rg * 8 / 1e9, 2),
+           "S_GB": round(prob.n_S * 8 / 1e9, 2)}
+    log("ring/exchange leg: %s" % row)
+    plan.close()
+    del f, T
+    torch.cuda.empty_cache()
     return row
 
 
