@@ -80,25 +80,35 @@ __device__ __forceinline__ void ring_unit(const RxUnit& u, const RxTerm* __restr
       V Pt[NT];
 #pragma unroll
       for (int b = 0; b < NT; ++b) Pt[b] = V{0, 0, 0, 0};
+      // k-steps in chunks of four: the chunk's operands are loaded together,
+      // then multiplied.  Steps past the source's PNOs read rows of L beyond
+      // its end (zero), so the last chunk needs no predicate.
+      for (int s0 = 0; s0 < nq4; s0 += 4) {
+        double xv[4], lb[4][NT];
 #pragma unroll
-      for (int s = 0; s < 16; ++s) {
-        if (s >= nq4) break;
-        const double xv = w * Mfma<double>::load(xr, xa + (uint32_t)s * xs + (uint32_t)td * xt);
+        for (int u = 0; u < 4; ++u) {
+          const int s = s0 + u;
+          xv[u] = Mfma<double>::load(xr, xa + (uint32_t)s * xs + (uint32_t)td * xt);
 #pragma unroll
-        for (int b = 0; b < NT; ++b)
-          Pt[b] = Mfma<double>::op(xv, Mfma<double>::load(br, (uint32_t)(4 * s + g) * n + 16 * b + r), Pt[b]);
+          for (int b = 0; b < NT; ++b) lb[u][b] = Mfma<double>::load(br, (uint32_t)(4 * s + g) * n + 16 * b + r);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int b = 0; b < NT; ++b) Pt[b] = Mfma<double>::op(w * xv[u], lb[u][b], Pt[b]);
       }
+      // rows of M past the source's PNOs are zero (beyond its end)
+      double la[4][NT];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        if (4 * td + i >= nq4) break;
-        double la[NT];
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int a = 0; a < NT; ++a) la[a] = Mfma<double>::load(ar, (uint32_t)(16 * td + 4 * i + g) * n + 16 * a + r);
+        for (int a = 0; a < NT; ++a) la[i][a] = Mfma<double>::load(ar, (uint32_t)(16 * td + 4 * i + g) * n + 16 * a + r);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int a = 0; a < NT; ++a)
 #pragma unroll
-          for (int b = 0; b < NT; ++b) Z[a][b] = Mfma<double>::op(la[a], Pt[b][i], Z[a][b]);
-      }
+          for (int b = 0; b < NT; ++b) Z[a][b] = Mfma<double>::op(la[i][a], Pt[b][i], Z[a][b]);
     }
   }
 
