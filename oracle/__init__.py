@@ -39,7 +39,8 @@ Parity status per function (what pins it, see tests/test_oracle_*.py):
 """
 from .model import (Inputs, OccInts, stored_blocks, residual_os, residual_cs, jacobi,  # noqa: F401
                     pair_energies, pair_energies_cs, denominators, t_lookup, hole_terms,
-                    quadratic_weight, RingInts, ring_block)
+                    quadratic_weight, RingInts, ring_block,
+                    occ_intermediate, occ_quadratic_block)
 from .spinorbital import residual_spinorbital  # noqa: F401
 from .solver import DIIS, solve, dense_solution, apply_operator  # noqa: F401
 from .adjoint import vjp  # noqa: F401

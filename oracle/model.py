@@ -90,6 +90,7 @@ class Inputs:
         self.occ_ints = occ_ints
         self.n_sv = None if n_sv is None else [int(x) for x in n_sv]
         self.quadratic = False   # add the quadratic term over the hole-hole couplings
+        self.quadratic_occ = False   # add the quadratic part of the occupied Fock intermediate
         self.ring = ring
 
     def B(self, p):
@@ -97,6 +98,13 @@ class Inputs:
 
     def S(self, p, q):
         return self._S(p, q) if callable(self._S) else self._S[(p, q)]
+
+    def has_S(self, p, q):
+        """Whether the problem lists an overlap block of target p and source q
+        (always, for overlaps given as a function)."""
+        if getattr(self, "_listed", None) is not None:
+            return (p, q) in self._listed
+        return callable(self._S) or (p, q) in self._S
 
     def npno(self, p):
         return len(self.eps_a[p])
@@ -182,7 +190,9 @@ class Inputs:
         n_sv = getattr(prob, "n_sv", None)
         ring = _WorkloadRing(prob) if getattr(prob, "n_ring", 0) > 0 else None
         inp = cls(prob.n_occ, prob.is_somo, pairs, Bf, Kd, ea, eb, prob.f_a, prob.f_b, Sf, occ, n_sv, ring)
+        inp._listed = set(where)
         inp.quadratic = bool(getattr(prob, "quadratic", False))
+        inp.quadratic_occ = bool(getattr(prob, "quadratic_occ", False))
         return inp
 
 
@@ -373,6 +383,70 @@ def hole_terms(inp, T, p, name, quadratic=False):
     return out
 
 
+def occ_intermediate(inp, T, m, j, s):
+    """Quadratic part of the occupied Fock intermediate, F^s_{mj} =
+    1/2 sum_{N,E,F} t_{(j s) N}^{EF} <(m s) N||EF>.  Reduced to spin blocks,
+    the two spin assignments of (E, F) make each block count once with
+    factor 1:  F^s_{mj} = sum_{n, s_n} <G_(m,n), T^{s s_n}_{(j,n)}>, over
+    occupied n of either spin (n in occ_{s_n}), with G[e][f] = (m e | n f)
+    over the PNOs of pair {j, n}.  Reading (as in quadratic_weight): those
+    integrals are the projection S_{jn,mn} K_(m,n) S_{mn,jn} of pair {m, n}'s
+    exchange integrals (K of {m, n}, transposed for m > n); for m = j they
+    are K_(j,n) itself.  Terms whose pairs are not retained, or whose overlap
+    block the problem does not list (a coupling outside its lists), vanish."""
+    total = 0.0
+    for n in range(inp.n_occ):
+        r = inp.index.get((min(m, n), max(m, n)))
+        if r is None:
+            continue
+        Kmn = inp.K[r] if m <= n else inp.K[r].T
+        for sn in (0, 1):
+            if sn == 1 and inp.is_somo[n]:
+                continue
+            src = t_lookup(inp, T, j, n, s, sn)
+            if src is None:
+                continue
+            q = src[0]
+            if q == r:
+                G = Kmn
+            else:
+                if not inp.has_S(q, r):        # coupling not listed: local truncation
+                    continue
+                Sqr = inp.S(q, r)
+                G = Sqr @ Kmn @ Sqr.T
+            total += float(np.sum(G * src[3]))
+    return total
+
+
+def occ_quadratic_block(inp, T, p, name, F):
+    """-P(IJ) sum_M t_IM^AB F_MJ for block `name` of pair p = (i, j), F a dict
+    (m, j, s) -> F^s_{mj}.  t_JM^AB = -t_MJ^AB turns the exchanged half into
+    the same form as the first, like the occupied-Fock projections:
+      - sum_{m in occ_s} F^s_{mi} S T^{ss'}_{(m,j)} S^T
+      - sum_{m in occ_s'} F^{s'}_{mj} S T^{ss'}_{(i,m)} S^T,
+    m = i and m = j included (the pair itself, identity overlap); sources
+    whose overlap block the problem does not list are left out."""
+    i, j = inp.pairs[p]
+    s1, s2 = SPIN[name]
+    out = np.zeros_like(T[(p, name)])
+    for side, (s, rep_, keep) in enumerate(((s1, i, j), (s2, j, i))):
+        for m in inp.occ(s):
+            f = F.get((m, rep_, s), 0.0)
+            if f == 0.0:
+                continue
+            src = t_lookup(inp, T, m, j, s1, s2) if side == 0 else t_lookup(inp, T, i, m, s1, s2)
+            if src is None:
+                continue
+            if src[0] == p:
+                out -= f * src[3]
+            else:
+                if not inp.has_S(p, src[0]):
+                    continue
+                Spq = inp.S(p, src[0])
+                out -= f * (Spq @ src[3] @ Spq.T)
+    return out
+
+
 class RingInts:
     """Integrals of the ring/exchange term, listed per target pair.
 
@@ -452,17 +526,29 @@ def ring_block(inp, T, p, name):
             - ring_part(inp, T, p, 0, s2, s1, s1, s2).T + ring_part(inp, T, p, 1, s2, s1, s1, s2).T)
 
 
-def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladder", "hole", "quadratic", "ring")):
+def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladder", "hole", "quadratic", "ring",
+                                           "quadratic_occ")):
     """Open-shell residual blocks {(p, name): R} for the given target pairs.
     The hole-hole term is present only when inp.occ_ints is given; with
     inp.quadratic set, its couplings carry the quadratic CCSD term too
     (quadratic_weight); the ring/exchange term only when inp.ring is given
-    (ring_block).  With SOMO
+    (ring_block); with inp.quadratic_occ the quadratic part of the occupied
+    Fock intermediate (occ_intermediate, occ_quadratic_block).  With SOMO
     virtual functions (inp.n_sv) each block is the model residual restricted
     to its spins' virtual spaces (the rows of an alpha virtual index and the
     columns of an alpha virtual index vanish at SOMO functions); amplitudes
     must vanish there too."""
     R = {}
+    Focc = None
+    if "quadratic_occ" in terms and getattr(inp, "quadratic_occ", False):
+        Focc = {}
+        for s in (0, 1):
+            occ = inp.occ(s)
+            for j in occ:
+                for m in occ:
+                    v = occ_intermediate(inp, T, m, j, s)
+                    if v != 0.0:
+                        Focc[(m, j, s)] = v
     for p in (range(len(inp.pairs)) if pairs is None else pairs):
         Bp = inp.B(p) if "ladder" in terms else None
         for name in inp.blocks(p):
@@ -483,6 +569,8 @@ def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladd
                     r += w * (Spq @ src[3] @ Spq.T)
             if "ring" in terms and getattr(inp, "ring", None) is not None:
                 r += ring_block(inp, T, p, name)
+            if Focc is not None:
+                r += occ_quadratic_block(inp, T, p, name, Focc)
             if inp.n_sv is not None:
                 s1, s2 = SPIN[name]
                 r = r * (inp.vmask(s1, p)[:, None] & inp.vmask(s2, p)[None, :])

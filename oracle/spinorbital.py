@@ -12,6 +12,7 @@ terms of the model are formed from explicit antisymmetrised integrals:
             + 1/2 sum_KL <KL||IJ> t_KL^AB
            [+ 1/4 sum_KLCD <KL||CD> t_IJ^CD t_KL^AB]
            [+ P(IJ) P(AB) sum_KC <KB||CJ> t_IK^AC]
+           [- P(IJ) sum_M t_IM^AB F_MJ,  F_MJ = 1/2 sum_NEF t_JN^EF <MN||EF>]
   E       = 1/4 sum_IJAB <IJ||AB> t_IJ^AB
 
 with (ac|bd) = sum_Q B^Q_ac B^Q_bd, (ia|jb) given per ordered pair and the
@@ -32,7 +33,7 @@ def _spin_orbitals(n_occ, is_somo, V, n_sv=0):
 
 
 def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblocks, pairs, g_occ=None, n_sv=0,
-                         quadratic=False, g_ovvo=None, g_oovv=None):
+                         quadratic=False, g_ovvo=None, g_oovv=None, quadratic_occ=False):
     """Pair blocks of the residual and the total energy of the given amplitudes.
 
     Bg       (m, V, V) three-index integrals shared by all pairs
@@ -44,6 +45,7 @@ def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblo
     quadratic  add 1/4 sum_KLCD <KL||CD> t_IJ^CD t_KL^AB
     g_ovvo, g_oovv  optional (n_occ, V, V, n_occ) and (n_occ, n_occ, V, V) arrays
              of the ring term (both or neither)
+    quadratic_occ  add -P(IJ) sum_M t_IM^AB F_MJ, F_MJ = 1/2 sum_NEF t_JN^EF <MN||EF>
     Returns ({((i, j), name): V x V residual block, zero outside the blocks'
     virtual spaces}, energy of the amplitudes).
     """
@@ -122,6 +124,11 @@ def residual_spinorbital(n_occ, is_somo, Bg, Kpair, eps_a, eps_b, f_a, f_b, Tblo
     if quadratic:
         # <KL||CD> = <CD||KL> (real orbitals) = g_vvoo[C, D, K, L]
         R = R + 0.25 * np.einsum("cdkl,ijcd,klab->ijab", g_vvoo, t, t)
+    if quadratic_occ:
+        # <MN||EF> = <EF||MN> (real orbitals) = g_vvoo[E, F, M, N]
+        Fmj = 0.5 * np.einsum("jnef,efmn->mj", t, g_vvoo)
+        X = np.einsum("imab,mj->ijab", t, Fmj)
+        R = R - (X - X.transpose(1, 0, 2, 3))
     if g_ovvo is not None:
         # <KB||CJ> = <KB|CJ> - <KB|JC> = (KC|BJ) - (KJ|BC), each charge
         # distribution of one spin

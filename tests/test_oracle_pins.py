@@ -577,3 +577,51 @@ def test_ring_term_is_linear_and_separate():
         d1, d2 = Rf[k] - Rb[k], Rf2[k] - Rb2[k]
         np.testing.assert_allclose(d2, 2.0 * d1, rtol=1e-12, atol=1e-15)
     assert max(np.abs(Rf[k] - Rb[k]).max() for k in Rf) > 1e-4
+
+
+# --------------- quadratic part of the occupied Fock intermediate F_MJ
+@pytest.mark.parametrize("somos,n_sv", [((), 0), ((1,), 0), ((1, 3), 0), ((1, 3), 2)])
+def test_occupied_intermediate_canonical_limit_matches_bruteforce(somos, n_sv):
+    # -P(IJ) sum_M t_IM^AB F_MJ with F_MJ = 1/2 sum_NEF t_JN^EF <MN||EF> from
+    # explicit antisymmetrised integrals, against the pair form: the occupied
+    # Fock weights f_kj dressed by F^s_kj, the pair itself included (m = i, j)
+    rng = np.random.default_rng(81 + len(somos) + 10 * n_sv)
+    inp = make_inputs(rng, n_occ=5, somos=somos, npno=4 + n_sv, naux=6, shared_space=True)
+    if n_sv:
+        inp.n_sv = [n_sv] * len(inp.pairs)
+    inp.quadratic_occ = True
+    T = random_T(rng, inp, scale=0.2)
+    if n_sv:
+        T = _mask_T(inp, T)
+    R = oracle.residual_os(inp, T)
+    Tb = {(inp.pairs[p], name): v for (p, name), v in T.items()}
+    Kp = {inp.pairs[p]: inp.K[p] for p in range(len(inp.pairs))}
+    args = (inp.n_occ, inp.is_somo, inp.B(0), Kp, inp.eps_a[0], inp.eps_b[0], inp.f_a, inp.f_b, Tb, inp.pairs)
+    Rbf, _ = oracle.residual_spinorbital(*args, n_sv=n_sv, quadratic_occ=True)
+    Rlin, _ = oracle.residual_spinorbital(*args, n_sv=n_sv)
+    big = 0.0
+    for (p, name), r in R.items():
+        np.testing.assert_allclose(r, Rbf[(inp.pairs[p], name)], rtol=0, atol=1e-13)
+        big = max(big, np.abs(Rbf[(inp.pairs[p], name)] - Rlin[(inp.pairs[p], name)]).max())
+    assert big > 1e-4
+
+
+def test_occupied_intermediate_is_quadratic_and_uses_the_diagonal():
+    # the term scales as T^2; F^s_jj (m = j) contributes
+    rng = np.random.default_rng(83)
+    inp = make_inputs(rng, n_occ=6, somos=(2,), npno=[6] * 21, naux=5)
+    T = random_T(rng, inp, scale=0.1)
+    lin = ("driver", "fock", "projection", "ladder")
+
+    def quad(x):
+        Tx = {k: x * v for k, v in T.items()}
+        inp.quadratic_occ = True
+        Rq = oracle.residual_os(inp, Tx)
+        inp.quadratic_occ = False
+        Rl = oracle.residual_os(inp, Tx, terms=lin)
+        return {k: Rq[k] - Rl[k] for k in Rq}
+    d1, d2 = quad(1.0), quad(2.0)
+    for k in d1:
+        np.testing.assert_allclose(d2[k], 4.0 * d1[k], rtol=1e-9, atol=1e-13)
+    assert max(np.abs(v).max() for v in d1.values()) > 1e-6
+    assert abs(oracle.occ_intermediate(inp, T, 0, 0, 0)) > 0.0

@@ -140,6 +140,8 @@ class Problem:
     n_sv: np.ndarray = None
     # the quadratic CCSD term over the hole-hole couplings (needs hole_ladder)
     quadratic: bool = False
+    # the quadratic part of the occupied Fock intermediate on the Fock couplings
+    quadratic_occ: bool = False
     # ring/exchange-term couplings (CSR by target pair; empty when the term is
     # off): role (0: the target's i is shared, 1: its j), replacing occupied m,
     # source pair {x, m}, overlap block, and the integral blocks X = (m e|b y),
@@ -352,6 +354,9 @@ def build_problem(name="tiny", **override):
     retained (the pair itself included: its overlap block is the identity);
     quadratic=True (with hole_ladder): the quadratic CCSD term over the
     hole-hole couplings is part of the residual (Problem.quadratic);
+    quadratic_occ=True: the quadratic part of the occupied Fock intermediate,
+    over the occupied-Fock couplings, is part of the residual
+    (Problem.quadratic_occ; no further inputs);
     ring=c, ring_range=d: the ring/exchange term, with one coupling per target
     pair (i, j), role (x = i, y = j or, for i < j, x = j, y = i) and occupied
     m with |m - x| <= d whose pair {x, m} is retained (the pair itself
@@ -655,4 +660,5 @@ def build_problem(name="tiny", **override):
                    n_sv=n_sv, quadratic=bool(cfg.get("quadratic", False)) and hh_scale != 0.0,
                    ring_rowptr=ring_rowptr, ring_src=ring_src, ring_role=ring_role, ring_m=ring_m,
                    ring_off_S=ring_off_S, ring_off_X=r_off[0::2].copy(), ring_off_J=r_off[1::2].copy(),
-                   n_Rg=n_Rg, ring_scale=ring_scale, ring_range=ring_range)
+                   n_Rg=n_Rg, ring_scale=ring_scale, ring_range=ring_range,
+                   quadratic_occ=bool(cfg.get("quadratic_occ", False)))
