@@ -216,6 +216,20 @@ typedef struct {
  * such plans. */
 #define DLPNO_FLAG_QUADRATIC 2
 
+/* Adds the quadratic part of the occupied Fock intermediate of CCSD,
+ * -P(IJ) sum_M t_IM^AB F_MJ with F_MJ = 1/2 sum_NEF t_JN^EF <MN||EF> (FP64
+ * plans only).  Reduced to spin blocks, F^s_mj = sum over occupied n and its
+ * spin of <G_(m,n), T^{s s_n}_(j,n)> with G[e][f] = (m e | n f) over the PNOs
+ * of {j, n}, taken as the projection S K_(m,n) S^T of the exchange integrals
+ * of {m, n} (transposed for m > n) through the listed occupied-Fock coupling
+ * of {j, n} in which m replaces j, and K_(j,n) itself for m = j; the term
+ * then dresses the occupied Fock weight of every listed projection term,
+ * f^s_kj -> f^s_kj + F^s_kj, and adds -(F^s_ii + F^s'_jj) T to each block.
+ * Sums run over the listed couplings only.  The factors S K S^T are built once
+ * by dlpno_plan_create; every residual evaluation forms F from T first (phase
+ * 9 of dlpno_phase_times).  The vector-Jacobian product refuses such plans. */
+#define DLPNO_FLAG_QUADRATIC_OCC 4
+
 typedef struct dlpno_plan dlpno_plan;   /* opaque, owned by the library */
 
 /* Validates the descriptors (ranges, offsets against the buffer sizes, the
@@ -379,8 +393,9 @@ dlpno_status dlpno_autotune_cached(dlpno_plan* plan, const double* T, double* R,
  *   waves per SIMD (FP64 plans: pairs of at most 48 PNOs), 7 cooperative
  *   ladder launch (FP64 plans: pairs of 49 to 64 PNOs, one workgroup per
  *   item), 8 projection items run at two waves per SIMD (FP64 plans: target
- *   and source pairs of at most 48 PNOs), 9 weights of the quadratic term
- *   (DLPNO_FLAG_QUADRATIC), 10 ring/exchange term (n_ring > 0). */
+ *   and source pairs of at most 48 PNOs), 9 weights of the quadratic terms
+ *   (DLPNO_FLAG_QUADRATIC, DLPNO_FLAG_QUADRATIC_OCC), 10 ring/exchange term
+ *   (n_ring > 0). */
 dlpno_status dlpno_set_profiling(dlpno_plan* plan, int32_t enable);
 /* Useful FP64 flops of the ring/exchange term per residual evaluation
  * (2 n_p n_q (n_q + n_p) per contraction S_{p,q} op(T_q) X) and the number

@@ -99,11 +99,11 @@ class Inputs:
     def S(self, p, q):
         return self._S(p, q) if callable(self._S) else self._S[(p, q)]
 
-    def has_S(self, p, q):
-        """Whether the problem lists an overlap block of target p and source q
-        (always, for overlaps given as a function)."""
-        if getattr(self, "_listed", None) is not None:
-            return (p, q) in self._listed
+    def fock_listed(self, p, q):
+        """Whether the problem lists an occupied-Fock coupling of target p and
+        source q (always, for overlaps given as a function)."""
+        if getattr(self, "_fock_listed", None) is not None:
+            return (p, q) in self._fock_listed
         return callable(self._S) or (p, q) in self._S
 
     def npno(self, p):
@@ -190,7 +190,8 @@ class Inputs:
         n_sv = getattr(prob, "n_sv", None)
         ring = _WorkloadRing(prob) if getattr(prob, "n_ring", 0) > 0 else None
         inp = cls(prob.n_occ, prob.is_somo, pairs, Bf, Kd, ea, eb, prob.f_a, prob.f_b, Sf, occ, n_sv, ring)
-        inp._listed = set(where)
+        inp._fock_listed = {(p, int(prob.cpl_src[e])) for p in range(P)
+                            for e in range(prob.cpl_rowptr[p], prob.cpl_rowptr[p + 1])}
         inp.quadratic = bool(getattr(prob, "quadratic", False))
         inp.quadratic_occ = bool(getattr(prob, "quadratic_occ", False))
         return inp
@@ -392,8 +393,9 @@ def occ_intermediate(inp, T, m, j, s):
     over the PNOs of pair {j, n}.  Reading (as in quadratic_weight): those
     integrals are the projection S_{jn,mn} K_(m,n) S_{mn,jn} of pair {m, n}'s
     exchange integrals (K of {m, n}, transposed for m > n); for m = j they
-    are K_(j,n) itself.  Terms whose pairs are not retained, or whose overlap
-    block the problem does not list (a coupling outside its lists), vanish."""
+    are K_(j,n) itself.  Terms whose pairs are not retained, or whose pairs
+    the problem does not couple by an occupied-Fock coupling (local
+    truncation), vanish."""
     total = 0.0
     for n in range(inp.n_occ):
         r = inp.index.get((min(m, n), max(m, n)))
@@ -410,7 +412,7 @@ def occ_intermediate(inp, T, m, j, s):
             if q == r:
                 G = Kmn
             else:
-                if not inp.has_S(q, r):        # coupling not listed: local truncation
+                if not inp.fock_listed(q, r):  # coupling not listed: local truncation
                     continue
                 Sqr = inp.S(q, r)
                 G = Sqr @ Kmn @ Sqr.T
@@ -418,30 +420,41 @@ def occ_intermediate(inp, T, m, j, s):
     return total
 
 
+class OccIntermediate:
+    """F^s_{mj} of amplitudes T, computed when first asked for (occ_intermediate)."""
+
+    def __init__(self, inp, T):
+        self.inp, self.T, self.cache = inp, T, {}
+
+    def get(self, key):
+        if key not in self.cache:
+            m, j, s = key
+            self.cache[key] = occ_intermediate(self.inp, self.T, m, j, s)
+        return self.cache[key]
+
+
 def occ_quadratic_block(inp, T, p, name, F):
-    """-P(IJ) sum_M t_IM^AB F_MJ for block `name` of pair p = (i, j), F a dict
-    (m, j, s) -> F^s_{mj}.  t_JM^AB = -t_MJ^AB turns the exchanged half into
+    """-P(IJ) sum_M t_IM^AB F_MJ for block `name` of pair p = (i, j), F an
+    OccIntermediate (get((m, j, s)) -> F^s_{mj}).  t_JM^AB = -t_MJ^AB turns the exchanged half into
     the same form as the first, like the occupied-Fock projections:
       - sum_{m in occ_s} F^s_{mi} S T^{ss'}_{(m,j)} S^T
       - sum_{m in occ_s'} F^{s'}_{mj} S T^{ss'}_{(i,m)} S^T,
     m = i and m = j included (the pair itself, identity overlap); sources
-    whose overlap block the problem does not list are left out."""
+    without a listed occupied-Fock coupling to p are left out."""
     i, j = inp.pairs[p]
     s1, s2 = SPIN[name]
     out = np.zeros_like(T[(p, name)])
     for side, (s, rep_, keep) in enumerate(((s1, i, j), (s2, j, i))):
         for m in inp.occ(s):
-            f = F.get((m, rep_, s), 0.0)
-            if f == 0.0:
-                continue
             src = t_lookup(inp, T, m, j, s1, s2) if side == 0 else t_lookup(inp, T, i, m, s1, s2)
             if src is None:
                 continue
+            if src[0] != p and not inp.fock_listed(p, src[0]):
+                continue
+            f = F.get((m, rep_, s))
             if src[0] == p:
                 out -= f * src[3]
             else:
-                if not inp.has_S(p, src[0]):
-                    continue
                 Spq = inp.S(p, src[0])
                 out -= f * (Spq @ src[3] @ Spq.T)
     return out
@@ -541,14 +554,7 @@ def residual_os(inp, T, pairs=None, terms=("driver", "fock", "projection", "ladd
     R = {}
     Focc = None
     if "quadratic_occ" in terms and getattr(inp, "quadratic_occ", False):
-        Focc = {}
-        for s in (0, 1):
-            occ = inp.occ(s)
-            for j in occ:
-                for m in occ:
-                    v = occ_intermediate(inp, T, m, j, s)
-                    if v != 0.0:
-                        Focc[(m, j, s)] = v
+        Focc = OccIntermediate(inp, T)
     for p in (range(len(inp.pairs)) if pairs is None else pairs):
         Bp = inp.B(p) if "ladder" in terms else None
         for name in inp.blocks(p):

@@ -181,6 +181,10 @@ static dlpno_status check_vjp_preconditions(dlpno_plan* P, hipStream_t s) {
     P->vjp_reason = "vector-Jacobian product: not available with the quadratic term";
     return fail(DLPNO_ERR_UNSUPPORTED, P->vjp_reason);
   }
+  if (P->qocc) {
+    P->vjp_reason = "vector-Jacobian product: not available with the occupied-intermediate quadratic term";
+    return fail(DLPNO_ERR_UNSUPPORTED, P->vjp_reason);
+  }
   if (P->n_ring > 0) {
     P->vjp_reason = "vector-Jacobian product: not available with the ring/exchange term";
     return fail(DLPNO_ERR_UNSUPPORTED, P->vjp_reason);

@@ -81,6 +81,7 @@ __global__ __launch_bounds__(kEwThreads) void finish_kernel(FinishArgs a) {
     }
     double r = (a.drv ? a.drv[bk.off_T + idx] : kk) + D * t;
     r += part[y * n + x];
+    if (a.shift) r -= a.shift[blk] * t;           // diagonal part of the occupied intermediate
     if (x >= bk.rows || y >= bk.cols) r = 0.0;   // alpha index on a SOMO function
     if (!isfinite(r)) bad = true;
     rmax = fmax(rmax, fabs(r));

@@ -55,6 +55,23 @@ struct QuadCpl {
   double w0[4], c[4];
 };
 
+// Quadratic part of the occupied Fock intermediate (quadratic.hip): one
+// contribution <G, T_(j,n)> to F^s_{mj} for each spin s, over the blocks of
+// the dotted pair {j, n} with the ordered spins (s, s_n), s_n either spin.
+struct OccCtb {
+  int64_t off_G;          // G (n x n): in the plan's factor table, or the dotted pair's K (from_K)
+  int32_t n, from_K;
+  int32_t key[2];         // index of F^s_{mj} for s = 0, 1 (-1: none)
+  int64_t off_T[2][2];    // per spin, up to two amplitude blocks (-1: none)
+  int32_t tr[2][2];       // 1: the block enters transposed, <G^T, T>
+};
+// A projection term whose weight the intermediate dresses: w = w0 + F[key].
+struct OccTerm {
+  int64_t term;           // index into the term table
+  int32_t key, pad;
+  double w0;              // the occupied Fock element
+};
+
 // One contraction of the ring/exchange term (ring.hip):  Out += w L^T op(T_q) M
 // with L and M n_q x n_p row-major blocks ([c][a]) read from the overlap
 // buffer S or the ring integral buffer, op(T_q) = T_q or T_q^T.
@@ -193,6 +210,27 @@ hipError_t launch_quad_prepare(const QuadCpl* list, int64_t n, const double* S, 
                                hipStream_t s);
 hipError_t launch_quad_weights(const QuadCpl* list, int64_t n, const double* G, const double* T, TermDev* terms,
                                hipStream_t s);
+// F^s_{mj} from T (dots per contribution, then per key in CSR order), the
+// dressed weights of the listed terms and the per-block diagonal shift
+// F^{s1}_ii + F^{s2}_jj
+struct OccArgs {
+  const OccCtb* ctb;
+  int64_t n_ctb;
+  const double* G;
+  const double* K;
+  double* dots;             // [2 n_ctb]
+  const int64_t* key_rowptr; // [n_keys + 1] into key_src
+  const int64_t* key_src;   // entries of dots, in a fixed order
+  int64_t n_keys;
+  double* F;                // [n_keys]
+  const OccTerm* oterms;
+  int64_t n_oterms;
+  TermDev* terms;
+  const int32_t* blk_key;   // [2 n_blocks]: keys of F^{s1}_ii and F^{s2}_jj (-1: none)
+  int32_t n_blocks;
+  double* shift;            // [n_blocks]
+};
+hipError_t launch_occ_weights(const OccArgs& a, const double* T, hipStream_t s);
 // ring.hip: every unit's ring contractions into its block's last partial slot
 hipError_t launch_ring(const RxUnit* units, int64_t n_units, const RxTerm* terms, const BlockDev* blocks,
                        const double* T, const double* S, const double* ring_ints, double* ws, hipStream_t s);
@@ -231,6 +269,7 @@ struct FinishArgs {
   double* ring_vecs;
   double* ring_errs;
   int64_t ring_stride;
+  const double* shift;     // when set: R -= shift[block] * T (diagonal part of the occupied intermediate)
 };
 hipError_t launch_finish(const FinishArgs& a, hipStream_t s);
 // flag |= 1 when some element of x[0..n) is not zero (NaN included); the caller zeroes flag

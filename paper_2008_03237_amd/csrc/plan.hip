@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <string>
 #include <unordered_map>
 #include <utility>
@@ -438,6 +439,13 @@ std::string dlpno::describe(const dlpno_plan* P) {
     buf[0] = 0;
   }
   s += buf;
+  if (P->qocc) {
+    snprintf(buf, sizeof buf,
+             "occupied-intermediate quadratic term: %zu contributions, %zu dressed terms, factors %.3f GB (%.4e flops, "
+             "once), %.4e flops per residual\n",
+             P->occ_ctb_h.size(), P->occ_terms_h.size(), P->n_occG * 8e-9, P->flops_occ_prep, P->flops_occ);
+    s += buf;
+  }
   if (P->n_ring > 0) {
     snprintf(buf, sizeof buf, "ring/exchange term: %lld couplings, %zu contractions over %zu blocks, %.4e flops\n",
              (long long)P->n_ring, P->rx_terms_h.size(), P->rx_units_h.size(), P->flops_rx);
@@ -471,8 +479,11 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if (opt.precision < DLPNO_FP64 || opt.precision > DLPNO_FP16X2)
     return fail(DLPNO_ERR_INVALID_ARG, "unknown precision");
   if (opt.diis_max < 0 || opt.diis_max > 8) return fail(DLPNO_ERR_INVALID_ARG, "diis_max must be in 0..8");
-  if ((opt.flags & ~(DLPNO_FLAG_GENERAL_T | DLPNO_FLAG_QUADRATIC)) != 0)
+  if ((opt.flags & ~(DLPNO_FLAG_GENERAL_T | DLPNO_FLAG_QUADRATIC | DLPNO_FLAG_QUADRATIC_OCC)) != 0)
     return fail(DLPNO_ERR_INVALID_ARG, "unknown option flag");
+  const bool qocc = (opt.flags & DLPNO_FLAG_QUADRATIC_OCC) != 0;
+  if (qocc && opt.precision != DLPNO_FP64)
+    return fail(DLPNO_ERR_UNSUPPORTED, "the occupied-intermediate quadratic term needs an FP64 plan");
   const bool quad = (opt.flags & DLPNO_FLAG_QUADRATIC) != 0;
   if (quad && prob->n_hh <= 0) return fail(DLPNO_ERR_INVALID_ARG, "the quadratic term needs hole-hole couplings");
   if (prob->n_ring > 0 && opt.precision != DLPNO_FP64)
@@ -645,7 +656,8 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
         scode = block_code(s2, s1);
         trans = 1;
       }
-      if (!(q.blocks & kCodeBit[scode]) || (w == 0.0 && !(quad && is_hh))) return;
+      // zero weights are kept where a T-dependent part is added to them
+      if (!(q.blocks & kCodeBit[scode]) || (w == 0.0 && !(quad && is_hh) && !(qocc && !is_hh))) return;
       int sslot = 0;
       for (int cc = 0; cc < scode; ++cc)
         if (q.blocks & kCodeBit[cc]) ++sslot;
@@ -781,6 +793,134 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
           P->flops_quad_prep += 2.0 * pd.n * (double)qc.nq * (pd.n + qc.nq);
         }
       }
+    }
+  }
+  // ---- quadratic part of the occupied Fock intermediate ----
+  // F^s_mj = sum_{n, s_n} <G_(m,n), T^{s s_n}_(j,n)>, G[e][f] = (m e|n f) over
+  // the PNOs of the dotted pair {j, n}: S K_(m,n) S^T through a listed Fock
+  // coupling of {j, n} with m replacing j, or K_(j,n) itself for m = j.  It
+  // dresses the Fock weights f^s_kj of the listed projection terms and adds
+  // -(F^s1_ii + F^s2_jj) T per block.
+  P->qocc = qocc;
+  std::vector<QuadCpl> occ_prep;   // factors S K S^T built once (the prepare kernel of the quadratic term)
+  if (qocc) {
+    std::map<std::tuple<int, int, int>, int32_t> keyid;
+    auto key_add = [&](int m, int j, int sp) -> int32_t {
+      const auto key = std::make_tuple(m, j, sp);
+      auto it = keyid.find(key);
+      if (it != keyid.end()) return it->second;
+      const int32_t id = (int32_t)keyid.size();
+      keyid.emplace(key, id);
+      return id;
+    };
+    auto key_find = [&](int m, int j, int sp) -> int32_t {
+      auto it = keyid.find(std::make_tuple(m, j, sp));
+      return it == keyid.end() ? -1 : it->second;
+    };
+    P->occ_blk_key_h.assign(2 * (size_t)nblk_total, -1);
+    for (int p = 0; p < npairs; ++p) {
+      const dlpno_pair& d = prob->pairs[p];
+      const PairDev& pd = P->pairs_h[p];
+      for (int64_t e = P->rowptr_h[p]; e < P->rowptr_h[p + 1]; ++e) {
+        const int side = P->cpl_side_h[e];
+        if (side == 2) continue;                           // hole-hole couplings are not dressed
+        const int k = P->cpl_k_h[e], rep = side == 0 ? d.i : d.j;
+        int slot = 0;
+        for (int code = 0; code < 4; ++code) {
+          if (!(d.blocks & kCodeBit[code])) continue;
+          const int this_slot = slot++;
+          const TermDev& tm = P->terms_h[(size_t)e * 4 + this_slot];
+          if (tm.src_off < 0) continue;
+          const int sp = side == 0 ? kCodeS1[code] : kCodeS2[code];
+          P->occ_terms_h.push_back(OccTerm{e * 4 + this_slot, key_add(k, rep, sp), 0, tm.w});
+        }
+      }
+      int slot = 0;
+      for (int code = 0; code < 4; ++code) {
+        if (!(d.blocks & kCodeBit[code])) continue;
+        const int b = pd.blk0 + slot++;
+        P->occ_blk_key_h[2 * (size_t)b] = key_add(d.i, d.i, kCodeS1[code]);
+        P->occ_blk_key_h[2 * (size_t)b + 1] = key_add(d.j, d.j, kCodeS2[code]);
+      }
+    }
+    std::vector<std::vector<int64_t>> per_key(keyid.size());
+    for (int q = 0; q < npairs; ++q) {
+      const dlpno_pair& d = prob->pairs[q];
+      const int64_t nq = d.npno, nn = nq * nq;
+      // one contribution: F^s_(m, j) += <G, T_(j,n)> (G from K of q when from_K)
+      auto add = [&](int m, int j, int n, int from_K, int64_t off_G, int trG, const QuadCpl* prep) {
+        OccCtb c{};
+        c.n = (int32_t)nq;
+        c.from_K = from_K;
+        c.off_G = off_G;
+        bool any = false;
+        for (int sp = 0; sp < 2; ++sp) {
+          c.key[sp] = key_find(m, j, sp);
+          int nb = 0;
+          c.off_T[sp][0] = c.off_T[sp][1] = -1;
+          c.tr[sp][0] = c.tr[sp][1] = 0;
+          if (c.key[sp] < 0) continue;
+          for (int sn = 0; sn < 2; ++sn) {
+            int code, trT;
+            if (d.i == d.j) {
+              if (sp == sn) continue;
+              code = 2;
+              trT = sp == 1;
+            } else if (j == d.i) {
+              code = block_code(sp, sn);
+              trT = 0;
+            } else {
+              code = block_code(sn, sp);
+              trT = 1;
+            }
+            if (!(d.blocks & kCodeBit[code])) continue;
+            int sslot = 0;
+            for (int cc = 0; cc < code; ++cc)
+              if (d.blocks & kCodeBit[cc]) ++sslot;
+            c.off_T[sp][nb] = d.off_T + (int64_t)sslot * nn;
+            c.tr[sp][nb] = trT ^ trG;
+            ++nb;
+            P->flops_occ += 2.0 * (double)nn;
+          }
+          if (nb > 0) any = true;
+        }
+        if (!any) return;
+        if (prep) {
+          QuadCpl qc = *prep;
+          qc.off_G = P->n_occG;
+          c.off_G = P->n_occG;
+          P->n_occG += nn;
+          occ_prep.push_back(qc);
+          P->flops_occ_prep += 2.0 * nq * (double)qc.nq * (nq + qc.nq);
+        }
+        const int64_t ci = (int64_t)P->occ_ctb_h.size();
+        for (int sp = 0; sp < 2; ++sp)
+          if (c.key[sp] >= 0 && c.off_T[sp][0] >= 0) per_key[c.key[sp]].push_back(2 * ci + sp);
+        P->occ_ctb_h.push_back(c);
+      };
+      // m = j: K of the pair itself, (j e|n f) = K_q (j = i) or K_q^T (j = j)
+      add(d.i, d.i, d.j, 1, d.off_K, 0, nullptr);
+      if (d.j != d.i) add(d.j, d.j, d.i, 1, d.off_K, 1, nullptr);
+      // m != j: the listed Fock couplings of q, m replacing j, n kept (a
+      // diagonal pair lists each source once per side: it is dotted once)
+      for (int64_t e = P->rowptr_h[q]; e < P->rowptr_h[q + 1]; ++e) {
+        const int side = P->cpl_side_h[e];
+        if (side == 2 || (side == 1 && d.i == d.j)) continue;
+        const int m = P->cpl_k_h[e], j = side == 0 ? d.i : d.j, n = side == 0 ? d.j : d.i;
+        const int r = P->cpl_h[e].src;
+        QuadCpl qc{};
+        qc.off_S = P->cpl_h[e].off_S;
+        qc.off_K = prob->pairs[r].off_K;
+        qc.np = (int32_t)nq;
+        qc.nq = P->cpl_h[e].nsrc;
+        qc.transK = m > n;
+        add(m, j, n, 0, 0, 0, &qc);
+      }
+    }
+    P->occ_key_rowptr_h.assign(per_key.size() + 1, 0);
+    for (size_t k = 0; k < per_key.size(); ++k) {
+      P->occ_key_rowptr_h[k + 1] = P->occ_key_rowptr_h[k] + (int64_t)per_key[k].size();
+      P->occ_key_src_h.insert(P->occ_key_src_h.end(), per_key[k].begin(), per_key[k].end());
     }
   }
   // ---- ring/exchange term ----
@@ -945,6 +1085,31 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
         hipStreamSynchronize(s) != hipSuccess)
       return destroy_fail(fail(DLPNO_ERR_HIP, "quadratic-term factors"));
   }
+  if (P->qocc) {
+    if ((st = upload(&P->d_occ_ctb, P->occ_ctb_h, "occupied-intermediate contributions", s)) != DLPNO_OK ||
+        (st = upload(&P->d_occ_terms, P->occ_terms_h, "occupied-intermediate terms", s)) != DLPNO_OK ||
+        (st = upload(&P->d_occ_blk_key, P->occ_blk_key_h, "occupied-intermediate block keys", s)) != DLPNO_OK ||
+        (st = upload(&P->d_occ_key_rowptr, P->occ_key_rowptr_h, "occupied-intermediate keys", s)) != DLPNO_OK ||
+        (st = upload(&P->d_occ_key_src, P->occ_key_src_h, "occupied-intermediate keys", s)) != DLPNO_OK ||
+        (st = dev_alloc(&P->d_occ_dots, std::max<size_t>(2 * P->occ_ctb_h.size(), 1), "occupied-intermediate dots")) !=
+            DLPNO_OK ||
+        (st = dev_alloc(&P->d_occF, std::max<size_t>(P->occ_key_rowptr_h.size(), 1), "occupied intermediate")) !=
+            DLPNO_OK ||
+        (st = dev_alloc(&P->d_occ_shift, std::max(nblk_total, 1), "occupied-intermediate shifts")) != DLPNO_OK ||
+        (st = dev_alloc(&P->d_occG, (size_t)std::max<int64_t>(P->n_occG, 1), "occupied-intermediate factors")) !=
+            DLPNO_OK)
+      return destroy_fail(st);
+    // the shift is read by every finish; until a residual has formed it, zero
+    HIPCK(launch_fill(P->d_occ_shift, 0.0, std::max(nblk_total, 1), s));
+    if (!occ_prep.empty()) {
+      QuadCpl* d_prep = nullptr;
+      if ((st = upload(&d_prep, occ_prep, "occupied-intermediate factor list", s)) != DLPNO_OK) return destroy_fail(st);
+      const hipError_t pe = launch_quad_prepare(d_prep, (int64_t)occ_prep.size(), P->in.S, P->in.K, P->d_occG, s);
+      const hipError_t se = hipStreamSynchronize(s);
+      (void)hipFree(d_prep);
+      if (pe != hipSuccess || se != hipSuccess) return destroy_fail(fail(DLPNO_ERR_HIP, "occupied-intermediate factors"));
+    }
+  }
   if (!P->rx_units_h.empty()) {
     if ((st = upload(&P->d_rx_terms, P->rx_terms_h, "ring term table", s)) != DLPNO_OK) return destroy_fail(st);
     if ((st = upload(&P->d_rx_units, P->rx_units_h, "ring unit table", s)) != DLPNO_OK) return destroy_fail(st);
@@ -1044,7 +1209,9 @@ extern "C" dlpno_status dlpno_plan_destroy(dlpno_plan* P) {
                   P->d_vjp_items, P->d_mixed, P->G32, P->d_pair_boff, P->d_blk_toff, P->d_cpl_soff,
                   P->d_cpl_target, P->d_pair_bscale, P->d_blk_tscale, P->Bs_hi, P->Bs_lo, P->Ss_hi, P->Ss_lo,
                   P->Tts_hi, P->Tts_lo, P->Ts_hi, P->Ts_lo, P->d_mix_r, P->d_mix_delta, P->d_hist_iter, P->d_quad,
-                  P->d_quadG, P->d_flagz, P->d_rx_terms, P->d_rx_units};
+                  P->d_quadG, P->d_flagz, P->d_rx_terms, P->d_rx_units, P->d_occ_ctb, P->d_occ_terms,
+                  P->d_occ_blk_key, P->d_occ_key_rowptr, P->d_occ_key_src, P->d_occG, P->d_occ_dots, P->d_occF,
+                  P->d_occ_shift};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete P;
@@ -1126,6 +1293,17 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
     phase_end(P, s);
     if (e != hipSuccess) return e;
   }
+  // the occupied intermediate from T: dressed Fock weights and the diagonal
+  // shift that the finishing kernel applies (FP64 plans only)
+  if (P->qocc) {
+    OccArgs oa{P->d_occ_ctb, (int64_t)P->occ_ctb_h.size(), P->d_occG, P->in.K, P->d_occ_dots, P->d_occ_key_rowptr,
+               P->d_occ_key_src, (int64_t)P->occ_key_rowptr_h.size() - 1, P->d_occF, P->d_occ_terms,
+               (int64_t)P->occ_terms_h.size(), P->d_terms, P->d_occ_blk_key, P->n_blocks, P->d_occ_shift};
+    phase_begin(P, 9, s);
+    e = launch_occ_weights(oa, T, s);
+    phase_end(P, s);
+    if (e != hipSuccess) return e;
+  }
   if (prec == DLPNO_FP32) {
     phase_begin(P, 4, s);
     if ((e = launch_convert_f32(T, P->T32, P->n_T, s)) != hipSuccess) return e;
@@ -1196,6 +1374,7 @@ FinishArgs finish_args(dlpno_plan* P, const double* T, const double* ws) {
   f.rmax_block = P->d_rmax_block;
   f.nonfinite = P->d_nonfinite;
   f.with_driver = 1;
+  f.shift = P->d_occ_shift;
   return f;
 }
 
@@ -1219,6 +1398,7 @@ hipError_t enqueue_iteration(dlpno_plan* P, double* T, double* R, double* e_pair
   if (!zero_T && (e = run_grouped(P, T, s, prec, false, nullptr, drv == nullptr)) != hipSuccess) return e;
   FinishArgs f = finish_args(P, T);
   f.no_partials = zero_T ? 1 : 0;
+  if (zero_T) f.shift = nullptr;     // T = 0: the diagonal part vanishes with the rest
   f.R = R;
   f.drv = drv;
   if (diis) {

@@ -61,6 +61,23 @@ struct dlpno_plan {
   int64_t n_quadG = 0;
   double flops_quad = 0.0;               // the weights' dot products per residual
   double flops_quad_prep = 0.0;          // building the factors S K S^T (once)
+  // quadratic part of the occupied Fock intermediate (DLPNO_FLAG_QUADRATIC_OCC)
+  bool qocc = false;
+  std::vector<dlpno::OccCtb> occ_ctb_h;
+  std::vector<dlpno::OccTerm> occ_terms_h;
+  std::vector<int32_t> occ_blk_key_h;
+  std::vector<int64_t> occ_key_rowptr_h, occ_key_src_h;
+  int64_t n_occG = 0;
+  dlpno::OccCtb* d_occ_ctb = nullptr;
+  dlpno::OccTerm* d_occ_terms = nullptr;
+  int32_t* d_occ_blk_key = nullptr;
+  int64_t* d_occ_key_rowptr = nullptr;
+  int64_t* d_occ_key_src = nullptr;
+  double* d_occG = nullptr;
+  double* d_occ_dots = nullptr;
+  double* d_occF = nullptr;
+  double* d_occ_shift = nullptr;
+  double flops_occ = 0.0, flops_occ_prep = 0.0;
   // ring/exchange term: contractions per target block (units), last partial slot
   std::vector<dlpno::RxTerm> rx_terms_h;
   std::vector<dlpno::RxUnit> rx_units_h;

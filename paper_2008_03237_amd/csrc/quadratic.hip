@@ -17,7 +17,20 @@
 // only forms <G, T_p> for the coupling's target blocks (one wave per coupling,
 // reduced in a fixed order), writing the new weight into the term table that
 // the projection launches of the same residual then read.
+//
+// The quadratic part of the occupied Fock intermediate, F_MJ = 1/2 sum_NEF
+// t_JN^EF <MN||EF>, enters the doubles residual as -P(IJ) sum_M t_IM^AB F_MJ:
+// the occupied-Fock projection weights f^s_kj become f^s_kj + F^s_kj and the
+// pair itself adds -(F^s_ii + F^s'_jj) T.  Per spin, F^s_mj = sum over n and
+// its spin of <G_(m,n), T^{s s_n}_(j,n)>, G[e][f] = (m e | n f) over the PNOs
+// of {j, n}, taken as S K_(m,n) S^T of the source pair {m, n} (built once,
+// like the factors above; K_(j,n) itself for m = j).  Per residual: one wave
+// per contribution forms its dots, one thread per F adds its contributions in
+// a fixed order, one thread per term or block writes the dressed weight or
+// the diagonal shift that the finishing kernel applies.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "internal.h"
 
@@ -100,7 +113,85 @@ __global__ __launch_bounds__(256) void quad_weights_kernel(const QuadCpl* __rest
   }
 }
 
+// one wave per contribution: <G, T_b> (or <G^T, T_b>) summed over its blocks
+// per spin, in a fixed order
+__global__ __launch_bounds__(256) void occ_dots_kernel(const OccCtb* __restrict__ list, int64_t n,
+                                                       const double* __restrict__ G, const double* __restrict__ K,
+                                                       const double* __restrict__ T, double* __restrict__ dots) {
+  const int lane = threadIdx.x & 63;
+  const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+  for (int64_t e = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); e < n; e += waves) {
+    const OccCtb c = list[e];
+    const double* Gp = (c.from_K ? K : G) + c.off_G;
+    const int nd = c.n, nn = c.n * c.n;
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    for (int x = lane; x < nn; x += 64) {
+      const double gv = Gp[x];
+      const int xr = x / nd, xc = x - xr * nd, xt = xc * nd + xr;
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          if (c.off_T[sp][b] >= 0) acc[sp][b] += gv * T[c.off_T[sp][b] + (c.tr[sp][b] ? xt : x)];
+    }
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        for (int o = 32; o > 0; o >>= 1) acc[sp][b] += __shfl_xor(acc[sp][b], o);
+    if (lane == 0) {
+      dots[2 * e] = acc[0][0] + acc[0][1];
+      dots[2 * e + 1] = acc[1][0] + acc[1][1];
+    }
+  }
+}
+
+// F per key: its contributions added in CSR order
+__global__ __launch_bounds__(256) void occ_f_kernel(const int64_t* __restrict__ rowptr,
+                                                    const int64_t* __restrict__ src, int64_t n_keys,
+                                                    const double* __restrict__ dots, double* __restrict__ F) {
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n_keys; k += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int64_t x = rowptr[k]; x < rowptr[k + 1]; ++x) v += dots[src[x]];
+    F[k] = v;
+  }
+}
+
+// dressed weights of the listed projection terms, and the per-block shift
+__global__ __launch_bounds__(256) void occ_apply_kernel(const OccTerm* __restrict__ ot, int64_t n_ot,
+                                                        const double* __restrict__ F, TermDev* __restrict__ terms,
+                                                        const int32_t* __restrict__ blk_key, int32_t n_blocks,
+                                                        double* __restrict__ shift) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n_ot; t += stride)
+    terms[ot[t].term].w = ot[t].w0 + F[ot[t].key];
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < n_blocks; b += stride) {
+    const int32_t ki = blk_key[2 * b], kj = blk_key[2 * b + 1];
+    shift[b] = (ki >= 0 ? F[ki] : 0.0) + (kj >= 0 ? F[kj] : 0.0);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_occ_weights(const OccArgs& a, const double* T, hipStream_t s) {
+  if (a.n_ctb > 0) {
+    const int64_t blocks = (a.n_ctb + 3) / 4;
+    const int64_t grid = blocks < (1 << 20) ? blocks : (1 << 20);
+    hipLaunchKernelGGL(occ_dots_kernel, dim3((unsigned)grid), dim3(256), 0, s, a.ctb, a.n_ctb, a.G, a.K, T, a.dots);
+  }
+  if (a.n_keys > 0) {
+    const int64_t grid = std::min<int64_t>((a.n_keys + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(occ_f_kernel, dim3((unsigned)grid), dim3(256), 0, s, a.key_rowptr, a.key_src, a.n_keys,
+                       a.dots, a.F);
+  }
+  const int64_t m = std::max<int64_t>(a.n_oterms, a.n_blocks);
+  if (m > 0) {
+    const int64_t grid = std::min<int64_t>((m + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(occ_apply_kernel, dim3((unsigned)grid), dim3(256), 0, s, a.oterms, a.n_oterms, a.F, a.terms,
+                       a.blk_key, a.n_blocks, a.shift);
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_quad_prepare(const QuadCpl* list, int64_t n, const double* S, const double* K, double* G,
                                hipStream_t s) {

@@ -10,6 +10,7 @@ FP64, FP32, BF16X2, FP16X2 = 0, 1, 2, 3
 _PREC = {"fp64": FP64, "fp32": FP32, "bf16x2": BF16X2, "fp16x2": FP16X2}
 FLAG_GENERAL_T = 1     # same-spin amplitude blocks need not be antisymmetric
 FLAG_QUADRATIC = 2     # quadratic CCSD term over the hole-hole couplings
+FLAG_QUADRATIC_OCC = 4  # quadratic part of the occupied Fock intermediate
 
 
 class DlpnoError(RuntimeError):
@@ -151,7 +152,7 @@ class Plan:
     """
 
     def __init__(self, desc, B, S, K, eps_a, eps_b, precision="fp64", diis_max=8, diis_start=3, n_workers=0,
-                 items_per_wave=0, general_T=False, quadratic=False, ring_ints=None):
+                 items_per_wave=0, general_T=False, quadratic=False, ring_ints=None, quadratic_occ=False):
         import torch
         L = lib()
         P = len(desc.pi)
@@ -200,7 +201,8 @@ class Plan:
         inp = Inputs(B.data_ptr(), S.data_ptr() if S is not None else None, K.data_ptr(), eps_a.data_ptr(),
                      eps_b.data_ptr(), ring_ints.data_ptr() if ring_ints is not None else None)
         prec = _PREC[precision] if isinstance(precision, str) else int(precision)
-        flags = (FLAG_GENERAL_T if general_T else 0) | (FLAG_QUADRATIC if quadratic else 0)
+        flags = ((FLAG_GENERAL_T if general_T else 0) | (FLAG_QUADRATIC if quadratic else 0)
+                 | (FLAG_QUADRATIC_OCC if quadratic_occ else 0))
         opt = Options(prec, diis_max, diis_start, n_workers, int(items_per_wave), flags)
         self.precision = prec
         self.n_T, self.n_B, self.n_pairs = int(desc.n_T), int(desc.n_B), P
