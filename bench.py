@@ -119,6 +119,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-path leg")
     ap.add_argument("--no-hole", action="store_true", help="skip the hole-hole ladder leg")
     ap.add_argument("--no-ring", action="store_true", help="skip the ring/exchange-term leg")
+    ap.add_argument("--no-occ", action="store_true",
+                    help="skip the leg with the quadratic part of the occupied Fock intermediate")
     ap.add_argument("--ring-scale", type=float, default=0.05,
                     help="scale of the synthetic integral blocks of the ring/exchange-term leg")
     ap.add_argument("--no-pno", action="store_true", help="skip the PNO-construction leg")
@@ -283,6 +285,8 @@ def main():
         out["hole_ladder"] = hole_leg(args, dev, eps_a, eps_b, fl_proj, log)
     if not args.no_ring and args.precision == "fp64":
         out["ring"] = ring_leg(args, dev, eps_a, eps_b, log)
+    if not args.no_occ and args.precision == "fp64":
+        out["quadratic_occ"] = occ_leg(args, prob, dev, eps_a, eps_b, log)
     if not args.no_pno:
         out["pno"] = pno_leg(args, log)
     plan.close()
@@ -607,6 +611,51 @@ def ring_leg(args, dev, eps_a, eps_b, log):
     log("ring/exchange leg: %s" % row)
     plan.close()
     del f, T
+    torch.cuda.empty_cache()
+    return row
+
+
+def occ_leg(args, prob, dev, eps_a, eps_b, log):
+    """The same workload with the quadratic part of the occupied Fock
+    intermediate (DLPNO_FLAG_QUADRATIC_OCC): per residual F^s_mj is formed from
+    T over every occupied-Fock coupling (factors S K S^T built once) and
+    dresses the projection weights.  FP64 iterations from T = 0, timed like the
+    main leg; the kernels forming F against HBM (they read the factors and the
+    dotted amplitude blocks once)."""
+    import torch
+
+    from paper_2008_03237_amd import Plan
+    from workload import build_problem
+    pq = build_problem(args.workload, quadratic_occ=True)
+    t0 = time.perf_counter()
+    plan = Plan(pq, dev["B"], dev["S"], dev["K"], eps_a, eps_b, quadratic_occ=True)
+    setup_s = time.perf_counter() - t0
+    T = torch.zeros(max(pq.n_T, 1), dtype=torch.float64, device="cuda")
+    plan.iterate(args.warmup, T)
+    torch.cuda.synchronize()
+    plan.set_profiling(True)
+    t0 = time.perf_counter()
+    _, _, e_tot, rmax = plan.iterate(args.steps, T)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) / max(args.steps, 1) * 1e3
+    ms, cnt = plan.phase_times()
+    plan.set_profiling(False)
+    line = [l for l in plan.info().splitlines() if l.startswith("occupied-intermediate")]
+    words = line[0].split() if line else []
+    factors_gb = float(words[words.index("factors") + 1]) if "factors" in words else None
+    flops = float(words[-4]) if line else None
+    occ_ms = ms[9] / max(cnt[9], 1)
+    # algorithmic bytes: the factors once per residual (the dotted amplitude
+    # blocks, read by every contribution of their pair, are mostly L2 hits)
+    gbps = factors_gb / (occ_ms / 1e3) if factors_gb and occ_ms > 0 else None
+    row = {"ms_per_step": round(ms_step, 3), "occ_kernels_ms": round(occ_ms, 3), "flops_per_residual": flops,
+           "factors_GB": factors_gb, "factor_read_GBps": round(gbps, 1) if gbps else None,
+           "factor_read_hbm_frac": round(gbps / 8000.0, 4) if gbps else None, "setup_s": round(setup_s, 1),
+           "energy_after": float(e_tot.cpu()[0]), "iterations": args.warmup + args.steps,
+           "max_abs_R": float(rmax.cpu()[0])}
+    log("occupied-intermediate leg: %s" % row)
+    plan.close()
+    del T
     torch.cuda.empty_cache()
     return row
 
