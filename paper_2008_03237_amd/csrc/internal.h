@@ -231,6 +231,8 @@ struct OccArgs {
   double* shift;            // [n_blocks]
 };
 hipError_t launch_occ_weights(const OccArgs& a, const double* T, hipStream_t s);
+// G[offs[b] ..] (ns[b] x ns[b]) transposed in place, for every b < count
+hipError_t launch_transpose_blocks(const int64_t* offs, const int32_t* ns, int64_t count, double* G, hipStream_t s);
 // ring.hip: every unit's ring contractions into its block's last partial slot
 hipError_t launch_ring(const RxUnit* units, int64_t n_units, const RxTerm* terms, const BlockDev* blocks,
                        const double* T, const double* S, const double* ring_ints, double* ws, hipStream_t s);

@@ -803,6 +803,8 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   // -(F^s1_ii + F^s2_jj) T per block.
   P->qocc = qocc;
   std::vector<QuadCpl> occ_prep;   // factors S K S^T built once (the prepare kernel of the quadratic term)
+  std::vector<int64_t> occ_tr_off;  // factors stored transposed (their dots then read T row by row)
+  std::vector<int32_t> occ_tr_n;
   if (qocc) {
     std::map<std::tuple<int, int, int>, int32_t> keyid;
     auto key_add = [&](int m, int j, int sp) -> int32_t {
@@ -889,6 +891,10 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
           QuadCpl qc = *prep;
           qc.off_G = P->n_occG;
           c.off_G = P->n_occG;
+          if (trG) {
+            occ_tr_off.push_back(P->n_occG);
+            occ_tr_n.push_back((int32_t)nq);
+          }
           P->n_occG += nn;
           occ_prep.push_back(qc);
           P->flops_occ_prep += 2.0 * nq * (double)qc.nq * (nq + qc.nq);
@@ -914,7 +920,10 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
         qc.np = (int32_t)nq;
         qc.nq = P->cpl_h[e].nsrc;
         qc.transK = m > n;
-        add(m, j, n, 0, 0, 0, &qc);
+        // for j the pair's second index every block of the dot enters
+        // transposed: the factor is stored transposed instead, so that the
+        // dots read both operands in the same order
+        add(m, j, n, 0, 0, (j == d.j && d.i != d.j) ? 1 : 0, &qc);
       }
     }
     P->occ_key_rowptr_h.assign(per_key.size() + 1, 0);
@@ -1105,9 +1114,24 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
       QuadCpl* d_prep = nullptr;
       if ((st = upload(&d_prep, occ_prep, "occupied-intermediate factor list", s)) != DLPNO_OK) return destroy_fail(st);
       const hipError_t pe = launch_quad_prepare(d_prep, (int64_t)occ_prep.size(), P->in.S, P->in.K, P->d_occG, s);
+      int64_t* d_toff = nullptr;
+      int32_t* d_tn = nullptr;
+      hipError_t te = hipSuccess;
+      if (pe == hipSuccess && !occ_tr_off.empty()) {
+        if ((st = upload(&d_toff, occ_tr_off, "factor transposes", s)) != DLPNO_OK ||
+            (st = upload(&d_tn, occ_tr_n, "factor transposes", s)) != DLPNO_OK) {
+          (void)hipFree(d_prep);
+          (void)hipFree(d_toff);
+          return destroy_fail(st);
+        }
+        te = launch_transpose_blocks(d_toff, d_tn, (int64_t)occ_tr_off.size(), P->d_occG, s);
+      }
       const hipError_t se = hipStreamSynchronize(s);
       (void)hipFree(d_prep);
-      if (pe != hipSuccess || se != hipSuccess) return destroy_fail(fail(DLPNO_ERR_HIP, "occupied-intermediate factors"));
+      (void)hipFree(d_toff);
+      (void)hipFree(d_tn);
+      if (pe != hipSuccess || te != hipSuccess || se != hipSuccess)
+        return destroy_fail(fail(DLPNO_ERR_HIP, "occupied-intermediate factors"));
     }
   }
   if (!P->rx_units_h.empty()) {

@@ -125,14 +125,33 @@ __global__ __launch_bounds__(256) void occ_dots_kernel(const OccCtb* __restrict_
     const double* Gp = (c.from_K ? K : G) + c.off_G;
     const int nd = c.n, nn = c.n * c.n;
     double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    for (int x = lane; x < nn; x += 64) {
-      const double gv = Gp[x];
-      const int xr = x / nd, xc = x - xr * nd, xt = xc * nd + xr;
+    if (!(c.tr[0][0] | c.tr[0][1] | c.tr[1][0] | c.tr[1][1])) {
+      // every block in the factor's order (all but some dots of diagonal
+      // pairs): four elements per lane and pass, no index arithmetic
+      for (int x0 = lane; x0 < nn; x0 += 256) {
+        double gv[4];
 #pragma unroll
-      for (int sp = 0; sp < 2; ++sp)
+        for (int u = 0; u < 4; ++u) gv[u] = x0 + 64 * u < nn ? Gp[x0 + 64 * u] : 0.0;
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
-          if (c.off_T[sp][b] >= 0) acc[sp][b] += gv * T[c.off_T[sp][b] + (c.tr[sp][b] ? xt : x)];
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            if (c.off_T[sp][b] >= 0) {
+#pragma unroll
+              for (int u = 0; u < 4; ++u)
+                if (x0 + 64 * u < nn) acc[sp][b] += gv[u] * T[c.off_T[sp][b] + x0 + 64 * u];
+            }
+      }
+    } else {
+      for (int x = lane; x < nn; x += 64) {
+        const double gv = Gp[x];
+        const int xr = x / nd, xc = x - xr * nd, xt = xc * nd + xr;
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            if (c.off_T[sp][b] >= 0) acc[sp][b] += gv * T[c.off_T[sp][b] + (c.tr[sp][b] ? xt : x)];
+      }
     }
 #pragma unroll
     for (int sp = 0; sp < 2; ++sp)
@@ -171,7 +190,35 @@ __global__ __launch_bounds__(256) void occ_apply_kernel(const OccTerm* __restric
   }
 }
 
+// in-place transposes of square blocks (n <= 64), one workgroup per block
+__global__ __launch_bounds__(256) void transpose_blocks_kernel(const int64_t* __restrict__ offs,
+                                                               const int32_t* __restrict__ ns, int64_t count,
+                                                               double* __restrict__ G) {
+  __shared__ double tile[64 * 65];
+  for (int64_t b = blockIdx.x; b < count; b += gridDim.x) {
+    const int64_t o = offs[b];
+    const int nd = ns[b], nn = nd * nd;
+    __syncthreads();
+    for (int x = threadIdx.x; x < nn; x += blockDim.x) {
+      const int r = x / nd, c = x - r * nd;
+      tile[r * 65 + c] = G[o + x];
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < nn; x += blockDim.x) {
+      const int r = x / nd, c = x - r * nd;
+      G[o + x] = tile[c * 65 + r];
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_transpose_blocks(const int64_t* offs, const int32_t* ns, int64_t count, double* G, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  const int64_t grid = count < (1 << 20) ? count : (1 << 20);
+  hipLaunchKernelGGL(transpose_blocks_kernel, dim3((unsigned)grid), dim3(256), 0, s, offs, ns, count, G);
+  return hipGetLastError();
+}
 
 hipError_t launch_occ_weights(const OccArgs& a, const double* T, hipStream_t s) {
   if (a.n_ctb > 0) {
