@@ -28,10 +28,12 @@
 // finishing kernel adds to the residual: the result is deterministic.
 //
 // Operands are read with raw buffer loads whose resource covers exactly one
-// matrix: reads past its end return zero.  Padding the source index to
-// whole tiles only reaches rows of op(T_q) or M beyond the source's PNOs
-// (zero) or, inside the matrix, elements that meet such zeros; padding the
-// target index only reaches output rows and columns that are never stored.
+// matrix: reads past its end return zero.  Padding the source index (to
+// chunks of four k-steps and tiles of 16) only reaches rows of L or M beyond
+// the source's PNOs, which lie past the end of their block and read as zero,
+// and elements of the source block that are finite and meet those zeros;
+// padding the target index only reaches output rows and columns that are
+// never stored.
 #include <hip/hip_runtime.h>
 
 #include "grouped_impl.h"
