@@ -1,4 +1,6 @@
-// Weights of the quadratic CCSD term on the hole-hole couplings.
+// T-dependent weights of the quadratic CCSD terms: the quadratic term on the
+// hole-hole couplings, and the quadratic part of the occupied Fock
+// intermediate on the occupied-Fock couplings.
 //
 // The spin-orbital term 1/4 sum_KLCD <KL||CD> t_IJ^CD t_KL^AB is the
 // hole-hole ladder 1/2 sum_KL W_KLIJ t_KL^AB with <KL||IJ> replaced by
@@ -24,8 +26,11 @@
 // pair itself adds -(F^s_ii + F^s'_jj) T.  Per spin, F^s_mj = sum over n and
 // its spin of <G_(m,n), T^{s s_n}_(j,n)>, G[e][f] = (m e | n f) over the PNOs
 // of {j, n}, taken as S K_(m,n) S^T of the source pair {m, n} (built once,
-// like the factors above; K_(j,n) itself for m = j).  Per residual: one wave
-// per contribution forms its dots, one thread per F adds its contributions in
+// like the factors above; K_(j,n) itself for m = j).  When j is the pair's
+// second index the blocks enter the dot transposed, so such factors are
+// stored transposed once and every dot but some of diagonal pairs reads the
+// factor and the blocks in the same order.  Per residual: one wave per
+// contribution forms its dots, one thread per F adds its contributions in
 // a fixed order, one thread per term or block writes the dressed weight or
 // the diagonal shift that the finishing kernel applies.
 #include <hip/hip_runtime.h>
