@@ -127,6 +127,18 @@ def test_full_chain_sampled():
     plan.close()
 
 
+def test_noalloc_residual_applies_the_shift():
+    prob = _prob("mini")
+    plan, dev = device_problem(prob, quadratic_occ=True)
+    R = plan.residual(dev["T"])
+    R2 = torch.full_like(R, float("nan"))
+    plan.residual_noalloc(dev["T"], R2)
+    torch.cuda.synchronize()
+    ins = _inside(prob)
+    assert torch.equal(R[ins], R2[ins])
+    plan.close()
+
+
 def test_refusals():
     from paper_2008_03237_amd import DlpnoError
     prob = _prob("tiny")

@@ -625,3 +625,23 @@ def test_occupied_intermediate_is_quadratic_and_uses_the_diagonal():
         np.testing.assert_allclose(d2[k], 4.0 * d1[k], rtol=1e-9, atol=1e-13)
     assert max(np.abs(v).max() for v in d1.values()) > 1e-6
     assert abs(oracle.occ_intermediate(inp, T, 0, 0, 0)) > 0.0
+
+
+@pytest.mark.parametrize("somos", [(), (1, 3)])
+def test_all_further_terms_together_match_bruteforce(somos):
+    # hole-hole ladder, its quadratic term, ring/exchange term and the
+    # occupied intermediate at once: the pair form and the spin-orbital brute
+    # force agree, so no term double-counts another
+    rng = np.random.default_rng(91 + len(somos))
+    inp = make_inputs(rng, n_occ=5, somos=somos, npno=4, naux=6, shared_space=True, hole=0.05, ring=0.05)
+    inp.quadratic = True
+    inp.quadratic_occ = True
+    T = random_T(rng, inp, scale=0.1)
+    R = oracle.residual_os(inp, T)
+    Tb = {(inp.pairs[p], name): v for (p, name), v in T.items()}
+    Kp = {inp.pairs[p]: inp.K[p] for p in range(len(inp.pairs))}
+    Rbf, _ = oracle.residual_spinorbital(inp.n_occ, inp.is_somo, inp.B(0), Kp, inp.eps_a[0], inp.eps_b[0],
+                                         inp.f_a, inp.f_b, Tb, inp.pairs, g_occ=inp.g_occ, quadratic=True,
+                                         g_ovvo=inp.g_ovvo, g_oovv=inp.g_oovv, quadratic_occ=True)
+    for (p, name), r in R.items():
+        np.testing.assert_allclose(r, Rbf[(inp.pairs[p], name)], rtol=0, atol=1e-13)
