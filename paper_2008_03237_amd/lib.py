@@ -149,6 +149,11 @@ class Plan:
     workload.Problem.  B, S, K, eps_a, eps_b: device tensors (kept referenced).
     The same-spin blocks of the amplitudes passed to residual/iterate must be
     antisymmetric (as physical amplitudes are) unless general_T is set.
+    Optional descriptor fields switch on the further CCSD terms: hh_* (the
+    hole-hole ladder; with quadratic=True also its quadratic term) and ring_*
+    (the ring/exchange term, with its integral blocks in the device tensor
+    ring_ints); quadratic_occ=True adds the quadratic part of the occupied
+    Fock intermediate (no further inputs).
     """
 
     def __init__(self, desc, B, S, K, eps_a, eps_b, precision="fp64", diis_max=8, diis_start=3, n_workers=0,
