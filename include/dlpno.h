@@ -139,8 +139,11 @@ typedef struct {
  * each spin, linear in the amplitudes, to every stored block: per block,
  * spin of M and orientation, terms +-S_{p,q} op(T_q) X or J (and their
  * transposes) over the source blocks that exist.  A diagonal target (i == j)
- * lists role 0 only; each of its couplings serves both index orders.  FP64
- * plans only; the vector-Jacobian product refuses such plans. */
+ * lists role 0 only; each of its couplings serves both index orders.  The
+ * contractions run in FP64 on the FP64 amplitudes in every precision (in
+ * dlpno_solve_mixed also on the corrections of the low-precision
+ * iterations: the term is linear).  The vector-Jacobian product refuses
+ * such plans. */
 typedef struct {
   int32_t src_pair;
   int32_t m;
@@ -202,7 +205,7 @@ typedef struct {
 #define DLPNO_FLAG_GENERAL_T 1
 
 /* Adds the quadratic CCSD term 1/4 sum_KLCD <KL||CD> t_IJ^CD t_KL^AB over the
- * hole-hole couplings (so n_hh > 0 is required; FP64 plans only).  Reduced to
+ * hole-hole couplings (so n_hh > 0 is required).  Reduced to
  * spin blocks it is the hole-hole ladder with the weights (k i | l j) +
  * c <K_(k,l), S_pq^T T_p S_pq>, c = 1/2 same spin and 1 opposite spin,
  * K_(k,l)[c][d] = (k c | l d) over the source pair's PNOs (its K block, or the
@@ -217,8 +220,7 @@ typedef struct {
 #define DLPNO_FLAG_QUADRATIC 2
 
 /* Adds the quadratic part of the occupied Fock intermediate of CCSD,
- * -P(IJ) sum_M t_IM^AB F_MJ with F_MJ = 1/2 sum_NEF t_JN^EF <MN||EF> (FP64
- * plans only).  Reduced to spin blocks, F^s_mj = sum over occupied n and its
+ * -P(IJ) sum_M t_IM^AB F_MJ with F_MJ = 1/2 sum_NEF t_JN^EF <MN||EF>.  Reduced to spin blocks, F^s_mj = sum over occupied n and its
  * spin of <G_(m,n), T^{s s_n}_(j,n)> with G[e][f] = (m e | n f) over the PNOs
  * of {j, n}, taken as the projection S K_(m,n) S^T of the exchange integrals
  * of {m, n} (transposed for m > n) through the listed occupied-Fock coupling
@@ -226,8 +228,11 @@ typedef struct {
  * then dresses the occupied Fock weight of every listed projection term,
  * f^s_kj -> f^s_kj + F^s_kj, and adds -(F^s_ii + F^s'_jj) T to each block.
  * Sums run over the listed couplings only.  The factors S K S^T are built once
- * by dlpno_plan_create; every residual evaluation forms F from T first (phase
- * 9 of dlpno_phase_times).  The vector-Jacobian product refuses such plans. */
+ * by dlpno_plan_create; every residual evaluation of T forms F from T first,
+ * in FP64 (phase 9 of dlpno_phase_times).  In dlpno_solve_mixed the FP64
+ * refinement residuals form it and the low-precision iterations on the
+ * correction equation keep it.  The vector-Jacobian product refuses such
+ * plans. */
 #define DLPNO_FLAG_QUADRATIC_OCC 4
 
 typedef struct dlpno_plan dlpno_plan;   /* opaque, owned by the library */

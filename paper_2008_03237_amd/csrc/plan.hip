@@ -482,12 +482,8 @@ extern "C" dlpno_status dlpno_plan_create(const dlpno_problem* prob, const dlpno
   if ((opt.flags & ~(DLPNO_FLAG_GENERAL_T | DLPNO_FLAG_QUADRATIC | DLPNO_FLAG_QUADRATIC_OCC)) != 0)
     return fail(DLPNO_ERR_INVALID_ARG, "unknown option flag");
   const bool qocc = (opt.flags & DLPNO_FLAG_QUADRATIC_OCC) != 0;
-  if (qocc && opt.precision != DLPNO_FP64)
-    return fail(DLPNO_ERR_UNSUPPORTED, "the occupied-intermediate quadratic term needs an FP64 plan");
   const bool quad = (opt.flags & DLPNO_FLAG_QUADRATIC) != 0;
   if (quad && prob->n_hh <= 0) return fail(DLPNO_ERR_INVALID_ARG, "the quadratic term needs hole-hole couplings");
-  if (prob->n_ring > 0 && opt.precision != DLPNO_FP64)
-    return fail(DLPNO_ERR_UNSUPPORTED, "the ring/exchange term needs an FP64 plan");
   if (opt.diis_max > 0 && (opt.diis_start < 1 || opt.diis_start > opt.diis_max))
     return fail(DLPNO_ERR_INVALID_ARG, "diis_start must be in 1..diis_max");
   for (int k = 0; k < n_occ; ++k)
@@ -1298,7 +1294,8 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
                        bool weights) {
   hipError_t e;
   double* const wsp = ws ? ws : P->d_ws;
-  // ring/exchange contractions (FP64 plans only) into the blocks' last slots
+  // ring/exchange contractions into the blocks' last slots, in FP64 on the
+  // FP64 amplitudes (or corrections) whatever the plan's precision
   if (!P->rx_units_h.empty()) {
     phase_begin(P, 10, s);
     e = launch_ring(P->d_rx_units, (int64_t)P->rx_units_h.size(), P->d_rx_terms, P->d_blocks, T, P->in.S,
@@ -1317,9 +1314,11 @@ hipError_t run_grouped(dlpno_plan* P, const double* T, hipStream_t s, int prec, 
     phase_end(P, s);
     if (e != hipSuccess) return e;
   }
-  // the occupied intermediate from T: dressed Fock weights and the diagonal
-  // shift that the finishing kernel applies (FP64 plans only)
-  if (P->qocc) {
+  // the occupied intermediate from T in FP64: dressed Fock weights and the
+  // diagonal shift that the finishing kernel applies; the correction
+  // equations of the mixed solve (weights = false) keep those of the last
+  // FP64 refinement residual
+  if (P->qocc && weights) {
     OccArgs oa{P->d_occ_ctb, (int64_t)P->occ_ctb_h.size(), P->d_occG, P->in.K, P->d_occ_dots, P->d_occ_key_rowptr,
                P->d_occ_key_src, (int64_t)P->occ_key_rowptr_h.size() - 1, P->d_occF, P->d_occ_terms,
                (int64_t)P->occ_terms_h.size(), P->d_terms, P->d_occ_blk_key, P->n_blocks, P->d_occ_shift};
