@@ -37,6 +37,7 @@
 
 #include <algorithm>
 
+#include "grouped_impl.h"
 #include "internal.h"
 
 namespace dlpno {
@@ -118,44 +119,71 @@ __global__ __launch_bounds__(256) void quad_weights_kernel(const QuadCpl* __rest
   }
 }
 
-// one wave per contribution: <G, T_b> (or <G^T, T_b>) summed over its blocks
-// per spin, in a fixed order
+// One wave per contribution: <G, T_b> (or <G^T, T_b>) summed over its blocks
+// per spin, in a fixed order.  Every pass issues all its loads before the
+// first product: the factor and the (up to four) blocks are read through
+// buffer resources that cover exactly one matrix (an absent block has an
+// empty one), so reads past the end, or of an absent block, return zero
+// without a branch, and the trip count is the same for every lane.
 __global__ __launch_bounds__(256) void occ_dots_kernel(const OccCtb* __restrict__ list, int64_t n,
                                                        const double* __restrict__ G, const double* __restrict__ K,
                                                        const double* __restrict__ T, double* __restrict__ dots) {
+  constexpr int U = 4;                       // elements per lane and pass
   const int lane = threadIdx.x & 63;
   const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
   for (int64_t e = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); e < n; e += waves) {
-    const OccCtb c = list[e];
-    const double* Gp = (c.from_K ? K : G) + c.off_G;
-    const int nd = c.n, nn = c.n * c.n;
-    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
-    if (!(c.tr[0][0] | c.tr[0][1] | c.tr[1][0] | c.tr[1][1])) {
-      // every block in the factor's order (all but some dots of diagonal
-      // pairs): four elements per lane and pass, no index arithmetic
-      for (int x0 = lane; x0 < nn; x0 += 256) {
-        double gv[4];
+    const OccCtb& c = list[e];
+    const int nd = uni(c.n);
+    const uint32_t nn = (uint32_t)nd * (uint32_t)nd;
+    const __amdgpu_buffer_rsrc_t gr = rsrc((uni(c.from_K) ? K : G) + uni(c.off_G), nn);
+    __amdgpu_buffer_rsrc_t tr[2][2];
+    bool any_tr = false;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) gv[u] = x0 + 64 * u < nn ? Gp[x0 + 64 * u] : 0.0;
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int64_t o = uni(c.off_T[sp][b]);
+        tr[sp][b] = rsrc(T + (o >= 0 ? o : 0), o >= 0 ? nn : 0u);
+        any_tr |= uni(c.tr[sp][b]) != 0;
+      }
+    double acc[2][2] = {{0.0, 0.0}, {0.0, 0.0}};
+    if (!any_tr) {
+      // every block in the factor's order (all but some dots of diagonal
+      // pairs)
+      for (uint32_t p = 0; p < nn; p += 64 * U) {
+        double gv[U], tv[2][2][U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) gv[u] = Mfma<double>::load(gr, p + 64 * u + lane);
 #pragma unroll
         for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
           for (int b = 0; b < 2; ++b)
-            if (c.off_T[sp][b] >= 0) {
 #pragma unroll
-              for (int u = 0; u < 4; ++u)
-                if (x0 + 64 * u < nn) acc[sp][b] += gv[u] * T[c.off_T[sp][b] + x0 + 64 * u];
-            }
+            for (int u = 0; u < U; ++u) tv[sp][b][u] = Mfma<double>::load(tr[sp][b], p + 64 * u + lane);
+#pragma unroll
+        for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int u = 0; u < U; ++u) acc[sp][b] += gv[u] * tv[sp][b][u];
       }
     } else {
-      for (int x = lane; x < nn; x += 64) {
-        const double gv = Gp[x];
-        const int xr = x / nd, xc = x - xr * nd, xt = xc * nd + xr;
+      int trs[2][2];
+#pragma unroll
+      for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) trs[sp][b] = uni(c.tr[sp][b]);
+      for (uint32_t p = 0; p < nn; p += 64) {
+        // x < nn: element (xr, xc) of the factor; past its end the factor
+        // reads zero, and the block reads an element of the same block
+        // (finite) or, past the block's end, zero
+        const uint32_t x = p + lane;
+        const uint32_t xr = x / (uint32_t)nd, xc = x - xr * (uint32_t)nd, xt = xc * (uint32_t)nd + xr;
+        const double gv = Mfma<double>::load(gr, x);
 #pragma unroll
         for (int sp = 0; sp < 2; ++sp)
 #pragma unroll
-          for (int b = 0; b < 2; ++b)
-            if (c.off_T[sp][b] >= 0) acc[sp][b] += gv * T[c.off_T[sp][b] + (c.tr[sp][b] ? xt : x)];
+          for (int b = 0; b < 2; ++b) acc[sp][b] += gv * Mfma<double>::load(tr[sp][b], trs[sp][b] ? xt : x);
       }
     }
 #pragma unroll
