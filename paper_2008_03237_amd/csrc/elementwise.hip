@@ -63,8 +63,16 @@ __global__ __launch_bounds__(kEwThreads) void finish_kernel(FinishArgs a) {
   __shared__ double part[64 * 64];
   const int nslot = a.no_partials ? 0 : bk.nslot;
   for (int idx = threadIdx.x; idx < nn; idx += kEwThreads) {
+    // four slots' loads in flight at a time, added in slot order
     double v = 0.0;
-    for (int sl = 0; sl < nslot; ++sl) v += ws[(int64_t)sl * nn + idx];
+    for (int sl = 0; sl < nslot; sl += 4) {
+      double p[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) p[u] = sl + u < nslot ? ws[(int64_t)(sl + u) * nn + idx] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (sl + u < nslot) v += p[u];
+    }
     part[idx] = v;
   }
   __syncthreads();
@@ -72,16 +80,22 @@ __global__ __launch_bounds__(kEwThreads) void finish_kernel(FinishArgs a) {
   bool bad = false;
   for (int idx = threadIdx.x; idx < nn; idx += kEwThreads) {
     const int x = idx / n, y = idx - x * n;          // element [a = x][b = y]
+    // every load of the element is issued before the first use
     const double t = T[idx];
-    const double D = (ea[x] + eb[y]) - bk.fsum;
+    const double eax = ea[x], eby = eb[y];
+    const double k0 = a.with_driver ? K[idx] : 0.0;
+    const double k1 = a.with_driver && bk.anti ? K[y * n + x] : 0.0;
+    const double dv = a.drv ? a.drv[bk.off_T + idx] : 0.0;
+    const double sh = a.shift ? a.shift[blk] : 0.0;
+    const double D = (eax + eby) - bk.fsum;
     double kk = 0.0;
     if (a.with_driver) {
-      kk = K[idx];
-      if (bk.anti) kk -= K[y * n + x];
+      kk = k0;
+      if (bk.anti) kk -= k1;
     }
-    double r = (a.drv ? a.drv[bk.off_T + idx] : kk) + D * t;
+    double r = (a.drv ? dv : kk) + D * t;
     r += part[y * n + x];
-    if (a.shift) r -= a.shift[blk] * t;           // diagonal part of the occupied intermediate
+    if (a.shift) r -= sh * t;                     // diagonal part of the occupied intermediate
     if (x >= bk.rows || y >= bk.cols) r = 0.0;   // alpha index on a SOMO function
     if (!isfinite(r)) bad = true;
     rmax = fmax(rmax, fabs(r));
