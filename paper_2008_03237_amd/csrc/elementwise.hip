@@ -277,33 +277,54 @@ __global__ __launch_bounds__(256) void diis_dots_kernel(const double* errs, int6
   }
 }
 
-// symmetric eigenvalues by cyclic Jacobi (n <= 9), for the condition number
-__device__ void sym_eigs(double* A, int n, double* ev) {
+// symmetric eigenvalues by cyclic Jacobi (n <= 9), for the condition number.
+// The matrix is held in registers: every loop is unrolled to the bound 9 with
+// guards on n, so all indices are constants (with run-time indices the
+// elements lived in LDS or scratch memory, and each dependent access paid
+// its latency on the single thread that runs this).
+__device__ void sym_eigs(const double* Ain, int n, double* ev) {
+  double A[9][9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+#pragma unroll
+    for (int j = 0; j < 9; ++j) A[i][j] = (i < n && j < n) ? Ain[i * 9 + j] : 0.0;
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) off += A[p * 9 + q] * A[p * 9 + q];
+#pragma unroll
+    for (int p = 0; p < 9; ++p)
+#pragma unroll
+      for (int q = p + 1; q < 9; ++q)
+        if (q < n) off += A[p][q] * A[p][q];
     if (off < 1e-300) break;
-    for (int p = 0; p < n; ++p)
-      for (int q = p + 1; q < n; ++q) {
-        const double apq = A[p * 9 + q];
+#pragma unroll
+    for (int p = 0; p < 9; ++p)
+#pragma unroll
+      for (int q = p + 1; q < 9; ++q) {
+        if (q >= n) continue;
+        const double apq = A[p][q];
         if (apq == 0.0) continue;
-        const double theta = (A[q * 9 + q] - A[p * 9 + p]) / (2.0 * apq);
+        const double theta = (A[q][q] - A[p][p]) / (2.0 * apq);
         const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
         const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
-        for (int k = 0; k < n; ++k) {
-          const double akp = A[k * 9 + p], akq = A[k * 9 + q];
-          A[k * 9 + p] = c * akp - s * akq;
-          A[k * 9 + q] = s * akp + c * akq;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          if (k >= n) continue;
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - s * akq;
+          A[k][q] = s * akp + c * akq;
         }
-        for (int k = 0; k < n; ++k) {
-          const double apk = A[p * 9 + k], aqk = A[q * 9 + k];
-          A[p * 9 + k] = c * apk - s * aqk;
-          A[q * 9 + k] = s * apk + c * aqk;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+          if (k >= n) continue;
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - s * aqk;
+          A[q][k] = s * apk + c * aqk;
         }
       }
   }
-  for (int k = 0; k < n; ++k) ev[k] = A[k * 9 + k];
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+    if (k < n) ev[k] = A[k][k];
 }
 
 // Gram update, bordered system [[G, -1], [-1, 0]] c = [0, -1] with
