@@ -255,14 +255,18 @@ __global__ __launch_bounds__(256) void diis_dots_kernel(const double* errs, int6
   double acc[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+  int64_t so[8];                                    // k-th newest vector
+#pragma unroll
+  for (int k = 0; k < 8; ++k) so[k] = (int64_t)((head - k + mx) % mx) * n;
   for (int64_t x = lo + threadIdx.x; x < hi; x += 256) {
+    // every load of the element is issued before the first product
     const double v = eh[x];
+    double e[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) e[k] = k < cnt ? errs[so[k] + x] : 0.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k)
-      if (k < cnt) {
-        const int slot = (head - k + mx) % mx;      // k-th newest
-        acc[k] += v * errs[(int64_t)slot * n + x];
-      }
+      if (k < cnt) acc[k] += v * e[k];
   }
   __shared__ double ls[8][4];
 #pragma unroll
@@ -433,19 +437,25 @@ __global__ __launch_bounds__(256) void diis_solve_kernel(DiisState* st, const do
 __global__ __launch_bounds__(256) void diis_extrap_kernel(const double* vecs, int64_t n, const DiisState* st,
                                                           double* T) {
   const int cnt = st->count, head = st->head, mx = st->max;
-  int sl[8];
+  // oldest to newest; loops unrolled to the bound 8 with guards on the count,
+  // so the slots and coefficients stay in registers and every load of an
+  // element is issued before the first product
+  int64_t so[8];
   double c[8];
+#pragma unroll
   for (int k = 0; k < 8; ++k) {
-    sl[k] = 0;
-    c[k] = 0.0;
-  }
-  for (int k = 0; k < cnt; ++k) {
-    sl[k] = (head - (cnt - 1 - k) + mx) % mx;
-    c[k] = st->coef[sl[k]];
+    const int sl = k < cnt ? (head - (cnt - 1 - k) + mx) % mx : 0;
+    so[k] = (int64_t)sl * n;
+    c[k] = k < cnt ? st->coef[sl] : 0.0;
   }
   for (int64_t x = (int64_t)blockIdx.x * 256 + threadIdx.x; x < n; x += (int64_t)gridDim.x * 256) {
+    double v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = k < cnt ? vecs[so[k] + x] : 0.0;
     double s = 0.0;
-    for (int k = 0; k < cnt; ++k) s += c[k] * vecs[(int64_t)sl[k] * n + x];
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < cnt) s += c[k] * v[k];
     T[x] = s;
   }
 }
